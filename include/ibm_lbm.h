@@ -1,0 +1,214 @@
+/*
+ * ibm_lbm.h -- C ABI of the MI355X (gfx950) library for the coupled immersed
+ * boundary / lattice Boltzmann / finite element capsule timestep of Krueger,
+ * Varnik and Raabe, arXiv:1004.2416.
+ *
+ * One timestep (Sec. II.C, sub-steps 1-5) is:
+ *   1. Skalak membrane forces of every node from its faces (Sec. II.B),
+ *   2. spreading of those forces to the lattice through the m-point discrete
+ *      delta function (Sec. II.C, Eq. forcespreading),
+ *   3. D3Q19 BGK collision with Guo forcing and streaming, periodic in x and
+ *      y, moving-wall bounce-back at the z walls (Sec. II.A),
+ *   4. interpolation of the new lattice velocity to the old node positions
+ *      (Sec. II.C, Eq. velocityinterpolation),
+ *   5. Euler advection of the nodes (Sec. II.C, Eq. positionupdate).
+ *
+ * Units are lattice units (Delta x = Delta t = 1, rho_0 = 1).  The lattice
+ * has nx * ny * nz fluid nodes at integer coordinates; walls lie at
+ * z = -1/2 (moving with -u_w along x) and z = nz - 1/2 (moving with +u_w).
+ *
+ * Memory: the library allocates no device memory.  The caller allocates the
+ * lattice state and the membrane state as device buffers of the sizes the
+ * *_bytes queries report (for instance as torch tensors) and keeps them alive
+ * until ibm_destroy; the library never frees them.  Host arrays passed to the
+ * library are copied before the call returns.
+ *
+ * Streams: all work is enqueued on the hipStream_t given at creation.
+ * ibm_step and ibm_set_* return without waiting; ibm_get_*, ibm_observables
+ * and ibm_synchronize wait for the stream and report device-side errors.
+ *
+ * Errors: every call returns IBM_OK (0) or a negative IBM_ERR_* code and then
+ * ibm_last_error() describes the failure (thread-local string).  No C++
+ * exception crosses this interface.  A handle whose device state reported an
+ * error stays usable; the flags are cleared when reported.
+ *
+ * Threading: a handle must not be used from two threads at once.
+ */
+#ifndef IBM_LBM_H
+#define IBM_LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ------------------------------------------------------- */
+#define IBM_OK 0
+#define IBM_ERR_INVALID_ARG (-1)        /* bad size, pointer or parameter       */
+#define IBM_ERR_BAD_STATE (-2)          /* call not valid in the handle's state */
+#define IBM_ERR_HIP (-3)                /* a HIP runtime call failed            */
+#define IBM_ERR_STENCIL_HITS_WALL (-4)  /* a delta stencil reached z < 0 or z >= nz */
+#define IBM_ERR_NONFINITE (-5)          /* NaN or Inf found in observables      */
+#define IBM_ERR_INVERTED_FACE (-6)      /* a membrane face degenerated or flipped */
+
+/* ---- population storage ------------------------------------------------- */
+/* Populations are stored as deviations f_i - w_i from the lattice weights,
+ * structure of arrays [19][nz][ny][nx] (x fastest), arithmetic in FP32. */
+#define IBM_STORAGE_FP32 0
+#define IBM_STORAGE_FP16 1   /* deviations scaled per direction, FP16 storage */
+
+/* ---- equilibrium --------------------------------------------------------- */
+#define IBM_EQ_QUADRATIC 0   /* Sec. II.A, Eq. (equilibrium)                  */
+#define IBM_EQ_LINEAR 1      /* Sec. IV.A linearised form w_i rho (1 + 3 c.u) */
+
+/* ---- field selectors for ibm_get_fields / ibm_set_fields ----------------- */
+#define IBM_FIELD_POPS 0   /* [19][nz][ny][nx] f_i(x, t), unshifted, post-streaming */
+#define IBM_FIELD_RHO 1    /* [nz][ny][nx] density, Eq. (lbmmomenta0)              */
+#define IBM_FIELD_U 2      /* [3][nz][ny][nx] (sum_i c_i f_i + f/2)/rho with the force
+                              density f of the last step (zero before the first) */
+#define IBM_FIELD_FORCE 3  /* [3][nz][ny][nx] force density f(X) spread in the last step */
+
+/* ---- per-capsule observables (ibm_observables), Sec. III ------------------ */
+#define IBM_OBS_V 0        /* enclosed volume                                   */
+#define IBM_OBS_CX 1       /* volume centroid x, y, z (unwrapped coordinates)   */
+#define IBM_OBS_CY 2
+#define IBM_OBS_CZ 3
+#define IBM_OBS_D 4        /* Taylor deformation (r_a - r_c)/(r_a + r_c)        */
+#define IBM_OBS_THETA 5    /* inclination of the major axis in the xz plane, rad,
+                              in (-pi/2, pi/2]; NaN when the two smallest
+                              eigenvalues are degenerate                        */
+#define IBM_OBS_RA 6       /* semiaxes of the equivalent ellipsoid              */
+#define IBM_OBS_RB 7
+#define IBM_OBS_RC 8
+#define IBM_OBS_AREA 9     /* total face area                                   */
+#define IBM_OBS_IXX 10     /* inertia tensor per unit mass about the centroid:
+                              xx, yy, zz, xy, xz, yz                           */
+#define IBM_OBS_N 16
+
+/* ---- kernel phases (ibm_profile_step) ------------------------------------ */
+#define IBM_PHASE_FORCES 0   /* Skalak nodal forces            (step 1) */
+#define IBM_PHASE_SPREAD 1   /* force spreading                (step 2) */
+#define IBM_PHASE_LBM 2      /* collide + stream + walls       (step 3) */
+#define IBM_PHASE_INTERP 3   /* interpolation + advection      (steps 4, 5) */
+#define IBM_N_PHASES 4
+
+/* ---- options (ibm_set_option) --------------------------------------------- */
+#define IBM_OPT_GRAPH 0        /* 1 (default): replay the step chain as a
+                                  captured hipGraph; 0: plain launches      */
+#define IBM_OPT_EQUILIBRIUM 1  /* IBM_EQ_QUADRATIC (default) or IBM_EQ_LINEAR */
+#define IBM_OPT_ADVECTION 2    /* 0 (default): Euler, Eq. (positionupdate);
+                                  1: Adams-Bashforth, Sec. II.C             */
+#define IBM_OPT_RECENTER 3     /* steps between re-centring of the capsule
+                                  frames (default 64, >= 1)                 */
+
+typedef struct ibm_lattice ibm_lattice;
+
+/* Bytes of device memory the lattice state needs (populations, two force
+ * fields and their tile stamps, control words).  storage: IBM_STORAGE_*. */
+int ibm_lattice_bytes(int nx, int ny, int nz, int storage, size_t *bytes);
+
+/* Create a lattice of nx * ny * nz nodes with BGK relaxation time tau > 1/2
+ * (Sec. II.A, Eq. lbequation; nu = (tau - 1/2)/3).  dev_state: device buffer
+ * of at least ibm_lattice_bytes bytes, 256-byte aligned, owned by the caller.
+ * stream: the hipStream_t all work goes to (NULL: the null stream).  The
+ * fluid starts at rest (f_i = w_i) with the walls at rest.  On success *out
+ * receives the handle. */
+int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage,
+                       void *dev_state, size_t bytes, void *stream,
+                       ibm_lattice **out);
+
+/* Set the wall speed u_w (|u_w| < 0.3): the top wall moves with +u_w along
+ * x and the bottom wall with -u_w, shear rate 2 u_w / nz (Sec. II.A).  With
+ * init_profile = 1 the populations are also reset to the equilibrium of
+ * rho = 1 and the linear profile u_x(z) = u_w (2 z + 1 - nz) / nz, and the
+ * step counter to 0. */
+int ibm_set_shear(ibm_lattice *lat, double u_w, int init_profile);
+
+/* Bytes of device memory for a membrane of n_caps capsules with the given
+ * node and face counts. */
+int ibm_membrane_bytes(int n_caps, const int *nodes_per_cap,
+                       const int *faces_per_cap, size_t *bytes);
+
+/* Attach the capsules (at most one call per lattice).
+ *   xyz  host [sum nodes][3] FP64: stress-free reference shape in lattice
+ *        coordinates, which is also the initial shape (Sec. II.B, "all faces
+ *        undeformed" at t = 0).  Each capsule keeps an integer origin
+ *        floor(mean of its nodes) and FP32 node coordinates relative to it;
+ *        the reference geometry is computed in FP64 from those FP32 values.
+ *   tri  host [sum faces][3] node indices local to each capsule, counter-
+ *        clockwise seen from outside.
+ *   ks, ka  host [n_caps] surface shear and area dilation moduli of Skalak's
+ *        law (Sec. II.B, Eq. constitutivelaw); C = ka / ks.
+ *   m    delta width 2, 3 or 4 (Sec. II.C, Eqs. 2point, 3point, 4point).
+ *   dev_mem  device buffer of ibm_membrane_bytes bytes, owned by the caller.
+ * Fails with IBM_ERR_STENCIL_HITS_WALL if a stencil would reach a wall and
+ * with IBM_ERR_INVERTED_FACE for a degenerate face. */
+int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
+                        const int *faces_per_cap, const double *xyz,
+                        const int32_t *tri, const double *ks, const double *ka,
+                        int m, void *dev_mem, size_t bytes);
+
+/* Enqueue n >= 0 full timesteps (Sec. II.C sub-steps 1-5; without a membrane,
+ * only the lattice update). */
+int ibm_step(ibm_lattice *lat, int64_t n);
+
+/* Number of timesteps taken since creation or the last profile reset. */
+int64_t ibm_step_count(const ibm_lattice *lat);
+
+/* Write a field (IBM_FIELD_*) as FP64 into the device buffer dst (layouts
+ * above), then wait for the stream. */
+int ibm_get_fields(ibm_lattice *lat, int what, double *dst_dev);
+
+/* Overwrite the populations (what = IBM_FIELD_POPS) from the device FP64
+ * buffer src [19][nz][ny][nx] of unshifted post-streaming values; they are
+ * rounded to the storage format.  Enqueued, does not wait. */
+int ibm_set_fields(ibm_lattice *lat, int what, const double *src_dev);
+
+/* Write node positions (unwrapped lattice coordinates), the nodal forces
+ * F_i(t) and the node velocities u_i(t + 1) of the last step as FP64 [nn][3]
+ * into device buffers (any may be NULL), nodes in creation order; waits. */
+int ibm_get_mesh(ibm_lattice *lat, double *xyz_dev, double *force_dev,
+                 double *vel_dev);
+
+/* Overwrite all node positions from host FP64 [nn][3]; each capsule's origin
+ * becomes floor(mean of its new nodes).  The reference shape is unchanged.
+ * Fails with IBM_ERR_STENCIL_HITS_WALL if a stencil would reach a wall. */
+int ibm_set_mesh(ibm_lattice *lat, const double *xyz_host);
+
+/* Shape observables of every capsule (Sec. III): out_host [n_caps][IBM_OBS_N]
+ * FP64, from FP64 reductions on the device; waits. */
+int ibm_observables(ibm_lattice *lat, double *out_host);
+
+/* Wait for the stream; report device-side error flags. */
+int ibm_synchronize(ibm_lattice *lat);
+
+/* Set an option IBM_OPT_* (see above). */
+int ibm_set_option(ibm_lattice *lat, int option, int value);
+
+/* Run n timesteps with plain launches and HIP events between the kernels of
+ * every step; ms_per_phase[IBM_N_PHASES] receives the mean duration of each
+ * phase per step in milliseconds (a phase that did not run gets 0).  For
+ * measurement; waits. */
+int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase);
+
+/* Release the handle (not the caller's device buffers); waits first. */
+int ibm_destroy(ibm_lattice *lat);
+
+/* Thread-local description of the last error ("" if none). */
+const char *ibm_last_error(void);
+
+/* Icosahedron subdivided `level` times, nodes pushed radially onto the sphere
+ * of radius r about (cx, cy, cz) (Sec. II.D, Fig. 3): nn = 10 * 4^level + 2
+ * nodes, nf = 20 * 4^level faces, counter-clockwise seen from outside.
+ * xyz host [nn][3], tri host [nf][3].  0 <= level <= 7. */
+int ibm_icosphere_size(int level, int *nn, int *nf);
+int ibm_icosphere(int level, double r, double cx, double cy, double cz,
+                  double *xyz, int32_t *tri);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* IBM_LBM_H */
