@@ -1,0 +1,207 @@
+"""Benchmark: lattice-node updates per second (MLUPS) of the full coupled
+IB-LB-FEM timestep on one MI355X, with the HBM roofline fraction of the
+collide-stream kernel and the FP64 CPU oracle timed on the host beside it.
+
+    python bench.py [--steps K] [--warmup W] [--workload c2] [--storage fp32]
+
+One step = Skalak forces, spreading, collide-stream with walls, interpolation
+and advection (Sec. II.C) over the whole lattice and every capsule.  Inputs
+are synthetic (the shear-flow workloads of paper_1004_2416_amd.workloads) and
+resident in HBM before timing.  Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+METRIC = "IB-LBM step MLUPS, % HBM roofline; batched/FP16/adjoint vs plain FP32"
+KERNEL_SOURCES = ("paper_1004_2416_amd/csrc/lbm_kernels.hip", "paper_1004_2416_amd/csrc/common.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_stream_traffic.txt")
+
+
+def bytes_per_node(storage: str) -> int:
+    """Algorithmic bytes of one lattice-node update: the 19 populations read
+    once and written once (FP32: 4 B, FP16: 2 B each)."""
+    return 19 * 2 * (4 if storage == "fp32" else 2)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str, storage: str):
+    """HBM bytes per collide-stream launch from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    src = kernel_source_hash()
+    for line in open(TRAFFIC_FILE):
+        parts = line.split()
+        if len(parts) == 5 and parts[0] == workload and parts[1] == storage and parts[4] == src:
+            return float(parts[2]) + float(parts[3])
+    return None
+
+
+def setup(workload: str, storage: str, graph: bool):
+    from paper_1004_2416_amd import binding as B
+    from paper_1004_2416_amd import workloads as W
+
+    wl = W.config(workload)
+    lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau, storage=storage)
+    lat.set_shear(wl.u_w, init_profile=True)
+    meshes = [B.icosphere(c.level, c.r, c.center) for c in wl.capsules]
+    lat.add_capsules(meshes, [c.ks for c in wl.capsules], [c.ka for c in wl.capsules], wl.m)
+    lat.set_option(B.OPT_GRAPH, int(graph))
+    return wl, lat
+
+
+def cpu_baseline(workload: str, seconds: float):
+    """The FP64 oracle on the host cores: whole coupled steps of the same
+    workload from the same initial state, until `seconds` have passed."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1004_2416_amd import workloads as W
+
+    wl = W.config(workload)
+    xs, ts, ks, ka = [], [], [], []
+    off = 0
+    for c in wl.capsules:
+        x, t = O.icosphere(c.level, c.r, c.center)
+        xs.append(x)
+        ts.append(t + off)
+        off += len(x)
+        ks += [c.ks] * len(t)
+        ka += [c.ka] * len(t)
+    x = np.concatenate(xs)
+    f = np.empty((19, wl.nz, wl.ny, wl.nx))
+    for z in range(wl.nz):
+        ux = wl.u_w * (2 * z + 1 - wl.nz) / wl.nz
+        f[:, z] = O.equilibrium(1.0, [ux, 0.0, 0.0])[:, None, None]
+    sim = O.Simulation(f, x, x, np.concatenate(ts), ks, ka, wl.tau, wl.u_w, wl.m)
+    sim.run(1)  # first touch of the arrays
+    steps, t0 = 0, time.perf_counter()
+    while True:
+        sim.run(1)
+        steps += 1
+        dt = time.perf_counter() - t0
+        if dt >= seconds and steps >= 2:
+            break
+    return {"value": round(wl.n_nodes_lattice * steps / dt / 1e6, 3), "unit": "MLUPS",
+            "cores": O.max_threads(), "kind": "oracle",
+            "sample": f"{steps} full FP64 coupled steps of {wl.name} in {dt:.1f} s"}
+
+
+def copy_calibration(mib: int):
+    """A plain device-to-device copy of known size, for scaling the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = mib * (1 << 20) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 5}))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=1000)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--profile-steps", type=int, default=400)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mib", type=int, default=0)
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
+              "multi-GPU path; see DESIGN.md for how the timestep would shard.", flush=True)
+        sys.exit(2)
+    if args.copy_calibration_mib:
+        copy_calibration(args.copy_calibration_mib)
+        return
+
+    import torch
+    wl, lat = setup(args.workload, args.storage, not args.no_graph)
+    stream = lat.stream
+    lat.step(args.warmup)
+    lat.synchronize()
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    start.record(stream)
+    lat.step(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    lat.synchronize()
+    ms = start.elapsed_time(end)
+    ms_per_step = ms / args.steps
+    mlups = wl.n_nodes_lattice * args.steps / (ms * 1e-3) / 1e6
+
+    # per-kernel durations from HIP events on the library's stream
+    phases = lat.profile(args.profile_steps)
+    k1_ms = phases["lbm"]
+    algo = bytes_per_node(args.storage) * wl.n_nodes_lattice
+    achieved = algo / (k1_ms * 1e-3) / 1e9
+    obs = lat.observables()
+    lat.close()
+
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz,
+            "capsules": len(wl.capsules), "membrane_nodes": wl.n_membrane_nodes,
+            "delta_width": wl.m, "storage": args.storage, "graph": not args.no_graph,
+            "u_w": wl.u_w, "tau": wl.tau,
+        },
+        "membrane_node_updates_per_s": round(wl.n_membrane_nodes * args.steps / (ms * 1e-3), 1),
+        "step_pct_hbm_roofline": round(100 * mlups * 1e6 * bytes_per_node(args.storage)
+                                       / (HBM_PEAK_GBS * 1e9), 2),
+        "phase_ms": {k: round(v, 5) for k, v in phases.items()},
+        "wall_s": round(wall, 3),
+        "D_final": [round(float(d), 6) for d in obs[:4, 4]],
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(wl.name, args.storage),
+            "kernel": "k_collide_stream", "algorithmic_bytes_per_launch": algo,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -723,6 +723,9 @@ void orc_capsule_observables(int nn, int nf, const double *x, const int *tri,
  *   tri   [nf][3] faces; ks, ka [nf] moduli of each face
  *   m     stencil width (2, 3 or 4)
  *   ab2   0: Euler advection, Eq. (positionupdate); 1: Adams-Bashforth
+ *         (Sec. II.C) with un_prev = u_i(t) of the previous step; 2: the same,
+ *         starting now: u_i(t) is unknown at the first step, which therefore
+ *         takes the Euler rule
  *   un_prev [nn][3] u_i(t) for Adams-Bashforth (in/out, may be NULL if ab2 = 0)
  *   F_out [nn][3] nodal forces of the last step, or NULL
  *   un_out [nn][3] node velocities of the last step, or NULL
@@ -760,13 +763,11 @@ int orc_run(int nx, int ny, int nz, double tau, double uw, int m, int linear_eq,
             int e = orc_interpolate(nx, ny, nz, m, nn, x, u, un);
             if (e) err = e;
             /* 5. advect the nodes, Eq. (positionupdate) or Adams-Bashforth */
+            int use_ab2 = (ab2 == 1) || (ab2 == 2 && s > 0);
             for (size_t q = 0; q < 3 * (size_t)nn; ++q) {
-                if (ab2) {
-                    x[q] += 1.5 * un[q] - 0.5 * un_prev[q];
-                    un_prev[q] = un[q];
-                } else {
-                    x[q] += un[q];
-                }
+                if (use_ab2) x[q] += 1.5 * un[q] - 0.5 * un_prev[q];
+                else x[q] += un[q];
+                if (ab2) un_prev[q] = un[q];
             }
         }
     }

@@ -226,12 +226,17 @@ class Simulation:
         _, nz, ny, nx = self.f.shape
         self.g = np.zeros((3, nz, ny, nx))
         self.t = 0
+        self.have_prev = False
 
     def run(self, nsteps):
         _, nz, ny, nx = self.f.shape
         nn, nf = self.x.shape[0], self.tri.shape[0]
+        mode = 0
+        if self.ab2:
+            mode = 1 if self.have_prev else 2
+            self.have_prev = self.have_prev or nsteps > 0
         rc = lib().orc_run(nx, ny, nz, self.tau, self.uw, self.m, self.linear_eq,
-                           self.ab2, nn, nf, _p(self.tri), _p(self.xref), _p(self.ks),
+                           mode, nn, nf, _p(self.tri), _p(self.xref), _p(self.ks),
                            _p(self.ka), _p(self.f), _p(self.x), _p(self.un_prev),
                            _p(self.F), _p(self.un), _p(self.g), int(nsteps),
                            self.nthreads)

@@ -1,0 +1,241 @@
+"""Thin ctypes binding of libibmlbm.so (declared in include/ibm_lbm.h).
+
+Argument marshalling only: every step of the timestep runs in the library's
+HIP kernels.  PyTorch provides the device buffers the library works in and
+the stream it enqueues on.  Importing this module fails if the library has
+not been built (paper_1004_2416_amd/build.py); there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libibmlbm.so")
+
+IBM_OK = 0
+ERRORS = {
+    -1: "IBM_ERR_INVALID_ARG",
+    -2: "IBM_ERR_BAD_STATE",
+    -3: "IBM_ERR_HIP",
+    -4: "IBM_ERR_STENCIL_HITS_WALL",
+    -5: "IBM_ERR_NONFINITE",
+    -6: "IBM_ERR_INVERTED_FACE",
+}
+STORAGE = {"fp32": 0, "fp16": 1}
+FIELD_POPS, FIELD_RHO, FIELD_U, FIELD_FORCE = 0, 1, 2, 3
+OPT_GRAPH, OPT_EQUILIBRIUM, OPT_ADVECTION, OPT_RECENTER = 0, 1, 2, 3
+PHASES = ("forces", "spread", "lbm", "interp")
+OBS_FIELDS = ("V", "cx", "cy", "cz", "D", "theta", "ra", "rb", "rc", "area",
+              "Ixx", "Iyy", "Izz", "Ixy", "Ixz", "Iyz")
+OBS_N = 16
+
+
+class IBMError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python paper_1004_2416_amd/build.py` "
+            "(hipcc, gfx950); there is no CPU fallback")
+    L = ctypes.CDLL(LIB_PATH)
+    i, d, v, sz = ctypes.c_int, ctypes.c_double, ctypes.c_void_p, ctypes.c_size_t
+    i64 = ctypes.c_int64
+    sig = {
+        "ibm_lattice_bytes": ([i, i, i, i, ctypes.POINTER(sz)], i),
+        "ibm_lattice_create": ([i, i, i, d, i, v, sz, v, ctypes.POINTER(v)], i),
+        "ibm_set_shear": ([v, d, i], i),
+        "ibm_membrane_bytes": ([i, v, v, ctypes.POINTER(sz)], i),
+        "ibm_membrane_create": ([v, i, v, v, v, v, v, v, i, v, sz], i),
+        "ibm_step": ([v, i64], i),
+        "ibm_step_count": ([v], i64),
+        "ibm_get_fields": ([v, i, v], i),
+        "ibm_set_fields": ([v, i, v], i),
+        "ibm_get_mesh": ([v, v, v, v], i),
+        "ibm_set_mesh": ([v, v], i),
+        "ibm_observables": ([v, v], i),
+        "ibm_synchronize": ([v], i),
+        "ibm_set_option": ([v, i, i], i),
+        "ibm_profile_step": ([v, i64, v], i),
+        "ibm_destroy": ([v], i),
+        "ibm_last_error": ([], ctypes.c_char_p),
+        "ibm_icosphere_size": ([i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
+        "ibm_icosphere": ([i, d, d, d, d, v, v], i),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+lib = _load()
+
+
+def _check(rc: int):
+    if rc != IBM_OK:
+        raise IBMError(rc, lib.ibm_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def icosphere(level: int, r: float = 1.0, center=(0.0, 0.0, 0.0)):
+    """The library's icosahedron subdivision mesh (Sec. II.D)."""
+    nn, nf = ctypes.c_int(), ctypes.c_int()
+    _check(lib.ibm_icosphere_size(int(level), ctypes.byref(nn), ctypes.byref(nf)))
+    xyz = np.zeros((nn.value, 3))
+    tri = np.zeros((nf.value, 3), dtype=np.int32)
+    _check(lib.ibm_icosphere(int(level), float(r), float(center[0]), float(center[1]),
+                             float(center[2]), _ptr(xyz), _ptr(tri)))
+    return xyz, tri
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _aligned_buffer(nbytes: int, device):
+    """A caller-owned device buffer (torch uint8), 256-byte aligned view."""
+    torch = _torch()
+    raw = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    off = (-raw.data_ptr()) % 256
+    return raw, raw[off:off + nbytes]
+
+
+class Lattice:
+    """A lattice (and optionally its capsules) living in torch device memory.
+
+    nx, ny, nz   fluid nodes; walls at z = -1/2 and nz - 1/2 (Sec. II.A)
+    tau          BGK relaxation time (> 1/2)
+    storage      "fp32" or "fp16" (scaled deviations f_i - w_i)
+    stream       torch.cuda.Stream to enqueue on (default: the current one)
+    """
+
+    def __init__(self, nx: int, ny: int, nz: int, tau: float = 1.0, storage: str = "fp32",
+                 device="cuda", stream=None):
+        torch = _torch()
+        self.shape = (int(nz), int(ny), int(nx))
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        nbytes = ctypes.c_size_t()
+        _check(lib.ibm_lattice_bytes(nx, ny, nz, STORAGE[storage], ctypes.byref(nbytes)))
+        self._raw, self._state = _aligned_buffer(nbytes.value, self.device)
+        h = ctypes.c_void_p()
+        _check(lib.ibm_lattice_create(nx, ny, nz, float(tau), STORAGE[storage],
+                                      ctypes.c_void_p(self._state.data_ptr()), nbytes.value,
+                                      ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
+        self._h = h
+        self.n_caps = 0
+        self.nn = 0
+        self.nf = 0
+        self._mem = None
+
+    # -- setup ---------------------------------------------------------------
+    def set_shear(self, u_w: float, init_profile: bool = True):
+        _check(lib.ibm_set_shear(self._h, float(u_w), int(bool(init_profile))))
+
+    def add_capsules(self, meshes: Sequence, ks: Sequence[float], ka: Sequence[float], m: int):
+        """meshes: list of (xyz [n, 3] float64, tri [f, 3] int) in lattice
+        coordinates, each the stress-free reference and initial shape."""
+        xyz = np.ascontiguousarray(np.concatenate([np.asarray(x, np.float64) for x, _ in meshes]))
+        tri = np.ascontiguousarray(np.concatenate([np.asarray(t, np.int32) for _, t in meshes]))
+        nodes = np.array([len(x) for x, _ in meshes], dtype=np.int32)
+        faces = np.array([len(t) for _, t in meshes], dtype=np.int32)
+        ks = np.ascontiguousarray(ks, dtype=np.float64)
+        ka = np.ascontiguousarray(ka, dtype=np.float64)
+        nbytes = ctypes.c_size_t()
+        _check(lib.ibm_membrane_bytes(len(meshes), _ptr(nodes), _ptr(faces), ctypes.byref(nbytes)))
+        raw, buf = _aligned_buffer(nbytes.value, self.device)
+        _check(lib.ibm_membrane_create(self._h, len(meshes), _ptr(nodes), _ptr(faces), _ptr(xyz),
+                                       _ptr(tri), _ptr(ks), _ptr(ka), int(m),
+                                       ctypes.c_void_p(buf.data_ptr()), nbytes.value))
+        self._mem = (raw, buf)
+        self.n_caps = len(meshes)
+        self.nn = int(nodes.sum())
+        self.nf = int(faces.sum())
+
+    def set_option(self, option: int, value: int):
+        _check(lib.ibm_set_option(self._h, int(option), int(value)))
+
+    # -- stepping ------------------------------------------------------------
+    def step(self, n: int = 1):
+        _check(lib.ibm_step(self._h, int(n)))
+
+    @property
+    def steps(self) -> int:
+        return int(lib.ibm_step_count(self._h))
+
+    def synchronize(self):
+        _check(lib.ibm_synchronize(self._h))
+
+    def profile(self, n: int) -> dict:
+        out = np.zeros(4)
+        _check(lib.ibm_profile_step(self._h, int(n), _ptr(out)))
+        return dict(zip(PHASES, out.tolist()))
+
+    # -- I/O -----------------------------------------------------------------
+    def _field(self, what: int, comps: int):
+        torch = _torch()
+        nz, ny, nx = self.shape
+        out = torch.empty((comps, nz, ny, nx), dtype=torch.float64, device=self.device)
+        _check(lib.ibm_get_fields(self._h, what, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def populations(self):
+        return self._field(FIELD_POPS, 19)
+
+    def density(self):
+        return self._field(FIELD_RHO, 1)[0]
+
+    def velocity(self):
+        return self._field(FIELD_U, 3)
+
+    def force_density(self):
+        return self._field(FIELD_FORCE, 3)
+
+    def set_populations(self, f):
+        torch = _torch()
+        t = torch.as_tensor(np.asarray(f, dtype=np.float64) if not torch.is_tensor(f) else f)
+        t = t.to(device=self.device, dtype=torch.float64).contiguous()
+        assert tuple(t.shape) == (19,) + self.shape
+        _check(lib.ibm_set_fields(self._h, FIELD_POPS, ctypes.c_void_p(t.data_ptr())))
+        self.synchronize()
+
+    def mesh(self):
+        """(positions, forces F(t), velocities u(t+1)) of the last step,
+        float64 [nn, 3] device tensors."""
+        torch = _torch()
+        out = [torch.empty((self.nn, 3), dtype=torch.float64, device=self.device) for _ in range(3)]
+        _check(lib.ibm_get_mesh(self._h, *[ctypes.c_void_p(o.data_ptr()) for o in out]))
+        return tuple(out)
+
+    def set_mesh(self, xyz):
+        xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        assert xyz.shape == (self.nn, 3)
+        _check(lib.ibm_set_mesh(self._h, _ptr(xyz)))
+
+    def observables(self) -> np.ndarray:
+        out = np.zeros((self.n_caps, OBS_N))
+        _check(lib.ibm_observables(self._h, _ptr(out)))
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.ibm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

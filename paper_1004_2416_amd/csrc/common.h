@@ -1,0 +1,129 @@
+// Internal definitions shared by the kernels and the host runtime of the
+// IB-LB-FEM library (arXiv:1004.2416).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ibm {
+
+constexpr int Q = 19;
+
+// D3Q19 velocity set in the numbering of the paper's lattice sketch (Sec. II.A,
+// Fig. 1): 1-6 along the axes, 7-18 along the face diagonals, 2k-1 and 2k
+// opposite.  Indexed only with compile-time constants (fully unrolled loops).
+__host__ __device__ constexpr int cx(int i) {
+  constexpr int v[Q] = {0, 1, -1, 0, 0, 0, 0, 1, -1, -1, 1, -1, 1, 1, -1, 0, 0, 0, 0};
+  return v[i];
+}
+__host__ __device__ constexpr int cy(int i) {
+  constexpr int v[Q] = {0, 0, 0, 1, -1, 0, 0, 0, 0, -1, 1, 0, 0, -1, 1, -1, 1, -1, 1};
+  return v[i];
+}
+__host__ __device__ constexpr int cz(int i) {
+  constexpr int v[Q] = {0, 0, 0, 0, 0, 1, -1, 1, -1, 0, 0, 1, -1, 0, 0, 1, -1, -1, 1};
+  return v[i];
+}
+__host__ __device__ constexpr int opp(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+// Lattice weights of D3Q19 (Qian et al., cited in Sec. II.A).
+__host__ __device__ constexpr double wgt(int i) {
+  return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+
+// Force-density tiles: K2 stamps the tiles it writes with the step number so
+// that the collide-stream kernel reads (and later clears) the force field only
+// where a membrane stencil touched it.
+constexpr int TILE_X = 8, TILE_Y = 4, TILE_Z = 4;
+
+// Device-side error flags (Ctrl::err bits).
+constexpr int ERR_WALL = 1;      // a nonzero stencil weight beyond a wall
+constexpr int ERR_FACE = 2;      // a face with non-positive deformed area
+constexpr int ERR_NONFINITE = 4; // NaN/Inf in the observables
+
+struct alignas(256) Ctrl {
+  int step;   // number of completed timesteps (incremented by the last kernel)
+  int err;    // ERR_* bits, OR-ed by kernels, cleared by the host
+  int pad[62];
+};
+
+// Everything the lattice kernels need, passed by value.
+struct LatDev {
+  int nx, ny, nz;
+  int tnx, tny, tnz;      // tile grid
+  long long S;            // stride between population arrays (elements)
+  void *f[2];             // population buffers (float or __half), [19][S]
+  float *g[2];            // force density fields [3][S], by step parity
+  int *stamp[2];          // per-tile step stamps, by step parity
+  Ctrl *ctrl;
+  float inv_tau;          // 1 / tau
+  float guo_pre;          // 1 - 1 / (2 tau)
+  float uw;               // wall speed: top +uw, bottom -uw along x
+  float h_scale[Q];       // FP16 storage: stored = (f_i - w_i) * h_scale[i]
+};
+
+// Membrane arrays (all capsules concatenated).
+struct MemDev {
+  int n_caps, nn, nf, m;
+  float4 *x;        // node coordinates relative to the capsule origin [nn]
+  float4 *u;        // node velocities of the last step [nn]
+  float4 *F;        // nodal forces of the last step [nn]
+  int *node_cap;    // capsule of each node [nn]
+  int *csr_off;     // node -> incident (face, corner) list offsets [nn + 1]
+  int *csr_ent;     // entries: face * 4 + corner [3 nf]
+  int4 *tri;        // faces: global node ids a, b, c and capsule [nf]
+  float4 *ref_p;    // inverse reference edge matrix (p, q, s) and area A0 [nf]
+  float4 *ref_ghi;  // reference metric G0 = E0^T E0: (g11, g12, g22) high parts
+  float4 *ref_glo;  // low parts (G0 - high), so hi + lo carries FP64 accuracy
+  int4 *origin;     // integer frame origin of each capsule [n_caps]
+  float4 *moduli;   // (k_s, k_alpha) per capsule [n_caps]
+  int *cap_node_off;  // [n_caps + 1]
+  int *cap_face_off;  // [n_caps + 1]
+  double *obs;      // observables [n_caps][IBM_OBS_N]
+};
+
+// ---- discrete delta functions, Sec. II.C Eqs. (2point), (3point), (4point) ----
+// Evaluated for |r| inside the stencil; square-root arguments are clamped at 0
+// so that rounding at the support edge cannot produce NaN.
+template <int M>
+__device__ __forceinline__ float phi(float r) {
+  float a = fabsf(r);
+  if constexpr (M == 2) {
+    return fmaxf(1.0f - a, 0.0f);
+  } else if constexpr (M == 3) {
+    if (a <= 0.5f) return (1.0f + sqrtf(fmaxf(1.0f - 3.0f * a * a, 0.0f))) * (1.0f / 3.0f);
+    if (a < 1.5f) return (5.0f - 3.0f * a - sqrtf(fmaxf(-2.0f + 6.0f * a - 3.0f * a * a, 0.0f))) * (1.0f / 6.0f);
+    return 0.0f;
+  } else {
+    if (a <= 1.0f) return (3.0f - 2.0f * a + sqrtf(fmaxf(1.0f + 4.0f * a - 4.0f * a * a, 0.0f))) * 0.125f;
+    if (a < 2.0f) return (5.0f - 2.0f * a - sqrtf(fmaxf(-7.0f + 12.0f * a - 4.0f * a * a, 0.0f))) * 0.125f;
+    return 0.0f;
+  }
+}
+
+// First lattice coordinate of the M-point stencil around position p: the M
+// integers within M/2 of p.
+template <int M>
+__device__ __forceinline__ int stencil_lo(float p) {
+  if constexpr (M == 3) return (int)floorf(p + 0.5f) - 1;
+  else if constexpr (M == 4) return (int)floorf(p) - 1;
+  else return (int)floorf(p);
+}
+
+__device__ __forceinline__ int wrap_mod(int a, int n) {
+  int r = a % n;
+  return r < 0 ? r + n : r;
+}
+
+__device__ __forceinline__ int tile_of(const LatDev &L, int x, int y, int z) {
+  return ((z / TILE_Z) * L.tny + (y / TILE_Y)) * L.tnx + (x / TILE_X);
+}
+
+// Lane-group size for the (membrane node, stencil node) mapping: the M^3
+// stencil nodes of one membrane node occupy one power-of-two lane group.
+template <int M>
+__host__ __device__ constexpr int group_size() {
+  return M == 2 ? 8 : (M == 3 ? 32 : 64);
+}
+
+}  // namespace ibm

@@ -1,0 +1,28 @@
+// Host-side launchers of the kernels (one translation unit per kernel group).
+#pragma once
+
+#include "common.h"
+
+namespace ibm {
+
+// lbm_kernels.hip
+void launch_collide_stream(const LatDev &L, int fp16, int src, int par, bool force,
+                           bool linear, hipStream_t s);
+void launch_init_equilibrium(const LatDev &L, int fp16, int dst, double uw, hipStream_t s);
+void launch_get_field(const LatDev &L, int fp16, int src, int gpar, int what, double *out,
+                      hipStream_t s);
+void launch_set_pops(const LatDev &L, int fp16, int dst, const double *in, hipStream_t s);
+void launch_fill_u32(void *p, long long n, uint32_t v, hipStream_t s);
+
+// membrane_kernels.hip
+void launch_reference_geometry(const MemDev &M, Ctrl *ctrl, hipStream_t s);
+void launch_membrane_forces(const MemDev &M, Ctrl *ctrl, hipStream_t s);
+void launch_spread(const LatDev &L, const MemDev &M, int par, hipStream_t s);
+// advect: 0 Euler, 1 Adams-Bashforth with the stored velocity of the previous step
+void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
+                          int advect, hipStream_t s);
+void launch_recenter(const MemDev &M, hipStream_t s);
+void launch_observables(const MemDev &M, Ctrl *ctrl, hipStream_t s);
+void launch_get_mesh(const MemDev &M, double *xyz, double *F, double *u, hipStream_t s);
+
+}  // namespace ibm

@@ -1,0 +1,553 @@
+// Membrane and coupling kernels: Skalak finite-element forces (Sec. II.B),
+// force spreading and velocity interpolation with the discrete delta
+// functions (Sec. II.C), Euler / Adams-Bashforth advection, FP64 reference
+// geometry and shape observables (Sec. III).
+//
+// Node coordinates are FP32 relative to an integer origin per capsule, so a
+// capsule of radius r keeps ~r * 2^-24 absolute resolution wherever it sits
+// in the box.  Spreading and interpolation put the M^3 stencil nodes of one
+// membrane node on one power-of-two lane group (8, 32 or 64 lanes).
+#include "common.h"
+#include "launch.h"
+
+namespace ibm {
+
+// ---- finite-element forces ----------------------------------------------------
+
+// Rounding error of s = a + b (Knuth's TwoSum); s must be fl(a + b).
+__device__ __forceinline__ float two_sum_err(float a, float b, float s) {
+#pragma clang fp contract(off)
+  const float bb = s - a;
+  return (a - (s - bb)) + (b - bb);
+}
+
+// Difference of two FP32 coordinates as an unevaluated sum hi + lo, exactly.
+struct Edge {
+  float hx, hy, hz, lx, ly, lz;
+};
+
+__device__ __forceinline__ Edge edge_exact(const float4 a, const float4 b) {
+#pragma clang fp contract(off)
+  Edge e;
+  e.hx = b.x - a.x;
+  e.hy = b.y - a.y;
+  e.hz = b.z - a.z;
+  e.lx = two_sum_err(b.x, -a.x, e.hx);
+  e.ly = two_sum_err(b.y, -a.y, e.hy);
+  e.lz = two_sum_err(b.z, -a.z, e.hz);
+  return e;
+}
+
+// u.v - (hi0 + lo0) for exact edge vectors u, v, with the products and sums
+// carried error-free (FMA product errors, TwoSum) and the first-order low
+// parts added, so that the small metric change of a nearly undeformed face
+// keeps FP32 relative accuracy instead of being lost to cancellation.
+__device__ __forceinline__ float dot_minus_ref(const Edge &u, const Edge &v, float hi0,
+                                               float lo0) {
+#pragma clang fp contract(off)
+  const float p0 = u.hx * v.hx, p1 = u.hy * v.hy, p2 = u.hz * v.hz;
+  const float e0 = fmaf(u.hx, v.hx, -p0), e1 = fmaf(u.hy, v.hy, -p1), e2 = fmaf(u.hz, v.hz, -p2);
+  const float s1 = p0 + p1;
+  const float t1 = two_sum_err(p0, p1, s1);
+  const float s2 = s1 + p2;
+  const float t2 = two_sum_err(s1, p2, s2);
+  const float cross = (u.hx * v.lx + u.hy * v.ly + u.hz * v.lz) +
+                      (u.lx * v.hx + u.ly * v.hy + u.lz * v.hz);
+  const float d = s2 - hi0;
+  return d + (((((e0 + e1) + e2) + (t1 + t2)) + cross) - lo0);
+}
+
+// Gradient of the face energy A0 w_S (Sec. II.B, Eq. constitutivelaw) with
+// respect to its corners a, b, c.  With current edges E = [b - a, c - a],
+// the reference edge matrix P (E0 = B P in an orthonormal in-plane frame B),
+// the deformation gradient F = E P^-1 and C = F^T F:
+//   I1 = tr C - 2,  I2 = det C - 1,
+//   dW/dE = 2 A0 E P^-1 [w1 1 + w2 adj C] P^-T,
+//   w1 = dw/dI1 = (k_s/6)(I1 + 1),  w2 = dw/dI2 = (k_a I2 - k_s)/6.
+// Everything is formed from C - 1 = P^-T (E^T E - E0^T E0) P^-1 so that no
+// O(1) terms cancel: w1 1 + w2 adj C = (k_s I1 + k_a I2)/6 1 + w2 adj(C - 1).
+struct FaceRef {
+  float p, q, s, A0;       // P^-1 = [[p, q], [0, s]], reference area
+  float g11, g12, g22;     // E0^T E0, high parts
+  float l11, l12, l22;     // low parts
+};
+
+__device__ __forceinline__ void skalak_face_grad(const float4 a, const float4 b, const float4 c,
+                                                 const FaceRef &R, float ks, float ka,
+                                                 float3 &ga, float3 &gb, float3 &gc,
+                                                 bool &degenerate) {
+  const Edge u = edge_exact(a, b), v = edge_exact(a, c);
+  const float d11 = dot_minus_ref(u, u, R.g11, R.l11);
+  const float d12 = dot_minus_ref(u, v, R.g12, R.l12);
+  const float d22 = dot_minus_ref(v, v, R.g22, R.l22);
+  const float e1x = u.hx, e1y = u.hy, e1z = u.hz;
+  const float e2x = v.hx, e2y = v.hy, e2z = v.hz;
+  const float p = R.p, q = R.q, s = R.s;
+  const float c11 = p * p * d11;
+  const float c12 = p * (q * d11 + s * d12);
+  const float c22 = q * (q * d11 + s * d12) + s * (q * d12 + s * d22);
+  const float I1 = c11 + c22;
+  const float I2 = I1 + (c11 * c22 - c12 * c12);
+  const float sig = (ks * I1 + ka * I2) * (1.0f / 6.0f);
+  const float kap = (ka * I2 - ks) * (1.0f / 6.0f);
+  const float S11 = sig + kap * c22, S22 = sig + kap * c11, S12 = -kap * c12;
+  const float r1 = p * S11 + q * S12, r2 = p * S12 + q * S22;
+  const float T11 = r1 * p + r2 * q, T12 = r2 * s, T22 = s * s * S22;
+  const float k2 = 2.0f * R.A0;
+  gb = make_float3(k2 * (T11 * e1x + T12 * e2x), k2 * (T11 * e1y + T12 * e2y),
+                   k2 * (T11 * e1z + T12 * e2z));
+  gc = make_float3(k2 * (T12 * e1x + T22 * e2x), k2 * (T12 * e1y + T22 * e2y),
+                   k2 * (T12 * e1z + T22 * e2z));
+  ga = make_float3(-(gb.x + gc.x), -(gb.y + gc.y), -(gb.z + gc.z));
+  degenerate = !(1.0f + I2 > 1e-6f);
+}
+
+// F_n = -sum over the faces at node n of d(A0 w_S)/dx_n (Eq. forcefromenergy).
+// One thread per node gathers its incident faces: no atomics, fixed order.
+__global__ __launch_bounds__(256) void k_membrane_forces(MemDev M, Ctrl *ctrl) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= M.nn) return;
+  float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+  bool bad = false;
+  const int e0 = M.csr_off[n], e1 = M.csr_off[n + 1];
+  for (int e = e0; e < e1; ++e) {
+    const int ent = M.csr_ent[e];
+    const int j = ent >> 2, k = ent & 3;
+    const int4 t = M.tri[j];
+    const float4 rp = M.ref_p[j], gh = M.ref_ghi[j], gl = M.ref_glo[j];
+    const FaceRef R{rp.x, rp.y, rp.z, rp.w, gh.x, gh.y, gh.z, gl.x, gl.y, gl.z};
+    const float4 mod = M.moduli[t.w];
+    float3 ga, gb, gc;
+    bool deg;
+    skalak_face_grad(M.x[t.x], M.x[t.y], M.x[t.z], R, mod.x, mod.y, ga, gb, gc, deg);
+    const float3 g = (k == 0) ? ga : ((k == 1) ? gb : gc);
+    fx -= g.x;
+    fy -= g.y;
+    fz -= g.z;
+    bad |= deg;
+  }
+  M.F[n] = make_float4(fx, fy, fz, 0.0f);
+  if (bad) atomicOr(&ctrl->err, ERR_FACE);
+}
+
+void launch_membrane_forces(const MemDev &M, Ctrl *ctrl, hipStream_t s) {
+  if (M.nn <= 0) return;
+  k_membrane_forces<<<dim3((M.nn + 255) / 256), dim3(256), 0, s>>>(M, ctrl);
+}
+
+// ---- spreading, Eq. (forcespreading) -------------------------------------------
+// One lane per (membrane node, stencil node); FP32 atomics into the force
+// field of parity `par`, and the step stamp of every touched tile.
+template <int M>
+__global__ __launch_bounds__(256) void k_spread(LatDev L, MemDev Mm, int par) {
+  constexpr int GS = group_size<M>();
+  const int lane = threadIdx.x & (GS - 1);
+  const int node = (blockIdx.x * blockDim.x + threadIdx.x) / GS;
+  if (node >= Mm.nn || lane >= M * M * M) return;
+  const int sx = lane % M, sy = (lane / M) % M, sz = lane / (M * M);
+  const float4 p = Mm.x[node];
+  const int lx = stencil_lo<M>(p.x) + sx;
+  const int ly = stencil_lo<M>(p.y) + sy;
+  const int lz = stencil_lo<M>(p.z) + sz;
+  const float w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
+  if (w == 0.0f) return;
+  const int4 o = Mm.origin[Mm.node_cap[node]];
+  const int Z = o.z + lz;
+  if (Z < 0 || Z >= L.nz) {
+    atomicOr(&L.ctrl->err, ERR_WALL);
+    return;
+  }
+  const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
+  const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
+  const float4 F = Mm.F[node];
+  float *g = L.g[par];
+  unsafeAtomicAdd(g + n, w * F.x);
+  unsafeAtomicAdd(g + L.S + n, w * F.y);
+  unsafeAtomicAdd(g + 2 * L.S + n, w * F.z);
+  L.stamp[par][tile_of(L, X, Y, Z)] = L.ctrl->step;
+}
+
+void launch_spread(const LatDev &L, const MemDev &M, int par, hipStream_t s) {
+  if (M.nn <= 0) return;
+  const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
+  const long long lanes = (long long)M.nn * gs;
+  const dim3 grid((unsigned)((lanes + 255) / 256)), block(256);
+  if (M.m == 2) k_spread<2><<<grid, block, 0, s>>>(L, M, par);
+  else if (M.m == 3) k_spread<3><<<grid, block, 0, s>>>(L, M, par);
+  else k_spread<4><<<grid, block, 0, s>>>(L, M, par);
+}
+
+// ---- interpolation + advection, Eqs. (velocityinterpolation), (positionupdate)
+// u(X, t+1) = (sum_i c_i f_i(X, t+1) + f(X, t)/2) / rho(X, t+1) at each stencil
+// node, weighted and summed over the lane group; the group's first lane moves
+// the node.  advect: 0 Euler; 1 Adams-Bashforth x += 3/2 u(t+1) - 1/2 u(t)
+// with u(t) the stored velocity of the previous step.  The last thread to
+// finish nothing else advances the device step counter.
+template <typename T>
+__device__ __forceinline__ float ld_pop(const T *p, long long idx, float inv_scale);
+template <>
+__device__ __forceinline__ float ld_pop<float>(const float *p, long long idx, float) {
+  return p[idx];
+}
+template <>
+__device__ __forceinline__ float ld_pop<__half>(const __half *p, long long idx, float inv_scale) {
+  return __half2float(p[idx]) * inv_scale;
+}
+
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_interp_advect(LatDev L, MemDev Mm, int fsrc, int par,
+                                                       int advect) {
+  constexpr int GS = group_size<M>();
+  const int lane = threadIdx.x & (GS - 1);
+  const int node = (blockIdx.x * blockDim.x + threadIdx.x) / GS;
+  const bool live = node < Mm.nn;
+  float ux = 0.0f, uy = 0.0f, uz = 0.0f;
+  float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  if (live) {
+    p = Mm.x[node];
+    if (lane < M * M * M) {
+      const int sx = lane % M, sy = (lane / M) % M, sz = lane / (M * M);
+      const int lx = stencil_lo<M>(p.x) + sx;
+      const int ly = stencil_lo<M>(p.y) + sy;
+      const int lz = stencil_lo<M>(p.z) + sz;
+      const float w =
+          phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
+      if (w != 0.0f) {
+        const int4 o = Mm.origin[Mm.node_cap[node]];
+        const int Z = o.z + lz;
+        if (Z < 0 || Z >= L.nz) {
+          atomicOr(&L.ctrl->err, ERR_WALL);
+        } else {
+          const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
+          const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
+          const T *f = static_cast<const T *>(L.f[fsrc]);
+          float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+          for (int i = 0; i < Q; ++i) {
+            const float d = ld_pop<T>(f, i * L.S + n, 1.0f / L.h_scale[i]);
+            drho += d;
+            if (cx(i)) jx += cx(i) * d;
+            if (cy(i)) jy += cy(i) * d;
+            if (cz(i)) jz += cz(i) * d;
+          }
+          const float *g = L.g[par];
+          const float inv_rho = 1.0f / (1.0f + drho);
+          ux = w * ((jx + 0.5f * g[n]) * inv_rho);
+          uy = w * ((jy + 0.5f * g[L.S + n]) * inv_rho);
+          uz = w * ((jz + 0.5f * g[2 * L.S + n]) * inv_rho);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int off = GS / 2; off > 0; off >>= 1) {
+    ux += __shfl_xor(ux, off, GS);
+    uy += __shfl_xor(uy, off, GS);
+    uz += __shfl_xor(uz, off, GS);
+  }
+  if (live && lane == 0) {
+    if (advect == 1) {
+      const float4 up = Mm.u[node];
+      p.x += 1.5f * ux - 0.5f * up.x;
+      p.y += 1.5f * uy - 0.5f * up.y;
+      p.z += 1.5f * uz - 0.5f * up.z;
+    } else {
+      p.x += ux;
+      p.y += uy;
+      p.z += uz;
+    }
+    Mm.u[node] = make_float4(ux, uy, uz, 0.0f);
+    Mm.x[node] = p;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
+}
+
+void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
+                          int advect, hipStream_t s) {
+  if (M.nn <= 0) return;
+  const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
+  const long long lanes = (long long)M.nn * gs;
+  const dim3 grid((unsigned)((lanes + 255) / 256)), block(256);
+#define IBM_LAUNCH_INTERP(T)                                                         \
+  do {                                                                               \
+    if (M.m == 2) k_interp_advect<T, 2><<<grid, block, 0, s>>>(L, M, fsrc, par, advect); \
+    else if (M.m == 3) k_interp_advect<T, 3><<<grid, block, 0, s>>>(L, M, fsrc, par, advect); \
+    else k_interp_advect<T, 4><<<grid, block, 0, s>>>(L, M, fsrc, par, advect);     \
+  } while (0)
+  if (fp16) IBM_LAUNCH_INTERP(__half);
+  else IBM_LAUNCH_INTERP(float);
+#undef IBM_LAUNCH_INTERP
+}
+
+// ---- capsule frame re-centring -------------------------------------------------
+// Shift each capsule's integer origin towards its node centroid (and the FP32
+// coordinates by the opposite integer) once the centroid has drifted by more
+// than 1.5 lattice spacings; positions are unchanged up to FP32 rounding.
+__global__ __launch_bounds__(256) void k_recenter(MemDev M) {
+  __shared__ float red[3][256];
+  __shared__ int shift[3];
+  const int c = blockIdx.x;
+  const int n0 = M.cap_node_off[c], n1 = M.cap_node_off[c + 1];
+  float sx = 0.0f, sy = 0.0f, sz = 0.0f;
+  for (int n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+    const float4 p = M.x[n];
+    sx += p.x;
+    sy += p.y;
+    sz += p.z;
+  }
+  red[0][threadIdx.x] = sx;
+  red[1][threadIdx.x] = sy;
+  red[2][threadIdx.x] = sz;
+  __syncthreads();
+  for (int k = blockDim.x / 2; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k)
+      for (int d = 0; d < 3; ++d) red[d][threadIdx.x] += red[d][threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const float inv = 1.0f / (float)(n1 - n0 > 0 ? n1 - n0 : 1);
+    for (int d = 0; d < 3; ++d) {
+      const float mean = red[d][0] * inv;
+      shift[d] = fabsf(mean) > 1.5f ? (int)rintf(mean) : 0;
+    }
+  }
+  __syncthreads();
+  const int s0 = shift[0], s1 = shift[1], s2 = shift[2];
+  if ((s0 | s1 | s2) == 0) return;
+  for (int n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+    float4 p = M.x[n];
+    p.x -= (float)s0;
+    p.y -= (float)s1;
+    p.z -= (float)s2;
+    M.x[n] = p;
+  }
+  if (threadIdx.x == 0) {
+    int4 o = M.origin[c];
+    o.x += s0;
+    o.y += s1;
+    o.z += s2;
+    M.origin[c] = o;
+  }
+}
+
+void launch_recenter(const MemDev &M, hipStream_t s) {
+  if (M.n_caps <= 0) return;
+  k_recenter<<<dim3(M.n_caps), dim3(256), 0, s>>>(M);
+}
+
+// ---- reference geometry (FP64) --------------------------------------------------
+// Per face from the stored (exactly representable) initial coordinates: the
+// in-plane reference edge matrix P = [[|e1|, e1.e2/|e1|], [0, |e1 x e2|/|e1|]],
+// its inverse, the area A0 = |e1 x e2| / 2 and the metric E0^T E0 split into
+// FP32 high and low parts.
+__global__ __launch_bounds__(256) void k_reference_geometry(MemDev M, Ctrl *ctrl) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M.nf) return;
+  const int4 t = M.tri[j];
+  const float4 a = M.x[t.x], b = M.x[t.y], c = M.x[t.z];
+  const double e1x = (double)b.x - a.x, e1y = (double)b.y - a.y, e1z = (double)b.z - a.z;
+  const double e2x = (double)c.x - a.x, e2y = (double)c.y - a.y, e2z = (double)c.z - a.z;
+  const double g11 = e1x * e1x + e1y * e1y + e1z * e1z;
+  const double g12 = e1x * e2x + e1y * e2y + e1z * e2z;
+  const double g22 = e2x * e2x + e2y * e2y + e2z * e2z;
+  const double nx = e1y * e2z - e1z * e2y, ny = e1z * e2x - e1x * e2z, nz = e1x * e2y - e1y * e2x;
+  const double area2 = sqrt(nx * nx + ny * ny + nz * nz);
+  const double l1 = sqrt(g11);
+  if (!(area2 > 1e-12 * g11) || !(l1 > 0.0)) {
+    atomicOr(&ctrl->err, ERR_FACE);
+    M.ref_p[j] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    return;
+  }
+  const double P11 = l1, P12 = g12 / l1, P22 = area2 / l1;
+  M.ref_p[j] = make_float4((float)(1.0 / P11), (float)(-P12 / (P11 * P22)), (float)(1.0 / P22),
+                           (float)(0.5 * area2));
+  const float h11 = (float)g11, h12 = (float)g12, h22 = (float)g22;
+  M.ref_ghi[j] = make_float4(h11, h12, h22, 0.0f);
+  M.ref_glo[j] = make_float4((float)(g11 - h11), (float)(g12 - h12), (float)(g22 - h22), 0.0f);
+}
+
+void launch_reference_geometry(const MemDev &M, Ctrl *ctrl, hipStream_t s) {
+  if (M.nf <= 0) return;
+  k_reference_geometry<<<dim3((M.nf + 255) / 256), dim3(256), 0, s>>>(M, ctrl);
+}
+
+// ---- observables (FP64), Sec. III -------------------------------------------------
+
+// Symmetric 3x3 eigen-decomposition by Jacobi rotations on the largest
+// off-diagonal element.  a is overwritten; eigenvectors in the columns of v.
+__device__ void sym3_eigen(double a[3][3], double v[3][3]) {
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) v[i][j] = (i == j) ? 1.0 : 0.0;
+  for (int it = 0; it < 60; ++it) {
+    int p = 0, q = 1;
+    double big = fabs(a[0][1]);
+    if (fabs(a[0][2]) > big) { p = 0; q = 2; big = fabs(a[0][2]); }
+    if (fabs(a[1][2]) > big) { p = 1; q = 2; big = fabs(a[1][2]); }
+    const double diag = fabs(a[0][0]) + fabs(a[1][1]) + fabs(a[2][2]);
+    if (big <= 1e-18 * diag || big == 0.0) break;
+    const double th = 0.5 * atan2(2.0 * a[p][q], a[q][q] - a[p][p]);
+    const double c = cos(th), s = sin(th);
+    for (int k = 0; k < 3; ++k) {  // columns p, q of a
+      const double akp = a[k][p], akq = a[k][q];
+      a[k][p] = c * akp - s * akq;
+      a[k][q] = s * akp + c * akq;
+    }
+    for (int k = 0; k < 3; ++k) {  // rows p, q
+      const double apk = a[p][k], aqk = a[q][k];
+      a[p][k] = c * apk - s * aqk;
+      a[q][k] = s * apk + c * aqk;
+    }
+    for (int k = 0; k < 3; ++k) {
+      const double vkp = v[k][p], vkq = v[k][q];
+      v[k][p] = c * vkp - s * vkq;
+      v[k][q] = s * vkp + c * vkq;
+    }
+  }
+}
+
+template <int K>
+__device__ void block_sum(double (*red)[256], double *vals) {
+  for (int k = 0; k < K; ++k) red[k][threadIdx.x] = vals[k];
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s)
+      for (int k = 0; k < K; ++k) red[k][threadIdx.x] += red[k][threadIdx.x + s];
+    __syncthreads();
+  }
+  for (int k = 0; k < K; ++k) vals[k] = red[k][0];
+  __syncthreads();
+}
+
+// One block per capsule.  Volume V = sum (a . (b x c))/6 and the volume
+// centroid from signed tetrahedra; I = (1/5) sum_faces A (r^2 1 - r r)(r . n)
+// with r the face centroid relative to the volume centroid, per unit mass
+// (divided by V); the ellipsoid with that tensor has
+// r_a^2 = 5/2 (E2 + E3 - E1), r_b^2 = 5/2 (E1 + E3 - E2),
+// r_c^2 = 5/2 (E1 + E2 - E3) for eigenvalues E1 <= E2 <= E3.
+__global__ __launch_bounds__(256) void k_observables(MemDev M, Ctrl *ctrl) {
+  __shared__ double red[7][256];
+  __shared__ double cen[3];
+  const int c = blockIdx.x;
+  const int f0 = M.cap_face_off[c], f1 = M.cap_face_off[c + 1];
+  double v1[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int j = f0 + threadIdx.x; j < f1; j += blockDim.x) {
+    const int4 t = M.tri[j];
+    const float4 A = M.x[t.x], B = M.x[t.y], C = M.x[t.z];
+    const double ax = A.x, ay = A.y, az = A.z, bx = B.x, by = B.y, bz = B.z;
+    const double cx_ = C.x, cy_ = C.y, cz_ = C.z;
+    const double vt =
+        (ax * (by * cz_ - bz * cy_) + ay * (bz * cx_ - bx * cz_) + az * (bx * cy_ - by * cx_)) / 6.0;
+    v1[0] += vt;
+    v1[1] += vt * (ax + bx + cx_) * 0.25;
+    v1[2] += vt * (ay + by + cy_) * 0.25;
+    v1[3] += vt * (az + bz + cz_) * 0.25;
+  }
+  block_sum<4>(red, v1);
+  const double V = v1[0];
+  if (threadIdx.x == 0) {
+    cen[0] = v1[1] / V;
+    cen[1] = v1[2] / V;
+    cen[2] = v1[3] / V;
+  }
+  __syncthreads();
+  double s7[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int j = f0 + threadIdx.x; j < f1; j += blockDim.x) {
+    const int4 t = M.tri[j];
+    const float4 A = M.x[t.x], B = M.x[t.y], C = M.x[t.z];
+    const double e1x = (double)B.x - A.x, e1y = (double)B.y - A.y, e1z = (double)B.z - A.z;
+    const double e2x = (double)C.x - A.x, e2y = (double)C.y - A.y, e2z = (double)C.z - A.z;
+    const double anx = 0.5 * (e1y * e2z - e1z * e2y);
+    const double any = 0.5 * (e1z * e2x - e1x * e2z);
+    const double anz = 0.5 * (e1x * e2y - e1y * e2x);
+    const double rx = ((double)A.x + B.x + C.x) / 3.0 - cen[0];
+    const double ry = ((double)A.y + B.y + C.y) / 3.0 - cen[1];
+    const double rz = ((double)A.z + B.z + C.z) / 3.0 - cen[2];
+    const double rn = rx * anx + ry * any + rz * anz;
+    const double r2 = rx * rx + ry * ry + rz * rz;
+    s7[0] += (r2 - rx * rx) * rn;
+    s7[1] += (r2 - ry * ry) * rn;
+    s7[2] += (r2 - rz * rz) * rn;
+    s7[3] += -rx * ry * rn;
+    s7[4] += -rx * rz * rn;
+    s7[5] += -ry * rz * rn;
+    s7[6] += sqrt(anx * anx + any * any + anz * anz);
+  }
+  block_sum<7>(red, s7);
+  if (threadIdx.x != 0) return;
+  const double k = 1.0 / (5.0 * V);
+  double I[6];
+  for (int q = 0; q < 6; ++q) I[q] = s7[q] * k;
+  double a[3][3] = {{I[0], I[3], I[4]}, {I[3], I[1], I[5]}, {I[4], I[5], I[2]}};
+  double vec[3][3];
+  sym3_eigen(a, vec);
+  double e[3] = {a[0][0], a[1][1], a[2][2]};
+  int id[3] = {0, 1, 2};
+  for (int i = 0; i < 3; ++i)
+    for (int j = i + 1; j < 3; ++j)
+      if (e[id[j]] < e[id[i]]) {
+        const int tmp = id[i];
+        id[i] = id[j];
+        id[j] = tmp;
+      }
+  const double E1 = e[id[0]], E2 = e[id[1]], E3 = e[id[2]];
+  const double ra = sqrt(fmax(2.5 * (E2 + E3 - E1), 0.0));
+  const double rb = sqrt(fmax(2.5 * (E1 + E3 - E2), 0.0));
+  const double rc = sqrt(fmax(2.5 * (E1 + E2 - E3), 0.0));
+  double th = atan2(vec[2][id[0]], vec[0][id[0]]);
+  if (th <= -M_PI / 2) th += M_PI;
+  if (th > M_PI / 2) th -= M_PI;
+  if (!((E2 - E1) > 1e-12 * fabs(E3))) th = __longlong_as_double(0x7ff8000000000000LL);
+  const int4 o = M.origin[c];
+  double *out = M.obs + (size_t)c * 16;
+  out[0] = V;
+  out[1] = cen[0] + o.x;
+  out[2] = cen[1] + o.y;
+  out[3] = cen[2] + o.z;
+  out[4] = (ra - rc) / (ra + rc);
+  out[5] = th;
+  out[6] = ra;
+  out[7] = rb;
+  out[8] = rc;
+  out[9] = s7[6];
+  for (int q = 0; q < 6; ++q) out[10 + q] = I[q];
+  bool finite = isfinite(V) && isfinite(out[4]);
+  for (int q = 0; q < 6; ++q) finite = finite && isfinite(I[q]);
+  if (!finite) atomicOr(&ctrl->err, ERR_NONFINITE);
+}
+
+void launch_observables(const MemDev &M, Ctrl *ctrl, hipStream_t s) {
+  if (M.n_caps <= 0) return;
+  k_observables<<<dim3(M.n_caps), dim3(256), 0, s>>>(M, ctrl);
+}
+
+// ---- mesh output (FP64, unwrapped lattice coordinates) -----------------------------
+__global__ __launch_bounds__(256) void k_get_mesh(MemDev M, double *xyz, double *F, double *u) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= M.nn) return;
+  if (xyz) {
+    const float4 p = M.x[n];
+    const int4 o = M.origin[M.node_cap[n]];
+    xyz[3 * n + 0] = (double)o.x + (double)p.x;
+    xyz[3 * n + 1] = (double)o.y + (double)p.y;
+    xyz[3 * n + 2] = (double)o.z + (double)p.z;
+  }
+  if (F) {
+    const float4 f = M.F[n];
+    F[3 * n + 0] = f.x;
+    F[3 * n + 1] = f.y;
+    F[3 * n + 2] = f.z;
+  }
+  if (u) {
+    const float4 v = M.u[n];
+    u[3 * n + 0] = v.x;
+    u[3 * n + 1] = v.y;
+    u[3 * n + 2] = v.z;
+  }
+}
+
+void launch_get_mesh(const MemDev &M, double *xyz, double *F, double *u, hipStream_t s) {
+  if (M.nn <= 0) return;
+  k_get_mesh<<<dim3((M.nn + 255) / 256), dim3(256), 0, s>>>(M, xyz, F, u);
+}
+
+}  // namespace ibm
