@@ -54,7 +54,7 @@ def measured_traffic(workload: str, storage: str):
     return None
 
 
-def setup(workload: str, storage: str, graph: bool):
+def setup(workload: str, storage: str, graph: bool, variant: int = -1):
     from paper_1004_2416_amd import binding as B
     from paper_1004_2416_amd import workloads as W
 
@@ -64,6 +64,8 @@ def setup(workload: str, storage: str, graph: bool):
     meshes = [B.icosphere(c.level, c.r, c.center) for c in wl.capsules]
     lat.add_capsules(meshes, [c.ks for c in wl.capsules], [c.ka for c in wl.capsules], wl.m)
     lat.set_option(B.OPT_GRAPH, int(graph))
+    if variant >= 0:
+        lat.set_option(B.OPT_LBM_VARIANT, int(variant))
     return wl, lat
 
 
@@ -105,15 +107,23 @@ def cpu_baseline(workload: str, seconds: float):
 
 def copy_calibration(mib: int):
     """A plain device-to-device copy of known size, for scaling the
-    rocprofv3 FETCH_SIZE / WRITE_SIZE counters."""
+    rocprofv3 FETCH_SIZE / WRITE_SIZE counters; also times it (the
+    achievable streaming bandwidth next to the 8 TB/s vendor figure)."""
     import torch
     n = mib * (1 << 20) // 4
     a = torch.ones(n, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
     for _ in range(5):
         b.copy_(a)
+    e1.record()
     torch.cuda.synchronize()
-    print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 5}))
+    ms = e0.elapsed_time(e1) / 5
+    print(json.dumps({"copy_calibration_bytes_read": n * 4, "bytes_written": n * 4, "launches": 6,
+                      "copy_ms": round(ms, 4), "copy_GBps": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}))
 
 
 def main():
@@ -124,6 +134,9 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--lbm-variant", type=int, default=-1,
+                    help="collide-stream launch variant (IBM_OPT_LBM_VARIANT bits; "
+                         "-1: the library default)")
     ap.add_argument("--profile-steps", type=int, default=400)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -139,7 +152,7 @@ def main():
         return
 
     import torch
-    wl, lat = setup(args.workload, args.storage, not args.no_graph)
+    wl, lat = setup(args.workload, args.storage, not args.no_graph, args.lbm_variant)
     stream = lat.stream
     lat.step(args.warmup)
     lat.synchronize()
@@ -183,7 +196,7 @@ def main():
             "workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz,
             "capsules": len(wl.capsules), "membrane_nodes": wl.n_membrane_nodes,
             "delta_width": wl.m, "storage": args.storage, "graph": not args.no_graph,
-            "u_w": wl.u_w, "tau": wl.tau,
+            "u_w": wl.u_w, "tau": wl.tau, "lbm_variant": args.lbm_variant,
         },
         "membrane_node_updates_per_s": round(wl.n_membrane_nodes * args.steps / (ms * 1e-3), 1),
         "step_pct_hbm_roofline": round(100 * mlups * 1e6 * bytes_per_node(args.storage)

@@ -102,11 +102,20 @@ extern "C" {
                                   1: Adams-Bashforth, Sec. II.C             */
 #define IBM_OPT_RECENTER 3     /* steps between re-centring of the capsule
                                   frames (default 64, >= 1)                 */
+#define IBM_OPT_LBM_VARIANT 4  /* launch variant of the collide-stream kernel,
+                                  0..31 (bit 0: two nodes per thread, bit 1:
+                                  non-temporal accesses, bit 2: 128-thread,
+                                  bit 3: 64-thread blocks, bit 4: four nodes
+                                  per thread with whole x rows per wavefront,
+                                  used when nx / 4 divides 64; default 23);
+                                  results are identical, only the speed
+                                  differs                                    */
 
 typedef struct ibm_lattice ibm_lattice;
 
-/* Bytes of device memory the lattice state needs (populations, two force
- * fields and their tile stamps, control words).  storage: IBM_STORAGE_*. */
+/* Bytes of device memory the lattice state needs (two population buffers,
+ * two force densities and their tile stamps, control words).  storage:
+ * IBM_STORAGE_*. */
 int ibm_lattice_bytes(int nx, int ny, int nz, int storage, size_t *bytes);
 
 /* Create a lattice of nx * ny * nz nodes with BGK relaxation time tau > 1/2
@@ -143,8 +152,9 @@ int ibm_membrane_bytes(int n_caps, const int *nodes_per_cap,
  *        law (Sec. II.B, Eq. constitutivelaw); C = ka / ks.
  *   m    delta width 2, 3 or 4 (Sec. II.C, Eqs. 2point, 3point, 4point).
  *   dev_mem  device buffer of ibm_membrane_bytes bytes, owned by the caller.
- * Fails with IBM_ERR_STENCIL_HITS_WALL if a stencil would reach a wall and
- * with IBM_ERR_INVERTED_FACE for a degenerate face. */
+ * nx and ny must be at least m.  Fails with IBM_ERR_STENCIL_HITS_WALL if a
+ * stencil would reach a wall and with IBM_ERR_INVERTED_FACE for a degenerate
+ * face. */
 int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
                         const int *faces_per_cap, const double *xyz,
                         const int32_t *tri, const double *ks, const double *ka,

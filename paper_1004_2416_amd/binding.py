@@ -27,7 +27,7 @@ ERRORS = {
 }
 STORAGE = {"fp32": 0, "fp16": 1}
 FIELD_POPS, FIELD_RHO, FIELD_U, FIELD_FORCE = 0, 1, 2, 3
-OPT_GRAPH, OPT_EQUILIBRIUM, OPT_ADVECTION, OPT_RECENTER = 0, 1, 2, 3
+OPT_GRAPH, OPT_EQUILIBRIUM, OPT_ADVECTION, OPT_RECENTER, OPT_LBM_VARIANT = 0, 1, 2, 3, 4
 PHASES = ("forces", "spread", "lbm", "interp")
 OBS_FIELDS = ("V", "cx", "cy", "cz", "D", "theta", "ra", "rb", "rc", "area",
               "Ixx", "Iyy", "Izz", "Ixy", "Ixz", "Iyz")

@@ -80,7 +80,7 @@ LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
 }
 
 struct MembraneLayout {
-  size_t x, u, F, node_cap, csr_off, csr_ent, tri, ref_p, ref_ghi, ref_glo, origin, moduli,
+  size_t x, u, F, face_grad, ext_id, node_cap, csr_off, csr_ent, tri, ref_p, ref_ghi, ref_glo, origin, moduli,
       cap_node_off, cap_face_off, obs, total;
 };
 
@@ -95,6 +95,8 @@ MembraneLayout membrane_layout(int nc, long long nn, long long nf) {
   l.x = take(nn * 16);
   l.u = take(nn * 16);
   l.F = take(nn * 16);
+  l.face_grad = take(3 * nf * 16);
+  l.ext_id = take(nn * 4);
   l.node_cap = take(nn * 4);
   l.csr_off = take((nn + 1) * 4);
   l.csr_ent = take(3 * nf * 4);
@@ -126,8 +128,11 @@ struct ibm_lattice {
   bool has_mem = false;
   ibm::MemDev M{};
   std::vector<int> node_off, face_off;
+  std::vector<int> int_of_ext;  // caller's node index -> internal (sorted) index
 
-  int use_graph = 1, eq_linear = 0, ab2 = 0, recenter_every = 64;
+  // default collide-stream form: whole-row vectors where the row fits a
+  // wavefront, else two nodes per thread, non-temporal, 128-thread blocks
+  int use_graph = 1, eq_linear = 0, ab2 = 0, recenter_every = 64, lbm_variant = 16 | 7;
   bool have_prev_u = false;
   int64_t since_recenter = 0;
 
@@ -156,16 +161,17 @@ void reset_force_state(ibm_lattice *lat, hipStream_t s) {
 // Enqueue one full timestep on stream s (Sec. II.C, sub-steps 1-5).
 void enqueue_step(ibm_lattice *lat, hipStream_t s, int advect) {
   const int src = (int)(lat->steps & 1);
-  const int par = src;
+  const int par = src;  // force field of this step's parity
   if (lat->has_mem) {
-    ibm::launch_membrane_forces(lat->M, lat->L.ctrl, s);                 // 1: F(t)
+    ibm::launch_face_gradients(lat->M, lat->L.ctrl, s);                  // 1: F(t)
     ibm::launch_spread(lat->L, lat->M, par, s);                          // 2: f(X, t)
     ibm::launch_collide_stream(lat->L, lat->storage, src, par, true,     // 3: f_i(t+1)
-                               lat->eq_linear != 0, s);
+                               lat->eq_linear != 0, lat->lbm_variant, s);
     ibm::launch_interp_advect(lat->L, lat->M, lat->storage, src ^ 1,     // 4, 5
                               par, advect, s);
   } else {
-    ibm::launch_collide_stream(lat->L, lat->storage, src, par, false, lat->eq_linear != 0, s);
+    ibm::launch_collide_stream(lat->L, lat->storage, src, par, false, lat->eq_linear != 0,
+                               lat->lbm_variant, s);
   }
   lat->steps += 1;
   lat->since_recenter += 1;
@@ -218,7 +224,8 @@ bool finite_all(const double *v, size_t n) {
 }
 
 // Integer origin floor(mean) of each capsule and FP32 coordinates relative to
-// it; checks that every stencil weight stays between the walls.
+// it, stored at the nodes' internal positions; checks that every stencil
+// weight stays between the walls.  xyz is in the caller's node order.
 int frame_positions(const ibm_lattice *lat, const double *xyz, std::vector<float4> &xl,
                     std::vector<int4> &org) {
   const int nc = (int)lat->node_off.size() - 1;
@@ -237,7 +244,7 @@ int frame_positions(const ibm_lattice *lat, const double *xyz, std::vector<float
     for (int n = n0; n < n1; ++n) {
       float v[3];
       for (int d = 0; d < 3; ++d) v[d] = (float)(xyz[3 * (size_t)n + d] - o[d]);
-      xl[n] = make_float4(v[0], v[1], v[2], 0.0f);
+      xl[lat->int_of_ext[n]] = make_float4(v[0], v[1], v[2], 0.0f);
       // lattice nodes Z with |Z - z| < m/2 carry weight: all must lie in [0, nz)
       const double z = (double)o[2] + (double)v[2];
       if (!(z > half - 1.0) || !(z < lat->nz - half))
@@ -247,6 +254,33 @@ int frame_positions(const ibm_lattice *lat, const double *xyz, std::vector<float
     }
   }
   return IBM_OK;
+}
+
+// Order of a capsule's nodes along a Morton (Z-order) curve through their
+// bounding box, so that consecutive nodes are spatial neighbours.
+std::vector<int> morton_order(const double *xyz, int n) {
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int k = 0; k < n; ++k)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], xyz[3 * (size_t)k + d]);
+      hi[d] = std::max(hi[d], xyz[3 * (size_t)k + d]);
+    }
+  std::vector<std::pair<uint32_t, int>> key(n);
+  for (int k = 0; k < n; ++k) {
+    uint32_t code = 0;
+    uint32_t q[3];
+    for (int d = 0; d < 3; ++d) {
+      const double span = hi[d] - lo[d] > 0 ? hi[d] - lo[d] : 1.0;
+      q[d] = (uint32_t)std::min(1023.0, std::floor((xyz[3 * (size_t)k + d] - lo[d]) / span * 1024.0));
+    }
+    for (int b = 9; b >= 0; --b)
+      for (int d = 0; d < 3; ++d) code = (code << 1) | ((q[d] >> b) & 1u);
+    key[k] = {code, k};
+  }
+  std::sort(key.begin(), key.end());
+  std::vector<int> order(n);
+  for (int k = 0; k < n; ++k) order[k] = key[k].second;
+  return order;
 }
 
 }  // namespace
@@ -355,7 +389,7 @@ int ibm_membrane_bytes(int n_caps, const int *nodes_per_cap, const int *faces_pe
     nn += nodes_per_cap[c];
     nf += faces_per_cap[c];
   }
-  if (nn > (1LL << 28) || nf > (1LL << 28)) return fail(IBM_ERR_INVALID_ARG, "membrane too large");
+  if (nn > (1LL << 24) || nf > (1LL << 26)) return fail(IBM_ERR_INVALID_ARG, "membrane too large");
   *bytes = membrane_layout(n_caps, nn, nf).total;
   return ok();
 }
@@ -370,6 +404,8 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
   if (rc) return rc;
   if (!xyz || !tri || !ks || !ka || !dev_mem) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
   if (m < 2 || m > 4) return fail(IBM_ERR_INVALID_ARG, "delta width m must be 2, 3 or 4");
+  if (lat->nx < m || lat->ny < m)
+    return fail(IBM_ERR_INVALID_ARG, "nx and ny must be at least the delta width %d", m);
   if (((uintptr_t)dev_mem) % ALIGN) return fail(IBM_ERR_INVALID_ARG, "dev_mem not 256-byte aligned");
   if (bytes < need) return fail(IBM_ERR_INVALID_ARG, "dev_mem has %zu bytes, %zu needed", bytes, need);
 
@@ -383,7 +419,17 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
   const int nn = node_off[n_caps], nf = face_off[n_caps];
   if (!finite_all(xyz, 3 * (size_t)nn)) return fail(IBM_ERR_INVALID_ARG, "non-finite node position");
 
-  // faces with global node ids and the node -> (face, corner) lists
+  // internal node order: each capsule's nodes sorted along a Morton curve
+  std::vector<int> ext_of_int(nn), int_of_ext(nn);
+  for (int c = 0; c < n_caps; ++c) {
+    const int n0 = node_off[c];
+    const std::vector<int> order = morton_order(xyz + 3 * (size_t)n0, nodes_per_cap[c]);
+    for (int k = 0; k < nodes_per_cap[c]; ++k) {
+      ext_of_int[n0 + k] = n0 + order[k];
+      int_of_ext[n0 + order[k]] = n0 + k;
+    }
+  }
+  // faces with global internal node ids and the node -> (face, corner) lists
   std::vector<int4> t4(nf);
   std::vector<int> deg(nn, 0), node_cap(nn);
   std::vector<int> cap_node_off(node_off), cap_face_off(face_off);
@@ -396,7 +442,7 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
         if (v < 0 || v >= nodes_per_cap[c])
           return fail(IBM_ERR_INVALID_ARG, "capsule %d face %d: node index %d out of range", c,
                       j - face_off[c], v);
-        g[k] = node_off[c] + v;
+        g[k] = int_of_ext[node_off[c] + v];
       }
       if (g[0] == g[1] || g[1] == g[2] || g[0] == g[2])
         return fail(IBM_ERR_INVALID_ARG, "capsule %d face %d repeats a node", c, j - face_off[c]);
@@ -425,6 +471,9 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
   M.x = reinterpret_cast<float4 *>(b + ml.x);
   M.u = reinterpret_cast<float4 *>(b + ml.u);
   M.F = reinterpret_cast<float4 *>(b + ml.F);
+  M.face_grad = reinterpret_cast<float4 *>(b + ml.face_grad);
+  M.ext_id = reinterpret_cast<int *>(b + ml.ext_id);
+
   M.node_cap = reinterpret_cast<int *>(b + ml.node_cap);
   M.csr_off = reinterpret_cast<int *>(b + ml.csr_off);
   M.csr_ent = reinterpret_cast<int *>(b + ml.csr_ent);
@@ -439,6 +488,7 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
   M.obs = reinterpret_cast<double *>(b + ml.obs);
   lat->node_off = node_off;
   lat->face_off = face_off;
+  lat->int_of_ext = int_of_ext;
 
   std::vector<float4> xl;
   std::vector<int4> org;
@@ -452,6 +502,7 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
   hipStream_t s = lat->stream;
   IBM_HIP(hipMemcpyAsync(M.x, xl.data(), nn * sizeof(float4), hipMemcpyHostToDevice, s));
   IBM_HIP(hipMemcpyAsync(M.node_cap, node_cap.data(), nn * sizeof(int), hipMemcpyHostToDevice, s));
+  IBM_HIP(hipMemcpyAsync(M.ext_id, ext_of_int.data(), nn * sizeof(int), hipMemcpyHostToDevice, s));
   IBM_HIP(hipMemcpyAsync(M.csr_off, csr_off.data(), (nn + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   IBM_HIP(hipMemcpyAsync(M.csr_ent, csr_ent.data(), 3 * (size_t)nf * sizeof(int), hipMemcpyHostToDevice, s));
   IBM_HIP(hipMemcpyAsync(M.tri, t4.data(), nf * sizeof(int4), hipMemcpyHostToDevice, s));
@@ -461,6 +512,7 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
   IBM_HIP(hipMemcpyAsync(M.cap_face_off, cap_face_off.data(), (n_caps + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   ibm::launch_fill_u32(M.u, 4LL * nn, 0u, s);
   ibm::launch_fill_u32(M.F, 4LL * nn, 0u, s);
+  ibm::launch_fill_u32(M.face_grad, 12LL * nf, 0u, s);
   ibm::launch_reference_geometry(M, lat->L.ctrl, s);
   IBM_HIP(hipGetLastError());
   IBM_HIP(hipStreamSynchronize(s));  // host vectors must outlive the copies
@@ -595,6 +647,10 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
       if (value < 1) return fail(IBM_ERR_INVALID_ARG, "recentre interval must be >= 1");
       lat->recenter_every = value;
       break;
+    case IBM_OPT_LBM_VARIANT:
+      if (value < 0 || value > 31) return fail(IBM_ERR_INVALID_ARG, "variant is 0..31");
+      lat->lbm_variant = value;
+      break;
     default:
       return fail(IBM_ERR_INVALID_ARG, "unknown option %d", option);
   }
@@ -614,17 +670,19 @@ int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase) {
     const int src = (int)(lat->steps & 1), par = src;
     IBM_HIP(hipEventRecord(e[0], s));
     if (lat->has_mem) {
-      ibm::launch_membrane_forces(lat->M, lat->L.ctrl, s);
+      ibm::launch_face_gradients(lat->M, lat->L.ctrl, s);
       IBM_HIP(hipEventRecord(e[1], s));
       ibm::launch_spread(lat->L, lat->M, par, s);
       IBM_HIP(hipEventRecord(e[2], s));
-      ibm::launch_collide_stream(lat->L, lat->storage, src, par, true, lat->eq_linear != 0, s);
+      ibm::launch_collide_stream(lat->L, lat->storage, src, par, true, lat->eq_linear != 0,
+                                 lat->lbm_variant, s);
       IBM_HIP(hipEventRecord(e[3], s));
       ibm::launch_interp_advect(lat->L, lat->M, lat->storage, src ^ 1, par, advect_mode(lat), s);
       IBM_HIP(hipEventRecord(e[4], s));
       if (lat->ab2) lat->have_prev_u = true;
     } else {
-      ibm::launch_collide_stream(lat->L, lat->storage, src, par, false, lat->eq_linear != 0, s);
+      ibm::launch_collide_stream(lat->L, lat->storage, src, par, false, lat->eq_linear != 0,
+                                 lat->lbm_variant, s);
       IBM_HIP(hipEventRecord(e[1], s));
     }
     lat->steps += 1;

@@ -31,10 +31,11 @@ __host__ __device__ constexpr double wgt(int i) {
   return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
 }
 
-// Force-density tiles: K2 stamps the tiles it writes with the step number so
-// that the collide-stream kernel reads (and later clears) the force field only
-// where a membrane stencil touched it.
-constexpr int TILE_X = 8, TILE_Y = 4, TILE_Z = 4;
+// Force-density tiles of TILE_X x TILE_Y x TILE_Z lattice nodes.  Spreading
+// stamps every tile it adds force to with the step number; the collide-stream
+// kernel reads the force field only in tiles stamped with the current step
+// and clears the other (previous step's) field where that one was stamped.
+constexpr int TILE_X = 4, TILE_Y = 4, TILE_Z = 4;
 
 // Device-side error flags (Ctrl::err bits).
 constexpr int ERR_WALL = 1;      // a nonzero stencil weight beyond a wall
@@ -53,8 +54,8 @@ struct LatDev {
   int tnx, tny, tnz;      // tile grid
   long long S;            // stride between population arrays (elements)
   void *f[2];             // population buffers (float or __half), [19][S]
-  float *g[2];            // force density fields [3][S], by step parity
-  int *stamp[2];          // per-tile step stamps, by step parity
+  float *g[2];            // force density [3][S] of even and odd steps
+  int *stamp[2];          // per-tile step stamps of the two fields
   Ctrl *ctrl;
   float inv_tau;          // 1 / tau
   float guo_pre;          // 1 - 1 / (2 tau)
@@ -68,6 +69,8 @@ struct MemDev {
   float4 *x;        // node coordinates relative to the capsule origin [nn]
   float4 *u;        // node velocities of the last step [nn]
   float4 *F;        // nodal forces of the last step [nn]
+  float4 *face_grad;  // d(A0 w_S)/dx of each face's corners a, b, c [3 nf]
+  int *ext_id;      // caller's index of each (spatially sorted) node [nn]
   int *node_cap;    // capsule of each node [nn]
   int *csr_off;     // node -> incident (face, corner) list offsets [nn + 1]
   int *csr_ent;     // entries: face * 4 + corner [3 nf]

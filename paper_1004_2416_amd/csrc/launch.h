@@ -6,8 +6,9 @@
 namespace ibm {
 
 // lbm_kernels.hip
+// variant: tuning bits of the collide-stream kernel (see lbm_kernels.hip)
 void launch_collide_stream(const LatDev &L, int fp16, int src, int par, bool force,
-                           bool linear, hipStream_t s);
+                           bool linear, int variant, hipStream_t s);
 void launch_init_equilibrium(const LatDev &L, int fp16, int dst, double uw, hipStream_t s);
 void launch_get_field(const LatDev &L, int fp16, int src, int gpar, int what, double *out,
                       hipStream_t s);
@@ -16,7 +17,7 @@ void launch_fill_u32(void *p, long long n, uint32_t v, hipStream_t s);
 
 // membrane_kernels.hip
 void launch_reference_geometry(const MemDev &M, Ctrl *ctrl, hipStream_t s);
-void launch_membrane_forces(const MemDev &M, Ctrl *ctrl, hipStream_t s);
+void launch_face_gradients(const MemDev &M, Ctrl *ctrl, hipStream_t s);
 void launch_spread(const LatDev &L, const MemDev &M, int par, hipStream_t s);
 // advect: 0 Euler, 1 Adams-Bashforth with the stored velocity of the previous step
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,

@@ -14,52 +14,96 @@
 
 namespace ibm {
 
+// Population storage access.  FP32: the deviation itself.  FP16: the
+// deviation times a per-direction scale.  NT selects non-temporal loads and
+// stores (streamed data that will not be reused before it leaves the caches).
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
 template <typename T>
-__device__ __forceinline__ float ld_dev(const T *p, long long idx, float inv_scale);
+struct Pop;
+
 template <>
-__device__ __forceinline__ float ld_dev<float>(const float *p, long long idx, float) {
-  return p[idx];
-}
+struct Pop<float> {
+  template <bool NT>
+  static __device__ __forceinline__ float ld(const float *p, long long i, float) {
+    if (NT) return __builtin_nontemporal_load(p + i);
+    return p[i];
+  }
+  template <bool NT>
+  static __device__ __forceinline__ void ld2(const float *p, long long i, float, float &a, float &b) {
+    const f32x2 *q = reinterpret_cast<const f32x2 *>(p + i);
+    const f32x2 v = NT ? __builtin_nontemporal_load(q) : *q;
+    a = v.x;
+    b = v.y;
+  }
+  template <bool NT>
+  static __device__ __forceinline__ void st(float *p, long long i, float v, float) {
+    if (NT) __builtin_nontemporal_store(v, p + i);
+    else p[i] = v;
+  }
+  template <bool NT>
+  static __device__ __forceinline__ void st2(float *p, long long i, float a, float b, float) {
+    f32x2 v;
+    v.x = a;
+    v.y = b;
+    f32x2 *q = reinterpret_cast<f32x2 *>(p + i);
+    if (NT) __builtin_nontemporal_store(v, q);
+    else *q = v;
+  }
+};
+
 template <>
-__device__ __forceinline__ float ld_dev<__half>(const __half *p, long long idx, float inv_scale) {
-  return __half2float(p[idx]) * inv_scale;
+struct Pop<__half> {
+  template <bool NT>
+  static __device__ __forceinline__ float ld(const __half *p, long long i, float inv) {
+    const unsigned short *q = reinterpret_cast<const unsigned short *>(p) + i;
+    const unsigned short r = NT ? __builtin_nontemporal_load(q) : *q;
+    return __half2float(__ushort_as_half(r)) * inv;
+  }
+  template <bool NT>
+  static __device__ __forceinline__ void ld2(const __half *p, long long i, float inv, float &a,
+                                             float &b) {
+    const unsigned int *q = reinterpret_cast<const unsigned int *>(p + i);
+    const unsigned int r = NT ? __builtin_nontemporal_load(q) : *q;
+    a = __half2float(__ushort_as_half((unsigned short)(r & 0xffffu))) * inv;
+    b = __half2float(__ushort_as_half((unsigned short)(r >> 16))) * inv;
+  }
+  template <bool NT>
+  static __device__ __forceinline__ void st(__half *p, long long i, float v, float scale) {
+    const unsigned short r = __half_as_ushort(__float2half_rn(v * scale));
+    unsigned short *q = reinterpret_cast<unsigned short *>(p) + i;
+    if (NT) __builtin_nontemporal_store(r, q);
+    else *q = r;
+  }
+  template <bool NT>
+  static __device__ __forceinline__ void st2(__half *p, long long i, float a, float b, float scale) {
+    const unsigned int r = (unsigned int)__half_as_ushort(__float2half_rn(a * scale)) |
+                           ((unsigned int)__half_as_ushort(__float2half_rn(b * scale)) << 16);
+    unsigned int *q = reinterpret_cast<unsigned int *>(p + i);
+    if (NT) __builtin_nontemporal_store(r, q);
+    else *q = r;
+  }
+};
+
+// Scalar accessors for the non-hot kernels.
+template <typename T>
+__device__ __forceinline__ float ld_dev(const T *p, long long idx, float inv_scale) {
+  return Pop<T>::template ld<false>(p, idx, inv_scale);
 }
 template <typename T>
-__device__ __forceinline__ void st_dev(T *p, long long idx, float v, float scale);
-template <>
-__device__ __forceinline__ void st_dev<float>(float *p, long long idx, float v, float) {
-  p[idx] = v;
-}
-template <>
-__device__ __forceinline__ void st_dev<__half>(__half *p, long long idx, float v, float scale) {
-  p[idx] = __float2half_rn(v * scale);
+__device__ __forceinline__ void st_dev(T *p, long long idx, float v, float scale) {
+  Pop<T>::template st<false>(p, idx, v, scale);
 }
 
-// One lattice update at node (x, y, z) of buffer `src` into buffer src ^ 1.
+// Post-collision deviations of one node.
 //   Moments (Eqs. lbmmomenta0/1): rho = 1 + sum d_i, rho u = sum c_i d_i + g/2
 //   (sum c_i w_i = 0).  Equilibrium deviation (Eq. equilibrium):
-//   feq_i - w_i = w_i (rho - 1) + w_i rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u).
-//   Guo term (Eq. latticeforce), BGK relaxation (Eq. lbequation), then
-//   streaming to x + c_i, periodic in x and y; populations leaving through a
-//   wall return to x reversed, with -2 w_i rho_w (c_i . u_wall) / c_s^2,
-//   rho_w = 1 (bounce-back for moving walls).
-template <typename T, bool LINEAR, bool FORCE>
-__global__ __launch_bounds__(256) void k_collide_stream(LatDev L, int src, int par) {
-  const int x = blockIdx.x * blockDim.x + threadIdx.x;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x >= L.nx || y >= L.ny) return;
-  const long long S = L.S;
-  const long long nxl = L.nx;
-  const long long plane = nxl * L.ny;
-  const long long n = (long long)z * plane + (long long)y * nxl + x;
-  const T *__restrict__ fs = static_cast<const T *>(L.f[src]);
-  T *__restrict__ fd = static_cast<T *>(L.f[src ^ 1]);
-
-  float d[Q];
-#pragma unroll
-  for (int i = 0; i < Q; ++i) d[i] = ld_dev<T>(fs, i * S + n, 1.0f / L.h_scale[i]);
-
+//   feq_i - w_i = w_i (rho - 1) + w_i rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u),
+//   or w_i (rho - 1) + 3 w_i rho c.u for the linearised form (Sec. IV.A).
+//   Guo term (Eq. latticeforce) and BGK relaxation (Eq. lbequation).
+template <bool LINEAR, bool FORCE>
+__device__ __forceinline__ void collide(float (&d)[Q], float gx, float gy, float gz,
+                                        float inv_tau, float guo_pre) {
   float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -69,38 +113,12 @@ __global__ __launch_bounds__(256) void k_collide_stream(LatDev L, int src, int p
     if (cz(i)) jz += cz(i) * d[i];
   }
   const float rho = 1.0f + drho;
-
-  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
-  if (FORCE) {
-    const int t = L.ctrl->step;
-    const int tile = tile_of(L, x, y, z);
-    if (L.stamp[par][tile] == t) {
-      const float *g = L.g[par];
-      gx = g[n];
-      gy = g[S + n];
-      gz = g[2 * S + n];
-    }
-    // The other field was spread one step ago and has been interpolated
-    // from; clear it where it was touched so the next spreading starts at 0.
-    if (L.stamp[par ^ 1][tile] == t - 1) {
-      float *go = L.g[par ^ 1];
-      go[n] = 0.0f;
-      go[S + n] = 0.0f;
-      go[2 * S + n] = 0.0f;
-    }
-  }
   const float inv_rho = 1.0f / rho;
   const float ux = (jx + 0.5f * gx) * inv_rho;
   const float uy = (jy + 0.5f * gy) * inv_rho;
   const float uz = (jz + 0.5f * gz) * inv_rho;
   const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
   const float gu = ux * gx + uy * gy + uz * gz;
-
-  const int xm = (x == 0) ? L.nx - 1 : x - 1;
-  const int xp = (x == L.nx - 1) ? 0 : x + 1;
-  const int ym = (y == 0) ? L.ny - 1 : y - 1;
-  const int yp = (y == L.ny - 1) ? 0 : y + 1;
-
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float w = (float)wgt(i);
@@ -108,55 +126,313 @@ __global__ __launch_bounds__(256) void k_collide_stream(LatDev L, int src, int p
     float deq;
     if (LINEAR) deq = w * (drho + rho * 3.0f * cu);
     else deq = w * (drho + rho * (3.0f * cu + 4.5f * cu * cu - usq15));
-    float post = d[i] - (d[i] - deq) * L.inv_tau;
+    float post = d[i] - (d[i] - deq) * inv_tau;
     if (FORCE) {
       const float cg = cx(i) * gx + cy(i) * gy + cz(i) * gz;
-      post += L.guo_pre * w * (3.0f * (cg - gu) + 9.0f * cu * cg);
+      post += guo_pre * w * (3.0f * (cg - gu) + 9.0f * cu * cg);
     }
+    d[i] = post;
+  }
+}
+
+// One lattice update of VEC consecutive x nodes (x0 .. x0 + VEC - 1) of buffer
+// `src`, pushed into buffer src ^ 1: streaming to x + c_i, periodic in x and y;
+// populations leaving through a wall return to their node reversed, with
+// -2 w_i rho_w (c_i . u_wall) / c_s^2, rho_w = 1 (bounce-back for moving
+// walls).  VEC = 2 needs an even nx (vector accesses stay aligned).
+template <typename T, bool LINEAR, bool FORCE, int VEC, bool NT>
+__global__ __launch_bounds__(256) void k_collide_stream(LatDev L, int src, int par) {
+  const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x0 >= L.nx || y >= L.ny) return;
+  const long long S = L.S;
+  const long long nxl = L.nx;
+  const long long plane = nxl * L.ny;
+  const long long n0 = (long long)z * plane + (long long)y * nxl + x0;
+  const T *__restrict__ fs = static_cast<const T *>(L.f[src]);
+  T *__restrict__ fd = static_cast<T *>(L.f[src ^ 1]);
+
+  float d[VEC][Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float inv = 1.0f / L.h_scale[i];
+    if constexpr (VEC == 2) Pop<T>::template ld2<NT>(fs, i * S + n0, inv, d[0][i], d[1][i]);
+    else d[0][i] = Pop<T>::template ld<NT>(fs, i * S + n0, inv);
+  }
+
+  float g[VEC][3];
+#pragma unroll
+  for (int v = 0; v < VEC; ++v) g[v][0] = g[v][1] = g[v][2] = 0.0f;
+  if (FORCE) {
+    // one tile holds all VEC nodes (TILE_X is a multiple of VEC)
+    const int t = L.ctrl->step;
+    const int tile = tile_of(L, x0, y, z);
+    if (L.stamp[par][tile] == t) {
+      const float *gp = L.g[par];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if constexpr (VEC == 2) Pop<float>::template ld2<false>(gp, c * S + n0, 1.0f, g[0][c], g[1][c]);
+        else g[0][c] = gp[c * S + n0];
+      }
+    }
+    // The other field was spread one step ago and has been interpolated
+    // from; clear it where it was touched so the next spreading starts at 0.
+    if (L.stamp[par ^ 1][tile] == t - 1) {
+      float *go = L.g[par ^ 1];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        if constexpr (VEC == 2) Pop<float>::template st2<false>(go, c * S + n0, 0.0f, 0.0f, 1.0f);
+        else go[c * S + n0] = 0.0f;
+      }
+    }
+  }
+#pragma unroll
+  for (int v = 0; v < VEC; ++v)
+    collide<LINEAR, FORCE>(d[v], g[v][0], g[v][1], g[v][2], L.inv_tau, L.guo_pre);
+
+  const int ym = (y == 0) ? L.ny - 1 : y - 1;
+  const int yp = (y == L.ny - 1) ? 0 : y + 1;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
     const int zt = z + cz(i);
     if (cz(i) != 0 && (zt < 0 || zt >= L.nz)) {
       const float uwall = (zt < 0) ? -L.uw : L.uw;
-      const float v = post - 6.0f * w * (float)cx(i) * uwall;
-      st_dev<T>(fd, opp(i) * S + n, v, L.h_scale[opp(i)]);
+      const float kick = 6.0f * (float)wgt(i) * (float)cx(i) * uwall;
+      const long long at = opp(i) * S + n0;
+      if constexpr (VEC == 2)
+        Pop<T>::template st2<NT>(fd, at, d[0][i] - kick, d[1][i] - kick, L.h_scale[opp(i)]);
+      else Pop<T>::template st<NT>(fd, at, d[0][i] - kick, L.h_scale[opp(i)]);
     } else {
-      const int xt = cx(i) > 0 ? xp : (cx(i) < 0 ? xm : x);
       const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
-      const long long nt = (long long)zt * plane + (long long)yt * nxl + xt;
-      st_dev<T>(fd, i * S + nt, post, L.h_scale[i]);
+      const long long row = i * S + (long long)zt * plane + (long long)yt * nxl;
+      if (cx(i) == 0) {
+        if constexpr (VEC == 2) Pop<T>::template st2<NT>(fd, row + x0, d[0][i], d[1][i], L.h_scale[i]);
+        else Pop<T>::template st<NT>(fd, row + x0, d[0][i], L.h_scale[i]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VEC; ++v) {
+          int xt = x0 + v + cx(i);
+          xt = xt < 0 ? xt + L.nx : (xt >= L.nx ? xt - L.nx : xt);
+          Pop<T>::template st<NT>(fd, row + xt, d[v][i], L.h_scale[i]);
+        }
+      }
     }
   }
 }
 
-// Block shape: whole x rows (up to 256 nodes), stacked in y to 256 threads.
-static dim3 lattice_block(const LatDev &L) {
-  int bx = ((L.nx + 31) / 32) * 32;
-  if (bx > 256) bx = 256;
-  int by = 256 / bx;
+// Row-vector form of the same update for rows that fit one wavefront: each
+// thread owns VEC = 4 consecutive x nodes and tpr = nx / 4 threads (a divisor
+// of 64) hold one whole row, so every population is loaded and stored as one
+// aligned 16-byte vector.  The +-x streaming shift moves one value per row
+// segment to the neighbouring thread with a lane shuffle (the row's ends wrap
+// into each other, which is the periodic boundary along x).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T>
+struct Pop4;
+
+template <>
+struct Pop4<float> {
+  static __device__ __forceinline__ void ld(const float *p, long long i, float, float (&v)[4]) {
+    const f32x4 r = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p + i));
+    v[0] = r.x;
+    v[1] = r.y;
+    v[2] = r.z;
+    v[3] = r.w;
+  }
+  static __device__ __forceinline__ void st(float *p, long long i, float a, float b, float c,
+                                            float d, float) {
+    f32x4 r;
+    r.x = a;
+    r.y = b;
+    r.z = c;
+    r.w = d;
+    __builtin_nontemporal_store(r, reinterpret_cast<f32x4 *>(p + i));
+  }
+};
+
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+template <>
+struct Pop4<__half> {
+  static __device__ __forceinline__ float h(unsigned int bits, float inv) {
+    return __half2float(__ushort_as_half((unsigned short)bits)) * inv;
+  }
+  static __device__ __forceinline__ unsigned int q(float v, float scale) {
+    return (unsigned int)__half_as_ushort(__float2half_rn(v * scale));
+  }
+  static __device__ __forceinline__ void ld(const __half *p, long long i, float inv, float (&v)[4]) {
+    const u32x2 r = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p + i));
+    v[0] = h(r.x & 0xffffu, inv);
+    v[1] = h(r.x >> 16, inv);
+    v[2] = h(r.y & 0xffffu, inv);
+    v[3] = h(r.y >> 16, inv);
+  }
+  static __device__ __forceinline__ void st(__half *p, long long i, float a, float b, float c,
+                                            float d, float scale) {
+    u32x2 r;
+    r.x = q(a, scale) | (q(b, scale) << 16);
+    r.y = q(c, scale) | (q(d, scale) << 16);
+    __builtin_nontemporal_store(r, reinterpret_cast<u32x2 *>(p + i));
+  }
+};
+
+template <typename T, bool LINEAR, bool FORCE>
+__global__ __launch_bounds__(256) void k_collide_stream_rows(LatDev L, int src, int par, int tpr) {
+  constexpr int VEC = 4;
+  const int lane = threadIdx.x & 63;
+  const int t = lane % tpr;                    // thread within its row
+  const int row = (blockIdx.x * (int)blockDim.x + (int)threadIdx.x) / tpr;
+  const bool live = row < L.ny * L.nz;
+  const int y = live ? row % L.ny : 0;
+  const int z = live ? row / L.ny : 0;
+  const int x0 = t * VEC;
+  const long long S = L.S;
+  const long long nxl = L.nx;
+  const long long plane = nxl * L.ny;
+  const long long n0 = (long long)z * plane + (long long)y * nxl + x0;
+  const T *__restrict__ fs = static_cast<const T *>(L.f[src]);
+  T *__restrict__ fd = static_cast<T *>(L.f[src ^ 1]);
+  // lanes holding the left and right neighbours of this segment in the row
+  const int row_lane0 = lane - t;
+  const int left = row_lane0 + (t == 0 ? tpr - 1 : t - 1);
+  const int right = row_lane0 + (t == tpr - 1 ? 0 : t + 1);
+
+  float d[VEC][Q];
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      float v[4];
+      Pop4<T>::ld(fs, i * S + n0, 1.0f / L.h_scale[i], v);
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) d[k][i] = v[k];
+    }
+    float g[VEC][3];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) g[k][0] = g[k][1] = g[k][2] = 0.0f;
+    if (FORCE) {
+      const int step = L.ctrl->step;
+      const int tile = tile_of(L, x0, y, z);
+      if (L.stamp[par][tile] == step) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+          float v[4];
+          Pop4<float>::ld(L.g[par], c * S + n0, 1.0f, v);
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) g[k][c] = v[k];
+        }
+      }
+      if (L.stamp[par ^ 1][tile] == step - 1) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) Pop4<float>::st(L.g[par ^ 1], c * S + n0, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < VEC; ++k)
+      collide<LINEAR, FORCE>(d[k], g[k][0], g[k][1], g[k][2], L.inv_tau, L.guo_pre);
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+#pragma unroll
+      for (int k = 0; k < VEC; ++k) d[k][i] = 0.0f;
+  }
+
+  const int ym = (y == 0) ? L.ny - 1 : y - 1;
+  const int yp = (y == L.ny - 1) ? 0 : y + 1;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    // every lane takes part in the shuffles, live or not
+    float in = 0.0f;
+    if (cx(i) > 0) in = __shfl(d[VEC - 1][i], left);
+    if (cx(i) < 0) in = __shfl(d[0][i], right);
+    if (!live) continue;
+    const int zt = z + cz(i);
+    if (cz(i) != 0 && (zt < 0 || zt >= L.nz)) {
+      const float uwall = (zt < 0) ? -L.uw : L.uw;
+      const float kick = 6.0f * (float)wgt(i) * (float)cx(i) * uwall;
+      Pop4<T>::st(fd, opp(i) * S + n0, d[0][i] - kick, d[1][i] - kick, d[2][i] - kick,
+                  d[3][i] - kick, L.h_scale[opp(i)]);
+    } else {
+      const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
+      const long long at = i * S + (long long)zt * plane + (long long)yt * nxl + x0;
+      if (cx(i) > 0) Pop4<T>::st(fd, at, in, d[0][i], d[1][i], d[2][i], L.h_scale[i]);
+      else if (cx(i) < 0) Pop4<T>::st(fd, at, d[1][i], d[2][i], d[3][i], in, L.h_scale[i]);
+      else Pop4<T>::st(fd, at, d[0][i], d[1][i], d[2][i], d[3][i], L.h_scale[i]);
+    }
+  }
+}
+
+template <typename T>
+static bool launch_cs_rows(const LatDev &L, int src, int par, bool force, bool linear,
+                           hipStream_t s) {
+  if (L.nx % 4 != 0) return false;
+  const int tpr = L.nx / 4;
+  if (tpr > 64 || 64 % tpr != 0) return false;
+  const long long rows = (long long)L.ny * L.nz;
+  const long long threads = rows * tpr;
+  const dim3 b(256), g((unsigned)((threads + 255) / 256));
+  if (force) {
+    if (linear) k_collide_stream_rows<T, true, true><<<g, b, 0, s>>>(L, src, par, tpr);
+    else k_collide_stream_rows<T, false, true><<<g, b, 0, s>>>(L, src, par, tpr);
+  } else {
+    if (linear) k_collide_stream_rows<T, true, false><<<g, b, 0, s>>>(L, src, par, tpr);
+    else k_collide_stream_rows<T, false, false><<<g, b, 0, s>>>(L, src, par, tpr);
+  }
+  return true;
+}
+
+// Block shape: whole x rows (up to `threads` nodes / VEC threads), stacked in y.
+static dim3 lattice_block(const LatDev &L, int vec = 1, int threads = 256) {
+  const int cols = (L.nx + vec - 1) / vec;
+  int bx = ((cols + 31) / 32) * 32;
+  if (bx > threads) bx = threads;
+  int by = threads / bx;
   if (by < 1) by = 1;
   return dim3(bx, by, 1);
 }
 
-static dim3 lattice_grid(const LatDev &L, dim3 b) {
-  return dim3((L.nx + b.x - 1) / b.x, (L.ny + b.y - 1) / b.y, L.nz);
+static dim3 lattice_grid(const LatDev &L, dim3 b, int vec = 1) {
+  const int cols = (L.nx + vec - 1) / vec;
+  return dim3((cols + b.x - 1) / b.x, (L.ny + b.y - 1) / b.y, L.nz);
+}
+
+template <typename T, int VEC, bool NT>
+static void launch_cs_v(const LatDev &L, int src, int par, bool force, bool linear,
+                        int threads, hipStream_t s) {
+  dim3 b = lattice_block(L, VEC, threads), g = lattice_grid(L, b, VEC);
+  if (force) {
+    if (linear) k_collide_stream<T, true, true, VEC, NT><<<g, b, 0, s>>>(L, src, par);
+    else k_collide_stream<T, false, true, VEC, NT><<<g, b, 0, s>>>(L, src, par);
+  } else {
+    if (linear) k_collide_stream<T, true, false, VEC, NT><<<g, b, 0, s>>>(L, src, par);
+    else k_collide_stream<T, false, false, VEC, NT><<<g, b, 0, s>>>(L, src, par);
+  }
 }
 
 template <typename T>
 static void launch_cs_t(const LatDev &L, int src, int par, bool force, bool linear,
-                        hipStream_t s) {
-  dim3 b = lattice_block(L), g = lattice_grid(L, b);
-  if (force) {
-    if (linear) k_collide_stream<T, true, true><<<g, b, 0, s>>>(L, src, par);
-    else k_collide_stream<T, false, true><<<g, b, 0, s>>>(L, src, par);
+                        int variant, hipStream_t s) {
+  // variant bits: 1 = two nodes per thread, 2 = non-temporal accesses,
+  // 4 = 128-thread blocks, 8 = 64-thread blocks, 16 = row-vector kernel
+  // (four nodes per thread, whole rows per wavefront) where the row fits
+  if ((variant & 16) && launch_cs_rows<T>(L, src, par, force, linear, s)) return;
+  const bool vec2 = (variant & 1) && (L.nx % 2 == 0);
+  const bool nt = (variant & 2) != 0;
+  const int threads = (variant & 8) ? 64 : ((variant & 4) ? 128 : 256);
+  if (vec2) {
+    if (nt) launch_cs_v<T, 2, true>(L, src, par, force, linear, threads, s);
+    else launch_cs_v<T, 2, false>(L, src, par, force, linear, threads, s);
   } else {
-    if (linear) k_collide_stream<T, true, false><<<g, b, 0, s>>>(L, src, par);
-    else k_collide_stream<T, false, false><<<g, b, 0, s>>>(L, src, par);
+    if (nt) launch_cs_v<T, 1, true>(L, src, par, force, linear, threads, s);
+    else launch_cs_v<T, 1, false>(L, src, par, force, linear, threads, s);
   }
 }
 
 void launch_collide_stream(const LatDev &L, int fp16, int src, int par, bool force,
-                           bool linear, hipStream_t s) {
-  if (fp16) launch_cs_t<__half>(L, src, par, force, linear, s);
-  else launch_cs_t<float>(L, src, par, force, linear, s);
+                           bool linear, int variant, hipStream_t s) {
+  if (fp16) launch_cs_t<__half>(L, src, par, force, linear, variant, s);
+  else launch_cs_t<float>(L, src, par, force, linear, variant, s);
 }
 
 // ---- initialisation: f = feq(rho = 1, u = (uw (2 z + 1 - nz) / nz, 0, 0)) ----
@@ -184,8 +460,8 @@ void launch_init_equilibrium(const LatDev &L, int fp16, int dst, double uw, hipS
 }
 
 // ---- FP64 field I/O ----------------------------------------------------------
-// what: 0 populations, 1 density, 2 velocity, 3 force density.  gpar < 0: no
-// force field yet (velocity without the half-force term, force = 0).
+// what: 0 populations, 1 density, 2 velocity, 3 force density.  gpar: the
+// field of the last step (its tiles stamped with that step), or -1 for none.
 template <typename T>
 __global__ __launch_bounds__(256) void k_get_field(LatDev L, int src, int gpar, int what,
                                                    double *out) {
@@ -197,11 +473,10 @@ __global__ __launch_bounds__(256) void k_get_field(LatDev L, int src, int gpar, 
   const long long n = ((long long)z * L.ny + y) * L.nx + x;
   const T *f = static_cast<const T *>(L.f[src]);
   double gx = 0.0, gy = 0.0, gz = 0.0;
-  if (gpar >= 0) {
-    const float *g = L.g[gpar];
-    gx = g[n];
-    gy = g[L.S + n];
-    gz = g[2 * L.S + n];
+  if (gpar >= 0 && L.stamp[gpar][tile_of(L, x, y, z)] == L.ctrl->step - 1) {
+    gx = L.g[gpar][n];
+    gy = L.g[gpar][L.S + n];
+    gz = L.g[gpar][2 * L.S + n];
   }
   if (what == 3) {
     out[n] = gx;

@@ -7,6 +7,8 @@
 // capsule of radius r keeps ~r * 2^-24 absolute resolution wherever it sits
 // in the box.  Spreading and interpolation put the M^3 stencil nodes of one
 // membrane node on one power-of-two lane group (8, 32 or 64 lanes).
+#include <algorithm>
+
 #include "common.h"
 #include "launch.h"
 
@@ -102,48 +104,79 @@ __device__ __forceinline__ void skalak_face_grad(const float4 a, const float4 b,
   degenerate = !(1.0f + I2 > 1e-6f);
 }
 
-// F_n = -sum over the faces at node n of d(A0 w_S)/dx_n (Eq. forcefromenergy).
-// One thread per node gathers its incident faces: no atomics, fixed order.
-__global__ __launch_bounds__(256) void k_membrane_forces(MemDev M, Ctrl *ctrl) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= M.nn) return;
-  float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-  bool bad = false;
-  const int e0 = M.csr_off[n], e1 = M.csr_off[n + 1];
-  for (int e = e0; e < e1; ++e) {
-    const int ent = M.csr_ent[e];
-    const int j = ent >> 2, k = ent & 3;
-    const int4 t = M.tri[j];
-    const float4 rp = M.ref_p[j], gh = M.ref_ghi[j], gl = M.ref_glo[j];
-    const FaceRef R{rp.x, rp.y, rp.z, rp.w, gh.x, gh.y, gh.z, gl.x, gl.y, gl.z};
-    const float4 mod = M.moduli[t.w];
-    float3 ga, gb, gc;
-    bool deg;
-    skalak_face_grad(M.x[t.x], M.x[t.y], M.x[t.z], R, mod.x, mod.y, ga, gb, gc, deg);
-    const float3 g = (k == 0) ? ga : ((k == 1) ? gb : gc);
-    fx -= g.x;
-    fy -= g.y;
-    fz -= g.z;
-    bad |= deg;
-  }
-  M.F[n] = make_float4(fx, fy, fz, 0.0f);
-  if (bad) atomicOr(&ctrl->err, ERR_FACE);
+// Gradients of every face energy A0 w_S with respect to its three corners,
+// one thread per face; the nodal forces F_n = -sum over the faces at n
+// (Eq. forcefromenergy) are gathered by the spreading kernel.
+__global__ __launch_bounds__(256) void k_face_gradients(MemDev M, Ctrl *ctrl) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= M.nf) return;
+  const int4 t = M.tri[j];
+  const float4 rp = M.ref_p[j], gh = M.ref_ghi[j], gl = M.ref_glo[j];
+  const float4 mod = M.moduli[t.w];
+  const FaceRef R{rp.x, rp.y, rp.z, rp.w, gh.x, gh.y, gh.z, gl.x, gl.y, gl.z};
+  float3 ga, gb, gc;
+  bool deg;
+  skalak_face_grad(M.x[t.x], M.x[t.y], M.x[t.z], R, mod.x, mod.y, ga, gb, gc, deg);
+  M.face_grad[3 * j + 0] = make_float4(ga.x, ga.y, ga.z, 0.0f);
+  M.face_grad[3 * j + 1] = make_float4(gb.x, gb.y, gb.z, 0.0f);
+  M.face_grad[3 * j + 2] = make_float4(gc.x, gc.y, gc.z, 0.0f);
+  if (deg) atomicOr(&ctrl->err, ERR_FACE);
 }
 
-void launch_membrane_forces(const MemDev &M, Ctrl *ctrl, hipStream_t s) {
-  if (M.nn <= 0) return;
-  k_membrane_forces<<<dim3((M.nn + 255) / 256), dim3(256), 0, s>>>(M, ctrl);
+void launch_face_gradients(const MemDev &M, Ctrl *ctrl, hipStream_t s) {
+  if (M.nf <= 0) return;
+  k_face_gradients<<<dim3((M.nf + 255) / 256), dim3(256), 0, s>>>(M, ctrl);
+}
+
+// Work items of the lane-group kernels are handed out so that each XCD (the
+// hardware deals consecutive blocks to the 8 XCDs in turn) gets one contiguous
+// range of the spatially sorted membrane nodes: neighbouring stencils then
+// meet in the same L2.  Returns -1 for the padding blocks.
+__device__ __forceinline__ int xcd_block(int nblocks_real) {
+  const int per = (nblocks_real + 7) / 8;
+  const int b = (int)blockIdx.x;
+  const int logical = (b % 8) * per + b / 8;
+  return logical < nblocks_real ? logical : -1;
+}
+
+static unsigned xcd_grid(long long blocks) { return (unsigned)(((blocks + 7) / 8) * 8); }
+
+// Butterfly sum over a power-of-two lane group.
+template <int GS>
+__device__ __forceinline__ float group_sum(float v) {
+#pragma unroll
+  for (int off = GS / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, GS);
+  return v;
 }
 
 // ---- spreading, Eq. (forcespreading) -------------------------------------------
-// One lane per (membrane node, stencil node); FP32 atomics into the force
-// field of parity `par`, and the step stamp of every touched tile.
+// One lane group per membrane node: the group first gathers the node's force
+// from the face gradients of its incident faces, then each lane adds
+// F_n delta(X - x_n) to one stencil node X of the force field of parity `par`
+// (FP32 atomics; the field starts at zero, see the collide-stream kernel) and
+// stamps X's tile with the step number.
 template <int M>
-__global__ __launch_bounds__(256) void k_spread(LatDev L, MemDev Mm, int par) {
+__global__ __launch_bounds__(256) void k_spread(LatDev L, MemDev Mm, int par, int nblocks) {
   constexpr int GS = group_size<M>();
+  const int blk = xcd_block(nblocks);
+  if (blk < 0) return;
   const int lane = threadIdx.x & (GS - 1);
-  const int node = (blockIdx.x * blockDim.x + threadIdx.x) / GS;
-  if (node >= Mm.nn || lane >= M * M * M) return;
+  const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
+  if (node >= Mm.nn) return;  // whole groups leave together
+  float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+  const int e0 = Mm.csr_off[node], e1 = Mm.csr_off[node + 1];
+  for (int e = e0 + lane; e < e1; e += GS) {
+    const int ent = Mm.csr_ent[e];
+    const float4 g = Mm.face_grad[3 * (ent >> 2) + (ent & 3)];
+    fx -= g.x;
+    fy -= g.y;
+    fz -= g.z;
+  }
+  fx = group_sum<GS>(fx);
+  fy = group_sum<GS>(fy);
+  fz = group_sum<GS>(fz);
+  if (lane == 0) Mm.F[node] = make_float4(fx, fy, fz, 0.0f);
+  if (lane >= M * M * M) return;
   const int sx = lane % M, sy = (lane / M) % M, sz = lane / (M * M);
   const float4 p = Mm.x[node];
   const int lx = stencil_lo<M>(p.x) + sx;
@@ -159,11 +192,10 @@ __global__ __launch_bounds__(256) void k_spread(LatDev L, MemDev Mm, int par) {
   }
   const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
   const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
-  const float4 F = Mm.F[node];
   float *g = L.g[par];
-  unsafeAtomicAdd(g + n, w * F.x);
-  unsafeAtomicAdd(g + L.S + n, w * F.y);
-  unsafeAtomicAdd(g + 2 * L.S + n, w * F.z);
+  unsafeAtomicAdd(g + n, w * fx);
+  unsafeAtomicAdd(g + L.S + n, w * fy);
+  unsafeAtomicAdd(g + 2 * L.S + n, w * fz);
   L.stamp[par][tile_of(L, X, Y, Z)] = L.ctrl->step;
 }
 
@@ -171,18 +203,19 @@ void launch_spread(const LatDev &L, const MemDev &M, int par, hipStream_t s) {
   if (M.nn <= 0) return;
   const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
   const long long lanes = (long long)M.nn * gs;
-  const dim3 grid((unsigned)((lanes + 255) / 256)), block(256);
-  if (M.m == 2) k_spread<2><<<grid, block, 0, s>>>(L, M, par);
-  else if (M.m == 3) k_spread<3><<<grid, block, 0, s>>>(L, M, par);
-  else k_spread<4><<<grid, block, 0, s>>>(L, M, par);
+  const int nblocks = (int)((lanes + 255) / 256);
+  const dim3 grid(xcd_grid(nblocks)), block(256);
+  if (M.m == 2) k_spread<2><<<grid, block, 0, s>>>(L, M, par, nblocks);
+  else if (M.m == 3) k_spread<3><<<grid, block, 0, s>>>(L, M, par, nblocks);
+  else k_spread<4><<<grid, block, 0, s>>>(L, M, par, nblocks);
 }
 
 // ---- interpolation + advection, Eqs. (velocityinterpolation), (positionupdate)
 // u(X, t+1) = (sum_i c_i f_i(X, t+1) + f(X, t)/2) / rho(X, t+1) at each stencil
 // node, weighted and summed over the lane group; the group's first lane moves
 // the node.  advect: 0 Euler; 1 Adams-Bashforth x += 3/2 u(t+1) - 1/2 u(t)
-// with u(t) the stored velocity of the previous step.  The last thread to
-// finish nothing else advances the device step counter.
+// with u(t) the stored velocity of the previous step.  One thread advances
+// the device step counter, which no other thread of this kernel reads.
 template <typename T>
 __device__ __forceinline__ float ld_pop(const T *p, long long idx, float inv_scale);
 template <>
@@ -196,56 +229,52 @@ __device__ __forceinline__ float ld_pop<__half>(const __half *p, long long idx, 
 
 template <typename T, int M>
 __global__ __launch_bounds__(256) void k_interp_advect(LatDev L, MemDev Mm, int fsrc, int par,
-                                                       int advect) {
+                                                       int advect, int nblocks) {
   constexpr int GS = group_size<M>();
+  if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
+  const int blk = xcd_block(nblocks);
+  if (blk < 0) return;
   const int lane = threadIdx.x & (GS - 1);
-  const int node = (blockIdx.x * blockDim.x + threadIdx.x) / GS;
-  const bool live = node < Mm.nn;
+  const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
+  if (node >= Mm.nn) return;  // whole groups leave together
   float ux = 0.0f, uy = 0.0f, uz = 0.0f;
-  float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  if (live) {
-    p = Mm.x[node];
-    if (lane < M * M * M) {
-      const int sx = lane % M, sy = (lane / M) % M, sz = lane / (M * M);
-      const int lx = stencil_lo<M>(p.x) + sx;
-      const int ly = stencil_lo<M>(p.y) + sy;
-      const int lz = stencil_lo<M>(p.z) + sz;
-      const float w =
-          phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
-      if (w != 0.0f) {
-        const int4 o = Mm.origin[Mm.node_cap[node]];
-        const int Z = o.z + lz;
-        if (Z < 0 || Z >= L.nz) {
-          atomicOr(&L.ctrl->err, ERR_WALL);
-        } else {
-          const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
-          const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
-          const T *f = static_cast<const T *>(L.f[fsrc]);
-          float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+  float4 p = Mm.x[node];
+  if (lane < M * M * M) {
+    const int sx = lane % M, sy = (lane / M) % M, sz = lane / (M * M);
+    const int lx = stencil_lo<M>(p.x) + sx;
+    const int ly = stencil_lo<M>(p.y) + sy;
+    const int lz = stencil_lo<M>(p.z) + sz;
+    const float w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
+    if (w != 0.0f) {
+      const int4 o = Mm.origin[Mm.node_cap[node]];
+      const int Z = o.z + lz;
+      if (Z < 0 || Z >= L.nz) {
+        atomicOr(&L.ctrl->err, ERR_WALL);
+      } else {
+        const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
+        const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
+        const T *f = static_cast<const T *>(L.f[fsrc]);
+        float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
-          for (int i = 0; i < Q; ++i) {
-            const float d = ld_pop<T>(f, i * L.S + n, 1.0f / L.h_scale[i]);
-            drho += d;
-            if (cx(i)) jx += cx(i) * d;
-            if (cy(i)) jy += cy(i) * d;
-            if (cz(i)) jz += cz(i) * d;
-          }
-          const float *g = L.g[par];
-          const float inv_rho = 1.0f / (1.0f + drho);
-          ux = w * ((jx + 0.5f * g[n]) * inv_rho);
-          uy = w * ((jy + 0.5f * g[L.S + n]) * inv_rho);
-          uz = w * ((jz + 0.5f * g[2 * L.S + n]) * inv_rho);
+        for (int i = 0; i < Q; ++i) {
+          const float d = ld_pop<T>(f, i * L.S + n, 1.0f / L.h_scale[i]);
+          drho += d;
+          if (cx(i)) jx += cx(i) * d;
+          if (cy(i)) jy += cy(i) * d;
+          if (cz(i)) jz += cz(i) * d;
         }
+        const float *g = L.g[par];
+        const float inv_rho = 1.0f / (1.0f + drho);
+        ux = w * ((jx + 0.5f * g[n]) * inv_rho);
+        uy = w * ((jy + 0.5f * g[L.S + n]) * inv_rho);
+        uz = w * ((jz + 0.5f * g[2 * L.S + n]) * inv_rho);
       }
     }
   }
-#pragma unroll
-  for (int off = GS / 2; off > 0; off >>= 1) {
-    ux += __shfl_xor(ux, off, GS);
-    uy += __shfl_xor(uy, off, GS);
-    uz += __shfl_xor(uz, off, GS);
-  }
-  if (live && lane == 0) {
+  ux = group_sum<GS>(ux);
+  uy = group_sum<GS>(uy);
+  uz = group_sum<GS>(uz);
+  if (lane == 0) {
     if (advect == 1) {
       const float4 up = Mm.u[node];
       p.x += 1.5f * ux - 0.5f * up.x;
@@ -259,7 +288,6 @@ __global__ __launch_bounds__(256) void k_interp_advect(LatDev L, MemDev Mm, int 
     Mm.u[node] = make_float4(ux, uy, uz, 0.0f);
     Mm.x[node] = p;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
 }
 
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
@@ -267,12 +295,13 @@ void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, 
   if (M.nn <= 0) return;
   const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
   const long long lanes = (long long)M.nn * gs;
-  const dim3 grid((unsigned)((lanes + 255) / 256)), block(256);
-#define IBM_LAUNCH_INTERP(T)                                                         \
-  do {                                                                               \
-    if (M.m == 2) k_interp_advect<T, 2><<<grid, block, 0, s>>>(L, M, fsrc, par, advect); \
-    else if (M.m == 3) k_interp_advect<T, 3><<<grid, block, 0, s>>>(L, M, fsrc, par, advect); \
-    else k_interp_advect<T, 4><<<grid, block, 0, s>>>(L, M, fsrc, par, advect);     \
+  const int nblocks = (int)((lanes + 255) / 256);
+  const dim3 grid(xcd_grid(nblocks)), block(256);
+#define IBM_LAUNCH_INTERP(T)                                                                   \
+  do {                                                                                         \
+    if (M.m == 2) k_interp_advect<T, 2><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks); \
+    else if (M.m == 3) k_interp_advect<T, 3><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks); \
+    else k_interp_advect<T, 4><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);     \
   } while (0)
   if (fp16) IBM_LAUNCH_INTERP(__half);
   else IBM_LAUNCH_INTERP(float);
@@ -521,27 +550,30 @@ void launch_observables(const MemDev &M, Ctrl *ctrl, hipStream_t s) {
 }
 
 // ---- mesh output (FP64, unwrapped lattice coordinates) -----------------------------
+// Node n (internal, spatially sorted order) goes to row ext_id[n] (the
+// caller's order).
 __global__ __launch_bounds__(256) void k_get_mesh(MemDev M, double *xyz, double *F, double *u) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= M.nn) return;
+  const int e = M.ext_id[n];
   if (xyz) {
     const float4 p = M.x[n];
     const int4 o = M.origin[M.node_cap[n]];
-    xyz[3 * n + 0] = (double)o.x + (double)p.x;
-    xyz[3 * n + 1] = (double)o.y + (double)p.y;
-    xyz[3 * n + 2] = (double)o.z + (double)p.z;
+    xyz[3 * e + 0] = (double)o.x + (double)p.x;
+    xyz[3 * e + 1] = (double)o.y + (double)p.y;
+    xyz[3 * e + 2] = (double)o.z + (double)p.z;
   }
   if (F) {
     const float4 f = M.F[n];
-    F[3 * n + 0] = f.x;
-    F[3 * n + 1] = f.y;
-    F[3 * n + 2] = f.z;
+    F[3 * e + 0] = f.x;
+    F[3 * e + 1] = f.y;
+    F[3 * e + 2] = f.z;
   }
   if (u) {
     const float4 v = M.u[n];
-    u[3 * n + 0] = v.x;
-    u[3 * n + 1] = v.y;
-    u[3 * n + 2] = v.z;
+    u[3 * e + 0] = v.x;
+    u[3 * e + 1] = v.y;
+    u[3 * e + 2] = v.z;
   }
 }
 

@@ -141,6 +141,33 @@ def test_coupled_step_parity_several_capsules(B):
     compare_one_step(B, c, f_s, x_s)
 
 
+def test_coupled_step_parity_dense_mesh(B):
+    """A 20480-face capsule of radius 6 with the 4-point delta: about a
+    thousand membrane nodes reach each force tile near the membrane."""
+    say("dense mesh")
+    c = small_case(n=(24, 24, 24), m=4, level=5, r=6.0, ca=0.02)
+    f_s, x_s = deformed_state(c, 3)
+    compare_one_step(B, c, f_s, x_s)
+
+
+def test_coupled_step_parity_crowded_overlapping_capsules(B):
+    """Seventy small overlapping capsules around one point: hundreds of
+    stencil contributions land on the same lattice nodes."""
+    say("crowded tiles")
+    nx = ny = nz = 16
+    uw = 0.02
+    rng = np.random.default_rng(8)
+    caps = []
+    for k in range(70):
+        cen = tuple(7.5 + rng.uniform(-1.0, 1.0, 3))
+        r = 2.0 + 0.5 * rng.uniform()
+        ks = W.ks_from_capillary(0.05, uw, nz, r)
+        caps.append(W.CapsuleSpec(0, r, cen, ks, ks))
+    c = Case(W.Workload("crowded", nx, ny, nz, 1.0, uw, 2, 0, caps))
+    f_s, x_s = deformed_state(c, 5)
+    compare_one_step(B, c, f_s, x_s)
+
+
 def test_undeformed_capsule_has_zero_force(B):
     c = small_case(m=2)
     lat = c.gpu(graph=False)
@@ -311,3 +338,24 @@ def test_bad_arguments(B):
         lat.mesh()
     lat.step(0)
     lat.close()
+
+
+def test_collide_stream_variants_agree(B):
+    """Every launch variant of the collide-stream kernel computes the same
+    update (odd nx falls back to one node per thread, nx not a multiple of 4
+    to the per-node kernels)."""
+    for shape in ((32, 20, 16), (30, 20, 16), (27, 19, 18)):
+        c = small_case(n=shape, m=3, ca=0.02)
+        ref = None
+        for v in range(32):
+            lat = c.gpu(graph=False)
+            lat.set_option(B.OPT_LBM_VARIANT, v)
+            lat.step(6)
+            f = lat.populations().cpu().numpy()
+            x = lat.mesh()[0].cpu().numpy()
+            lat.close()
+            if ref is None:
+                ref = (f, x)
+            else:
+                assert rel_err(f, ref[0]) < 1e-6, v
+                assert np.max(np.abs(x - ref[1])) < 1e-6, v
