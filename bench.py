@@ -48,6 +48,8 @@ def measured_traffic(workload: str, storage: str):
         return None
     src = kernel_source_hash()
     for line in open(TRAFFIC_FILE):
+        if line.startswith("#"):
+            continue
         parts = line.split()
         if len(parts) == 5 and parts[0] == workload and parts[1] == storage and parts[4] == src:
             return float(parts[2]) + float(parts[3])
