@@ -56,7 +56,7 @@ def measured_traffic(workload: str, storage: str):
     return None
 
 
-def setup(workload: str, storage: str, graph: bool, variant: int = -1):
+def setup(workload: str, storage: str, graph: bool, variant: int = -1, chunk: int = -1):
     from paper_1004_2416_amd import binding as B
     from paper_1004_2416_amd import workloads as W
 
@@ -68,17 +68,17 @@ def setup(workload: str, storage: str, graph: bool, variant: int = -1):
     lat.set_option(B.OPT_GRAPH, int(graph))
     if variant >= 0:
         lat.set_option(B.OPT_LBM_VARIANT, int(variant))
+    if chunk >= 0 and wl.capsules:
+        lat.set_option(B.OPT_CHUNK_NODES, int(chunk))
     return wl, lat
 
 
-def cpu_baseline(workload: str, seconds: float):
+def cpu_baseline(wl, seconds: float):
     """The FP64 oracle on the host cores: whole coupled steps of the same
     workload from the same initial state, until `seconds` have passed."""
     import numpy as np
     from oracle import oracle as O
-    from paper_1004_2416_amd import workloads as W
 
-    wl = W.config(workload)
     xs, ts, ks, ka = [], [], [], []
     off = 0
     for c in wl.capsules:
@@ -133,9 +133,13 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5"])
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+                    help="c4: the batched sweep of 64 independent runs")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--chunk-nodes", type=int, default=-1,
+                    help="membrane nodes per chunk of the coupling kernels (0: none; "
+                         "-1: library default)")
     ap.add_argument("--lbm-variant", type=int, default=-1,
                     help="collide-stream launch variant (IBM_OPT_LBM_VARIANT bits; "
                          "-1: the library default)")
@@ -153,8 +157,13 @@ def main():
         copy_calibration(args.copy_calibration_mib)
         return
 
+    if args.workload == "c4":
+        run_batch(args)
+        return
+
     import torch
-    wl, lat = setup(args.workload, args.storage, not args.no_graph, args.lbm_variant)
+    wl, lat = setup(args.workload, args.storage, not args.no_graph, args.lbm_variant,
+                    args.chunk_nodes)
     stream = lat.stream
     lat.step(args.warmup)
     lat.synchronize()
@@ -199,6 +208,7 @@ def main():
             "capsules": len(wl.capsules), "membrane_nodes": wl.n_membrane_nodes,
             "delta_width": wl.m, "storage": args.storage, "graph": not args.no_graph,
             "u_w": wl.u_w, "tau": wl.tau, "lbm_variant": args.lbm_variant,
+            "chunk_nodes": args.chunk_nodes,
         },
         "membrane_node_updates_per_s": round(wl.n_membrane_nodes * args.steps / (ms * 1e-3), 1),
         "step_pct_hbm_roofline": round(100 * mlups * 1e6 * bytes_per_node(args.storage)
@@ -214,7 +224,99 @@ def main():
         },
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(args.workload, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def run_batch(args):
+    """The batched sweep: 64 independent single-capsule runs of uneven size,
+    capillary number and delta width advanced together (one launch per
+    kernel of the step for all runs), against the same runs stepped one
+    after another."""
+    import torch
+    from paper_1004_2416_amd import binding as B
+    from paper_1004_2416_amd import workloads as W
+
+    wls = W.sweep_workloads()
+    lats = []
+    for wl in wls:
+        lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau, storage=args.storage)
+        lat.set_shear(wl.u_w, init_profile=True)
+        c = wl.capsules[0]
+        lat.add_capsules([B.icosphere(c.level, c.r, c.center)], [c.ks], [c.ka], wl.m)
+        lats.append(lat)
+    batch = B.Batch(lats)
+    stream = lats[0].stream
+    n_lat = sum(w.n_nodes_lattice for w in wls)
+    n_mem = sum(w.n_membrane_nodes for w in wls)
+    batch.step(args.warmup)
+    torch.cuda.synchronize()
+
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record(stream)
+    batch.step(args.steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    for lat in lats:
+        lat.synchronize()
+    ms = start.elapsed_time(end)
+    mlups = n_lat * args.steps / (ms * 1e-3) / 1e6
+
+    # the same runs, each stepped on its own (its own graphs), for comparison
+    k_single = max(16, (args.steps // 10) // 16 * 16)
+    start.record(stream)
+    for lat in lats:
+        lat.step(k_single)
+    end.record(stream)
+    torch.cuda.synchronize()
+    mlups_single = n_lat * k_single / (start.elapsed_time(end) * 1e-3) / 1e6
+
+    phases = batch.profile(args.profile_steps)
+    k1_ms = phases["lbm"]
+    algo = bytes_per_node(args.storage) * n_lat
+    achieved = algo / (k1_ms * 1e-3) / 1e9
+    D = [float(lat.observables()[0, 4]) for lat in lats[:4]]
+    batch.close()
+    for lat in lats:
+        lat.close()
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "batched_sweep_64runs", "runs": len(wls), "lattice_nodes": n_lat,
+            "membrane_nodes": n_mem, "storage": args.storage,
+            "run_sizes": sorted({w.nx for w in wls}), "delta_widths": sorted({w.m for w in wls}),
+        },
+        "unbatched_mlups": round(mlups_single, 1),
+        "batched_speedup": round(mlups / mlups_single, 3),
+        "membrane_node_updates_per_s": round(n_mem * args.steps / (ms * 1e-3), 1),
+        "step_pct_hbm_roofline": round(100 * mlups * 1e6 * bytes_per_node(args.storage)
+                                       / (HBM_PEAK_GBS * 1e9), 2),
+        "phase_ms": {k: round(v, 5) for k, v in phases.items()},
+        "wall_s": round(wall, 3),
+        "D_final": [round(d, 6) for d in D],
+        "roofline": {
+            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic("batched_sweep_64runs", args.storage),
+            "kernel": "k_batch_collide_stream", "algorithmic_bytes_per_launch": algo,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

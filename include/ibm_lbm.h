@@ -88,8 +88,10 @@ extern "C" {
 #define IBM_OBS_N 16
 
 /* ---- kernel phases (ibm_profile_step) ------------------------------------ */
-#define IBM_PHASE_FORCES 0   /* Skalak nodal forces            (step 1) */
-#define IBM_PHASE_SPREAD 1   /* force spreading                (step 2) */
+#define IBM_PHASE_FORCES 0   /* Skalak nodal forces (step 1): formed
+                                inside the spreading kernel, so this
+                                phase is always empty (0)            */
+#define IBM_PHASE_SPREAD 1   /* nodal forces + spreading  (steps 1, 2) */
 #define IBM_PHASE_LBM 2      /* collide + stream + walls       (step 3) */
 #define IBM_PHASE_INTERP 3   /* interpolation + advection      (steps 4, 5) */
 #define IBM_N_PHASES 4
@@ -110,6 +112,15 @@ extern "C" {
                                   used when nx / 4 divides 64; default 23);
                                   results are identical, only the speed
                                   differs                                    */
+#define IBM_OPT_CHUNK_NODES 5  /* spreading and interpolation work on chunks
+                                  of this many consecutive membrane nodes of
+                                  one capsule (16, 32, 64, 128 or 256),
+                                  summing overlapping stencils
+                                  in on-chip memory; 0: one lane group
+                                  per node without chunks (the default,
+                                  faster on the workloads measured).
+                                  Results agree to FP32 rounding
+                                  (summation order differs)                 */
 
 typedef struct ibm_lattice ibm_lattice;
 
@@ -205,6 +216,81 @@ int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase);
 
 /* Release the handle (not the caller's device buffers); waits first. */
 int ibm_destroy(ibm_lattice *lat);
+
+/* ---- forward sensitivities (tangent-linear model of the timestep) ----------
+ * The derivative of the whole state along one parameter direction, advanced
+ * beside the timestep by hand-differentiated kernels: the tangent of the
+ * Skalak forces (Sec. II.B), of spreading and interpolation including the
+ * motion of the delta stencils (Sec. II.C), and of collide + stream +
+ * bounce-back (Sec. II.A).  The direction is given by the rates of the
+ * parameters: d k_s and d k_alpha per capsule and d u_w; for the reduced
+ * shear rate G of Sec. III at fixed C, say, dks = -k_s / G, dka = C dks.
+ * Needs FP32 storage and Euler advection. */
+
+/* Device bytes of the tangent state of this lattice (and its membrane). */
+int ibm_tangent_bytes(ibm_lattice *lat, size_t *bytes);
+
+/* Attach a tangent state in dev_mem (caller-owned, 256-byte aligned, at least
+ * ibm_tangent_bytes) and start it: node and force tangents zero; population
+ * tangents zero, or with init_profile = 1 the derivative of the linear
+ * Couette start of ibm_set_shear(init_profile = 1) along duw.  dks, dka:
+ * host arrays of n_caps rates (NULL without a membrane).  From now on every
+ * ibm_step also advances the tangent.  The membrane must be attached first. */
+int ibm_tangent_attach(ibm_lattice *lat, const double *dks, const double *dka, double duw,
+                       int init_profile, void *dev_mem, size_t bytes);
+
+/* Stop advancing the tangent (dev_mem may then be reused). */
+int ibm_tangent_detach(ibm_lattice *lat);
+
+/* Tangent populations, dst_dev [19][nz][ny][nx] FP64 device; waits. */
+int ibm_tangent_get_pops(ibm_lattice *lat, double *dst_dev);
+
+/* Tangent node positions and velocities of the last step, [n_nodes][3] FP64
+ * device arrays in the caller's node order (either may be NULL); waits. */
+int ibm_tangent_get_mesh(ibm_lattice *lat, double *dxyz_dev, double *du_dev);
+
+/* Derivative of every observable (Sec. III) along the tangent: the FP64
+ * central difference (obs(x + h dx) - obs(x - h dx)) / (2 h) of the shape
+ * observables along the tangent node positions, out_host [n_caps][IBM_OBS_N].
+ * h (> 0, in units of the parameter) sets the difference step; waits. */
+int ibm_tangent_observables(ibm_lattice *lat, double h, double *out_host);
+
+/* ---- batches of independent runs (Sec. IV parameter studies) ---------------
+ * A batch advances many lattices (each with or without capsules, of any size,
+ * tau, wall speed and delta width) together: every kernel of the timestep is
+ * launched once for all runs, and whole-step sequences are replayed as one
+ * captured graph, so many small runs cost a few launches per step instead of
+ * a few per run.  The runs stay the caller's handles: fields, meshes and
+ * observables are read from them as usual, and they may be stepped alone
+ * between batch steps. */
+typedef struct ibm_batch ibm_batch;
+
+/* Device bytes the batch of runs[0 .. n_runs-1] needs for its tables. */
+int ibm_batch_bytes(int n_runs, ibm_lattice *const *runs, size_t *bytes);
+
+/* Group the runs.  They must share one stream (the batch enqueues on it) and,
+ * at every ibm_batch_step, have made the same number of steps and use the same
+ * storage, equilibrium and advection options.  dev_mem: caller-owned device
+ * buffer of at least ibm_batch_bytes bytes, 256-byte aligned, kept until
+ * ibm_batch_destroy.  The runs must outlive the batch; a run may not gain
+ * more membrane nodes or faces than it had here (IBM_ERR_BAD_STATE). */
+int ibm_batch_create(int n_runs, ibm_lattice *const *runs, void *dev_mem, size_t bytes,
+                     ibm_batch **out);
+
+/* Enqueue n timesteps of every run (Sec. II.C, sub-steps 1-5); asynchronous.
+ * Device-side errors of a run are reported by that run's next synchronising
+ * call.  The per-node coupling kernels are used whatever a run's
+ * IBM_OPT_CHUNK_NODES, and the lattice update is the one-node-per-thread
+ * form whatever its IBM_OPT_LBM_VARIANT. */
+int ibm_batch_step(ibm_batch *b, int64_t n);
+
+/* ibm_profile_step for a batch: n steps of every run with plain launches and
+ * HIP events between the batched kernels; ms_per_phase[IBM_N_PHASES] gets
+ * the mean duration per step of each phase.  For measurement; waits. */
+int ibm_batch_profile_step(ibm_batch *b, int64_t n, double *ms_per_phase);
+
+/* Release the batch (not the runs or dev_mem); waits first. */
+int ibm_batch_destroy(ibm_batch *b);
 
 /* Thread-local description of the last error ("" if none). */
 const char *ibm_last_error(void);

@@ -28,6 +28,7 @@ ERRORS = {
 STORAGE = {"fp32": 0, "fp16": 1}
 FIELD_POPS, FIELD_RHO, FIELD_U, FIELD_FORCE = 0, 1, 2, 3
 OPT_GRAPH, OPT_EQUILIBRIUM, OPT_ADVECTION, OPT_RECENTER, OPT_LBM_VARIANT = 0, 1, 2, 3, 4
+OPT_CHUNK_NODES = 5
 PHASES = ("forces", "spread", "lbm", "interp")
 OBS_FIELDS = ("V", "cx", "cy", "cz", "D", "theta", "ra", "rb", "rc", "area",
               "Ixx", "Iyy", "Izz", "Ixy", "Ixz", "Iyz")
@@ -68,6 +69,17 @@ def _load():
         "ibm_last_error": ([], ctypes.c_char_p),
         "ibm_icosphere_size": ([i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
         "ibm_icosphere": ([i, d, d, d, d, v, v], i),
+        "ibm_tangent_bytes": ([v, ctypes.POINTER(sz)], i),
+        "ibm_tangent_attach": ([v, v, v, d, i, v, sz], i),
+        "ibm_tangent_detach": ([v], i),
+        "ibm_tangent_get_pops": ([v, v], i),
+        "ibm_tangent_get_mesh": ([v, v, v], i),
+        "ibm_tangent_observables": ([v, d, v], i),
+        "ibm_batch_bytes": ([i, v, ctypes.POINTER(sz)], i),
+        "ibm_batch_create": ([i, v, v, sz, ctypes.POINTER(v)], i),
+        "ibm_batch_step": ([v, i64], i),
+        "ibm_batch_profile_step": ([v, i64, v], i),
+        "ibm_batch_destroy": ([v], i),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -229,9 +241,84 @@ class Lattice:
         _check(lib.ibm_observables(self._h, _ptr(out)))
         return out
 
+    # -- forward sensitivities ---------------------------------------------
+    def attach_tangent(self, dks=None, dka=None, duw: float = 0.0, init_profile: bool = False):
+        """Start a tangent along the parameter rates dks, dka (per capsule) and
+        duw; every later step advances it."""
+        nbytes = ctypes.c_size_t()
+        _check(lib.ibm_tangent_bytes(self._h, ctypes.byref(nbytes)))
+        self._tan = _aligned_buffer(nbytes.value, self.device)
+        if self.n_caps:
+            a = np.ascontiguousarray(np.broadcast_to(np.asarray(dks, np.float64), (self.n_caps,)))
+            b = np.ascontiguousarray(np.broadcast_to(np.asarray(dka, np.float64), (self.n_caps,)))
+            pa, pb = _ptr(a), _ptr(b)
+        else:
+            pa = pb = None
+        _check(lib.ibm_tangent_attach(self._h, pa, pb, float(duw), int(bool(init_profile)),
+                                      ctypes.c_void_p(self._tan[1].data_ptr()), nbytes.value))
+
+    def detach_tangent(self):
+        _check(lib.ibm_tangent_detach(self._h))
+        self._tan = None
+
+    def tangent_populations(self):
+        torch = _torch()
+        nz, ny, nx = self.shape
+        out = torch.empty((19, nz, ny, nx), dtype=torch.float64, device=self.device)
+        _check(lib.ibm_tangent_get_pops(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
+
+    def tangent_mesh(self):
+        """(d positions, d velocities), float64 [nn, 3] device tensors."""
+        torch = _torch()
+        out = [torch.empty((self.nn, 3), dtype=torch.float64, device=self.device) for _ in range(2)]
+        _check(lib.ibm_tangent_get_mesh(self._h, *[ctypes.c_void_p(o.data_ptr()) for o in out]))
+        return tuple(out)
+
+    def tangent_observables(self, h: float) -> np.ndarray:
+        out = np.zeros((self.n_caps, OBS_N))
+        _check(lib.ibm_tangent_observables(self._h, float(h), _ptr(out)))
+        return out
+
     def close(self):
         if getattr(self, "_h", None):
             lib.ibm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Independent runs (Lattice objects on one stream) advanced together:
+    one launch per kernel of the step for all of them."""
+
+    def __init__(self, lattices: Sequence[Lattice]):
+        self.runs = list(lattices)
+        n = len(self.runs)
+        handles = (ctypes.c_void_p * n)(*[r._h.value for r in self.runs])
+        nbytes = ctypes.c_size_t()
+        _check(lib.ibm_batch_bytes(n, handles, ctypes.byref(nbytes)))
+        self._raw, self._buf = _aligned_buffer(nbytes.value, self.runs[0].device)
+        h = ctypes.c_void_p()
+        _check(lib.ibm_batch_create(n, handles, ctypes.c_void_p(self._buf.data_ptr()), nbytes.value,
+                                    ctypes.byref(h)))
+        self._h = h
+
+    def step(self, n: int = 1):
+        _check(lib.ibm_batch_step(self._h, int(n)))
+
+    def profile(self, n: int) -> dict:
+        out = np.zeros(4)
+        _check(lib.ibm_batch_profile_step(self._h, int(n), _ptr(out)))
+        return dict(zip(PHASES, out.tolist()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.ibm_batch_destroy(self._h)
             self._h = None
 
     def __del__(self):

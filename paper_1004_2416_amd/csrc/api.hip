@@ -80,8 +80,8 @@ LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
 }
 
 struct MembraneLayout {
-  size_t x, u, F, face_grad, ext_id, node_cap, csr_off, csr_ent, tri, ref_p, ref_ghi, ref_glo, origin, moduli,
-      cap_node_off, cap_face_off, obs, total;
+  size_t x, u, F, ext_id, node_cap, csr_off, csr_ent, tri, ref_p, ref_ghi, ref_glo, origin, moduli,
+      cap_node_off, cap_face_off, obs, chunk, chunk_face_off, chunk_face, total;
 };
 
 MembraneLayout membrane_layout(int nc, long long nn, long long nf) {
@@ -95,7 +95,6 @@ MembraneLayout membrane_layout(int nc, long long nn, long long nf) {
   l.x = take(nn * 16);
   l.u = take(nn * 16);
   l.F = take(nn * 16);
-  l.face_grad = take(3 * nf * 16);
   l.ext_id = take(nn * 4);
   l.node_cap = take(nn * 4);
   l.csr_off = take((nn + 1) * 4);
@@ -109,6 +108,9 @@ MembraneLayout membrane_layout(int nc, long long nn, long long nf) {
   l.cap_node_off = take(((size_t)nc + 1) * 4);
   l.cap_face_off = take(((size_t)nc + 1) * 4);
   l.obs = take((size_t)nc * IBM_OBS_N * 8);
+  l.chunk = take((size_t)(nn / ibm::CHUNK_MIN + nc + 1) * 8);  // at the smallest chunk size
+  l.chunk_face_off = take((size_t)(nn / ibm::CHUNK_MIN + nc + 2) * 4);
+  l.chunk_face = take(3 * (size_t)nf * 4);  // a face lies in at most three chunks
   l.total = off;
   return l;
 }
@@ -129,15 +131,20 @@ struct ibm_lattice {
   ibm::MemDev M{};
   std::vector<int> node_off, face_off;
   std::vector<int> int_of_ext;  // caller's node index -> internal (sorted) index
+  std::vector<int> csr_off, csr_ent;  // host copy of the node -> (face, corner) lists
 
   // default collide-stream form: whole-row vectors where the row fits a
   // wavefront, else two nodes per thread, non-temporal, 128-thread blocks
   int use_graph = 1, eq_linear = 0, ab2 = 0, recenter_every = 64, lbm_variant = 16 | 7;
+  int chunk_nodes = 0;  // membrane nodes per chunk of the coupling kernels (0: none)
   bool have_prev_u = false;
   int64_t since_recenter = 0;
 
   hipGraphExec_t gexec = nullptr;
   bool graph_valid = false;
+
+  bool has_tan = false;  // a tangent (forward sensitivity) state is attached
+  ibm::TanDev T{};
 };
 
 namespace {
@@ -162,19 +169,65 @@ void reset_force_state(ibm_lattice *lat, hipStream_t s) {
 void enqueue_step(ibm_lattice *lat, hipStream_t s, int advect) {
   const int src = (int)(lat->steps & 1);
   const int par = src;  // force field of this step's parity
+  const bool tan = lat->has_tan;
   if (lat->has_mem) {
-    ibm::launch_face_gradients(lat->M, lat->L.ctrl, s);                  // 1: F(t)
-    ibm::launch_spread(lat->L, lat->M, par, s);                          // 2: f(X, t)
+    ibm::launch_spread(lat->L, lat->M, par, s);                          // 1, 2: F(t), f(X, t)
+    if (tan) ibm::launch_tangent_spread(lat->L, lat->M, lat->T, par, s);
     ibm::launch_collide_stream(lat->L, lat->storage, src, par, true,     // 3: f_i(t+1)
                                lat->eq_linear != 0, lat->lbm_variant, s);
+    if (tan) {
+      ibm::launch_tangent_collide_stream(lat->L, lat->T, src, par, lat->eq_linear != 0, s);
+      // before the positions move: the tangent needs x(t)
+      ibm::launch_tangent_interp(lat->L, lat->M, lat->T, src ^ 1, par, s);
+    }
     ibm::launch_interp_advect(lat->L, lat->M, lat->storage, src ^ 1,     // 4, 5
                               par, advect, s);
   } else {
     ibm::launch_collide_stream(lat->L, lat->storage, src, par, false, lat->eq_linear != 0,
                                lat->lbm_variant, s);
+    if (tan) ibm::launch_tangent_collide_stream(lat->L, lat->T, src, par, lat->eq_linear != 0, s);
   }
   lat->steps += 1;
   lat->since_recenter += 1;
+}
+
+// Chunk tables of the coupling kernels for the current chunk size: runs of
+// chunk_nodes consecutive nodes, cut at capsule ends, and for each chunk the
+// faces with at least one corner in it.
+int upload_chunks(ibm_lattice *lat) {
+  ibm::MemDev &M = lat->M;
+  std::vector<int2> ch;
+  std::vector<int> cfo(1, 0), cf;
+  if (lat->chunk_nodes > 0) {
+    std::vector<int> seen((size_t)M.nf, -1);
+    for (size_t c = 0; c + 1 < lat->node_off.size(); ++c)
+      for (int n = lat->node_off[c]; n < lat->node_off[c + 1]; n += lat->chunk_nodes) {
+        const int q = (int)ch.size(), e = std::min(n + lat->chunk_nodes, lat->node_off[c + 1]);
+        ch.push_back(make_int2(n, e));
+        for (int v = n; v < e; ++v)
+          for (int k = lat->csr_off[v]; k < lat->csr_off[v + 1]; ++k) {
+            const int j = lat->csr_ent[k] >> 2;
+            if (seen[j] != q) {
+              seen[j] = q;
+              cf.push_back(j);
+            }
+          }
+        cfo.push_back((int)cf.size());
+      }
+  }
+  const size_t cap = (size_t)M.nn / ibm::CHUNK_MIN + M.n_caps + 1;
+  if (ch.size() > cap || cf.size() > 3 * (size_t)M.nf)
+    return fail(IBM_ERR_BAD_STATE, "chunk table overflow");
+  if (!ch.empty()) {
+    hipStream_t s = lat->stream;
+    IBM_HIP(hipMemcpyAsync(M.chunk, ch.data(), ch.size() * sizeof(int2), hipMemcpyHostToDevice, s));
+    IBM_HIP(hipMemcpyAsync(M.chunk_face_off, cfo.data(), cfo.size() * sizeof(int),
+                           hipMemcpyHostToDevice, s));
+    IBM_HIP(hipMemcpyAsync(M.chunk_face, cf.data(), cf.size() * sizeof(int), hipMemcpyHostToDevice, s));
+    IBM_HIP(hipStreamSynchronize(s));  // the host tables must outlive the copies
+  }
+  M.n_chunks = (int)ch.size();
+  return IBM_OK;
 }
 
 int advect_mode(ibm_lattice *lat) { return (lat->ab2 && lat->have_prev_u) ? 1 : 0; }
@@ -281,6 +334,170 @@ std::vector<int> morton_order(const double *xyz, int n) {
   std::vector<int> order(n);
   for (int k = 0; k < n; ++k) order[k] = key[k].second;
   return order;
+}
+
+}  // namespace
+
+struct ibm_batch {
+  std::vector<ibm_lattice *> runs;
+  hipStream_t stream = nullptr;      // the first run's stream
+  hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+  char *dev = nullptr;
+  size_t bytes = 0;
+  size_t cap_lat = 0, cap_node = 0;  // work-item capacities
+  ibm::BatchDev B{};
+  std::vector<char> image;  // host copy of the device tables last uploaded
+  hipGraphExec_t gexec = nullptr;
+  bool graph_valid = false;
+  int graph_advect = -1, graph_linear = -1;  // options the graph was captured with
+};
+
+namespace {
+
+struct BatchLayout {
+  size_t lat, mem, lat_items, node_items, total;
+};
+
+BatchLayout batch_layout(size_t n, size_t cap_lat, size_t cap_node) {
+  BatchLayout l{};
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t at = off;
+    off += round_up(b, ALIGN);
+    return at;
+  };
+  l.lat = take(n * sizeof(ibm::LatDev));
+  l.mem = take(n * sizeof(ibm::MemDev));
+  l.lat_items = take(cap_lat * sizeof(int2));
+  l.node_items = take(cap_node * sizeof(int2));
+  l.total = off;
+  return l;
+}
+
+long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
+
+int group_lanes(int m) {
+  return m == 2 ? ibm::group_size<2>() : (m == 3 ? ibm::group_size<3>() : ibm::group_size<4>());
+}
+
+// Work items of the batched kernels for the runs' current state.
+void batch_items(const std::vector<ibm_lattice *> &runs, std::vector<int2> &li,
+                 std::vector<int2> &ni) {
+  li.clear();
+  ni.clear();
+  for (size_t r = 0; r < runs.size(); ++r) {
+    const ibm_lattice *lat = runs[r];
+    const long long nb = ceil_div((long long)lat->nx * lat->ny * lat->nz, 256);
+    for (long long b = 0; b < nb; ++b) li.push_back(make_int2((int)r, (int)b));
+    if (!lat->has_mem) continue;
+    const long long nbn = ceil_div((long long)lat->M.nn * group_lanes(lat->M.m), 256);
+    for (long long b = 0; b < nbn; ++b) ni.push_back(make_int2((int)r, (int)b));
+  }
+}
+
+// Whether the runs with capsules hold the node velocities of a previous step
+// (needed by Adams-Bashforth advection).
+bool batch_prev_u(const ibm_batch *b) {
+  for (const ibm_lattice *lat : b->runs)
+    if (lat->has_mem) return lat->have_prev_u;
+  return false;
+}
+
+void batch_invalidate_graph(ibm_batch *b) {
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  b->gexec = nullptr;
+  b->graph_valid = false;
+}
+
+// Check that the runs can step together and bring the device tables up to
+// date with their current state (a run's membrane or chunk options may have
+// changed since the last batch step).
+int batch_sync_tables(ibm_batch *b) {
+  const ibm_lattice *r0 = b->runs[0];
+  for (const ibm_lattice *lat : b->runs) {
+    if (lat->steps != r0->steps)
+      return fail(IBM_ERR_BAD_STATE, "batched runs must have made the same number of steps");
+    if (lat->storage != r0->storage || lat->eq_linear != r0->eq_linear || lat->ab2 != r0->ab2)
+      return fail(IBM_ERR_BAD_STATE,
+                  "batched runs need the same storage, equilibrium and advection options");
+    if (lat->stream != r0->stream)
+      return fail(IBM_ERR_BAD_STATE, "batched runs must share one stream");
+    if (lat->has_tan) return fail(IBM_ERR_BAD_STATE, "batched runs cannot carry a tangent");
+    if (lat->has_mem && lat->have_prev_u != batch_prev_u(b))
+      return fail(IBM_ERR_BAD_STATE, "batched runs differ in their stored node velocities");
+  }
+  std::vector<int2> li, ni;
+  batch_items(b->runs, li, ni);
+  if (li.size() > b->cap_lat || ni.size() > b->cap_node)
+    return fail(IBM_ERR_BAD_STATE, "the runs' membranes grew since the batch was created");
+  const size_t n = b->runs.size();
+  const BatchLayout bl = batch_layout(n, b->cap_lat, b->cap_node);
+  std::vector<char> img(bl.total, 0);
+  for (size_t r = 0; r < n; ++r) {
+    std::memcpy(img.data() + bl.lat + r * sizeof(ibm::LatDev), &b->runs[r]->L, sizeof(ibm::LatDev));
+    std::memcpy(img.data() + bl.mem + r * sizeof(ibm::MemDev), &b->runs[r]->M, sizeof(ibm::MemDev));
+  }
+  std::memcpy(img.data() + bl.lat_items, li.data(), li.size() * sizeof(int2));
+  std::memcpy(img.data() + bl.node_items, ni.data(), ni.size() * sizeof(int2));
+  ibm::BatchDev B{};
+  B.lat = reinterpret_cast<const ibm::LatDev *>(b->dev + bl.lat);
+  B.mem = reinterpret_cast<const ibm::MemDev *>(b->dev + bl.mem);
+  B.lat_items = reinterpret_cast<const int2 *>(b->dev + bl.lat_items);
+  B.node_items = reinterpret_cast<const int2 *>(b->dev + bl.node_items);
+  B.n_lat_items = (int)li.size();
+  B.n_node_items = (int)ni.size();
+  const bool same = img == b->image && std::memcmp(&B, &b->B, sizeof(B)) == 0;
+  if (!same) {
+    IBM_HIP(hipMemcpyAsync(b->dev, img.data(), img.size(), hipMemcpyHostToDevice, b->stream));
+    IBM_HIP(hipStreamSynchronize(b->stream));  // img must outlive the copy
+    b->image.swap(img);
+    b->B = B;
+    batch_invalidate_graph(b);
+  }
+  return IBM_OK;
+}
+
+// Enqueue one timestep of every run (Sec. II.C, sub-steps 1-5), one launch
+// per kernel.
+void enqueue_batch_step(ibm_batch *b, hipStream_t s, int advect) {
+  const ibm_lattice *r0 = b->runs[0];
+  const int src = (int)(r0->steps & 1), par = src;
+  ibm::launch_batch_spread(b->B, par, s);
+  ibm::launch_batch_collide_stream(b->B, r0->storage, src, par, r0->eq_linear != 0, s);
+  ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, s);
+  for (ibm_lattice *lat : b->runs) {
+    lat->steps += 1;
+    lat->since_recenter += 1;
+  }
+}
+
+int batch_capture_graph(ibm_batch *b, int advect) {
+  batch_invalidate_graph(b);
+  if (!b->cap_stream) IBM_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
+  std::vector<int64_t> steps, since;
+  for (ibm_lattice *lat : b->runs) {
+    steps.push_back(lat->steps);
+    since.push_back(lat->since_recenter);
+  }
+  hipGraph_t graph = nullptr;
+  IBM_HIP(hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal));
+  for (int k = 0; k < GRAPH_STEPS; ++k) enqueue_batch_step(b, b->cap_stream, advect);
+  hipError_t e = hipStreamEndCapture(b->cap_stream, &graph);
+  for (size_t r = 0; r < b->runs.size(); ++r) {
+    b->runs[r]->steps = steps[r];
+    b->runs[r]->since_recenter = since[r];
+  }
+  if (e != hipSuccess) return fail(IBM_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+  e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e != hipSuccess) {
+    b->gexec = nullptr;
+    return fail(IBM_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+  }
+  b->graph_valid = true;
+  b->graph_advect = advect;
+  b->graph_linear = b->runs[0]->eq_linear;
+  return IBM_OK;
 }
 
 }  // namespace
@@ -399,6 +616,7 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
                         const double *ks, const double *ka, int m, void *dev_mem, size_t bytes) {
   if (!lat) return fail(IBM_ERR_INVALID_ARG, "lat is NULL");
   if (lat->has_mem) return fail(IBM_ERR_BAD_STATE, "a membrane is already attached");
+  if (lat->has_tan) return fail(IBM_ERR_BAD_STATE, "detach the tangent before adding a membrane");
   size_t need = 0;
   int rc = ibm_membrane_bytes(n_caps, nodes_per_cap, faces_per_cap, &need);
   if (rc) return rc;
@@ -471,7 +689,6 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
   M.x = reinterpret_cast<float4 *>(b + ml.x);
   M.u = reinterpret_cast<float4 *>(b + ml.u);
   M.F = reinterpret_cast<float4 *>(b + ml.F);
-  M.face_grad = reinterpret_cast<float4 *>(b + ml.face_grad);
   M.ext_id = reinterpret_cast<int *>(b + ml.ext_id);
 
   M.node_cap = reinterpret_cast<int *>(b + ml.node_cap);
@@ -486,6 +703,12 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
   M.cap_node_off = reinterpret_cast<int *>(b + ml.cap_node_off);
   M.cap_face_off = reinterpret_cast<int *>(b + ml.cap_face_off);
   M.obs = reinterpret_cast<double *>(b + ml.obs);
+  M.chunk = reinterpret_cast<int2 *>(b + ml.chunk);
+  M.chunk_face_off = reinterpret_cast<int *>(b + ml.chunk_face_off);
+  M.chunk_face = reinterpret_cast<int *>(b + ml.chunk_face);
+  M.n_chunks = 0;
+  lat->csr_off = csr_off;
+  lat->csr_ent = csr_ent;
   lat->node_off = node_off;
   lat->face_off = face_off;
   lat->int_of_ext = int_of_ext;
@@ -512,12 +735,16 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
   IBM_HIP(hipMemcpyAsync(M.cap_face_off, cap_face_off.data(), (n_caps + 1) * sizeof(int), hipMemcpyHostToDevice, s));
   ibm::launch_fill_u32(M.u, 4LL * nn, 0u, s);
   ibm::launch_fill_u32(M.F, 4LL * nn, 0u, s);
-  ibm::launch_fill_u32(M.face_grad, 12LL * nf, 0u, s);
   ibm::launch_reference_geometry(M, lat->L.ctrl, s);
   IBM_HIP(hipGetLastError());
   IBM_HIP(hipStreamSynchronize(s));  // host vectors must outlive the copies
   lat->has_mem = true;
   rc = check_device(lat);
+  if (rc) {
+    lat->has_mem = false;
+    return rc;
+  }
+  rc = upload_chunks(lat);
   if (rc) {
     lat->has_mem = false;
     return rc;
@@ -534,6 +761,8 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
 int ibm_step(ibm_lattice *lat, int64_t n) {
   if (!lat) return fail(IBM_ERR_INVALID_ARG, "lat is NULL");
   if (n < 0) return fail(IBM_ERR_INVALID_ARG, "negative step count");
+  if (lat->has_tan && lat->ab2)
+    return fail(IBM_ERR_BAD_STATE, "the tangent model follows Euler advection only");
   while (n > 0) {
     if (lat->has_mem && lat->since_recenter >= lat->recenter_every) {
       ibm::launch_recenter(lat->M, lat->stream);
@@ -651,6 +880,16 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
       if (value < 0 || value > 31) return fail(IBM_ERR_INVALID_ARG, "variant is 0..31");
       lat->lbm_variant = value;
       break;
+    case IBM_OPT_CHUNK_NODES: {
+      if (value != 0 && (value < ibm::CHUNK_MIN || value > ibm::CHUNK_MAX || (value & (value - 1))))
+        return fail(IBM_ERR_INVALID_ARG, "chunk size is 0 or a power of two in 16..256");
+      lat->chunk_nodes = value;
+      if (lat->has_mem) {
+        const int rc = upload_chunks(lat);
+        if (rc) return rc;
+      }
+      break;
+    }
     default:
       return fail(IBM_ERR_INVALID_ARG, "unknown option %d", option);
   }
@@ -660,6 +899,7 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
 
 int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase) {
   if (!lat || !ms_per_phase) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  if (lat->has_tan) return fail(IBM_ERR_BAD_STATE, "detach the tangent before profiling");
   if (n < 1 || n > 4096) return fail(IBM_ERR_INVALID_ARG, "profile 1..4096 steps");
   const int ne = lat->has_mem ? 5 : 2;
   std::vector<hipEvent_t> ev((size_t)n * ne);
@@ -670,8 +910,7 @@ int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase) {
     const int src = (int)(lat->steps & 1), par = src;
     IBM_HIP(hipEventRecord(e[0], s));
     if (lat->has_mem) {
-      ibm::launch_face_gradients(lat->M, lat->L.ctrl, s);
-      IBM_HIP(hipEventRecord(e[1], s));
+      IBM_HIP(hipEventRecord(e[1], s));  // the forces are formed by the spreading kernel
       ibm::launch_spread(lat->L, lat->M, par, s);
       IBM_HIP(hipEventRecord(e[2], s));
       ibm::launch_collide_stream(lat->L, lat->storage, src, par, true, lat->eq_linear != 0,
@@ -716,6 +955,276 @@ int ibm_destroy(ibm_lattice *lat) {
   invalidate_graph(lat);
   if (lat->cap_stream) (void)hipStreamDestroy(lat->cap_stream);
   delete lat;
+  return ok();
+}
+
+// ---- tangent (forward sensitivity) --------------------------------------------------
+namespace {
+struct TangentLayout {
+  size_t df[2], dg[2], dx, du, dF, dmod, obs, total;
+};
+
+TangentLayout tangent_layout(const ibm_lattice *lat) {
+  TangentLayout l{};
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t at = off;
+    off += round_up(b, ALIGN);
+    return at;
+  };
+  const size_t S = (size_t)lat->lay.S;
+  const size_t nn = lat->has_mem ? (size_t)lat->M.nn : 0, nc = lat->has_mem ? (size_t)lat->M.n_caps : 0;
+  for (int k = 0; k < 2; ++k) l.df[k] = take(ibm::Q * S * sizeof(float));
+  for (int k = 0; k < 2; ++k) l.dg[k] = take(3 * S * sizeof(float));
+  l.dx = take(nn * 16);
+  l.du = take(nn * 16);
+  l.dF = take(nn * 16);
+  l.dmod = take(nc * 8);
+  l.obs = take(2 * nc * IBM_OBS_N * sizeof(double));
+  l.total = off;
+  return l;
+}
+}  // namespace
+
+int ibm_tangent_bytes(ibm_lattice *lat, size_t *bytes) {
+  if (!lat || !bytes) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  *bytes = tangent_layout(lat).total;
+  return ok();
+}
+
+int ibm_tangent_attach(ibm_lattice *lat, const double *dks, const double *dka, double duw,
+                       int init_profile, void *dev_mem, size_t bytes) {
+  if (!lat) return fail(IBM_ERR_INVALID_ARG, "lat is NULL");
+  if (lat->storage != IBM_STORAGE_FP32)
+    return fail(IBM_ERR_BAD_STATE, "the tangent model needs FP32 population storage");
+  if (lat->has_mem && (!dks || !dka)) return fail(IBM_ERR_INVALID_ARG, "dks and dka are needed");
+  if (!std::isfinite(duw)) return fail(IBM_ERR_INVALID_ARG, "duw must be finite");
+  const TangentLayout tl = tangent_layout(lat);
+  if (!dev_mem || ((uintptr_t)dev_mem) % ALIGN)
+    return fail(IBM_ERR_INVALID_ARG, "dev_mem NULL or not 256-byte aligned");
+  if (bytes < tl.total) return fail(IBM_ERR_INVALID_ARG, "dev_mem has %zu bytes, %zu needed", bytes, tl.total);
+  char *b = static_cast<char *>(dev_mem);
+  ibm::TanDev T{};
+  for (int k = 0; k < 2; ++k) {
+    T.df[k] = reinterpret_cast<float *>(b + tl.df[k]);
+    T.dg[k] = reinterpret_cast<float *>(b + tl.dg[k]);
+  }
+  T.dx = reinterpret_cast<float4 *>(b + tl.dx);
+  T.du = reinterpret_cast<float4 *>(b + tl.du);
+  T.dF = reinterpret_cast<float4 *>(b + tl.dF);
+  T.dmod = reinterpret_cast<float2 *>(b + tl.dmod);
+  T.obs = reinterpret_cast<double *>(b + tl.obs);
+  T.duw = (float)duw;
+  hipStream_t s = lat->stream;
+  std::vector<float2> dm;
+  if (lat->has_mem) {
+    for (int c = 0; c < lat->M.n_caps; ++c) {
+      if (!std::isfinite(dks[c]) || !std::isfinite(dka[c]))
+        return fail(IBM_ERR_INVALID_ARG, "capsule %d: non-finite modulus rate", c);
+      dm.push_back(make_float2((float)dks[c], (float)dka[c]));
+    }
+    IBM_HIP(hipMemcpyAsync(T.dmod, dm.data(), dm.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+    for (float4 *p : {T.dx, T.du, T.dF}) ibm::launch_fill_u32(p, 4LL * lat->M.nn, 0u, s);
+  }
+  for (int k = 0; k < 2; ++k) {
+    ibm::launch_fill_u32(T.dg[k], 3 * lat->lay.S, 0u, s);
+    ibm::launch_fill_u32(T.df[k], (long long)ibm::Q * lat->lay.S, 0u, s);
+  }
+  ibm::launch_tangent_init(lat->L, T, (int)(lat->steps & 1), init_profile ? 1 : 0,
+                           lat->eq_linear, s);
+  IBM_HIP(hipGetLastError());
+  IBM_HIP(hipStreamSynchronize(s));  // dm must outlive the copy
+  lat->T = T;
+  lat->has_tan = true;
+  invalidate_graph(lat);
+  return ok();
+}
+
+int ibm_tangent_detach(ibm_lattice *lat) {
+  if (!lat) return fail(IBM_ERR_INVALID_ARG, "lat is NULL");
+  IBM_HIP(hipStreamSynchronize(lat->stream));
+  lat->has_tan = false;
+  lat->T = ibm::TanDev{};
+  invalidate_graph(lat);
+  return ok();
+}
+
+int ibm_tangent_get_pops(ibm_lattice *lat, double *dst_dev) {
+  if (!lat || !dst_dev) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  if (!lat->has_tan) return fail(IBM_ERR_BAD_STATE, "no tangent attached");
+  ibm::launch_get_tangent_pops(lat->L, lat->T, (int)(lat->steps & 1), dst_dev, lat->stream);
+  IBM_HIP(hipGetLastError());
+  int rc = check_device(lat);
+  return rc ? rc : ok();
+}
+
+int ibm_tangent_get_mesh(ibm_lattice *lat, double *dxyz_dev, double *du_dev) {
+  if (!lat) return fail(IBM_ERR_INVALID_ARG, "lat is NULL");
+  if (!lat->has_tan || !lat->has_mem) return fail(IBM_ERR_BAD_STATE, "no tangent membrane state");
+  ibm::MemDev M2 = lat->M;  // the mesh readout, pointed at the tangent arrays
+  M2.F = lat->T.dx;
+  M2.u = lat->T.du;
+  ibm::launch_get_mesh(M2, nullptr, dxyz_dev, du_dev, lat->stream);
+  IBM_HIP(hipGetLastError());
+  int rc = check_device(lat);
+  return rc ? rc : ok();
+}
+
+int ibm_tangent_observables(ibm_lattice *lat, double h, double *out_host) {
+  if (!lat || !out_host) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  if (!lat->has_tan || !lat->has_mem) return fail(IBM_ERR_BAD_STATE, "no tangent membrane state");
+  if (!(h > 0.0) || !std::isfinite(h)) return fail(IBM_ERR_INVALID_ARG, "h must be > 0");
+  const size_t k = (size_t)lat->M.n_caps * IBM_OBS_N;
+  ibm::launch_observables_shifted(lat->M, lat->L.ctrl, lat->T.dx, h, lat->T.obs, lat->stream);
+  ibm::launch_observables_shifted(lat->M, lat->L.ctrl, lat->T.dx, -h, lat->T.obs + k, lat->stream);
+  IBM_HIP(hipGetLastError());
+  std::vector<double> both(2 * k);
+  IBM_HIP(hipMemcpyAsync(both.data(), lat->T.obs, 2 * k * sizeof(double), hipMemcpyDeviceToHost,
+                         lat->stream));
+  int rc = check_device(lat);
+  if (rc) return rc;
+  for (size_t q = 0; q < k; ++q) out_host[q] = (both[q] - both[k + q]) / (2.0 * h);
+  return ok();
+}
+
+int ibm_batch_bytes(int n_runs, ibm_lattice *const *runs, size_t *bytes) {
+  if (n_runs < 1 || !runs || !bytes) return fail(IBM_ERR_INVALID_ARG, "need n_runs >= 1 and runs");
+  for (int r = 0; r < n_runs; ++r)
+    if (!runs[r]) return fail(IBM_ERR_INVALID_ARG, "run %d is NULL", r);
+  std::vector<ibm_lattice *> v(runs, runs + n_runs);
+  std::vector<int2> li, ni;
+  batch_items(v, li, ni);
+  *bytes = batch_layout(v.size(), li.size(), ni.size()).total;
+  return ok();
+}
+
+int ibm_batch_create(int n_runs, ibm_lattice *const *runs, void *dev_mem, size_t bytes,
+                     ibm_batch **out) {
+  if (!out) return fail(IBM_ERR_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  size_t need = 0;
+  int rc = ibm_batch_bytes(n_runs, runs, &need);
+  if (rc) return rc;
+  if (!dev_mem || ((uintptr_t)dev_mem) % ALIGN)
+    return fail(IBM_ERR_INVALID_ARG, "dev_mem NULL or not 256-byte aligned");
+  if (bytes < need) return fail(IBM_ERR_INVALID_ARG, "dev_mem has %zu bytes, %zu needed", bytes, need);
+  std::vector<ibm_lattice *> v(runs, runs + n_runs);
+  for (int r = 0; r < n_runs; ++r)
+    for (int q = 0; q < r; ++q)
+      if (v[q] == v[r]) return fail(IBM_ERR_INVALID_ARG, "run %d appears twice", r);
+  std::vector<int2> li, ni;
+  batch_items(v, li, ni);
+  ibm_batch *b = new ibm_batch();
+  b->runs = v;
+  b->stream = v[0]->stream;
+  b->dev = static_cast<char *>(dev_mem);
+  b->bytes = bytes;
+  b->cap_lat = li.size();
+  b->cap_node = ni.size();
+  rc = batch_sync_tables(b);
+  if (rc) {
+    delete b;
+    return rc;
+  }
+  *out = b;
+  return ok();
+}
+
+int ibm_batch_step(ibm_batch *b, int64_t n) {
+  if (!b) return fail(IBM_ERR_INVALID_ARG, "batch is NULL");
+  if (n < 0) return fail(IBM_ERR_INVALID_ARG, "negative step count");
+  int rc = batch_sync_tables(b);
+  if (rc) return rc;
+  ibm_lattice *r0 = b->runs[0];
+  while (n > 0) {
+    bool room = true;
+    for (ibm_lattice *lat : b->runs) {
+      if (lat->has_mem && lat->since_recenter >= lat->recenter_every) {
+        ibm::launch_recenter(lat->M, b->stream);
+        lat->since_recenter = 0;
+      }
+      if (lat->has_mem && lat->since_recenter + GRAPH_STEPS > lat->recenter_every) room = false;
+    }
+    const bool prev = batch_prev_u(b);
+    const int advect = (r0->ab2 && prev) ? 1 : 0;
+    const bool graph_ok = (r0->steps & 1) == 0 && n >= GRAPH_STEPS && room && (!r0->ab2 || prev);
+    if (graph_ok) {
+      if (!b->graph_valid || b->graph_advect != advect || b->graph_linear != r0->eq_linear) {
+        rc = batch_capture_graph(b, advect);
+        if (rc) return rc;
+      }
+      IBM_HIP(hipGraphLaunch(b->gexec, b->stream));
+      for (ibm_lattice *lat : b->runs) {
+        lat->steps += GRAPH_STEPS;
+        lat->since_recenter += GRAPH_STEPS;
+      }
+      n -= GRAPH_STEPS;
+    } else {
+      enqueue_batch_step(b, b->stream, advect);
+      if (r0->ab2)
+        for (ibm_lattice *lat : b->runs)
+          if (lat->has_mem) lat->have_prev_u = true;
+      n -= 1;
+    }
+  }
+  IBM_HIP(hipGetLastError());
+  return ok();
+}
+
+int ibm_batch_profile_step(ibm_batch *b, int64_t n, double *ms_per_phase) {
+  if (!b || !ms_per_phase) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  if (n < 1 || n > 4096) return fail(IBM_ERR_INVALID_ARG, "profile 1..4096 steps");
+  int rc = batch_sync_tables(b);
+  if (rc) return rc;
+  ibm_lattice *r0 = b->runs[0];
+  std::vector<hipEvent_t> ev((size_t)n * 4);
+  for (auto &e : ev) IBM_HIP(hipEventCreate(&e));
+  hipStream_t s = b->stream;
+  for (int64_t k = 0; k < n; ++k) {
+    for (ibm_lattice *lat : b->runs)
+      if (lat->has_mem && lat->since_recenter >= lat->recenter_every) {
+        ibm::launch_recenter(lat->M, s);
+        lat->since_recenter = 0;
+      }
+    hipEvent_t *e = &ev[(size_t)k * 4];
+    const int src = (int)(r0->steps & 1), par = src;
+    const int advect = (r0->ab2 && batch_prev_u(b)) ? 1 : 0;
+    IBM_HIP(hipEventRecord(e[0], s));
+    ibm::launch_batch_spread(b->B, par, s);
+    IBM_HIP(hipEventRecord(e[1], s));
+    ibm::launch_batch_collide_stream(b->B, r0->storage, src, par, r0->eq_linear != 0, s);
+    IBM_HIP(hipEventRecord(e[2], s));
+    ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, s);
+    IBM_HIP(hipEventRecord(e[3], s));
+    for (ibm_lattice *lat : b->runs) {
+      lat->steps += 1;
+      lat->since_recenter += 1;
+      if (lat->ab2 && lat->has_mem) lat->have_prev_u = true;
+    }
+  }
+  IBM_HIP(hipGetLastError());
+  IBM_HIP(hipStreamSynchronize(s));
+  double acc[IBM_N_PHASES] = {0.0, 0.0, 0.0, 0.0};
+  const int phase_of[3] = {IBM_PHASE_SPREAD, IBM_PHASE_LBM, IBM_PHASE_INTERP};
+  for (int64_t k = 0; k < n; ++k) {
+    hipEvent_t *e = &ev[(size_t)k * 4];
+    for (int p = 0; p < 3; ++p) {
+      float ms = 0.0f;
+      IBM_HIP(hipEventElapsedTime(&ms, e[p], e[p + 1]));
+      acc[phase_of[p]] += ms;
+    }
+  }
+  for (auto &e : ev) (void)hipEventDestroy(e);
+  for (int p = 0; p < IBM_N_PHASES; ++p) ms_per_phase[p] = acc[p] / (double)n;
+  return ok();
+}
+
+int ibm_batch_destroy(ibm_batch *b) {
+  if (!b) return ok();
+  (void)hipStreamSynchronize(b->stream);
+  batch_invalidate_graph(b);
+  if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+  delete b;
   return ok();
 }
 

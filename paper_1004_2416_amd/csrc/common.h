@@ -52,8 +52,8 @@ struct alignas(256) Ctrl {
 struct LatDev {
   int nx, ny, nz;
   int tnx, tny, tnz;      // tile grid
-  long long S;            // stride between population arrays (elements)
-  void *f[2];             // population buffers (float or __half), [19][S]
+  long long S;            // stride between force-density components (elements)
+  void *f[2];             // population buffers (float or __half), [ny nz][19][nx]
   float *g[2];            // force density [3][S] of even and odd steps
   int *stamp[2];          // per-tile step stamps of the two fields
   Ctrl *ctrl;
@@ -69,7 +69,6 @@ struct MemDev {
   float4 *x;        // node coordinates relative to the capsule origin [nn]
   float4 *u;        // node velocities of the last step [nn]
   float4 *F;        // nodal forces of the last step [nn]
-  float4 *face_grad;  // d(A0 w_S)/dx of each face's corners a, b, c [3 nf]
   int *ext_id;      // caller's index of each (spatially sorted) node [nn]
   int *node_cap;    // capsule of each node [nn]
   int *csr_off;     // node -> incident (face, corner) list offsets [nn + 1]
@@ -83,7 +82,42 @@ struct MemDev {
   int *cap_node_off;  // [n_caps + 1]
   int *cap_face_off;  // [n_caps + 1]
   double *obs;      // observables [n_caps][IBM_OBS_N]
+  int2 *chunk;      // node ranges [begin, end) of the chunks, each inside one capsule
+  int *chunk_face_off;  // faces with a corner in chunk k: chunk_face[off[k] .. off[k + 1])
+  int *chunk_face;
+  int n_chunks;     // 0: spreading and interpolation work per node, without chunks
 };
+
+// Tangent-linear (forward sensitivity) state: the derivative of every
+// evolving quantity along one parameter direction, advanced by the tangent
+// kernels beside the timestep.
+struct TanDev {
+  float *df[2];   // tangent populations [19][S], same parity as the populations
+  float *dg[2];   // tangent force density [3][S], same parity as the force field
+  float4 *dx;     // tangent node positions [nn]
+  float4 *du;     // tangent node velocities of the last step [nn]
+  float4 *dF;     // tangent nodal forces of the last step [nn]
+  float2 *dmod;   // (d k_s, d k_alpha) per capsule
+  double *obs;    // [2][n_caps][16]: observables at x + h dx and at x - h dx
+  float duw;      // d u_w (wall speed)
+};
+
+// Independent runs advanced together: every kernel of the step is launched once
+// for all runs, each block working for one run.  Work items map a block to
+// (run, block index within that run's own launch).
+struct BatchDev {
+  const LatDev *lat;       // [n_runs]
+  const MemDev *mem;       // [n_runs]
+  const int2 *lat_items;   // lattice update: 256 nodes per block, one per thread
+  const int2 *node_items;  // spreading / interpolation: 256 / group_size lanes
+  int n_lat_items, n_node_items;
+};
+
+// Chunks: runs of at most CHUNK_MAX consecutive (spatially sorted) nodes of one
+// capsule.  Their stencils cover a compact box of lattice nodes that the
+// chunked kernels keep in LDS when it has at most BOX_CELLS nodes.
+constexpr int CHUNK_MIN = 16, CHUNK_MAX = 256;
+constexpr int BOX_CELLS = 4096;
 
 // ---- discrete delta functions, Sec. II.C Eqs. (2point), (3point), (4point) ----
 // Evaluated for |r| inside the stencil; square-root arguments are clamped at 0
@@ -104,6 +138,28 @@ __device__ __forceinline__ float phi(float r) {
   }
 }
 
+// Derivatives d phi / dr of the three deltas (zero outside the support; the
+// 2-point delta takes -sign(r), 0 at its kink r = 0).
+template <int M>
+__device__ __forceinline__ float dphi(float r) {
+  const float a = fabsf(r);
+  const float sg = r > 0.0f ? 1.0f : (r < 0.0f ? -1.0f : 0.0f);
+  if constexpr (M == 2) {
+    return a < 1.0f ? -sg : 0.0f;
+  } else if constexpr (M == 3) {
+    if (a <= 0.5f) return -r / sqrtf(fmaxf(1.0f - 3.0f * a * a, 1e-30f));
+    if (a < 1.5f)
+      return sg * (-0.5f - (1.0f - a) * 0.5f / sqrtf(fmaxf(-2.0f + 6.0f * a - 3.0f * a * a, 1e-30f)));
+    return 0.0f;
+  } else {
+    if (a <= 1.0f)
+      return sg * 0.25f * (-1.0f + (1.0f - 2.0f * a) / sqrtf(fmaxf(1.0f + 4.0f * a - 4.0f * a * a, 1e-30f)));
+    if (a < 2.0f)
+      return sg * 0.25f * (-1.0f - (3.0f - 2.0f * a) / sqrtf(fmaxf(-7.0f + 12.0f * a - 4.0f * a * a, 1e-30f)));
+    return 0.0f;
+  }
+}
+
 // First lattice coordinate of the M-point stencil around position p: the M
 // integers within M/2 of p.
 template <int M>
@@ -111,6 +167,14 @@ __device__ __forceinline__ int stencil_lo(float p) {
   if constexpr (M == 3) return (int)floorf(p + 0.5f) - 1;
   else if constexpr (M == 4) return (int)floorf(p) - 1;
   else return (int)floorf(p);
+}
+
+// Populations are stored row-interleaved, [row][i][x] with row = z ny + y: the
+// 19 values of one x row lie in 19 consecutive runs of nx values, so a row's
+// update reads and writes a few contiguous kilobytes instead of 19 arrays
+// that are megabytes apart.
+__device__ __forceinline__ long long pidx(const LatDev &L, int i, long long row, int x) {
+  return (row * Q + i) * (long long)L.nx + x;
 }
 
 __device__ __forceinline__ int wrap_mod(int a, int n) {

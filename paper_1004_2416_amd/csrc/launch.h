@@ -14,16 +14,33 @@ void launch_get_field(const LatDev &L, int fp16, int src, int gpar, int what, do
                       hipStream_t s);
 void launch_set_pops(const LatDev &L, int fp16, int dst, const double *in, hipStream_t s);
 void launch_fill_u32(void *p, long long n, uint32_t v, hipStream_t s);
+void launch_tangent_collide_stream(const LatDev &L, const TanDev &T, int src, int par, bool linear,
+                                   hipStream_t s);
+void launch_tangent_init(const LatDev &L, const TanDev &T, int dst, int profile, int linear,
+                         hipStream_t s);
+void launch_get_tangent_pops(const LatDev &L, const TanDev &T, int src, double *out,
+                             hipStream_t s);
+void launch_batch_collide_stream(const BatchDev &B, int fp16, int src, int par, bool linear,
+                                 hipStream_t s);
 
 // membrane_kernels.hip
 void launch_reference_geometry(const MemDev &M, Ctrl *ctrl, hipStream_t s);
-void launch_face_gradients(const MemDev &M, Ctrl *ctrl, hipStream_t s);
 void launch_spread(const LatDev &L, const MemDev &M, int par, hipStream_t s);
 // advect: 0 Euler, 1 Adams-Bashforth with the stored velocity of the previous step
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
                           int advect, hipStream_t s);
 void launch_recenter(const MemDev &M, hipStream_t s);
+void launch_batch_spread(const BatchDev &B, int par, hipStream_t s);
+void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect,
+                         hipStream_t s);
 void launch_observables(const MemDev &M, Ctrl *ctrl, hipStream_t s);
+// observables of the mesh x + h dx into obs [n_caps][16]
+void launch_observables_shifted(const MemDev &M, Ctrl *ctrl, const float4 *dx, double h,
+                                double *obs, hipStream_t s);
+void launch_tangent_spread(const LatDev &L, const MemDev &M, const TanDev &T, int par,
+                           hipStream_t s);
+void launch_tangent_interp(const LatDev &L, const MemDev &M, const TanDev &T, int fsrc, int par,
+                           hipStream_t s);
 void launch_get_mesh(const MemDev &M, double *xyz, double *F, double *u, hipStream_t s);
 
 }  // namespace ibm

@@ -141,15 +141,13 @@ __device__ __forceinline__ void collide(float (&d)[Q], float gx, float gy, float
 // -2 w_i rho_w (c_i . u_wall) / c_s^2, rho_w = 1 (bounce-back for moving
 // walls).  VEC = 2 needs an even nx (vector accesses stay aligned).
 template <typename T, bool LINEAR, bool FORCE, int VEC, bool NT>
-__global__ __launch_bounds__(256) void k_collide_stream(LatDev L, int src, int par) {
-  const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
-  const int y = blockIdx.y * blockDim.y + threadIdx.y;
-  const int z = blockIdx.z;
-  if (x0 >= L.nx || y >= L.ny) return;
+__device__ __forceinline__ void collide_stream_nodes(const LatDev &L, int src, int par, int x0,
+                                                     int y, int z) {
   const long long S = L.S;
   const long long nxl = L.nx;
   const long long plane = nxl * L.ny;
   const long long n0 = (long long)z * plane + (long long)y * nxl + x0;
+  const long long row0 = (long long)z * L.ny + y;
   const T *__restrict__ fs = static_cast<const T *>(L.f[src]);
   T *__restrict__ fd = static_cast<T *>(L.f[src ^ 1]);
 
@@ -157,8 +155,9 @@ __global__ __launch_bounds__(256) void k_collide_stream(LatDev L, int src, int p
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float inv = 1.0f / L.h_scale[i];
-    if constexpr (VEC == 2) Pop<T>::template ld2<NT>(fs, i * S + n0, inv, d[0][i], d[1][i]);
-    else d[0][i] = Pop<T>::template ld<NT>(fs, i * S + n0, inv);
+    const long long at = pidx(L, i, row0, x0);
+    if constexpr (VEC == 2) Pop<T>::template ld2<NT>(fs, at, inv, d[0][i], d[1][i]);
+    else d[0][i] = Pop<T>::template ld<NT>(fs, at, inv);
   }
 
   float g[VEC][3];
@@ -199,13 +198,13 @@ __global__ __launch_bounds__(256) void k_collide_stream(LatDev L, int src, int p
     if (cz(i) != 0 && (zt < 0 || zt >= L.nz)) {
       const float uwall = (zt < 0) ? -L.uw : L.uw;
       const float kick = 6.0f * (float)wgt(i) * (float)cx(i) * uwall;
-      const long long at = opp(i) * S + n0;
+      const long long at = pidx(L, opp(i), row0, x0);
       if constexpr (VEC == 2)
         Pop<T>::template st2<NT>(fd, at, d[0][i] - kick, d[1][i] - kick, L.h_scale[opp(i)]);
       else Pop<T>::template st<NT>(fd, at, d[0][i] - kick, L.h_scale[opp(i)]);
     } else {
       const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
-      const long long row = i * S + (long long)zt * plane + (long long)yt * nxl;
+      const long long row = pidx(L, i, (long long)zt * L.ny + yt, 0);
       if (cx(i) == 0) {
         if constexpr (VEC == 2) Pop<T>::template st2<NT>(fd, row + x0, d[0][i], d[1][i], L.h_scale[i]);
         else Pop<T>::template st<NT>(fd, row + x0, d[0][i], L.h_scale[i]);
@@ -219,6 +218,15 @@ __global__ __launch_bounds__(256) void k_collide_stream(LatDev L, int src, int p
       }
     }
   }
+}
+
+template <typename T, bool LINEAR, bool FORCE, int VEC, bool NT>
+__global__ __launch_bounds__(256) void k_collide_stream(LatDev L, int src, int par) {
+  const int x0 = (blockIdx.x * blockDim.x + threadIdx.x) * VEC;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x0 >= L.nx || y >= L.ny) return;
+  collide_stream_nodes<T, LINEAR, FORCE, VEC, NT>(L, src, par, x0, y, z);
 }
 
 // Row-vector form of the same update for rows that fit one wavefront: each
@@ -279,7 +287,8 @@ struct Pop4<__half> {
 };
 
 template <typename T, bool LINEAR, bool FORCE>
-__global__ __launch_bounds__(256) void k_collide_stream_rows(LatDev L, int src, int par, int tpr) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_collide_stream_rows(
+    LatDev L, int src, int par, int tpr) {
   constexpr int VEC = 4;
   const int lane = threadIdx.x & 63;
   const int t = lane % tpr;                    // thread within its row
@@ -292,6 +301,7 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(LatDev L, int src, 
   const long long nxl = L.nx;
   const long long plane = nxl * L.ny;
   const long long n0 = (long long)z * plane + (long long)y * nxl + x0;
+  const long long row0 = (long long)z * L.ny + y;
   const T *__restrict__ fs = static_cast<const T *>(L.f[src]);
   T *__restrict__ fd = static_cast<T *>(L.f[src ^ 1]);
   // lanes holding the left and right neighbours of this segment in the row
@@ -304,7 +314,7 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(LatDev L, int src, 
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       float v[4];
-      Pop4<T>::ld(fs, i * S + n0, 1.0f / L.h_scale[i], v);
+      Pop4<T>::ld(fs, pidx(L, i, row0, x0), 1.0f / L.h_scale[i], v);
 #pragma unroll
       for (int k = 0; k < VEC; ++k) d[k][i] = v[k];
     }
@@ -351,11 +361,11 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows(LatDev L, int src, 
     if (cz(i) != 0 && (zt < 0 || zt >= L.nz)) {
       const float uwall = (zt < 0) ? -L.uw : L.uw;
       const float kick = 6.0f * (float)wgt(i) * (float)cx(i) * uwall;
-      Pop4<T>::st(fd, opp(i) * S + n0, d[0][i] - kick, d[1][i] - kick, d[2][i] - kick,
+      Pop4<T>::st(fd, pidx(L, opp(i), row0, x0), d[0][i] - kick, d[1][i] - kick, d[2][i] - kick,
                   d[3][i] - kick, L.h_scale[opp(i)]);
     } else {
       const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
-      const long long at = i * S + (long long)zt * plane + (long long)yt * nxl + x0;
+      const long long at = pidx(L, i, (long long)zt * L.ny + yt, x0);
       if (cx(i) > 0) Pop4<T>::st(fd, at, in, d[0][i], d[1][i], d[2][i], L.h_scale[i]);
       else if (cx(i) < 0) Pop4<T>::st(fd, at, d[1][i], d[2][i], d[3][i], in, L.h_scale[i]);
       else Pop4<T>::st(fd, at, d[0][i], d[1][i], d[2][i], d[3][i], L.h_scale[i]);
@@ -442,14 +452,14 @@ __global__ __launch_bounds__(256) void k_init_equilibrium(LatDev L, int dst, dou
   const int y = blockIdx.y * blockDim.y + threadIdx.y;
   const int z = blockIdx.z;
   if (x >= L.nx || y >= L.ny) return;
-  const long long n = ((long long)z * L.ny + y) * L.nx + x;
+  const long long row = (long long)z * L.ny + y;
   const double ux = uw * (2.0 * z + 1.0 - L.nz) / L.nz;
   T *f = static_cast<T *>(L.f[dst]);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const double cu = cx(i) * ux;
     const double d = wgt(i) * (3.0 * cu + 4.5 * cu * cu - 1.5 * ux * ux);
-    st_dev<T>(f, i * L.S + n, (float)d, L.h_scale[i]);
+    st_dev<T>(f, pidx(L, i, row, x), (float)d, L.h_scale[i]);
   }
 }
 
@@ -487,7 +497,7 @@ __global__ __launch_bounds__(256) void k_get_field(LatDev L, int src, int gpar, 
   double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double d = ld_dev<T>(f, i * L.S + n, 1.0f / L.h_scale[i]);
+    const double d = ld_dev<T>(f, pidx(L, i, (long long)z * L.ny + y, x), 1.0f / L.h_scale[i]);
     if (what == 0) out[i * N + n] = wgt(i) + d;
     drho += d;
     jx += cx(i) * d;
@@ -520,13 +530,214 @@ __global__ __launch_bounds__(256) void k_set_pops(LatDev L, int dst, const doubl
   const long long n = ((long long)z * L.ny + y) * L.nx + x;
   T *f = static_cast<T *>(L.f[dst]);
 #pragma unroll
-  for (int i = 0; i < Q; ++i) st_dev<T>(f, i * L.S + n, (float)(in[i * N + n] - wgt(i)), L.h_scale[i]);
+  for (int i = 0; i < Q; ++i)
+    st_dev<T>(f, pidx(L, i, (long long)z * L.ny + y, x), (float)(in[i * N + n] - wgt(i)),
+              L.h_scale[i]);
 }
 
 void launch_set_pops(const LatDev &L, int fp16, int dst, const double *in, hipStream_t s) {
   dim3 b = lattice_block(L), g = lattice_grid(L, b);
   if (fp16) k_set_pops<__half><<<g, b, 0, s>>>(L, dst, in);
   else k_set_pops<float><<<g, b, 0, s>>>(L, dst, in);
+}
+
+// ---- tangent (forward sensitivity) of the lattice update -------------------------
+// Derivative of collide + stream + walls along the tangent populations t_i,
+// the tangent force density dg and the wall-speed rate duw, at the current
+// FP32 populations (the product rule through the moments, the equilibrium and
+// Guo's term; streaming is linear).  One node per thread.
+template <bool LINEAR>
+__global__ __launch_bounds__(256) void k_tangent_collide_stream(LatDev L, TanDev Tn, int src,
+                                                                int par) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= L.nx || y >= L.ny) return;
+  const long long S = L.S;
+  const long long n0 = ((long long)z * L.ny + y) * L.nx + x;
+  const float *fs = static_cast<const float *>(L.f[src]);
+  const float *ts = Tn.df[src];
+  float *td = Tn.df[src ^ 1];
+  float d[Q], t[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    d[i] = fs[pidx(L, i, (long long)z * L.ny + y, x)];
+    t[i] = ts[i * S + n0];
+  }
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f, hx = 0.0f, hy = 0.0f, hz = 0.0f;
+  const int step = L.ctrl->step;
+  const int tile = tile_of(L, x, y, z);
+  if (L.stamp[par][tile] == step) {
+    gx = L.g[par][n0];
+    gy = L.g[par][S + n0];
+    gz = L.g[par][2 * S + n0];
+    hx = Tn.dg[par][n0];
+    hy = Tn.dg[par][S + n0];
+    hz = Tn.dg[par][2 * S + n0];
+  }
+  if (L.stamp[par ^ 1][tile] == step - 1) {
+    Tn.dg[par ^ 1][n0] = 0.0f;
+    Tn.dg[par ^ 1][S + n0] = 0.0f;
+    Tn.dg[par ^ 1][2 * S + n0] = 0.0f;
+  }
+  float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f, trho = 0.0f, tjx = 0.0f, tjy = 0.0f, tjz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    drho += d[i];
+    trho += t[i];
+    if (cx(i)) {
+      jx += cx(i) * d[i];
+      tjx += cx(i) * t[i];
+    }
+    if (cy(i)) {
+      jy += cy(i) * d[i];
+      tjy += cy(i) * t[i];
+    }
+    if (cz(i)) {
+      jz += cz(i) * d[i];
+      tjz += cz(i) * t[i];
+    }
+  }
+  const float rho = 1.0f + drho, inv_rho = 1.0f / rho;
+  const float ux = (jx + 0.5f * gx) * inv_rho, uy = (jy + 0.5f * gy) * inv_rho,
+              uz = (jz + 0.5f * gz) * inv_rho;
+  const float vx = (tjx + 0.5f * hx - ux * trho) * inv_rho;
+  const float vy = (tjy + 0.5f * hy - uy * trho) * inv_rho;
+  const float vz = (tjz + 0.5f * hz - uz * trho) * inv_rho;
+  const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+  const float duu3 = 3.0f * (ux * vx + uy * vy + uz * vz);
+  const float gu = ux * gx + uy * gy + uz * gz;
+  const float dgu = vx * gx + vy * gy + vz * gz + ux * hx + uy * hy + uz * hz;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float w = (float)wgt(i);
+    const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+    const float dcu = cx(i) * vx + cy(i) * vy + cz(i) * vz;
+    float tdeq;
+    if (LINEAR) tdeq = w * (trho + trho * 3.0f * cu + rho * 3.0f * dcu);
+    else
+      tdeq = w * (trho + trho * (3.0f * cu + 4.5f * cu * cu - usq15) +
+                  rho * (3.0f * dcu + 9.0f * cu * dcu - duu3));
+    const float cg = cx(i) * gx + cy(i) * gy + cz(i) * gz;
+    const float dcg = cx(i) * hx + cy(i) * hy + cz(i) * hz;
+    t[i] = t[i] - (t[i] - tdeq) * L.inv_tau +
+           L.guo_pre * w * (3.0f * (dcg - dgu) + 9.0f * (dcu * cg + cu * dcg));
+  }
+  const long long plane = (long long)L.nx * L.ny;
+  const int ym = (y == 0) ? L.ny - 1 : y - 1, yp = (y == L.ny - 1) ? 0 : y + 1;
+  const int xm = (x == 0) ? L.nx - 1 : x - 1, xp = (x == L.nx - 1) ? 0 : x + 1;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int zt = z + cz(i);
+    if (cz(i) != 0 && (zt < 0 || zt >= L.nz)) {
+      const float duwall = (zt < 0) ? -Tn.duw : Tn.duw;
+      td[opp(i) * S + n0] = t[i] - 6.0f * (float)wgt(i) * (float)cx(i) * duwall;
+    } else {
+      const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
+      const int xt = cx(i) > 0 ? xp : (cx(i) < 0 ? xm : x);
+      td[i * S + (long long)zt * plane + (long long)yt * L.nx + xt] = t[i];
+    }
+  }
+}
+
+void launch_tangent_collide_stream(const LatDev &L, const TanDev &T, int src, int par, bool linear,
+                                   hipStream_t s) {
+  dim3 b = lattice_block(L), g = lattice_grid(L, b);
+  if (linear) k_tangent_collide_stream<true><<<g, b, 0, s>>>(L, T, src, par);
+  else k_tangent_collide_stream<false><<<g, b, 0, s>>>(L, T, src, par);
+}
+
+// Initial tangent populations: zero, or (profile) the derivative of the Couette
+// equilibrium f_i^eq(1, u_w (2z + 1 - nz) / nz) with respect to u_w times duw.
+__global__ __launch_bounds__(256) void k_tangent_init(LatDev L, TanDev Tn, int dst, int profile,
+                                                      int linear) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= L.nx || y >= L.ny) return;
+  const long long n = ((long long)z * L.ny + y) * L.nx + x;
+  const double shape = (double)(2 * z + 1 - L.nz) / (double)L.nz;
+  const double ux = (double)L.uw * shape, dux = (double)Tn.duw * shape;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    double v = 0.0;
+    if (profile) {
+      const double c = cx(i);
+      v = linear ? wgt(i) * 3.0 * c * dux : wgt(i) * (3.0 * c + 9.0 * c * c * ux - 3.0 * ux) * dux;
+    }
+    Tn.df[dst][i * L.S + n] = (float)v;
+  }
+}
+
+void launch_tangent_init(const LatDev &L, const TanDev &T, int dst, int profile, int linear,
+                         hipStream_t s) {
+  dim3 b = lattice_block(L), g = lattice_grid(L, b);
+  k_tangent_init<<<g, b, 0, s>>>(L, T, dst, profile, linear);
+}
+
+// Tangent populations out, [19][nz][ny][nx] FP64.
+__global__ __launch_bounds__(256) void k_get_tangent_pops(LatDev L, TanDev Tn, int src,
+                                                          double *out) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= L.nx || y >= L.ny) return;
+  const long long N = (long long)L.nx * L.ny * L.nz;
+  const long long n = ((long long)z * L.ny + y) * L.nx + x;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) out[i * N + n] = Tn.df[src][i * L.S + n];
+}
+
+void launch_get_tangent_pops(const LatDev &L, const TanDev &T, int src, double *out,
+                             hipStream_t s) {
+  dim3 b = lattice_block(L), g = lattice_grid(L, b);
+  k_get_tangent_pops<<<g, b, 0, s>>>(L, T, src, out);
+}
+
+// ---- batches of runs -------------------------------------------------------------
+// The lattice update of many independent runs in one launch: block b updates
+// 256 consecutive nodes (one per thread) of run lat_items[b].x.  Runs without
+// capsules never stamp a tile, so reading the force field only where stamped
+// is correct for them as well.
+template <typename T, bool LINEAR>
+__global__ __launch_bounds__(256) void k_batch_collide_stream(BatchDev B, int src, int par) {
+  if ((int)blockIdx.x >= B.n_lat_items) return;
+  const int2 it = B.lat_items[blockIdx.x];
+  // a private copy with the buffers of this step in slot 0, so that the update
+  // indexes the pointer pairs with constants (registers, not scratch)
+  LatDev L = B.lat[it.x];
+  if (src) {
+    void *t = L.f[0];
+    L.f[0] = L.f[1];
+    L.f[1] = t;
+  }
+  if (par) {
+    float *tg = L.g[0];
+    L.g[0] = L.g[1];
+    L.g[1] = tg;
+    int *ts = L.stamp[0];
+    L.stamp[0] = L.stamp[1];
+    L.stamp[1] = ts;
+  }
+  const long long idx = (long long)it.y * 256 + threadIdx.x;
+  if (idx >= (long long)L.nx * L.ny * L.nz) return;
+  const int x = (int)(idx % L.nx);
+  const long long row = idx / L.nx;
+  collide_stream_nodes<T, LINEAR, true, 1, true>(L, 0, 0, x, (int)(row % L.ny),
+                                                 (int)(row / L.ny));
+}
+
+void launch_batch_collide_stream(const BatchDev &B, int fp16, int src, int par, bool linear,
+                                 hipStream_t s) {
+  if (B.n_lat_items <= 0) return;
+  const dim3 grid(B.n_lat_items), block(256);
+  if (fp16) {
+    if (linear) k_batch_collide_stream<__half, true><<<grid, block, 0, s>>>(B, src, par);
+    else k_batch_collide_stream<__half, false><<<grid, block, 0, s>>>(B, src, par);
+  } else {
+    if (linear) k_batch_collide_stream<float, true><<<grid, block, 0, s>>>(B, src, par);
+    else k_batch_collide_stream<float, false><<<grid, block, 0, s>>>(B, src, par);
+  }
 }
 
 // ---- fills (no hipMemset, so that the same code can be captured) --------------

@@ -74,58 +74,96 @@ struct FaceRef {
   float l11, l12, l22;     // low parts
 };
 
-__device__ __forceinline__ void skalak_face_grad(const float4 a, const float4 b, const float4 c,
-                                                 const FaceRef &R, float ks, float ka,
-                                                 float3 &ga, float3 &gb, float3 &gc,
-                                                 bool &degenerate) {
+// Intermediate quantities of one face, shared by the gradient and its tangent.
+struct FaceState {
+  float e1x, e1y, e1z, e2x, e2y, e2z;  // current edges b - a, c - a
+  float c11, c12, c22;                 // C - 1
+  float I1, I2, kap;
+  float T11, T12, T22;                 // P^-1 S P^-T
+  float k2;                            // 2 A0
+};
+
+__device__ __forceinline__ FaceState skalak_state(const float4 a, const float4 b, const float4 c,
+                                                  const FaceRef &R, float ks, float ka) {
   const Edge u = edge_exact(a, b), v = edge_exact(a, c);
   const float d11 = dot_minus_ref(u, u, R.g11, R.l11);
   const float d12 = dot_minus_ref(u, v, R.g12, R.l12);
   const float d22 = dot_minus_ref(v, v, R.g22, R.l22);
-  const float e1x = u.hx, e1y = u.hy, e1z = u.hz;
-  const float e2x = v.hx, e2y = v.hy, e2z = v.hz;
+  FaceState F;
+  F.e1x = u.hx;
+  F.e1y = u.hy;
+  F.e1z = u.hz;
+  F.e2x = v.hx;
+  F.e2y = v.hy;
+  F.e2z = v.hz;
   const float p = R.p, q = R.q, s = R.s;
-  const float c11 = p * p * d11;
-  const float c12 = p * (q * d11 + s * d12);
-  const float c22 = q * (q * d11 + s * d12) + s * (q * d12 + s * d22);
-  const float I1 = c11 + c22;
-  const float I2 = I1 + (c11 * c22 - c12 * c12);
-  const float sig = (ks * I1 + ka * I2) * (1.0f / 6.0f);
-  const float kap = (ka * I2 - ks) * (1.0f / 6.0f);
-  const float S11 = sig + kap * c22, S22 = sig + kap * c11, S12 = -kap * c12;
+  F.c11 = p * p * d11;
+  F.c12 = p * (q * d11 + s * d12);
+  F.c22 = q * (q * d11 + s * d12) + s * (q * d12 + s * d22);
+  F.I1 = F.c11 + F.c22;
+  F.I2 = F.I1 + (F.c11 * F.c22 - F.c12 * F.c12);
+  const float sig = (ks * F.I1 + ka * F.I2) * (1.0f / 6.0f);
+  F.kap = (ka * F.I2 - ks) * (1.0f / 6.0f);
+  const float S11 = sig + F.kap * F.c22, S22 = sig + F.kap * F.c11, S12 = -F.kap * F.c12;
   const float r1 = p * S11 + q * S12, r2 = p * S12 + q * S22;
-  const float T11 = r1 * p + r2 * q, T12 = r2 * s, T22 = s * s * S22;
-  const float k2 = 2.0f * R.A0;
-  gb = make_float3(k2 * (T11 * e1x + T12 * e2x), k2 * (T11 * e1y + T12 * e2y),
-                   k2 * (T11 * e1z + T12 * e2z));
-  gc = make_float3(k2 * (T12 * e1x + T22 * e2x), k2 * (T12 * e1y + T22 * e2y),
-                   k2 * (T12 * e1z + T22 * e2z));
+  F.T11 = r1 * p + r2 * q;
+  F.T12 = r2 * s;
+  F.T22 = s * s * S22;
+  F.k2 = 2.0f * R.A0;
+  return F;
+}
+
+__device__ __forceinline__ void skalak_face_grad(const float4 a, const float4 b, const float4 c,
+                                                 const FaceRef &R, float ks, float ka,
+                                                 float3 &ga, float3 &gb, float3 &gc,
+                                                 bool &degenerate) {
+  const FaceState F = skalak_state(a, b, c, R, ks, ka);
+  const float k2 = F.k2;
+  gb = make_float3(k2 * (F.T11 * F.e1x + F.T12 * F.e2x), k2 * (F.T11 * F.e1y + F.T12 * F.e2y),
+                   k2 * (F.T11 * F.e1z + F.T12 * F.e2z));
+  gc = make_float3(k2 * (F.T12 * F.e1x + F.T22 * F.e2x), k2 * (F.T12 * F.e1y + F.T22 * F.e2y),
+                   k2 * (F.T12 * F.e1z + F.T22 * F.e2z));
   ga = make_float3(-(gb.x + gc.x), -(gb.y + gc.y), -(gb.z + gc.z));
-  degenerate = !(1.0f + I2 > 1e-6f);
+  degenerate = !(1.0f + F.I2 > 1e-6f);
 }
 
-// Gradients of every face energy A0 w_S with respect to its three corners,
-// one thread per face; the nodal forces F_n = -sum over the faces at n
-// (Eq. forcefromenergy) are gathered by the spreading kernel.
-__global__ __launch_bounds__(256) void k_face_gradients(MemDev M, Ctrl *ctrl) {
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= M.nf) return;
-  const int4 t = M.tri[j];
-  const float4 rp = M.ref_p[j], gh = M.ref_ghi[j], gl = M.ref_glo[j];
-  const float4 mod = M.moduli[t.w];
-  const FaceRef R{rp.x, rp.y, rp.z, rp.w, gh.x, gh.y, gh.z, gl.x, gl.y, gl.z};
-  float3 ga, gb, gc;
-  bool deg;
-  skalak_face_grad(M.x[t.x], M.x[t.y], M.x[t.z], R, mod.x, mod.y, ga, gb, gc, deg);
-  M.face_grad[3 * j + 0] = make_float4(ga.x, ga.y, ga.z, 0.0f);
-  M.face_grad[3 * j + 1] = make_float4(gb.x, gb.y, gb.z, 0.0f);
-  M.face_grad[3 * j + 2] = make_float4(gc.x, gc.y, gc.z, 0.0f);
-  if (deg) atomicOr(&ctrl->err, ERR_FACE);
-}
-
-void launch_face_gradients(const MemDev &M, Ctrl *ctrl, hipStream_t s) {
-  if (M.nf <= 0) return;
-  k_face_gradients<<<dim3((M.nf + 255) / 256), dim3(256), 0, s>>>(M, ctrl);
+// Forward derivative of the three corner gradients along corner displacements
+// da, db, dc and modulus rates dks, dka: each quantity of skalak_state
+// differentiated by the product rule (C - 1 is bilinear in the edges, the
+// invariants are polynomials in C - 1, the stresses linear in the invariants).
+__device__ __forceinline__ void skalak_face_grad_tangent(const float4 a, const float4 b,
+                                                         const float4 c, const float4 da,
+                                                         const float4 db, const float4 dc,
+                                                         const FaceRef &R, float ks, float ka,
+                                                         float dks, float dka, float3 &tga,
+                                                         float3 &tgb, float3 &tgc) {
+  const FaceState F = skalak_state(a, b, c, R, ks, ka);
+  const float p = R.p, q = R.q, s = R.s;
+  const float dux = db.x - da.x, duy = db.y - da.y, duz = db.z - da.z;
+  const float dvx = dc.x - da.x, dvy = dc.y - da.y, dvz = dc.z - da.z;
+  const float dd11 = 2.0f * (F.e1x * dux + F.e1y * duy + F.e1z * duz);
+  const float dd12 = (dux * F.e2x + duy * F.e2y + duz * F.e2z) + (F.e1x * dvx + F.e1y * dvy + F.e1z * dvz);
+  const float dd22 = 2.0f * (F.e2x * dvx + F.e2y * dvy + F.e2z * dvz);
+  const float dc11 = p * p * dd11;
+  const float dc12 = p * (q * dd11 + s * dd12);
+  const float dc22 = q * (q * dd11 + s * dd12) + s * (q * dd12 + s * dd22);
+  const float dI1 = dc11 + dc22;
+  const float dI2 = dI1 + (dc11 * F.c22 + F.c11 * dc22 - 2.0f * F.c12 * dc12);
+  const float dsig = (dks * F.I1 + ks * dI1 + dka * F.I2 + ka * dI2) * (1.0f / 6.0f);
+  const float dkap = (dka * F.I2 + ka * dI2 - dks) * (1.0f / 6.0f);
+  const float dS11 = dsig + dkap * F.c22 + F.kap * dc22;
+  const float dS22 = dsig + dkap * F.c11 + F.kap * dc11;
+  const float dS12 = -(dkap * F.c12 + F.kap * dc12);
+  const float dr1 = p * dS11 + q * dS12, dr2 = p * dS12 + q * dS22;
+  const float dT11 = dr1 * p + dr2 * q, dT12 = dr2 * s, dT22 = s * s * dS22;
+  const float k2 = F.k2;
+  tgb = make_float3(k2 * (dT11 * F.e1x + F.T11 * dux + dT12 * F.e2x + F.T12 * dvx),
+                    k2 * (dT11 * F.e1y + F.T11 * duy + dT12 * F.e2y + F.T12 * dvy),
+                    k2 * (dT11 * F.e1z + F.T11 * duz + dT12 * F.e2z + F.T12 * dvz));
+  tgc = make_float3(k2 * (dT12 * F.e1x + F.T12 * dux + dT22 * F.e2x + F.T22 * dvx),
+                    k2 * (dT12 * F.e1y + F.T12 * duy + dT22 * F.e2y + F.T22 * dvy),
+                    k2 * (dT12 * F.e1z + F.T12 * duz + dT22 * F.e2z + F.T22 * dvz));
+  tga = make_float3(-(tgb.x + tgc.x), -(tgb.y + tgc.y), -(tgb.z + tgc.z));
 }
 
 // Work items of the lane-group kernels are handed out so that each XCD (the
@@ -150,24 +188,33 @@ __device__ __forceinline__ float group_sum(float v) {
 }
 
 // ---- spreading, Eq. (forcespreading) -------------------------------------------
-// One lane group per membrane node: the group first gathers the node's force
-// from the face gradients of its incident faces, then each lane adds
+// One lane group per membrane node: the group first forms the node's Skalak
+// force from its incident faces (Sec. II.B), then each lane adds
 // F_n delta(X - x_n) to one stencil node X of the force field of parity `par`
 // (FP32 atomics; the field starts at zero, see the collide-stream kernel) and
 // stamps X's tile with the step number.
 template <int M>
-__global__ __launch_bounds__(256) void k_spread(LatDev L, MemDev Mm, int par, int nblocks) {
+__device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, int par, int blk) {
   constexpr int GS = group_size<M>();
-  const int blk = xcd_block(nblocks);
-  if (blk < 0) return;
   const int lane = threadIdx.x & (GS - 1);
   const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
   if (node >= Mm.nn) return;  // whole groups leave together
+  // Eq. (forcefromenergy): F_n = -sum over the faces at n of d(A0 w_S)/dx_n,
+  // one incident face per lane (each face is evaluated by each of its corners)
   float fx = 0.0f, fy = 0.0f, fz = 0.0f;
   const int e0 = Mm.csr_off[node], e1 = Mm.csr_off[node + 1];
   for (int e = e0 + lane; e < e1; e += GS) {
     const int ent = Mm.csr_ent[e];
-    const float4 g = Mm.face_grad[3 * (ent >> 2) + (ent & 3)];
+    const int j = ent >> 2, corner = ent & 3;
+    const int4 tj = Mm.tri[j];
+    const float4 rp = Mm.ref_p[j], gh = Mm.ref_ghi[j], gl = Mm.ref_glo[j];
+    const float4 mod = Mm.moduli[tj.w];
+    const FaceRef R{rp.x, rp.y, rp.z, rp.w, gh.x, gh.y, gh.z, gl.x, gl.y, gl.z};
+    float3 ga, gb, gc;
+    bool deg;
+    skalak_face_grad(Mm.x[tj.x], Mm.x[tj.y], Mm.x[tj.z], R, mod.x, mod.y, ga, gb, gc, deg);
+    if (deg) atomicOr(&L.ctrl->err, ERR_FACE);
+    const float3 g = corner == 0 ? ga : (corner == 1 ? gb : gc);
     fx -= g.x;
     fy -= g.y;
     fz -= g.z;
@@ -199,8 +246,164 @@ __global__ __launch_bounds__(256) void k_spread(LatDev L, MemDev Mm, int par, in
   L.stamp[par][tile_of(L, X, Y, Z)] = L.ctrl->step;
 }
 
+template <int M>
+__global__ __launch_bounds__(256) void k_spread(LatDev L, MemDev Mm, int par, int nblocks) {
+  const int blk = xcd_block(nblocks);
+  if (blk >= 0) spread_lanes<M>(L, Mm, par, blk);
+}
+
+// ---- chunked spreading ----------------------------------------------------------
+// One block per chunk.  The chunk's node forces (gathered from the face
+// gradients) and positions go to LDS together with the bounding box of its
+// stencils.  When the box fits in LDS, every contribution F_n delta(X - x_n) is
+// summed there first and each touched lattice node then receives one atomic
+// add per component: the overlapping stencils of neighbouring membrane nodes
+// cost LDS atomics instead of global ones.  Otherwise the contributions go to
+// the global field directly.
+struct Bounds {
+  int x0, y0, z0, ex, ey, ez;
+  bool fits;
+};
+
+// Box of the M-point stencils of the chunk's nb nodes (positions already in
+// sp); all threads of the block must call it.
+template <int M>
+__device__ __forceinline__ Bounds chunk_bounds(const float4 *sp, int nb, int *bb) {
+  const int t = threadIdx.x;
+  if (t < 3) {
+    bb[t] = 0x7fffffff;
+    bb[t + 3] = -0x7fffffff;
+  }
+  __syncthreads();
+  for (int k = t; k < nb; k += blockDim.x) {
+    const float4 p = sp[k];
+    const int lx = stencil_lo<M>(p.x), ly = stencil_lo<M>(p.y), lz = stencil_lo<M>(p.z);
+    atomicMin(&bb[0], lx);
+    atomicMin(&bb[1], ly);
+    atomicMin(&bb[2], lz);
+    atomicMax(&bb[3], lx);
+    atomicMax(&bb[4], ly);
+    atomicMax(&bb[5], lz);
+  }
+  __syncthreads();
+  Bounds b;
+  b.x0 = bb[0];
+  b.y0 = bb[1];
+  b.z0 = bb[2];
+  b.ex = bb[3] - bb[0] + M;
+  b.ey = bb[4] - bb[1] + M;
+  b.ez = bb[5] - bb[2] + M;
+  b.fits = (long long)b.ex * b.ey * b.ez <= BOX_CELLS;
+  return b;
+}
+
+// The chunk's node forces are formed here as well: every face with a corner in
+// the chunk is evaluated (a face shared by several chunks in each of them, with
+// identical results) and its corner gradients are summed into the chunk's
+// nodes in LDS, so the step needs no separate face kernel.
+template <int M>
+__global__ __launch_bounds__(256) void k_spread_chunks(LatDev L, MemDev Mm, int par) {
+  constexpr int M3 = M * M * M;
+  __shared__ float box[3][BOX_CELLS];
+  __shared__ float4 sp[CHUNK_MAX];
+  __shared__ float sfx[CHUNK_MAX], sfy[CHUNK_MAX], sfz[CHUNK_MAX];
+  __shared__ int bb[6];
+  const int ch = xcd_block(Mm.n_chunks);
+  if (ch < 0) return;  // the whole block
+  const int2 range = Mm.chunk[ch];
+  const int a = range.x, nb = range.y - range.x;
+  const int t = threadIdx.x;
+  for (int k = t; k < nb; k += blockDim.x) {
+    sp[k] = Mm.x[a + k];
+    sfx[k] = 0.0f;
+    sfy[k] = 0.0f;
+    sfz[k] = 0.0f;
+  }
+  __syncthreads();
+  // Eq. (forcefromenergy): F_n = -sum over the faces at n of d(A0 w_S)/dx_n
+  const int j1 = Mm.chunk_face_off[ch + 1];
+  for (int e = Mm.chunk_face_off[ch] + t; e < j1; e += blockDim.x) {
+    const int j = Mm.chunk_face[e];
+    const int4 tj = Mm.tri[j];
+    const float4 rp = Mm.ref_p[j], gh = Mm.ref_ghi[j], gl = Mm.ref_glo[j];
+    const float4 mod = Mm.moduli[tj.w];
+    const FaceRef R{rp.x, rp.y, rp.z, rp.w, gh.x, gh.y, gh.z, gl.x, gl.y, gl.z};
+    float3 gc[3];
+    bool deg;
+    skalak_face_grad(Mm.x[tj.x], Mm.x[tj.y], Mm.x[tj.z], R, mod.x, mod.y, gc[0], gc[1], gc[2], deg);
+    if (deg) atomicOr(&L.ctrl->err, ERR_FACE);
+    const int corner[3] = {tj.x - a, tj.y - a, tj.z - a};
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      if (corner[c] < 0 || corner[c] >= nb) continue;
+      atomicAdd(&sfx[corner[c]], -gc[c].x);
+      atomicAdd(&sfy[corner[c]], -gc[c].y);
+      atomicAdd(&sfz[corner[c]], -gc[c].z);
+    }
+  }
+  __syncthreads();
+  for (int k = t; k < nb; k += blockDim.x) Mm.F[a + k] = make_float4(sfx[k], sfy[k], sfz[k], 0.0f);
+  const Bounds b = chunk_bounds<M>(sp, nb, bb);
+  const int V = b.fits ? b.ex * b.ey * b.ez : 0;
+  for (int c = t; c < V; c += blockDim.x) box[0][c] = box[1][c] = box[2][c] = 0.0f;
+  __syncthreads();
+  const int4 o = Mm.origin[Mm.node_cap[a]];
+  float *g = L.g[par];
+  const int step = L.ctrl->step;
+  for (int q = t; q < nb * M3; q += blockDim.x) {
+    const int k = q / M3, sidx = q - k * M3;
+    const int sx = sidx % M, sy = (sidx / M) % M, sz = sidx / (M * M);
+    const float4 p = sp[k];
+    const int lx = stencil_lo<M>(p.x) + sx;
+    const int ly = stencil_lo<M>(p.y) + sy;
+    const int lz = stencil_lo<M>(p.z) + sz;
+    const float w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
+    if (w == 0.0f) continue;
+    const int Z = o.z + lz;
+    if (Z < 0 || Z >= L.nz) {
+      atomicOr(&L.ctrl->err, ERR_WALL);
+      continue;
+    }
+    const float4 F = make_float4(sfx[k], sfy[k], sfz[k], 0.0f);
+    if (b.fits) {
+      const int c = ((lz - b.z0) * b.ey + (ly - b.y0)) * b.ex + (lx - b.x0);
+      atomicAdd(&box[0][c], w * F.x);
+      atomicAdd(&box[1][c], w * F.y);
+      atomicAdd(&box[2][c], w * F.z);
+    } else {
+      const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
+      const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
+      unsafeAtomicAdd(g + n, w * F.x);
+      unsafeAtomicAdd(g + L.S + n, w * F.y);
+      unsafeAtomicAdd(g + 2 * L.S + n, w * F.z);
+      L.stamp[par][tile_of(L, X, Y, Z)] = step;
+    }
+  }
+  if (!b.fits) return;  // the whole block
+  __syncthreads();
+  // box nodes that received force: only in-range z can have (see above)
+  for (int c = t; c < V; c += blockDim.x) {
+    const float vx = box[0][c], vy = box[1][c], vz = box[2][c];
+    if (vx == 0.0f && vy == 0.0f && vz == 0.0f) continue;
+    const int lx = b.x0 + c % b.ex, ly = b.y0 + (c / b.ex) % b.ey, lz = b.z0 + c / (b.ex * b.ey);
+    const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny), Z = o.z + lz;
+    const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
+    if (vx != 0.0f) unsafeAtomicAdd(g + n, vx);
+    if (vy != 0.0f) unsafeAtomicAdd(g + L.S + n, vy);
+    if (vz != 0.0f) unsafeAtomicAdd(g + 2 * L.S + n, vz);
+    L.stamp[par][tile_of(L, X, Y, Z)] = step;
+  }
+}
+
 void launch_spread(const LatDev &L, const MemDev &M, int par, hipStream_t s) {
   if (M.nn <= 0) return;
+  if (M.n_chunks > 0) {
+    const dim3 grid(xcd_grid(M.n_chunks)), block(256);
+    if (M.m == 2) k_spread_chunks<2><<<grid, block, 0, s>>>(L, M, par);
+    else if (M.m == 3) k_spread_chunks<3><<<grid, block, 0, s>>>(L, M, par);
+    else k_spread_chunks<4><<<grid, block, 0, s>>>(L, M, par);
+    return;
+  }
   const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
   const long long lanes = (long long)M.nn * gs;
   const int nblocks = (int)((lanes + 255) / 256);
@@ -228,12 +431,9 @@ __device__ __forceinline__ float ld_pop<__half>(const __half *p, long long idx, 
 }
 
 template <typename T, int M>
-__global__ __launch_bounds__(256) void k_interp_advect(LatDev L, MemDev Mm, int fsrc, int par,
-                                                       int advect, int nblocks) {
+__device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, int fsrc, int par,
+                                             int advect, int blk) {
   constexpr int GS = group_size<M>();
-  if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
-  const int blk = xcd_block(nblocks);
-  if (blk < 0) return;
   const int lane = threadIdx.x & (GS - 1);
   const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
   if (node >= Mm.nn) return;  // whole groups leave together
@@ -252,12 +452,13 @@ __global__ __launch_bounds__(256) void k_interp_advect(LatDev L, MemDev Mm, int 
         atomicOr(&L.ctrl->err, ERR_WALL);
       } else {
         const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
-        const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
+        const long long row = (long long)Z * L.ny + Y;
+        const long long n = row * L.nx + X;
         const T *f = static_cast<const T *>(L.f[fsrc]);
         float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-          const float d = ld_pop<T>(f, i * L.S + n, 1.0f / L.h_scale[i]);
+          const float d = ld_pop<T>(f, pidx(L, i, row, X), 1.0f / L.h_scale[i]);
           drho += d;
           if (cx(i)) jx += cx(i) * d;
           if (cy(i)) jy += cy(i) * d;
@@ -290,9 +491,162 @@ __global__ __launch_bounds__(256) void k_interp_advect(LatDev L, MemDev Mm, int 
   }
 }
 
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_interp_advect(LatDev L, MemDev Mm, int fsrc, int par,
+                                                       int advect, int nblocks) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
+  const int blk = xcd_block(nblocks);
+  if (blk >= 0) interp_lanes<T, M>(L, Mm, fsrc, par, advect, blk);
+}
+
+// Lattice velocity u(X, t+1) of Eq. (velocityinterpolation) at lattice node n.
+template <typename T>
+__device__ __forceinline__ float3 lattice_velocity(const LatDev &L, const T *f, const float *g,
+                                                   int X, int Y, int Z) {
+  const long long row = (long long)Z * L.ny + Y;
+  const long long n = row * L.nx + X;
+  float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float d = ld_pop<T>(f, pidx(L, i, row, X), 1.0f / L.h_scale[i]);
+    drho += d;
+    if (cx(i)) jx += cx(i) * d;
+    if (cy(i)) jy += cy(i) * d;
+    if (cz(i)) jz += cz(i) * d;
+  }
+  const float inv_rho = 1.0f / (1.0f + drho);
+  return make_float3((jx + 0.5f * g[n]) * inv_rho, (jy + 0.5f * g[L.S + n]) * inv_rho,
+                     (jz + 0.5f * g[2 * L.S + n]) * inv_rho);
+}
+
+// ---- chunked interpolation + advection ----------------------------------------
+// One block per chunk.  When the chunk's stencil box fits in LDS, the lattice
+// velocity is evaluated once at every box node a stencil touches with nonzero
+// weight (consecutive threads on consecutive x: coalesced population reads)
+// and the node sums are taken from LDS; otherwise every stencil node reads the
+// populations itself.  Node sums use the same lane groups as the per-node
+// kernel.  One thread advances the device step counter.
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_interp_chunks(LatDev L, MemDev Mm, int fsrc, int par,
+                                                       int advect) {
+  constexpr int M3 = M * M * M;
+  constexpr int GS = group_size<M>();
+  __shared__ float box[3][BOX_CELLS];
+  __shared__ unsigned char mark[BOX_CELLS];
+  __shared__ float4 sp[CHUNK_MAX];
+  __shared__ int bb[6];
+  if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
+  const int ch = xcd_block(Mm.n_chunks);
+  if (ch < 0) return;  // the whole block
+  const int2 range = Mm.chunk[ch];
+  const int a = range.x, nb = range.y - range.x;
+  const int t = threadIdx.x;
+  for (int k = t; k < nb; k += blockDim.x) sp[k] = Mm.x[a + k];
+  const Bounds b = chunk_bounds<M>(sp, nb, bb);
+  const int V = b.fits ? b.ex * b.ey * b.ez : 0;
+  const int4 o = Mm.origin[Mm.node_cap[a]];
+  const T *f = static_cast<const T *>(L.f[fsrc]);
+  const float *g = L.g[par];
+  if (b.fits) {
+    for (int c = t; c < V; c += blockDim.x) mark[c] = 0;
+    __syncthreads();
+    for (int q = t; q < nb * M3; q += blockDim.x) {
+      const int k = q / M3, sidx = q - k * M3;
+      const float4 p = sp[k];
+      const int lx = stencil_lo<M>(p.x) + sidx % M;
+      const int ly = stencil_lo<M>(p.y) + (sidx / M) % M;
+      const int lz = stencil_lo<M>(p.z) + sidx / (M * M);
+      const float w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
+      if (w != 0.0f) mark[((lz - b.z0) * b.ey + (ly - b.y0)) * b.ex + (lx - b.x0)] = 1;
+    }
+    __syncthreads();
+    for (int c = t; c < V; c += blockDim.x) {
+      if (!mark[c]) continue;
+      const int lx = b.x0 + c % b.ex, ly = b.y0 + (c / b.ex) % b.ey, lz = b.z0 + c / (b.ex * b.ey);
+      const int Z = o.z + lz;
+      float3 u = make_float3(0.0f, 0.0f, 0.0f);
+      if (Z < 0 || Z >= L.nz) {
+        atomicOr(&L.ctrl->err, ERR_WALL);
+      } else {
+        const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
+        u = lattice_velocity<T>(L, f, g, X, Y, Z);
+      }
+      box[0][c] = u.x;
+      box[1][c] = u.y;
+      box[2][c] = u.z;
+    }
+    __syncthreads();
+  }
+  const int lane = t & (GS - 1);
+  for (int k0 = 0; k0 < nb; k0 += (int)blockDim.x / GS) {
+    const int k = k0 + t / GS;
+    float ux = 0.0f, uy = 0.0f, uz = 0.0f;
+    float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    if (k < nb) {
+      p = sp[k];
+      if (lane < M3) {
+        const int lx = stencil_lo<M>(p.x) + lane % M;
+        const int ly = stencil_lo<M>(p.y) + (lane / M) % M;
+        const int lz = stencil_lo<M>(p.z) + lane / (M * M);
+        const float w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
+        if (w != 0.0f) {
+          float3 u;
+          if (b.fits) {
+            const int c = ((lz - b.z0) * b.ey + (ly - b.y0)) * b.ex + (lx - b.x0);
+            u = make_float3(box[0][c], box[1][c], box[2][c]);
+          } else {
+            const int Z = o.z + lz;
+            if (Z < 0 || Z >= L.nz) {
+              atomicOr(&L.ctrl->err, ERR_WALL);
+              u = make_float3(0.0f, 0.0f, 0.0f);
+            } else {
+              const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
+              u = lattice_velocity<T>(L, f, g, X, Y, Z);
+            }
+          }
+          ux = w * u.x;
+          uy = w * u.y;
+          uz = w * u.z;
+        }
+      }
+    }
+    ux = group_sum<GS>(ux);
+    uy = group_sum<GS>(uy);
+    uz = group_sum<GS>(uz);
+    if (k < nb && lane == 0) {
+      const int node = a + k;
+      if (advect == 1) {
+        const float4 up = Mm.u[node];
+        p.x += 1.5f * ux - 0.5f * up.x;
+        p.y += 1.5f * uy - 0.5f * up.y;
+        p.z += 1.5f * uz - 0.5f * up.z;
+      } else {
+        p.x += ux;
+        p.y += uy;
+        p.z += uz;
+      }
+      Mm.u[node] = make_float4(ux, uy, uz, 0.0f);
+      Mm.x[node] = p;
+    }
+  }
+}
+
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
                           int advect, hipStream_t s) {
   if (M.nn <= 0) return;
+  if (M.n_chunks > 0) {
+    const dim3 grid(xcd_grid(M.n_chunks)), block(256);
+#define IBM_LAUNCH_INTERP_CHUNKS(T)                                                            \
+  do {                                                                                         \
+    if (M.m == 2) k_interp_chunks<T, 2><<<grid, block, 0, s>>>(L, M, fsrc, par, advect);      \
+    else if (M.m == 3) k_interp_chunks<T, 3><<<grid, block, 0, s>>>(L, M, fsrc, par, advect); \
+    else k_interp_chunks<T, 4><<<grid, block, 0, s>>>(L, M, fsrc, par, advect);               \
+  } while (0)
+    if (fp16) IBM_LAUNCH_INTERP_CHUNKS(__half);
+    else IBM_LAUNCH_INTERP_CHUNKS(float);
+#undef IBM_LAUNCH_INTERP_CHUNKS
+    return;
+  }
   const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
   const long long lanes = (long long)M.nn * gs;
   const int nblocks = (int)((lanes + 255) / 256);
@@ -306,6 +660,204 @@ void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, 
   if (fp16) IBM_LAUNCH_INTERP(__half);
   else IBM_LAUNCH_INTERP(float);
 #undef IBM_LAUNCH_INTERP
+}
+
+// ---- tangent (forward sensitivity) of spreading and interpolation ----------------
+// With r = X - x_n and Phi(r) = phi(r_x) phi(r_y) phi(r_z), a node moving by dx
+// changes its weight at X by -grad Phi(r) . dx, so
+//   dg(X)  = sum_n [dF_n Phi(r) - F_n (grad Phi(r) . dx_n)]          (spreading)
+//   du_n   = sum_X [du(X) Phi(r) - u(X) (grad Phi(r) . dx_n)]        (interpolation)
+// with du(X) = (dj + dg/2 - u drho) / rho the derivative of the lattice velocity.
+template <int M>
+__device__ __forceinline__ void stencil_weight(const float4 p, const float4 dp, int lane, int &lx,
+                                               int &ly, int &lz, float &w, float &dw) {
+  lx = stencil_lo<M>(p.x) + lane % M;
+  ly = stencil_lo<M>(p.y) + (lane / M) % M;
+  lz = stencil_lo<M>(p.z) + lane / (M * M);
+  const float rx = (float)lx - p.x, ry = (float)ly - p.y, rz = (float)lz - p.z;
+  const float wx = phi<M>(rx), wy = phi<M>(ry), wz = phi<M>(rz);
+  w = wx * wy * wz;
+  dw = -(dphi<M>(rx) * wy * wz * dp.x + wx * dphi<M>(ry) * wz * dp.y + wx * wy * dphi<M>(rz) * dp.z);
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void k_tangent_spread(LatDev L, MemDev Mm, TanDev Tn, int par,
+                                                        int nblocks) {
+  constexpr int GS = group_size<M>();
+  const int blk = xcd_block(nblocks);
+  if (blk < 0) return;
+  const int lane = threadIdx.x & (GS - 1);
+  const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
+  if (node >= Mm.nn) return;  // whole groups leave together
+  float fx = 0.0f, fy = 0.0f, fz = 0.0f;
+  const int e0 = Mm.csr_off[node], e1 = Mm.csr_off[node + 1];
+  for (int e = e0 + lane; e < e1; e += GS) {
+    const int ent = Mm.csr_ent[e];
+    const int j = ent >> 2, corner = ent & 3;
+    const int4 tj = Mm.tri[j];
+    const float4 rp = Mm.ref_p[j], gh = Mm.ref_ghi[j], gl = Mm.ref_glo[j];
+    const float4 mod = Mm.moduli[tj.w];
+    const float2 dmod = Tn.dmod[tj.w];
+    const FaceRef R{rp.x, rp.y, rp.z, rp.w, gh.x, gh.y, gh.z, gl.x, gl.y, gl.z};
+    float3 ta, tb, tc;
+    skalak_face_grad_tangent(Mm.x[tj.x], Mm.x[tj.y], Mm.x[tj.z], Tn.dx[tj.x], Tn.dx[tj.y],
+                             Tn.dx[tj.z], R, mod.x, mod.y, dmod.x, dmod.y, ta, tb, tc);
+    const float3 t = corner == 0 ? ta : (corner == 1 ? tb : tc);
+    fx -= t.x;
+    fy -= t.y;
+    fz -= t.z;
+  }
+  fx = group_sum<GS>(fx);
+  fy = group_sum<GS>(fy);
+  fz = group_sum<GS>(fz);
+  if (lane == 0) Tn.dF[node] = make_float4(fx, fy, fz, 0.0f);
+  if (lane >= M * M * M) return;
+  int lx, ly, lz;
+  float w, dw;
+  stencil_weight<M>(Mm.x[node], Tn.dx[node], lane, lx, ly, lz, w, dw);
+  if (w == 0.0f) return;
+  const int4 o = Mm.origin[Mm.node_cap[node]];
+  const int Z = o.z + lz;
+  if (Z < 0 || Z >= L.nz) return;  // flagged by the spreading kernel
+  const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
+  const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
+  const float4 F = Mm.F[node];
+  float *dg = Tn.dg[par];
+  unsafeAtomicAdd(dg + n, w * fx + dw * F.x);
+  unsafeAtomicAdd(dg + L.S + n, w * fy + dw * F.y);
+  unsafeAtomicAdd(dg + 2 * L.S + n, w * fz + dw * F.z);
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void k_tangent_interp(LatDev L, MemDev Mm, TanDev Tn, int fsrc,
+                                                        int par, int nblocks) {
+  constexpr int GS = group_size<M>();
+  const int blk = xcd_block(nblocks);
+  if (blk < 0) return;
+  const int lane = threadIdx.x & (GS - 1);
+  const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
+  if (node >= Mm.nn) return;  // whole groups leave together
+  const float4 dp = Tn.dx[node];
+  float ux = 0.0f, uy = 0.0f, uz = 0.0f;
+  if (lane < M * M * M) {
+    int lx, ly, lz;
+    float w, dw;
+    stencil_weight<M>(Mm.x[node], dp, lane, lx, ly, lz, w, dw);
+    const int4 o = Mm.origin[Mm.node_cap[node]];
+    const int Z = o.z + lz;
+    if (w != 0.0f && Z >= 0 && Z < L.nz) {
+      const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
+      const long long row = (long long)Z * L.ny + Y;
+      const long long n = row * L.nx + X;
+      const float *f = static_cast<const float *>(L.f[fsrc]);
+      const float *df = Tn.df[fsrc];
+      float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+      float trho = 0.0f, tjx = 0.0f, tjy = 0.0f, tjz = 0.0f;
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const float d = f[pidx(L, i, row, X)], t = df[i * L.S + n];
+        drho += d;
+        trho += t;
+        if (cx(i)) {
+          jx += cx(i) * d;
+          tjx += cx(i) * t;
+        }
+        if (cy(i)) {
+          jy += cy(i) * d;
+          tjy += cy(i) * t;
+        }
+        if (cz(i)) {
+          jz += cz(i) * d;
+          tjz += cz(i) * t;
+        }
+      }
+      const float *g = L.g[par], *dg = Tn.dg[par];
+      const float inv_rho = 1.0f / (1.0f + drho);
+      const float vx = (jx + 0.5f * g[n]) * inv_rho;
+      const float vy = (jy + 0.5f * g[L.S + n]) * inv_rho;
+      const float vz = (jz + 0.5f * g[2 * L.S + n]) * inv_rho;
+      const float tvx = (tjx + 0.5f * dg[n] - vx * trho) * inv_rho;
+      const float tvy = (tjy + 0.5f * dg[L.S + n] - vy * trho) * inv_rho;
+      const float tvz = (tjz + 0.5f * dg[2 * L.S + n] - vz * trho) * inv_rho;
+      ux = w * tvx + dw * vx;
+      uy = w * tvy + dw * vy;
+      uz = w * tvz + dw * vz;
+    }
+  }
+  ux = group_sum<GS>(ux);
+  uy = group_sum<GS>(uy);
+  uz = group_sum<GS>(uz);
+  if (lane == 0) {
+    Tn.du[node] = make_float4(ux, uy, uz, 0.0f);
+    Tn.dx[node] = make_float4(dp.x + ux, dp.y + uy, dp.z + uz, 0.0f);
+  }
+}
+
+void launch_tangent_spread(const LatDev &L, const MemDev &M, const TanDev &T, int par,
+                           hipStream_t s) {
+  if (M.nn <= 0) return;
+  const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
+  const int nblocks = (int)(((long long)M.nn * gs + 255) / 256);
+  const dim3 grid(xcd_grid(nblocks)), block(256);
+  if (M.m == 2) k_tangent_spread<2><<<grid, block, 0, s>>>(L, M, T, par, nblocks);
+  else if (M.m == 3) k_tangent_spread<3><<<grid, block, 0, s>>>(L, M, T, par, nblocks);
+  else k_tangent_spread<4><<<grid, block, 0, s>>>(L, M, T, par, nblocks);
+}
+
+void launch_tangent_interp(const LatDev &L, const MemDev &M, const TanDev &T, int fsrc, int par,
+                           hipStream_t s) {
+  if (M.nn <= 0) return;
+  const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
+  const int nblocks = (int)(((long long)M.nn * gs + 255) / 256);
+  const dim3 grid(xcd_grid(nblocks)), block(256);
+  if (M.m == 2) k_tangent_interp<2><<<grid, block, 0, s>>>(L, M, T, fsrc, par, nblocks);
+  else if (M.m == 3) k_tangent_interp<3><<<grid, block, 0, s>>>(L, M, T, fsrc, par, nblocks);
+  else k_tangent_interp<4><<<grid, block, 0, s>>>(L, M, T, fsrc, par, nblocks);
+}
+
+// ---- batches of runs -------------------------------------------------------------
+// Spreading (with the Skalak forces) and interpolation of many independent
+// runs, one launch each; a block works for run items[b].x as block items[b].y of that
+// run's own launch (so a block never mixes runs).  The delta width is chosen
+// per block.
+__global__ __launch_bounds__(256) void k_batch_spread(BatchDev B, int par) {
+  const int b = xcd_block(B.n_node_items);
+  if (b < 0) return;
+  const int2 it = B.node_items[b];
+  const LatDev &L = B.lat[it.x];
+  const MemDev &Mm = B.mem[it.x];
+  const int m = Mm.m;
+  if (m == 2) spread_lanes<2>(L, Mm, par, it.y);
+  else if (m == 3) spread_lanes<3>(L, Mm, par, it.y);
+  else spread_lanes<4>(L, Mm, par, it.y);
+}
+
+// The first block of each run advances that run's device step counter.
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_interp(BatchDev B, int fsrc, int par, int advect) {
+  const int b = xcd_block(B.n_node_items);
+  if (b < 0) return;
+  const int2 it = B.node_items[b];
+  const LatDev &L = B.lat[it.x];
+  const MemDev &Mm = B.mem[it.x];
+  if (it.y == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
+  const int m = Mm.m;
+  if (m == 2) interp_lanes<T, 2>(L, Mm, fsrc, par, advect, it.y);
+  else if (m == 3) interp_lanes<T, 3>(L, Mm, fsrc, par, advect, it.y);
+  else interp_lanes<T, 4>(L, Mm, fsrc, par, advect, it.y);
+}
+
+void launch_batch_spread(const BatchDev &B, int par, hipStream_t s) {
+  if (B.n_node_items <= 0) return;
+  k_batch_spread<<<dim3(xcd_grid(B.n_node_items)), dim3(256), 0, s>>>(B, par);
+}
+
+void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect,
+                         hipStream_t s) {
+  if (B.n_node_items <= 0) return;
+  const dim3 grid(xcd_grid(B.n_node_items)), block(256);
+  if (fp16) k_batch_interp<__half><<<grid, block, 0, s>>>(B, fsrc, par, advect);
+  else k_batch_interp<float><<<grid, block, 0, s>>>(B, fsrc, par, advect);
 }
 
 // ---- capsule frame re-centring -------------------------------------------------
@@ -453,7 +1005,16 @@ __device__ void block_sum(double (*red)[256], double *vals) {
 // (divided by V); the ellipsoid with that tensor has
 // r_a^2 = 5/2 (E2 + E3 - E1), r_b^2 = 5/2 (E1 + E3 - E2),
 // r_c^2 = 5/2 (E1 + E2 - E3) for eigenvalues E1 <= E2 <= E3.
-__global__ __launch_bounds__(256) void k_observables(MemDev M, Ctrl *ctrl) {
+// Node n of the observables: stored coordinates, or x + h dx when dx is given.
+__device__ __forceinline__ double3 obs_node(const MemDev &M, const float4 *dx, double h, int n) {
+  const float4 p = M.x[n];
+  if (!dx) return make_double3(p.x, p.y, p.z);
+  const float4 d = dx[n];
+  return make_double3((double)p.x + h * d.x, (double)p.y + h * d.y, (double)p.z + h * d.z);
+}
+
+__global__ __launch_bounds__(256) void k_observables(MemDev M, Ctrl *ctrl, const float4 *dx,
+                                                     double h, double *obs) {
   __shared__ double red[7][256];
   __shared__ double cen[3];
   const int c = blockIdx.x;
@@ -461,7 +1022,7 @@ __global__ __launch_bounds__(256) void k_observables(MemDev M, Ctrl *ctrl) {
   double v1[4] = {0.0, 0.0, 0.0, 0.0};
   for (int j = f0 + threadIdx.x; j < f1; j += blockDim.x) {
     const int4 t = M.tri[j];
-    const float4 A = M.x[t.x], B = M.x[t.y], C = M.x[t.z];
+    const double3 A = obs_node(M, dx, h, t.x), B = obs_node(M, dx, h, t.y), C = obs_node(M, dx, h, t.z);
     const double ax = A.x, ay = A.y, az = A.z, bx = B.x, by = B.y, bz = B.z;
     const double cx_ = C.x, cy_ = C.y, cz_ = C.z;
     const double vt =
@@ -482,15 +1043,15 @@ __global__ __launch_bounds__(256) void k_observables(MemDev M, Ctrl *ctrl) {
   double s7[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int j = f0 + threadIdx.x; j < f1; j += blockDim.x) {
     const int4 t = M.tri[j];
-    const float4 A = M.x[t.x], B = M.x[t.y], C = M.x[t.z];
-    const double e1x = (double)B.x - A.x, e1y = (double)B.y - A.y, e1z = (double)B.z - A.z;
-    const double e2x = (double)C.x - A.x, e2y = (double)C.y - A.y, e2z = (double)C.z - A.z;
+    const double3 A = obs_node(M, dx, h, t.x), B = obs_node(M, dx, h, t.y), C = obs_node(M, dx, h, t.z);
+    const double e1x = B.x - A.x, e1y = B.y - A.y, e1z = B.z - A.z;
+    const double e2x = C.x - A.x, e2y = C.y - A.y, e2z = C.z - A.z;
     const double anx = 0.5 * (e1y * e2z - e1z * e2y);
     const double any = 0.5 * (e1z * e2x - e1x * e2z);
     const double anz = 0.5 * (e1x * e2y - e1y * e2x);
-    const double rx = ((double)A.x + B.x + C.x) / 3.0 - cen[0];
-    const double ry = ((double)A.y + B.y + C.y) / 3.0 - cen[1];
-    const double rz = ((double)A.z + B.z + C.z) / 3.0 - cen[2];
+    const double rx = (A.x + B.x + C.x) / 3.0 - cen[0];
+    const double ry = (A.y + B.y + C.y) / 3.0 - cen[1];
+    const double rz = (A.z + B.z + C.z) / 3.0 - cen[2];
     const double rn = rx * anx + ry * any + rz * anz;
     const double r2 = rx * rx + ry * ry + rz * rz;
     s7[0] += (r2 - rx * rx) * rn;
@@ -527,7 +1088,7 @@ __global__ __launch_bounds__(256) void k_observables(MemDev M, Ctrl *ctrl) {
   if (th > M_PI / 2) th -= M_PI;
   if (!((E2 - E1) > 1e-12 * fabs(E3))) th = __longlong_as_double(0x7ff8000000000000LL);
   const int4 o = M.origin[c];
-  double *out = M.obs + (size_t)c * 16;
+  double *out = obs + (size_t)c * 16;
   out[0] = V;
   out[1] = cen[0] + o.x;
   out[2] = cen[1] + o.y;
@@ -546,7 +1107,13 @@ __global__ __launch_bounds__(256) void k_observables(MemDev M, Ctrl *ctrl) {
 
 void launch_observables(const MemDev &M, Ctrl *ctrl, hipStream_t s) {
   if (M.n_caps <= 0) return;
-  k_observables<<<dim3(M.n_caps), dim3(256), 0, s>>>(M, ctrl);
+  k_observables<<<dim3(M.n_caps), dim3(256), 0, s>>>(M, ctrl, nullptr, 0.0, M.obs);
+}
+
+void launch_observables_shifted(const MemDev &M, Ctrl *ctrl, const float4 *dx, double h,
+                                double *obs, hipStream_t s) {
+  if (M.n_caps <= 0) return;
+  k_observables<<<dim3(M.n_caps), dim3(256), 0, s>>>(M, ctrl, dx, h, obs);
 }
 
 // ---- mesh output (FP64, unwrapped lattice coordinates) -----------------------------

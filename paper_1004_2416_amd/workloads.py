@@ -194,6 +194,14 @@ def batched_sweep(count: int = 64, seed: int = 1004) -> List[BatchRun]:
     return runs
 
 
+def sweep_workloads(count: int = 64, seed: int = 1004, steps: int = 5000) -> List[Workload]:
+    """The batched sweep as workloads: each run a centred single capsule in an
+    n^3 box (Sec. IV's parameter studies run many such independent cases)."""
+    return [single_capsule(f"sweep{k:02d}_{b.n}cube_r{b.r:g}_l{b.level}_phi{b.m}", b.n, b.u_w,
+                           b.level, b.r, b.ca, b.m, steps)
+            for k, b in enumerate(batched_sweep(count, seed))]
+
+
 def noise(shape, amplitude: float, seed: int) -> np.ndarray:
     """Seeded uniform noise in [-amplitude, amplitude]."""
     return np.random.default_rng(seed).uniform(-amplitude, amplitude, size=shape)

@@ -90,8 +90,10 @@ def deformed_state(c, steps):
     return rep_populations(sim.f), rep_positions(sim.x, c.node_counts)
 
 
-def compare_one_step(B, c, f_s, x_s, tol_f=1e-5, tol_m=1e-5):
+def compare_one_step(B, c, f_s, x_s, tol_f=1e-5, tol_m=1e-5, chunk=None):
     lat = c.gpu(graph=False)
+    if chunk is not None:
+        lat.set_option(B.OPT_CHUNK_NODES, chunk)
     lat.set_populations(f_s)
     lat.set_mesh(x_s)
     lat.step(1)
@@ -166,6 +168,27 @@ def test_coupled_step_parity_crowded_overlapping_capsules(B):
     c = Case(W.Workload("crowded", nx, ny, nz, 1.0, uw, 2, 0, caps))
     f_s, x_s = deformed_state(c, 5)
     compare_one_step(B, c, f_s, x_s)
+
+
+@pytest.mark.parametrize("chunk", [0, 16, 32, 128, 256])
+def test_coupling_chunk_sizes(B, chunk):
+    """Spreading and interpolation per lane group (0) and per chunk of
+    16..256 nodes (stencils summed in on-chip memory) all match the oracle."""
+    say("chunk size", chunk)
+    c = small_case(n=(40, 36, 30), m=4, level=3, r=8.0, ca=0.02, uw=0.03)
+    f_s, x_s = deformed_state(c, 10)
+    compare_one_step(B, c, f_s, x_s, chunk=chunk)
+
+
+@pytest.mark.parametrize("chunk", [16, 256])
+def test_coupling_chunk_box_too_large(B, chunk):
+    """A coarse capsule (42 nodes, radius 14): the stencil box of every chunk
+    exceeds the on-chip capacity, so the chunks add to and read the global
+    fields directly."""
+    say("oversized chunk boxes", chunk)
+    c = small_case(n=(40, 40, 40), m=3, level=1, r=14.0, ca=0.02, uw=0.03)
+    f_s, x_s = deformed_state(c, 10)
+    compare_one_step(B, c, f_s, x_s, chunk=chunk)
 
 
 def test_undeformed_capsule_has_zero_force(B):
