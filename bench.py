@@ -56,7 +56,8 @@ def measured_traffic(workload: str, storage: str):
     return None
 
 
-def setup(workload: str, storage: str, graph: bool, variant: int = -1, chunk: int = -1):
+def setup(workload: str, storage: str, graph: bool, variant: int = -1, chunk: int = -1,
+          box: int = -1):
     from paper_1004_2416_amd import binding as B
     from paper_1004_2416_amd import workloads as W
 
@@ -70,6 +71,8 @@ def setup(workload: str, storage: str, graph: bool, variant: int = -1, chunk: in
         lat.set_option(B.OPT_LBM_VARIANT, int(variant))
     if chunk >= 0 and wl.capsules:
         lat.set_option(B.OPT_CHUNK_NODES, int(chunk))
+    if box >= 0:
+        lat.set_option(B.OPT_STENCIL_BOX, int(box))
     return wl, lat
 
 
@@ -140,6 +143,10 @@ def main():
     ap.add_argument("--chunk-nodes", type=int, default=-1,
                     help="membrane nodes per chunk of the coupling kernels (0: none; "
                          "-1: library default)")
+    ap.add_argument("--stencil-box", type=int, default=-1,
+                    help="IBM_OPT_STENCIL_BOX bits (-1: library default)")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library time its kernel forms during warm-up")
     ap.add_argument("--lbm-variant", type=int, default=-1,
                     help="collide-stream launch variant (IBM_OPT_LBM_VARIANT bits; "
                          "-1: the library default)")
@@ -163,8 +170,9 @@ def main():
 
     import torch
     wl, lat = setup(args.workload, args.storage, not args.no_graph, args.lbm_variant,
-                    args.chunk_nodes)
+                    args.chunk_nodes, args.stencil_box)
     stream = lat.stream
+    tuned = lat.autotune(64) if args.autotune else None
     lat.step(args.warmup)
     lat.synchronize()
 
@@ -208,7 +216,8 @@ def main():
             "capsules": len(wl.capsules), "membrane_nodes": wl.n_membrane_nodes,
             "delta_width": wl.m, "storage": args.storage, "graph": not args.no_graph,
             "u_w": wl.u_w, "tau": wl.tau, "lbm_variant": args.lbm_variant,
-            "chunk_nodes": args.chunk_nodes,
+            "chunk_nodes": args.chunk_nodes, "stencil_box": args.stencil_box,
+            "autotuned": tuned,
         },
         "membrane_node_updates_per_s": round(wl.n_membrane_nodes * args.steps / (ms * 1e-3), 1),
         "step_pct_hbm_roofline": round(100 * mlups * 1e6 * bytes_per_node(args.storage)
@@ -244,6 +253,8 @@ def run_batch(args):
         lat.set_shear(wl.u_w, init_profile=True)
         c = wl.capsules[0]
         lat.add_capsules([B.icosphere(c.level, c.r, c.center)], [c.ks], [c.ka], wl.m)
+        if args.stencil_box >= 0:
+            lat.set_option(B.OPT_STENCIL_BOX, args.stencil_box)
         lats.append(lat)
     batch = B.Batch(lats)
     stream = lats[0].stream
@@ -299,6 +310,7 @@ def run_batch(args):
             "workload": "batched_sweep_64runs", "runs": len(wls), "lattice_nodes": n_lat,
             "membrane_nodes": n_mem, "storage": args.storage,
             "run_sizes": sorted({w.nx for w in wls}), "delta_widths": sorted({w.m for w in wls}),
+            "stencil_box": args.stencil_box,
         },
         "unbatched_mlups": round(mlups_single, 1),
         "batched_speedup": round(mlups / mlups_single, 3),

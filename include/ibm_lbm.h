@@ -112,6 +112,17 @@ extern "C" {
                                   used when nx / 4 divides 64; default 23);
                                   results are identical, only the speed
                                   differs                                    */
+#define IBM_OPT_STENCIL_BOX 6  /* bit 0: spreading, bit 1: interpolation of
+                                  the per-node kernels go through an LDS box
+                                  spanning the stencils of each block's
+                                  nodes (overlapping stencils are summed,
+                                  or their lattice velocities evaluated,
+                                  once per lattice node).  Default, set when
+                                  the membrane is attached unless chosen
+                                  before: 1 (box spreading) when the
+                                  membrane makes at least 256 blocks of
+                                  work, else 0.  Results agree to FP32
+                                  rounding (see also ibm_autotune)          */
 #define IBM_OPT_CHUNK_NODES 5  /* spreading and interpolation work on chunks
                                   of this many consecutive membrane nodes of
                                   one capsule (16, 32, 64, 128 or 256),
@@ -207,6 +218,15 @@ int ibm_synchronize(ibm_lattice *lat);
 
 /* Set an option IBM_OPT_* (see above). */
 int ibm_set_option(ibm_lattice *lat, int option, int value);
+
+/* Choose the fastest collide-stream form (IBM_OPT_LBM_VARIANT) and, with
+ * capsules, stencil-box mode (IBM_OPT_STENCIL_BOX) by timing whole steps of
+ * this lattice with HIP events: after 4 x steps_per_trial settling steps,
+ * each candidate runs 16 steps and is then timed twice over steps_per_trial
+ * steps (rounded up to a multiple of 16), keeping the better time.  The run
+ * advances by all these steps (the candidates compute the same update, to
+ * FP32 rounding).  chosen (nullable) receives {variant, box mode}.  Waits. */
+int ibm_autotune(ibm_lattice *lat, int steps_per_trial, int *chosen);
 
 /* Run n timesteps with plain launches and HIP events between the kernels of
  * every step; ms_per_phase[IBM_N_PHASES] receives the mean duration of each

@@ -28,7 +28,7 @@ ERRORS = {
 STORAGE = {"fp32": 0, "fp16": 1}
 FIELD_POPS, FIELD_RHO, FIELD_U, FIELD_FORCE = 0, 1, 2, 3
 OPT_GRAPH, OPT_EQUILIBRIUM, OPT_ADVECTION, OPT_RECENTER, OPT_LBM_VARIANT = 0, 1, 2, 3, 4
-OPT_CHUNK_NODES = 5
+OPT_CHUNK_NODES, OPT_STENCIL_BOX = 5, 6
 PHASES = ("forces", "spread", "lbm", "interp")
 OBS_FIELDS = ("V", "cx", "cy", "cz", "D", "theta", "ra", "rb", "rc", "area",
               "Ixx", "Iyy", "Izz", "Ixy", "Ixz", "Iyz")
@@ -65,6 +65,7 @@ def _load():
         "ibm_synchronize": ([v], i),
         "ibm_set_option": ([v, i, i], i),
         "ibm_profile_step": ([v, i64, v], i),
+        "ibm_autotune": ([v, i, v], i),
         "ibm_destroy": ([v], i),
         "ibm_last_error": ([], ctypes.c_char_p),
         "ibm_icosphere_size": ([i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
@@ -194,6 +195,13 @@ class Lattice:
         out = np.zeros(4)
         _check(lib.ibm_profile_step(self._h, int(n), _ptr(out)))
         return dict(zip(PHASES, out.tolist()))
+
+    def autotune(self, steps_per_trial: int = 64) -> dict:
+        """Pick the fastest kernel forms by timing real steps (the run
+        advances by them)."""
+        out = np.zeros(2, dtype=np.int32)
+        _check(lib.ibm_autotune(self._h, int(steps_per_trial), _ptr(out)))
+        return {"lbm_variant": int(out[0]), "stencil_box": int(out[1])}
 
     # -- I/O -----------------------------------------------------------------
     def _field(self, what: int, comps: int):

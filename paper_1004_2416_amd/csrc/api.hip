@@ -47,6 +47,8 @@ constexpr int GRAPH_STEPS = 16;
 
 struct LatticeLayout {
   long long N, S;
+  int gsh;             // log2 of the rows per population group
+  long long pop_elems;  // elements of one population buffer
   int tnx, tny, tnz;
   size_t off_ctrl, off_stamp[2], off_g[2], off_f[2], total;
 };
@@ -55,6 +57,13 @@ LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
   LatticeLayout l{};
   l.N = (long long)nx * ny * nz;
   l.S = (long long)round_up((size_t)l.N, 64);
+  // rows per group: the smallest power of two (up to 8) whose group holds at
+  // least 128 values per population, so short rows still fill cache lines
+  l.gsh = 0;
+  while (l.gsh < 3 && ((long long)nx << l.gsh) < 128) ++l.gsh;
+  const long long rows = (long long)ny * nz;
+  const long long g = 1LL << l.gsh;
+  l.pop_elems = (long long)ibm::Q * ((rows + g - 1) / g * g) * nx;
   l.tnx = (nx + ibm::TILE_X - 1) / ibm::TILE_X;
   l.tny = (ny + ibm::TILE_Y - 1) / ibm::TILE_Y;
   l.tnz = (nz + ibm::TILE_Z - 1) / ibm::TILE_Z;
@@ -73,7 +82,7 @@ LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
   }
   for (int k = 0; k < 2; ++k) {
     l.off_f[k] = off;
-    off += round_up((size_t)ibm::Q * l.S * es, ALIGN);
+    off += round_up((size_t)l.pop_elems * es, ALIGN);
   }
   l.total = off;
   return l;
@@ -137,6 +146,8 @@ struct ibm_lattice {
   // wavefront, else two nodes per thread, non-temporal, 128-thread blocks
   int use_graph = 1, eq_linear = 0, ab2 = 0, recenter_every = 64, lbm_variant = 16 | 7;
   int chunk_nodes = 0;  // membrane nodes per chunk of the coupling kernels (0: none)
+  int box_mode = 0;     // bit 0: spreading, bit 1: interpolation through per-block LDS boxes
+  bool box_set = false;  // box_mode chosen by the caller (else set with the membrane)
   bool have_prev_u = false;
   int64_t since_recenter = 0;
 
@@ -171,7 +182,7 @@ void enqueue_step(ibm_lattice *lat, hipStream_t s, int advect) {
   const int par = src;  // force field of this step's parity
   const bool tan = lat->has_tan;
   if (lat->has_mem) {
-    ibm::launch_spread(lat->L, lat->M, par, s);                          // 1, 2: F(t), f(X, t)
+    ibm::launch_spread(lat->L, lat->M, par, lat->box_mode & 1, s);       // 1, 2: F(t), f(X, t)
     if (tan) ibm::launch_tangent_spread(lat->L, lat->M, lat->T, par, s);
     ibm::launch_collide_stream(lat->L, lat->storage, src, par, true,     // 3: f_i(t+1)
                                lat->eq_linear != 0, lat->lbm_variant, s);
@@ -181,7 +192,7 @@ void enqueue_step(ibm_lattice *lat, hipStream_t s, int advect) {
       ibm::launch_tangent_interp(lat->L, lat->M, lat->T, src ^ 1, par, s);
     }
     ibm::launch_interp_advect(lat->L, lat->M, lat->storage, src ^ 1,     // 4, 5
-                              par, advect, s);
+                              par, advect, (lat->box_mode & 2) != 0, s);
   } else {
     ibm::launch_collide_stream(lat->L, lat->storage, src, par, false, lat->eq_linear != 0,
                                lat->lbm_variant, s);
@@ -349,7 +360,7 @@ struct ibm_batch {
   std::vector<char> image;  // host copy of the device tables last uploaded
   hipGraphExec_t gexec = nullptr;
   bool graph_valid = false;
-  int graph_advect = -1, graph_linear = -1;  // options the graph was captured with
+  int graph_advect = -1, graph_linear = -1, graph_box = -1;  // options the graph was captured with
 };
 
 namespace {
@@ -462,9 +473,9 @@ int batch_sync_tables(ibm_batch *b) {
 void enqueue_batch_step(ibm_batch *b, hipStream_t s, int advect) {
   const ibm_lattice *r0 = b->runs[0];
   const int src = (int)(r0->steps & 1), par = src;
-  ibm::launch_batch_spread(b->B, par, s);
+  ibm::launch_batch_spread(b->B, par, r0->box_mode & 1, s);
   ibm::launch_batch_collide_stream(b->B, r0->storage, src, par, r0->eq_linear != 0, s);
-  ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, s);
+  ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, (r0->box_mode & 2) != 0, s);
   for (ibm_lattice *lat : b->runs) {
     lat->steps += 1;
     lat->since_recenter += 1;
@@ -497,6 +508,7 @@ int batch_capture_graph(ibm_batch *b, int advect) {
   b->graph_valid = true;
   b->graph_advect = advect;
   b->graph_linear = b->runs[0]->eq_linear;
+  b->graph_box = b->runs[0]->box_mode;
   return IBM_OK;
 }
 
@@ -547,6 +559,7 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
   L.tny = lat->lay.tny;
   L.tnz = lat->lay.tnz;
   L.S = lat->lay.S;
+  L.gsh = lat->lay.gsh;
   for (int k = 0; k < 2; ++k) {
     L.f[k] = lat->base + lat->lay.off_f[k];
     L.g[k] = reinterpret_cast<float *>(lat->base + lat->lay.off_g[k]);
@@ -564,7 +577,7 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
   }
   reset_force_state(lat, lat->stream);
   for (int k = 0; k < 2; ++k) {
-    const size_t words = ((size_t)ibm::Q * lat->lay.S * (storage == IBM_STORAGE_FP16 ? 2 : 4)) / 4;
+    const size_t words = ((size_t)lat->lay.pop_elems * (storage == IBM_STORAGE_FP16 ? 2 : 4) + 3) / 4;
     ibm::launch_fill_u32(L.f[k], (long long)words, 0u, lat->stream);  // at rest: f_i = w_i
   }
   hipError_t e = hipGetLastError();
@@ -749,6 +762,12 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
     lat->has_mem = false;
     return rc;
   }
+  // Box spreading pays once there are enough blocks for atomic conflicts
+  // between overlapping stencils to dominate (measured: 256+ blocks).
+  if (!lat->box_set) {
+    const int gs = m == 2 ? ibm::group_size<2>() : (m == 3 ? ibm::group_size<3>() : ibm::group_size<4>());
+    lat->box_mode = (long long)nn * gs >= 256LL * 256 ? 1 : 0;
+  }
   // the force bookkeeping restarts with the membrane
   reset_force_state(lat, s);
   lat->have_prev_u = false;
@@ -880,6 +899,11 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
       if (value < 0 || value > 31) return fail(IBM_ERR_INVALID_ARG, "variant is 0..31");
       lat->lbm_variant = value;
       break;
+    case IBM_OPT_STENCIL_BOX:
+      if (value < 0 || value > 3) return fail(IBM_ERR_INVALID_ARG, "stencil box mode is 0..3");
+      lat->box_mode = value;
+      lat->box_set = true;
+      break;
     case IBM_OPT_CHUNK_NODES: {
       if (value != 0 && (value < ibm::CHUNK_MIN || value > ibm::CHUNK_MAX || (value & (value - 1))))
         return fail(IBM_ERR_INVALID_ARG, "chunk size is 0 or a power of two in 16..256");
@@ -897,6 +921,85 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
   return ok();
 }
 
+int ibm_autotune(ibm_lattice *lat, int steps_per_trial, int *chosen) {
+  if (!lat) return fail(IBM_ERR_INVALID_ARG, "lat is NULL");
+  if (steps_per_trial < GRAPH_STEPS || steps_per_trial > 65536)
+    return fail(IBM_ERR_INVALID_ARG, "steps_per_trial must be in %d..65536", GRAPH_STEPS);
+  const int n = (steps_per_trial + GRAPH_STEPS - 1) / GRAPH_STEPS * GRAPH_STEPS;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  IBM_HIP(hipEventCreate(&e0));
+  IBM_HIP(hipEventCreate(&e1));
+  int rc = IBM_OK;
+  // the better of two timings of n steps, after a settling graph replay
+  auto trial = [&](float &ms) -> int {
+    int r = ibm_step(lat, GRAPH_STEPS);
+    if (r) return r;
+    ms = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      IBM_HIP(hipEventRecord(e0, lat->stream));
+      r = ibm_step(lat, n);
+      if (r) return r;
+      IBM_HIP(hipEventRecord(e1, lat->stream));
+      IBM_HIP(hipEventSynchronize(e1));
+      float t = 0.0f;
+      IBM_HIP(hipEventElapsedTime(&t, e0, e1));
+      ms = std::min(ms, t);
+    }
+    return check_device(lat);
+  };
+  if (lat->steps & 1) rc = ibm_step(lat, 1);
+  if (!rc) rc = ibm_step(lat, 4 * n);  // clocks and caches settle before the first trial
+  // collide-stream form: the row-vector kernel where rows fit, and the
+  // per-node kernel with or without two nodes per thread, non-temporal
+  // accesses, 256- or 128-thread blocks
+  std::vector<int> cand;
+  const bool rows_ok = lat->nx % 4 == 0 && lat->nx / 4 <= 64 && 64 % (lat->nx / 4) == 0;
+  if (rows_ok) cand.push_back(16);
+  for (int nt : {2, 0})
+    for (int v2 : {1, 0})
+      for (int thr : {4, 0})
+        if (!(v2 && lat->nx % 2)) cand.push_back(nt | v2 | thr);
+  int best_v = lat->lbm_variant, best_b = lat->box_mode;
+  float best = 1e30f;
+  for (int v : cand) {
+    if (rc) break;
+    lat->lbm_variant = v;
+    invalidate_graph(lat);
+    float ms = 0.0f;
+    rc = trial(ms);
+    if (!rc && ms < best) {
+      best = ms;
+      best_v = v;
+    }
+  }
+  lat->lbm_variant = best_v;
+  invalidate_graph(lat);
+  if (!rc && lat->has_mem && lat->chunk_nodes == 0) {
+    best = 1e30f;
+    for (int bm = 0; bm < 4 && !rc; ++bm) {
+      lat->box_mode = bm;
+      invalidate_graph(lat);
+      float ms = 0.0f;
+      rc = trial(ms);
+      if (!rc && ms < best) {
+        best = ms;
+        best_b = bm;
+      }
+    }
+    lat->box_mode = best_b;
+    lat->box_set = true;
+    invalidate_graph(lat);
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (chosen) {
+    chosen[0] = lat->lbm_variant;
+    chosen[1] = lat->box_mode;
+  }
+  return ok();
+}
+
 int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase) {
   if (!lat || !ms_per_phase) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
   if (lat->has_tan) return fail(IBM_ERR_BAD_STATE, "detach the tangent before profiling");
@@ -911,12 +1014,13 @@ int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase) {
     IBM_HIP(hipEventRecord(e[0], s));
     if (lat->has_mem) {
       IBM_HIP(hipEventRecord(e[1], s));  // the forces are formed by the spreading kernel
-      ibm::launch_spread(lat->L, lat->M, par, s);
+      ibm::launch_spread(lat->L, lat->M, par, lat->box_mode & 1, s);
       IBM_HIP(hipEventRecord(e[2], s));
       ibm::launch_collide_stream(lat->L, lat->storage, src, par, true, lat->eq_linear != 0,
                                  lat->lbm_variant, s);
       IBM_HIP(hipEventRecord(e[3], s));
-      ibm::launch_interp_advect(lat->L, lat->M, lat->storage, src ^ 1, par, advect_mode(lat), s);
+      ibm::launch_interp_advect(lat->L, lat->M, lat->storage, src ^ 1, par, advect_mode(lat),
+                                (lat->box_mode & 2) != 0, s);
       IBM_HIP(hipEventRecord(e[4], s));
       if (lat->ab2) lat->have_prev_u = true;
     } else {
@@ -1149,7 +1253,8 @@ int ibm_batch_step(ibm_batch *b, int64_t n) {
     const int advect = (r0->ab2 && prev) ? 1 : 0;
     const bool graph_ok = (r0->steps & 1) == 0 && n >= GRAPH_STEPS && room && (!r0->ab2 || prev);
     if (graph_ok) {
-      if (!b->graph_valid || b->graph_advect != advect || b->graph_linear != r0->eq_linear) {
+      if (!b->graph_valid || b->graph_advect != advect || b->graph_linear != r0->eq_linear ||
+          b->graph_box != r0->box_mode) {
         rc = batch_capture_graph(b, advect);
         if (rc) return rc;
       }
@@ -1190,11 +1295,11 @@ int ibm_batch_profile_step(ibm_batch *b, int64_t n, double *ms_per_phase) {
     const int src = (int)(r0->steps & 1), par = src;
     const int advect = (r0->ab2 && batch_prev_u(b)) ? 1 : 0;
     IBM_HIP(hipEventRecord(e[0], s));
-    ibm::launch_batch_spread(b->B, par, s);
+    ibm::launch_batch_spread(b->B, par, r0->box_mode & 1, s);
     IBM_HIP(hipEventRecord(e[1], s));
     ibm::launch_batch_collide_stream(b->B, r0->storage, src, par, r0->eq_linear != 0, s);
     IBM_HIP(hipEventRecord(e[2], s));
-    ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, s);
+    ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, (r0->box_mode & 2) != 0, s);
     IBM_HIP(hipEventRecord(e[3], s));
     for (ibm_lattice *lat : b->runs) {
       lat->steps += 1;

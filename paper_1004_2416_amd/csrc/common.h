@@ -53,7 +53,8 @@ struct LatDev {
   int nx, ny, nz;
   int tnx, tny, tnz;      // tile grid
   long long S;            // stride between force-density components (elements)
-  void *f[2];             // population buffers (float or __half), [ny nz][19][nx]
+  int gsh;                // log2 of the x rows per population group
+  void *f[2];             // population buffers (float or __half), see pidx
   float *g[2];            // force density [3][S] of even and odd steps
   int *stamp[2];          // per-tile step stamps of the two fields
   Ctrl *ctrl;
@@ -169,12 +170,14 @@ __device__ __forceinline__ int stencil_lo(float p) {
   else return (int)floorf(p);
 }
 
-// Populations are stored row-interleaved, [row][i][x] with row = z ny + y: the
-// 19 values of one x row lie in 19 consecutive runs of nx values, so a row's
-// update reads and writes a few contiguous kilobytes instead of 19 arrays
-// that are megabytes apart.
+// Populations are stored interleaved by groups of G = 2^gsh x rows
+// (row = z ny + y): [row / G][i][row % G][x].  Each population of a group is
+// one contiguous run of G nx values (G chosen so that G nx >= 128 where
+// possible), so an update reads and writes a few contiguous kilobytes per
+// group instead of 19 arrays that are megabytes apart.
 __device__ __forceinline__ long long pidx(const LatDev &L, int i, long long row, int x) {
-  return (row * Q + i) * (long long)L.nx + x;
+  const long long g = row >> L.gsh, r = row - (g << L.gsh);
+  return (((g * Q + i) << L.gsh) + r) * (long long)L.nx + x;
 }
 
 __device__ __forceinline__ int wrap_mod(int a, int n) {

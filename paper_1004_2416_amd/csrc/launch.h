@@ -25,13 +25,14 @@ void launch_batch_collide_stream(const BatchDev &B, int fp16, int src, int par, 
 
 // membrane_kernels.hip
 void launch_reference_geometry(const MemDev &M, Ctrl *ctrl, hipStream_t s);
-void launch_spread(const LatDev &L, const MemDev &M, int par, hipStream_t s);
+// box: sum overlapping stencils of each block in an LDS box first
+void launch_spread(const LatDev &L, const MemDev &M, int par, bool box, hipStream_t s);
 // advect: 0 Euler, 1 Adams-Bashforth with the stored velocity of the previous step
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
-                          int advect, hipStream_t s);
+                          int advect, bool box, hipStream_t s);
 void launch_recenter(const MemDev &M, hipStream_t s);
-void launch_batch_spread(const BatchDev &B, int par, hipStream_t s);
-void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect,
+void launch_batch_spread(const BatchDev &B, int par, bool box, hipStream_t s);
+void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect, bool box,
                          hipStream_t s);
 void launch_observables(const MemDev &M, Ctrl *ctrl, hipStream_t s);
 // observables of the mesh x + h dx into obs [n_caps][16]

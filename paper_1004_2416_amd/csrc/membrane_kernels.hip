@@ -193,63 +193,167 @@ __device__ __forceinline__ float group_sum(float v) {
 // F_n delta(X - x_n) to one stencil node X of the force field of parity `par`
 // (FP32 atomics; the field starts at zero, see the collide-stream kernel) and
 // stamps X's tile with the step number.
-template <int M>
-__device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, int par, int blk) {
+// The block's M^3 contributions of 256 / GS membrane nodes are first summed
+// in an LDS box spanning their stencils (when it has at most SPREAD_BOX
+// lattice nodes), then every touched box node is added to the global field
+// once per component, consecutive threads on consecutive x.  Overlapping
+// stencils of neighbouring nodes would otherwise send many atomics to the
+// same addresses at once, which serialises them; spread over the box, the
+// adds are distinct and coalesced.
+// Bounding box of the block's nonzero-weight stencil nodes (unwrapped lattice
+// coordinates): wave-level min / max with shuffles, then across the block's
+// waves in LDS.  All threads of the block must call it.
+struct Box {
+  int x0, y0, z0, ex, ey, ez, V;
+  bool fits;
+};
+
+__device__ __forceinline__ Box block_box(int gx, int gy, int gz, bool has, int capacity, int *bb) {
+  int v[6] = {has ? gx : 0x7fffffff, has ? gy : 0x7fffffff, has ? gz : 0x7fffffff,
+              has ? gx : -0x7fffffff, has ? gy : -0x7fffffff, has ? gz : -0x7fffffff};
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      v[k] = min(v[k], __shfl_xor(v[k], off, 64));
+      v[k + 3] = max(v[k + 3], __shfl_xor(v[k + 3], off, 64));
+    }
+  }
+  if (threadIdx.x < 6) bb[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      atomicMin(&bb[k], v[k]);
+      atomicMax(&bb[k + 3], v[k + 3]);
+    }
+  }
+  __syncthreads();
+  Box b;
+  b.x0 = bb[0];
+  b.y0 = bb[1];
+  b.z0 = bb[2];
+  b.ex = bb[3] - bb[0] + 1;
+  b.ey = bb[4] - bb[1] + 1;
+  b.ez = bb[5] - bb[2] + 1;
+  b.fits = bb[0] <= bb[3] && (long long)b.ex * b.ey * b.ez <= capacity;
+  b.V = b.fits ? b.ex * b.ey * b.ez : 0;
+  return b;
+}
+
+constexpr int SPREAD_BOX = 1024;
+struct SpreadLDS {
+  float box[3][SPREAD_BOX];
+  int bb[6];
+};
+
+template <int M, bool BOX>
+__device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, int par, int blk,
+                                             SpreadLDS &sm) {
   constexpr int GS = group_size<M>();
   const int lane = threadIdx.x & (GS - 1);
   const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
-  if (node >= Mm.nn) return;  // whole groups leave together
+  const bool live = node < Mm.nn;  // whole groups alike
   // Eq. (forcefromenergy): F_n = -sum over the faces at n of d(A0 w_S)/dx_n,
   // one incident face per lane (each face is evaluated by each of its corners)
   float fx = 0.0f, fy = 0.0f, fz = 0.0f;
-  const int e0 = Mm.csr_off[node], e1 = Mm.csr_off[node + 1];
-  for (int e = e0 + lane; e < e1; e += GS) {
-    const int ent = Mm.csr_ent[e];
-    const int j = ent >> 2, corner = ent & 3;
-    const int4 tj = Mm.tri[j];
-    const float4 rp = Mm.ref_p[j], gh = Mm.ref_ghi[j], gl = Mm.ref_glo[j];
-    const float4 mod = Mm.moduli[tj.w];
-    const FaceRef R{rp.x, rp.y, rp.z, rp.w, gh.x, gh.y, gh.z, gl.x, gl.y, gl.z};
-    float3 ga, gb, gc;
-    bool deg;
-    skalak_face_grad(Mm.x[tj.x], Mm.x[tj.y], Mm.x[tj.z], R, mod.x, mod.y, ga, gb, gc, deg);
-    if (deg) atomicOr(&L.ctrl->err, ERR_FACE);
-    const float3 g = corner == 0 ? ga : (corner == 1 ? gb : gc);
-    fx -= g.x;
-    fy -= g.y;
-    fz -= g.z;
+  if (live) {
+    const int e0 = Mm.csr_off[node], e1 = Mm.csr_off[node + 1];
+    for (int e = e0 + lane; e < e1; e += GS) {
+      const int ent = Mm.csr_ent[e];
+      const int j = ent >> 2, corner = ent & 3;
+      const int4 tj = Mm.tri[j];
+      const float4 rp = Mm.ref_p[j], gh = Mm.ref_ghi[j], gl = Mm.ref_glo[j];
+      const float4 mod = Mm.moduli[tj.w];
+      const FaceRef R{rp.x, rp.y, rp.z, rp.w, gh.x, gh.y, gh.z, gl.x, gl.y, gl.z};
+      float3 ga, gb, gc;
+      bool deg;
+      skalak_face_grad(Mm.x[tj.x], Mm.x[tj.y], Mm.x[tj.z], R, mod.x, mod.y, ga, gb, gc, deg);
+      if (deg) atomicOr(&L.ctrl->err, ERR_FACE);
+      const float3 g = corner == 0 ? ga : (corner == 1 ? gb : gc);
+      fx -= g.x;
+      fy -= g.y;
+      fz -= g.z;
+    }
   }
   fx = group_sum<GS>(fx);
   fy = group_sum<GS>(fy);
   fz = group_sum<GS>(fz);
-  if (lane == 0) Mm.F[node] = make_float4(fx, fy, fz, 0.0f);
-  if (lane >= M * M * M) return;
-  const int sx = lane % M, sy = (lane / M) % M, sz = lane / (M * M);
-  const float4 p = Mm.x[node];
-  const int lx = stencil_lo<M>(p.x) + sx;
-  const int ly = stencil_lo<M>(p.y) + sy;
-  const int lz = stencil_lo<M>(p.z) + sz;
-  const float w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
-  if (w == 0.0f) return;
-  const int4 o = Mm.origin[Mm.node_cap[node]];
-  const int Z = o.z + lz;
-  if (Z < 0 || Z >= L.nz) {
-    atomicOr(&L.ctrl->err, ERR_WALL);
+  if (live && lane == 0) Mm.F[node] = make_float4(fx, fy, fz, 0.0f);
+  // this lane's stencil node, in unwrapped lattice coordinates
+  int gx = 0, gy = 0, gz = 0;
+  float w = 0.0f;
+  if (live && lane < M * M * M) {
+    const float4 p = Mm.x[node];
+    const int lx = stencil_lo<M>(p.x) + lane % M;
+    const int ly = stencil_lo<M>(p.y) + (lane / M) % M;
+    const int lz = stencil_lo<M>(p.z) + lane / (M * M);
+    w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
+    const int4 o = Mm.origin[Mm.node_cap[node]];
+    gx = o.x + lx;
+    gy = o.y + ly;
+    gz = o.z + lz;
+    if (w != 0.0f && (gz < 0 || gz >= L.nz)) {
+      atomicOr(&L.ctrl->err, ERR_WALL);
+      w = 0.0f;
+    }
+  }
+  const bool has = w != 0.0f;
+  float *g = L.g[par];
+  const int step = L.ctrl->step;
+  if constexpr (!BOX) {
+    if (has) {
+      const int X = wrap_mod(gx, L.nx), Y = wrap_mod(gy, L.ny);
+      const long long n = ((long long)gz * L.ny + Y) * L.nx + X;
+      unsafeAtomicAdd(g + n, w * fx);
+      unsafeAtomicAdd(g + L.S + n, w * fy);
+      unsafeAtomicAdd(g + 2 * L.S + n, w * fz);
+      L.stamp[par][tile_of(L, X, Y, gz)] = step;
+    }
     return;
   }
-  const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
-  const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
-  float *g = L.g[par];
-  unsafeAtomicAdd(g + n, w * fx);
-  unsafeAtomicAdd(g + L.S + n, w * fy);
-  unsafeAtomicAdd(g + 2 * L.S + n, w * fz);
-  L.stamp[par][tile_of(L, X, Y, Z)] = L.ctrl->step;
+  const Box b = block_box(gx, gy, gz, has, SPREAD_BOX, sm.bb);
+  const bool fits = b.fits;
+  const int x0 = b.x0, y0 = b.y0, z0 = b.z0, ex = b.ex, ey = b.ey;
+  const int V = b.V;
+  for (int c = threadIdx.x; c < V; c += blockDim.x) sm.box[0][c] = sm.box[1][c] = sm.box[2][c] = 0.0f;
+  __syncthreads();
+  if (has) {
+    if (fits) {
+      const int c = ((gz - z0) * ey + (gy - y0)) * ex + (gx - x0);
+      atomicAdd(&sm.box[0][c], w * fx);
+      atomicAdd(&sm.box[1][c], w * fy);
+      atomicAdd(&sm.box[2][c], w * fz);
+    } else {
+      const int X = wrap_mod(gx, L.nx), Y = wrap_mod(gy, L.ny);
+      const long long n = ((long long)gz * L.ny + Y) * L.nx + X;
+      unsafeAtomicAdd(g + n, w * fx);
+      unsafeAtomicAdd(g + L.S + n, w * fy);
+      unsafeAtomicAdd(g + 2 * L.S + n, w * fz);
+      L.stamp[par][tile_of(L, X, Y, gz)] = step;
+    }
+  }
+  if (!fits) return;  // the whole block
+  __syncthreads();
+  // only in-range z received force (see above)
+  for (int c = threadIdx.x; c < V; c += blockDim.x) {
+    const float vx = sm.box[0][c], vy = sm.box[1][c], vz = sm.box[2][c];
+    if (vx == 0.0f && vy == 0.0f && vz == 0.0f) continue;
+    const int X = wrap_mod(x0 + c % ex, L.nx), Y = wrap_mod(y0 + (c / ex) % ey, L.ny);
+    const int Z = z0 + c / (ex * ey);
+    const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
+    if (vx != 0.0f) unsafeAtomicAdd(g + n, vx);
+    if (vy != 0.0f) unsafeAtomicAdd(g + L.S + n, vy);
+    if (vz != 0.0f) unsafeAtomicAdd(g + 2 * L.S + n, vz);
+    L.stamp[par][tile_of(L, X, Y, Z)] = step;
+  }
 }
 
-template <int M>
+template <int M, bool BOX>
 __global__ __launch_bounds__(256) void k_spread(LatDev L, MemDev Mm, int par, int nblocks) {
+  __shared__ SpreadLDS sm;
   const int blk = xcd_block(nblocks);
-  if (blk >= 0) spread_lanes<M>(L, Mm, par, blk);
+  if (blk >= 0) spread_lanes<M, BOX>(L, Mm, par, blk, sm);
 }
 
 // ---- chunked spreading ----------------------------------------------------------
@@ -395,7 +499,7 @@ __global__ __launch_bounds__(256) void k_spread_chunks(LatDev L, MemDev Mm, int 
   }
 }
 
-void launch_spread(const LatDev &L, const MemDev &M, int par, hipStream_t s) {
+void launch_spread(const LatDev &L, const MemDev &M, int par, bool box, hipStream_t s) {
   if (M.nn <= 0) return;
   if (M.n_chunks > 0) {
     const dim3 grid(xcd_grid(M.n_chunks)), block(256);
@@ -408,9 +512,15 @@ void launch_spread(const LatDev &L, const MemDev &M, int par, hipStream_t s) {
   const long long lanes = (long long)M.nn * gs;
   const int nblocks = (int)((lanes + 255) / 256);
   const dim3 grid(xcd_grid(nblocks)), block(256);
-  if (M.m == 2) k_spread<2><<<grid, block, 0, s>>>(L, M, par, nblocks);
-  else if (M.m == 3) k_spread<3><<<grid, block, 0, s>>>(L, M, par, nblocks);
-  else k_spread<4><<<grid, block, 0, s>>>(L, M, par, nblocks);
+#define IBM_LAUNCH_SPREAD(BX)                                                         \
+  do {                                                                                \
+    if (M.m == 2) k_spread<2, BX><<<grid, block, 0, s>>>(L, M, par, nblocks);         \
+    else if (M.m == 3) k_spread<3, BX><<<grid, block, 0, s>>>(L, M, par, nblocks);    \
+    else k_spread<4, BX><<<grid, block, 0, s>>>(L, M, par, nblocks);                  \
+  } while (0)
+  if (box) IBM_LAUNCH_SPREAD(true);
+  else IBM_LAUNCH_SPREAD(false);
+#undef IBM_LAUNCH_SPREAD
 }
 
 // ---- interpolation + advection, Eqs. (velocityinterpolation), (positionupdate)
@@ -428,75 +538,6 @@ __device__ __forceinline__ float ld_pop<float>(const float *p, long long idx, fl
 template <>
 __device__ __forceinline__ float ld_pop<__half>(const __half *p, long long idx, float inv_scale) {
   return __half2float(p[idx]) * inv_scale;
-}
-
-template <typename T, int M>
-__device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, int fsrc, int par,
-                                             int advect, int blk) {
-  constexpr int GS = group_size<M>();
-  const int lane = threadIdx.x & (GS - 1);
-  const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
-  if (node >= Mm.nn) return;  // whole groups leave together
-  float ux = 0.0f, uy = 0.0f, uz = 0.0f;
-  float4 p = Mm.x[node];
-  if (lane < M * M * M) {
-    const int sx = lane % M, sy = (lane / M) % M, sz = lane / (M * M);
-    const int lx = stencil_lo<M>(p.x) + sx;
-    const int ly = stencil_lo<M>(p.y) + sy;
-    const int lz = stencil_lo<M>(p.z) + sz;
-    const float w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
-    if (w != 0.0f) {
-      const int4 o = Mm.origin[Mm.node_cap[node]];
-      const int Z = o.z + lz;
-      if (Z < 0 || Z >= L.nz) {
-        atomicOr(&L.ctrl->err, ERR_WALL);
-      } else {
-        const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
-        const long long row = (long long)Z * L.ny + Y;
-        const long long n = row * L.nx + X;
-        const T *f = static_cast<const T *>(L.f[fsrc]);
-        float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-          const float d = ld_pop<T>(f, pidx(L, i, row, X), 1.0f / L.h_scale[i]);
-          drho += d;
-          if (cx(i)) jx += cx(i) * d;
-          if (cy(i)) jy += cy(i) * d;
-          if (cz(i)) jz += cz(i) * d;
-        }
-        const float *g = L.g[par];
-        const float inv_rho = 1.0f / (1.0f + drho);
-        ux = w * ((jx + 0.5f * g[n]) * inv_rho);
-        uy = w * ((jy + 0.5f * g[L.S + n]) * inv_rho);
-        uz = w * ((jz + 0.5f * g[2 * L.S + n]) * inv_rho);
-      }
-    }
-  }
-  ux = group_sum<GS>(ux);
-  uy = group_sum<GS>(uy);
-  uz = group_sum<GS>(uz);
-  if (lane == 0) {
-    if (advect == 1) {
-      const float4 up = Mm.u[node];
-      p.x += 1.5f * ux - 0.5f * up.x;
-      p.y += 1.5f * uy - 0.5f * up.y;
-      p.z += 1.5f * uz - 0.5f * up.z;
-    } else {
-      p.x += ux;
-      p.y += uy;
-      p.z += uz;
-    }
-    Mm.u[node] = make_float4(ux, uy, uz, 0.0f);
-    Mm.x[node] = p;
-  }
-}
-
-template <typename T, int M>
-__global__ __launch_bounds__(256) void k_interp_advect(LatDev L, MemDev Mm, int fsrc, int par,
-                                                       int advect, int nblocks) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
-  const int blk = xcd_block(nblocks);
-  if (blk >= 0) interp_lanes<T, M>(L, Mm, fsrc, par, advect, blk);
 }
 
 // Lattice velocity u(X, t+1) of Eq. (velocityinterpolation) at lattice node n.
@@ -517,6 +558,106 @@ __device__ __forceinline__ float3 lattice_velocity(const LatDev &L, const T *f, 
   const float inv_rho = 1.0f / (1.0f + drho);
   return make_float3((jx + 0.5f * g[n]) * inv_rho, (jy + 0.5f * g[L.S + n]) * inv_rho,
                      (jz + 0.5f * g[2 * L.S + n]) * inv_rho);
+}
+
+// The lattice velocity is evaluated once per lattice node of the block's
+// stencil box that a stencil touches with nonzero weight (consecutive threads
+// on consecutive x: coalesced population reads; neighbouring nodes share most
+// of their stencil nodes) and the lanes read it from LDS.  Blocks whose box
+// has more than INTERP_BOX nodes read the populations per lane.
+constexpr int INTERP_BOX = 1024;
+struct InterpLDS {
+  float box[3][INTERP_BOX];
+  unsigned char mark[INTERP_BOX];
+  int bb[6];
+};
+
+template <typename T, int M, bool BOX>
+__device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, int fsrc, int par,
+                                             int advect, int blk, InterpLDS &sm) {
+  constexpr int GS = group_size<M>();
+  const int lane = threadIdx.x & (GS - 1);
+  const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
+  const bool live = node < Mm.nn;  // whole groups alike
+  float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  int gx = 0, gy = 0, gz = 0;
+  float w = 0.0f;
+  if (live) {
+    p = Mm.x[node];
+    if (lane < M * M * M) {
+      const int lx = stencil_lo<M>(p.x) + lane % M;
+      const int ly = stencil_lo<M>(p.y) + (lane / M) % M;
+      const int lz = stencil_lo<M>(p.z) + lane / (M * M);
+      w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
+      const int4 o = Mm.origin[Mm.node_cap[node]];
+      gx = o.x + lx;
+      gy = o.y + ly;
+      gz = o.z + lz;
+      if (w != 0.0f && (gz < 0 || gz >= L.nz)) {
+        atomicOr(&L.ctrl->err, ERR_WALL);
+        w = 0.0f;
+      }
+    }
+  }
+  const bool has = w != 0.0f;
+  const T *f = static_cast<const T *>(L.f[fsrc]);
+  const float *g = L.g[par];
+  Box b{0, 0, 0, 1, 1, 1, 0, false};
+  if constexpr (BOX) b = block_box(gx, gy, gz, has, INTERP_BOX, sm.bb);
+  const bool fits = b.fits;
+  const int x0 = b.x0, y0 = b.y0, z0 = b.z0, ex = b.ex, ey = b.ey;
+  const int V = b.V;
+  const int cell = ((gz - z0) * ey + (gy - y0)) * ex + (gx - x0);
+  if constexpr (BOX) {
+    for (int c = threadIdx.x; c < V; c += blockDim.x) sm.mark[c] = 0;
+    __syncthreads();
+    if (has && fits) sm.mark[cell] = 1;
+    __syncthreads();
+    for (int c = threadIdx.x; c < V; c += blockDim.x) {
+      if (!sm.mark[c]) continue;
+      const float3 u = lattice_velocity<T>(L, f, g, wrap_mod(x0 + c % ex, L.nx),
+                                           wrap_mod(y0 + (c / ex) % ey, L.ny), z0 + c / (ex * ey));
+      sm.box[0][c] = u.x;
+      sm.box[1][c] = u.y;
+      sm.box[2][c] = u.z;
+    }
+    __syncthreads();
+  }
+  float ux = 0.0f, uy = 0.0f, uz = 0.0f;
+  if (has) {
+    float3 u;
+    if (fits) u = make_float3(sm.box[0][cell], sm.box[1][cell], sm.box[2][cell]);
+    else u = lattice_velocity<T>(L, f, g, wrap_mod(gx, L.nx), wrap_mod(gy, L.ny), gz);
+    ux = w * u.x;
+    uy = w * u.y;
+    uz = w * u.z;
+  }
+  ux = group_sum<GS>(ux);
+  uy = group_sum<GS>(uy);
+  uz = group_sum<GS>(uz);
+  if (live && lane == 0) {
+    if (advect == 1) {
+      const float4 up = Mm.u[node];
+      p.x += 1.5f * ux - 0.5f * up.x;
+      p.y += 1.5f * uy - 0.5f * up.y;
+      p.z += 1.5f * uz - 0.5f * up.z;
+    } else {
+      p.x += ux;
+      p.y += uy;
+      p.z += uz;
+    }
+    Mm.u[node] = make_float4(ux, uy, uz, 0.0f);
+    Mm.x[node] = p;
+  }
+}
+
+template <typename T, int M, bool BOX>
+__global__ __launch_bounds__(256) void k_interp_advect(LatDev L, MemDev Mm, int fsrc, int par,
+                                                       int advect, int nblocks) {
+  __shared__ InterpLDS sm;
+  if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
+  const int blk = xcd_block(nblocks);
+  if (blk >= 0) interp_lanes<T, M, BOX>(L, Mm, fsrc, par, advect, blk, sm);
 }
 
 // ---- chunked interpolation + advection ----------------------------------------
@@ -632,7 +773,7 @@ __global__ __launch_bounds__(256) void k_interp_chunks(LatDev L, MemDev Mm, int 
 }
 
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
-                          int advect, hipStream_t s) {
+                          int advect, bool box, hipStream_t s) {
   if (M.nn <= 0) return;
   if (M.n_chunks > 0) {
     const dim3 grid(xcd_grid(M.n_chunks)), block(256);
@@ -651,14 +792,19 @@ void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, 
   const long long lanes = (long long)M.nn * gs;
   const int nblocks = (int)((lanes + 255) / 256);
   const dim3 grid(xcd_grid(nblocks)), block(256);
-#define IBM_LAUNCH_INTERP(T)                                                                   \
-  do {                                                                                         \
-    if (M.m == 2) k_interp_advect<T, 2><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks); \
-    else if (M.m == 3) k_interp_advect<T, 3><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks); \
-    else k_interp_advect<T, 4><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);     \
+#define IBM_LAUNCH_INTERP(T, BX)                                                                 \
+  do {                                                                                           \
+    if (M.m == 2) k_interp_advect<T, 2, BX><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks); \
+    else if (M.m == 3) k_interp_advect<T, 3, BX><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks); \
+    else k_interp_advect<T, 4, BX><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);     \
   } while (0)
-  if (fp16) IBM_LAUNCH_INTERP(__half);
-  else IBM_LAUNCH_INTERP(float);
+  if (fp16) {
+    if (box) IBM_LAUNCH_INTERP(__half, true);
+    else IBM_LAUNCH_INTERP(__half, false);
+  } else {
+    if (box) IBM_LAUNCH_INTERP(float, true);
+    else IBM_LAUNCH_INTERP(float, false);
+  }
 #undef IBM_LAUNCH_INTERP
 }
 
@@ -820,21 +966,24 @@ void launch_tangent_interp(const LatDev &L, const MemDev &M, const TanDev &T, in
 // runs, one launch each; a block works for run items[b].x as block items[b].y of that
 // run's own launch (so a block never mixes runs).  The delta width is chosen
 // per block.
+template <bool BOX>
 __global__ __launch_bounds__(256) void k_batch_spread(BatchDev B, int par) {
+  __shared__ SpreadLDS sm;
   const int b = xcd_block(B.n_node_items);
   if (b < 0) return;
   const int2 it = B.node_items[b];
   const LatDev &L = B.lat[it.x];
   const MemDev &Mm = B.mem[it.x];
   const int m = Mm.m;
-  if (m == 2) spread_lanes<2>(L, Mm, par, it.y);
-  else if (m == 3) spread_lanes<3>(L, Mm, par, it.y);
-  else spread_lanes<4>(L, Mm, par, it.y);
+  if (m == 2) spread_lanes<2, BOX>(L, Mm, par, it.y, sm);
+  else if (m == 3) spread_lanes<3, BOX>(L, Mm, par, it.y, sm);
+  else spread_lanes<4, BOX>(L, Mm, par, it.y, sm);
 }
 
 // The first block of each run advances that run's device step counter.
-template <typename T>
+template <typename T, bool BOX>
 __global__ __launch_bounds__(256) void k_batch_interp(BatchDev B, int fsrc, int par, int advect) {
+  __shared__ InterpLDS sm;
   const int b = xcd_block(B.n_node_items);
   if (b < 0) return;
   const int2 it = B.node_items[b];
@@ -842,22 +991,29 @@ __global__ __launch_bounds__(256) void k_batch_interp(BatchDev B, int fsrc, int 
   const MemDev &Mm = B.mem[it.x];
   if (it.y == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
   const int m = Mm.m;
-  if (m == 2) interp_lanes<T, 2>(L, Mm, fsrc, par, advect, it.y);
-  else if (m == 3) interp_lanes<T, 3>(L, Mm, fsrc, par, advect, it.y);
-  else interp_lanes<T, 4>(L, Mm, fsrc, par, advect, it.y);
+  if (m == 2) interp_lanes<T, 2, BOX>(L, Mm, fsrc, par, advect, it.y, sm);
+  else if (m == 3) interp_lanes<T, 3, BOX>(L, Mm, fsrc, par, advect, it.y, sm);
+  else interp_lanes<T, 4, BOX>(L, Mm, fsrc, par, advect, it.y, sm);
 }
 
-void launch_batch_spread(const BatchDev &B, int par, hipStream_t s) {
+void launch_batch_spread(const BatchDev &B, int par, bool box, hipStream_t s) {
   if (B.n_node_items <= 0) return;
-  k_batch_spread<<<dim3(xcd_grid(B.n_node_items)), dim3(256), 0, s>>>(B, par);
+  const dim3 grid(xcd_grid(B.n_node_items)), block(256);
+  if (box) k_batch_spread<true><<<grid, block, 0, s>>>(B, par);
+  else k_batch_spread<false><<<grid, block, 0, s>>>(B, par);
 }
 
-void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect,
+void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect, bool box,
                          hipStream_t s) {
   if (B.n_node_items <= 0) return;
   const dim3 grid(xcd_grid(B.n_node_items)), block(256);
-  if (fp16) k_batch_interp<__half><<<grid, block, 0, s>>>(B, fsrc, par, advect);
-  else k_batch_interp<float><<<grid, block, 0, s>>>(B, fsrc, par, advect);
+  if (fp16) {
+    if (box) k_batch_interp<__half, true><<<grid, block, 0, s>>>(B, fsrc, par, advect);
+    else k_batch_interp<__half, false><<<grid, block, 0, s>>>(B, fsrc, par, advect);
+  } else {
+    if (box) k_batch_interp<float, true><<<grid, block, 0, s>>>(B, fsrc, par, advect);
+    else k_batch_interp<float, false><<<grid, block, 0, s>>>(B, fsrc, par, advect);
+  }
 }
 
 // ---- capsule frame re-centring -------------------------------------------------

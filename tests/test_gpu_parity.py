@@ -90,10 +90,12 @@ def deformed_state(c, steps):
     return rep_populations(sim.f), rep_positions(sim.x, c.node_counts)
 
 
-def compare_one_step(B, c, f_s, x_s, tol_f=1e-5, tol_m=1e-5, chunk=None):
+def compare_one_step(B, c, f_s, x_s, tol_f=1e-5, tol_m=1e-5, chunk=None, opts=None):
     lat = c.gpu(graph=False)
     if chunk is not None:
         lat.set_option(B.OPT_CHUNK_NODES, chunk)
+    for k, v in (opts or {}).items():
+        lat.set_option(k, v)
     lat.set_populations(f_s)
     lat.set_mesh(x_s)
     lat.step(1)
@@ -180,15 +182,45 @@ def test_coupling_chunk_sizes(B, chunk):
     compare_one_step(B, c, f_s, x_s, chunk=chunk)
 
 
-@pytest.mark.parametrize("chunk", [16, 256])
+@pytest.mark.parametrize("m", [2, 3, 4])
+@pytest.mark.parametrize("box", [1, 2, 3])
+def test_stencil_box_modes(B, m, box):
+    """Spreading and/or interpolation through per-block LDS boxes match the
+    oracle like the direct per-lane form."""
+    say("stencil box", box, "m", m)
+    c = small_case(n=(40, 36, 30), m=m, level=3, r=8.0, ca=0.02, uw=0.03)
+    f_s, x_s = deformed_state(c, 10)
+    lat_opts = {B.OPT_STENCIL_BOX: box}
+    compare_one_step(B, c, f_s, x_s, opts=lat_opts)
+
+
+def test_autotune_keeps_the_run_on_the_oracle(B):
+    """The autotuner times real steps of every candidate; afterwards the run
+    is where the oracle is after the same number of steps."""
+    c = small_case(m=3, ca=0.02, uw=0.03)
+    lat = c.gpu(graph=True)
+    chosen = lat.autotune(16)
+    n = lat.steps
+    say("  autotune chose", chosen, "after", n, "steps")
+    assert 0 <= chosen["lbm_variant"] < 32 and 0 <= chosen["stencil_box"] < 4
+    sim = c.oracle()
+    assert sim.run(n) == 0
+    f = lat.populations().cpu().numpy()
+    xg = lat.mesh()[0].cpu().numpy()
+    lat.close()
+    assert rel_err(f, sim.f) < 1e-5
+    assert np.max(np.abs(xg - sim.x)) < 1e-3
+
+
+@pytest.mark.parametrize("chunk", [0, 16, 256])
 def test_coupling_chunk_box_too_large(B, chunk):
-    """A coarse capsule (42 nodes, radius 14): the stencil box of every chunk
-    exceeds the on-chip capacity, so the chunks add to and read the global
-    fields directly."""
+    """A coarse capsule (42 nodes, radius 14): the stencil box of every block
+    (chunk 0) or chunk exceeds the on-chip capacity, so the contributions go
+    to and come from the global fields directly."""
     say("oversized chunk boxes", chunk)
     c = small_case(n=(40, 40, 40), m=3, level=1, r=14.0, ca=0.02, uw=0.03)
     f_s, x_s = deformed_state(c, 10)
-    compare_one_step(B, c, f_s, x_s, chunk=chunk)
+    compare_one_step(B, c, f_s, x_s, chunk=chunk, opts={B.OPT_STENCIL_BOX: 3})
 
 
 def test_undeformed_capsule_has_zero_force(B):
