@@ -145,6 +145,8 @@ def main():
                          "-1: library default)")
     ap.add_argument("--stencil-box", type=int, default=-1,
                     help="IBM_OPT_STENCIL_BOX bits (-1: library default)")
+    ap.add_argument("--sensitivity", action="store_true",
+                    help="time the tangent-model gradient of D instead of the step")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time its kernel forms during warm-up")
     ap.add_argument("--lbm-variant", type=int, default=-1,
@@ -166,6 +168,9 @@ def main():
 
     if args.workload == "c4":
         run_batch(args)
+        return
+    if args.sensitivity:
+        run_sensitivity(args)
         return
 
     import torch
@@ -234,6 +239,51 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+def run_sensitivity(args):
+    """Seconds for the gradient of the Taylor deformation D(T) with respect to
+    (k_s, C, gamma) by the tangent model (one primal + tangent run per
+    parameter, T = --steps), next to the FP64 oracle's six central-difference
+    runs (timed on a bounded sample of oracle steps and scaled to 6 T)."""
+    import numpy as np
+    import torch
+    from paper_1004_2416_amd import binding as B
+    from paper_1004_2416_amd import workloads as W
+
+    wl = W.config(args.workload)
+    cap = wl.capsules[0]
+    mesh = B.icosphere(cap.level, cap.r, cap.center)
+    gamma = 2.0 * wl.u_w / wl.nz
+    dirs = {"ks": ([1.0], [cap.ka / cap.ks], 0.0, False, cap.ks),
+            "C": ([0.0], [cap.ks], 0.0, False, cap.ka / cap.ks),
+            "gamma": ([0.0], [0.0], wl.nz / 2.0, True, gamma)}
+    grads, t_total = {}, 0.0
+    for which, (dks, dka, duw, prof, p) in dirs.items():
+        lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau)
+        lat.set_shear(wl.u_w, init_profile=True)
+        lat.add_capsules([mesh], [cap.ks], [cap.ka], wl.m)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lat.attach_tangent(dks, dka, duw, init_profile=prof)
+        lat.step(args.steps)
+        grads[which] = float(lat.tangent_observables(1e-6 * p)[0, 4])
+        t_total += time.perf_counter() - t0
+        D = float(lat.observables()[0, 4])
+        lat.close()
+    out = {"metric": "seconds per gradient of D(T) w.r.t. (k_s, C, gamma)", "value": round(t_total, 3),
+           "unit": "s", "n_gpus": 1, "steps": args.steps, "higher_is_better": False,
+           "dtype": "f32", "data": "synthetic",
+           "config": {"workload": wl.name, "method": "tangent-linear, one pass per parameter"},
+           "D_T": D, "dD_dp": grads}
+    if not args.no_cpu_baseline:
+        base = cpu_baseline(wl, args.cpu_seconds)
+        per_step = wl.n_nodes_lattice / (base["value"] * 1e6)
+        out["cpu_baseline"] = {"value": round(6 * args.steps * per_step, 1), "unit": "s",
+                               "cores": base["cores"], "kind": "oracle",
+                               "sample": "six FP64 oracle runs of %d steps (central differences), "
+                                         "scaled from %s" % (args.steps, base["sample"])}
     print(json.dumps(out), flush=True)
 
 

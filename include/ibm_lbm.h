@@ -301,7 +301,9 @@ int ibm_batch_create(int n_runs, ibm_lattice *const *runs, void *dev_mem, size_t
  * Device-side errors of a run are reported by that run's next synchronising
  * call.  The per-node coupling kernels are used whatever a run's
  * IBM_OPT_CHUNK_NODES, and the lattice update is the one-node-per-thread
- * form whatever its IBM_OPT_LBM_VARIANT. */
+ * form whatever its IBM_OPT_LBM_VARIANT.  The stencil-box mode is the first
+ * run's IBM_OPT_STENCIL_BOX if it was set, else box spreading when the
+ * batch's membranes make at least 256 blocks of work. */
 int ibm_batch_step(ibm_batch *b, int64_t n);
 
 /* ibm_profile_step for a batch: n steps of every run with plain launches and

@@ -361,6 +361,7 @@ struct ibm_batch {
   hipGraphExec_t gexec = nullptr;
   bool graph_valid = false;
   int graph_advect = -1, graph_linear = -1, graph_box = -1;  // options the graph was captured with
+  int box_mode = 0;  // stencil-box mode of the batched coupling kernels
 };
 
 namespace {
@@ -457,6 +458,9 @@ int batch_sync_tables(ibm_batch *b) {
   B.node_items = reinterpret_cast<const int2 *>(b->dev + bl.node_items);
   B.n_lat_items = (int)li.size();
   B.n_node_items = (int)ni.size();
+  // the first run's explicit choice, else box spreading once the whole batch
+  // makes at least 256 blocks of coupling work
+  b->box_mode = r0->box_set ? r0->box_mode : (ni.size() >= 256 ? 1 : 0);
   const bool same = img == b->image && std::memcmp(&B, &b->B, sizeof(B)) == 0;
   if (!same) {
     IBM_HIP(hipMemcpyAsync(b->dev, img.data(), img.size(), hipMemcpyHostToDevice, b->stream));
@@ -473,9 +477,9 @@ int batch_sync_tables(ibm_batch *b) {
 void enqueue_batch_step(ibm_batch *b, hipStream_t s, int advect) {
   const ibm_lattice *r0 = b->runs[0];
   const int src = (int)(r0->steps & 1), par = src;
-  ibm::launch_batch_spread(b->B, par, r0->box_mode & 1, s);
+  ibm::launch_batch_spread(b->B, par, b->box_mode & 1, s);
   ibm::launch_batch_collide_stream(b->B, r0->storage, src, par, r0->eq_linear != 0, s);
-  ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, (r0->box_mode & 2) != 0, s);
+  ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, (b->box_mode & 2) != 0, s);
   for (ibm_lattice *lat : b->runs) {
     lat->steps += 1;
     lat->since_recenter += 1;
@@ -508,7 +512,7 @@ int batch_capture_graph(ibm_batch *b, int advect) {
   b->graph_valid = true;
   b->graph_advect = advect;
   b->graph_linear = b->runs[0]->eq_linear;
-  b->graph_box = b->runs[0]->box_mode;
+  b->graph_box = b->box_mode;
   return IBM_OK;
 }
 
@@ -1254,7 +1258,7 @@ int ibm_batch_step(ibm_batch *b, int64_t n) {
     const bool graph_ok = (r0->steps & 1) == 0 && n >= GRAPH_STEPS && room && (!r0->ab2 || prev);
     if (graph_ok) {
       if (!b->graph_valid || b->graph_advect != advect || b->graph_linear != r0->eq_linear ||
-          b->graph_box != r0->box_mode) {
+          b->graph_box != b->box_mode) {
         rc = batch_capture_graph(b, advect);
         if (rc) return rc;
       }
@@ -1295,11 +1299,11 @@ int ibm_batch_profile_step(ibm_batch *b, int64_t n, double *ms_per_phase) {
     const int src = (int)(r0->steps & 1), par = src;
     const int advect = (r0->ab2 && batch_prev_u(b)) ? 1 : 0;
     IBM_HIP(hipEventRecord(e[0], s));
-    ibm::launch_batch_spread(b->B, par, r0->box_mode & 1, s);
+    ibm::launch_batch_spread(b->B, par, b->box_mode & 1, s);
     IBM_HIP(hipEventRecord(e[1], s));
     ibm::launch_batch_collide_stream(b->B, r0->storage, src, par, r0->eq_linear != 0, s);
     IBM_HIP(hipEventRecord(e[2], s));
-    ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, (r0->box_mode & 2) != 0, s);
+    ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, (b->box_mode & 2) != 0, s);
     IBM_HIP(hipEventRecord(e[3], s));
     for (ibm_lattice *lat : b->runs) {
       lat->steps += 1;

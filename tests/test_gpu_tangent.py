@@ -98,6 +98,29 @@ def test_tangent_shape_derivative(B, which):
     assert abs(dobs[0, 4] - fd) < 1e-3 * abs(fd)
 
 
+def test_tangent_c5_workload(B):
+    """The 64^3 single-capsule workload (r = 8, 1280 faces, 3-point delta,
+    Ca = 0.05) for 500 steps: the three derivatives of D in one pass each,
+    against oracle central differences at full size (six FP64 runs)."""
+    steps = 500
+    wl = W.config("c5")
+    c = Case(wl)
+    for which in ("ks", "C", "gamma"):
+        p = param_value(c, which)
+        fd = (oracle_D(c, which, 1 + H_FD, steps)[0] - oracle_D(c, which, 1 - H_FD, steps)[0]) \
+            / (2 * H_FD * p)
+        lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau)
+        lat.set_shear(wl.u_w, init_profile=True)
+        lat.add_capsules(c.meshes(), c.ks, c.ka, wl.m)
+        dks, dka, duw = rates(c, which)
+        lat.attach_tangent(dks, dka, duw, init_profile=(which == "gamma"))
+        lat.step(steps)
+        got = lat.tangent_observables(1e-6 * p)[0, 4]
+        lat.close()
+        say("  c5 d D / d %s: tangent %.8e  oracle FD %.8e" % (which, got, fd))
+        assert abs(got - fd) < 1e-3 * abs(fd)
+
+
 def test_tangent_one_step_fields(B):
     """One step from a deformed injected state, direction k_s: tangent
     populations and node velocities against central differences of one
