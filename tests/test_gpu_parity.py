@@ -383,6 +383,23 @@ def test_stencil_touching_wall_is_rejected(B):
     lat.close()
 
 
+def test_collapsed_face_is_reported(B):
+    """A face whose current area vanishes (two corners on top of each other)
+    makes det C = 0: the step reports IBM_ERR_INVERTED_FACE at the next
+    synchronising call."""
+    c = small_case(m=2)
+    lat = c.gpu(graph=False)
+    x = c.xref.copy()
+    a, b, _ = c.tri[0]
+    x[b] = x[a]
+    lat.set_mesh(x)
+    lat.step(1)
+    with pytest.raises(B.IBMError) as e:
+        lat.synchronize()
+    assert e.value.code == -6
+    lat.close()
+
+
 def test_bad_arguments(B):
     lat = B.Lattice(8, 8, 8)
     with pytest.raises(B.IBMError):
