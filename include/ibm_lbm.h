@@ -275,6 +275,30 @@ int ibm_tangent_get_mesh(ibm_lattice *lat, double *dxyz_dev, double *du_dev);
  * h (> 0, in units of the parameter) sets the difference step; waits. */
 int ibm_tangent_observables(ibm_lattice *lat, double h, double *out_host);
 
+/* ---- reverse-mode gradient (discrete adjoint of the timestep) --------------
+ * The gradient of the Taylor deformation D(T) of one capsule (Sec. III) with
+ * respect to every capsule's k_s and k_alpha and the wall speed u_w, by the
+ * adjoint of the whole FP32 step: each step reversed (interpolation and
+ * advection, the lattice velocity, streaming with the moving-wall
+ * bounce-back, BGK + Guo, spreading, the Skalak forces through their Hessian
+ * product) with the states recomputed from checkpoints taken every
+ * checkpoint_every steps.  D(T)'s own gradient with respect to the node
+ * positions is taken by FP64 central differences of the observables.  Needs
+ * FP32 storage, Euler advection and no attached tangent. */
+
+/* Device bytes for ibm_adjoint_gradient over `steps` steps. */
+int ibm_adjoint_bytes(ibm_lattice *lat, int64_t steps, int checkpoint_every, size_t *bytes);
+
+/* Run `steps` steps from the current state (re-centring off meanwhile) and
+ * return D(T) of `capsule` and its gradient: dD_dks, dD_dka host arrays of
+ * n_caps values, *dD_duw (with couette_start = 1 including the dependence of
+ * a linear Couette start, as set by ibm_set_shear(init_profile = 1), on u_w).
+ * dev_mem: caller-owned scratch of ibm_adjoint_bytes bytes, 256-byte aligned.
+ * The lattice ends at step T as after ibm_step(steps).  Waits. */
+int ibm_adjoint_gradient(ibm_lattice *lat, int64_t steps, int checkpoint_every, int capsule,
+                         int couette_start, void *dev_mem, size_t bytes, double *D_out,
+                         double *dD_dks, double *dD_dka, double *dD_duw);
+
 /* ---- batches of independent runs (Sec. IV parameter studies) ---------------
  * A batch advances many lattices (each with or without capsules, of any size,
  * tau, wall speed and delta width) together: every kernel of the timestep is

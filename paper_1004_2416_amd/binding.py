@@ -76,6 +76,8 @@ def _load():
         "ibm_tangent_get_pops": ([v, v], i),
         "ibm_tangent_get_mesh": ([v, v, v], i),
         "ibm_tangent_observables": ([v, d, v], i),
+        "ibm_adjoint_bytes": ([v, i64, i, ctypes.POINTER(sz)], i),
+        "ibm_adjoint_gradient": ([v, i64, i, i, i, v, sz, v, v, v, v], i),
         "ibm_batch_bytes": ([i, v, ctypes.POINTER(sz)], i),
         "ibm_batch_create": ([i, v, v, sz, ctypes.POINTER(v)], i),
         "ibm_batch_step": ([v, i64], i),
@@ -287,6 +289,22 @@ class Lattice:
         out = np.zeros((self.n_caps, OBS_N))
         _check(lib.ibm_tangent_observables(self._h, float(h), _ptr(out)))
         return out
+
+    # -- reverse-mode gradient ---------------------------------------------
+    def adjoint_gradient(self, steps: int, checkpoint_every: int = 100, capsule: int = 0,
+                         couette_start: bool = False) -> dict:
+        """Run `steps` steps and return D(T) of `capsule` with its gradient
+        with respect to k_s, k_alpha (per capsule) and u_w, by the adjoint."""
+        nbytes = ctypes.c_size_t()
+        _check(lib.ibm_adjoint_bytes(self._h, int(steps), int(checkpoint_every), ctypes.byref(nbytes)))
+        raw, buf = _aligned_buffer(nbytes.value, self.device)
+        D = np.zeros(1)
+        dks, dka, duw = np.zeros(self.n_caps), np.zeros(self.n_caps), np.zeros(1)
+        _check(lib.ibm_adjoint_gradient(self._h, int(steps), int(checkpoint_every), int(capsule),
+                                        int(bool(couette_start)), ctypes.c_void_p(buf.data_ptr()),
+                                        nbytes.value, _ptr(D), _ptr(dks), _ptr(dka), _ptr(duw)))
+        del raw, buf
+        return {"D": float(D[0]), "dks": dks, "dka": dka, "duw": float(duw[0])}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1195,6 +1195,207 @@ int ibm_tangent_observables(ibm_lattice *lat, double h, double *out_host) {
   return ok();
 }
 
+// ---- adjoint (reverse-mode gradient) -------------------------------------------
+namespace {
+struct AdjointLayout {
+  long long n_ck, pop;
+  size_t ck_f, ck_x, seg_f, seg_x, lf[2], lU, lg, lx, lx_tmp, lF, pk, uw_col, stamp, part, total;
+};
+
+AdjointLayout adjoint_layout(const ibm_lattice *lat, int64_t steps, int K) {
+  AdjointLayout l{};
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t at = off;
+    off += round_up(b, ALIGN);
+    return at;
+  };
+  const size_t pop = (size_t)lat->lay.pop_elems, S = (size_t)lat->lay.S, nn = (size_t)lat->M.nn;
+  l.pop = (long long)pop;
+  l.n_ck = (steps + K - 1) / K + 1;  // every K steps from 0, and the final state
+  l.ck_f = take((size_t)l.n_ck * pop * 4);
+  l.ck_x = take((size_t)l.n_ck * nn * 16);
+  l.seg_f = take(((size_t)K + 1) * pop * 4);
+  l.seg_x = take((size_t)K * nn * 16);
+  for (int k = 0; k < 2; ++k) l.lf[k] = take(pop * 4);
+  l.lU = take(3 * S * 4);
+  l.lg = take(3 * S * 4);
+  l.lx = take(nn * 16);
+  l.lx_tmp = take(nn * 16);
+  l.lF = take(nn * 16);
+  l.pk = take(nn * 16);
+  l.uw_col = take(2 * (size_t)lat->nx * lat->ny * 8);
+  l.stamp = take((size_t)lat->lay.tnx * lat->lay.tny * lat->lay.tnz * 4);
+  l.part = take((size_t)ibm::adj_couette_blocks(lat->L) * 8);
+  l.total = off;
+  return l;
+}
+
+hipError_t copy_d2d(void *dst, const void *src, size_t bytes, hipStream_t s) {
+  return hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+}
+
+// Force fields cleared, tiles unstamped, device step counter set.
+void adjoint_reset_fields(ibm_lattice *lat, uint32_t step, hipStream_t s) {
+  const long long tiles = (long long)lat->lay.tnx * lat->lay.tny * lat->lay.tnz;
+  for (int k = 0; k < 2; ++k) {
+    ibm::launch_fill_u32(lat->L.stamp[k], tiles, (uint32_t)(-100), s);
+    ibm::launch_fill_u32(lat->L.g[k], 3 * lat->lay.S, 0u, s);
+  }
+  ibm::launch_fill_u32(&lat->L.ctrl->step, 1, step, s);
+}
+}  // namespace
+
+int ibm_adjoint_bytes(ibm_lattice *lat, int64_t steps, int checkpoint_every, size_t *bytes) {
+  if (!lat || !bytes) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  if (!lat->has_mem) return fail(IBM_ERR_BAD_STATE, "no membrane attached");
+  if (steps < 1 || checkpoint_every < 1) return fail(IBM_ERR_INVALID_ARG, "steps and checkpoint_every must be >= 1");
+  *bytes = adjoint_layout(lat, steps, checkpoint_every).total;
+  return ok();
+}
+
+int ibm_adjoint_gradient(ibm_lattice *lat, int64_t steps, int checkpoint_every, int capsule,
+                         int couette_start, void *dev_mem, size_t bytes, double *D_out,
+                         double *dD_dks, double *dD_dka, double *dD_duw) {
+  if (!lat || !dev_mem || !D_out || !dD_dks || !dD_dka || !dD_duw)
+    return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  if (!lat->has_mem) return fail(IBM_ERR_BAD_STATE, "no membrane attached");
+  if (lat->storage != IBM_STORAGE_FP32) return fail(IBM_ERR_BAD_STATE, "the adjoint needs FP32 storage");
+  if (lat->ab2) return fail(IBM_ERR_BAD_STATE, "the adjoint follows Euler advection only");
+  if (lat->has_tan) return fail(IBM_ERR_BAD_STATE, "detach the tangent first");
+  if (capsule < 0 || capsule >= lat->M.n_caps) return fail(IBM_ERR_INVALID_ARG, "no capsule %d", capsule);
+  if (steps < 1 || checkpoint_every < 1)
+    return fail(IBM_ERR_INVALID_ARG, "steps and checkpoint_every must be >= 1");
+  const int K = checkpoint_every;
+  const AdjointLayout al = adjoint_layout(lat, steps, K);
+  if (((uintptr_t)dev_mem) % ALIGN) return fail(IBM_ERR_INVALID_ARG, "dev_mem not 256-byte aligned");
+  if (bytes < al.total) return fail(IBM_ERR_INVALID_ARG, "dev_mem has %zu bytes, %zu needed", bytes, al.total);
+  int rc = check_device(lat);
+  if (rc) return rc;
+  hipStream_t s = lat->stream;
+  char *b = static_cast<char *>(dev_mem);
+  ibm::MemDev &M = lat->M;
+  const size_t pop_bytes = (size_t)al.pop * 4, x_bytes = (size_t)M.nn * 16;
+  auto ck_f = [&](long long k) { return b + al.ck_f + (size_t)k * pop_bytes; };
+  auto ck_x = [&](long long k) { return b + al.ck_x + (size_t)k * x_bytes; };
+  auto seg_f = [&](long long k) { return reinterpret_cast<float *>(b + al.seg_f + (size_t)k * pop_bytes); };
+  auto seg_x = [&](long long k) { return b + al.seg_x + (size_t)k * x_bytes; };
+  ibm::AdjDev A{};
+  for (int k = 0; k < 2; ++k) A.lf[k] = reinterpret_cast<float *>(b + al.lf[k]);
+  A.lU = reinterpret_cast<float *>(b + al.lU);
+  A.lg = reinterpret_cast<float *>(b + al.lg);
+  A.lx = reinterpret_cast<float4 *>(b + al.lx);
+  A.lx_tmp = reinterpret_cast<float4 *>(b + al.lx_tmp);
+  A.lF = reinterpret_cast<float4 *>(b + al.lF);
+  A.pk = reinterpret_cast<double2 *>(b + al.pk);
+  A.uw_col = reinterpret_cast<double *>(b + al.uw_col);
+  A.stamp = reinterpret_cast<int *>(b + al.stamp);
+  double *part = reinterpret_cast<double *>(b + al.part);
+
+  int c0 = 0;  // the device step counter the stamps refer to
+  IBM_HIP(hipMemcpy(&c0, &lat->L.ctrl->step, sizeof(int), hipMemcpyDeviceToHost));
+  const int64_t s0 = lat->steps;
+  const int saved_recenter = lat->recenter_every;
+  lat->recenter_every = 0x7fffffff;  // fixed frames: the reverse pass replays the same steps
+  invalidate_graph(lat);
+  auto fbuf = [&](int64_t t) { return lat->L.f[(s0 + t) & 1]; };
+  const bool linear = lat->eq_linear != 0;
+
+  // forward pass with checkpoints
+  for (int64_t t = 0; t < steps; ++t) {
+    if (t % K == 0) {
+      IBM_HIP(copy_d2d(ck_f(t / K), fbuf(t), pop_bytes, s));
+      IBM_HIP(copy_d2d(ck_x(t / K), M.x, x_bytes, s));
+    }
+    enqueue_step(lat, s, 0);
+  }
+  IBM_HIP(copy_d2d(ck_f(al.n_ck - 1), fbuf(steps), pop_bytes, s));
+  IBM_HIP(copy_d2d(ck_x(al.n_ck - 1), M.x, x_bytes, s));
+
+  // objective D(T) of the capsule and its gradient with respect to x(T)
+  ibm::launch_observables(M, lat->L.ctrl, s);
+  for (void *p : {(void *)A.lx, (void *)A.pk}) ibm::launch_fill_u32(p, 4LL * M.nn, 0u, s);
+  ibm::launch_obs_grad(M, capsule, lat->node_off[capsule + 1] - lat->node_off[capsule], 1e-5,
+                       A.lx, s);
+  for (int k = 0; k < 2; ++k) ibm::launch_fill_u32(A.lf[k], al.pop, 0u, s);
+  ibm::launch_fill_u32(A.lU, 3 * lat->lay.S, 0u, s);
+  ibm::launch_fill_u32(A.lg, 3 * lat->lay.S, 0u, s);
+  ibm::launch_fill_u32(A.uw_col, 4LL * lat->nx * lat->ny, 0u, s);
+  ibm::launch_fill_u32(A.stamp, (long long)lat->lay.tnx * lat->lay.tny * lat->lay.tnz,
+                       (uint32_t)(-100), s);
+
+  // reverse pass, segment by segment: recompute and store the segment's
+  // states from its checkpoint, then reverse its steps
+  int cur = 0;  // A.lf[cur] holds the adjoint of f(t + 1)
+  const long long nseg = (steps + K - 1) / K;
+  for (long long seg = nseg - 1; seg >= 0; --seg) {
+    const int64_t sb = seg * K, se = std::min<int64_t>(sb + K, steps);
+    lat->steps = s0 + sb;
+    IBM_HIP(copy_d2d(fbuf(sb), ck_f(seg), pop_bytes, s));
+    IBM_HIP(copy_d2d(M.x, ck_x(seg), x_bytes, s));
+    adjoint_reset_fields(lat, (uint32_t)(c0 + sb), s);
+    for (int64_t t = sb; t < se; ++t) {
+      IBM_HIP(copy_d2d(seg_f(t - sb), fbuf(t), pop_bytes, s));
+      IBM_HIP(copy_d2d(seg_x(t - sb), M.x, x_bytes, s));
+      enqueue_step(lat, s, 0);
+    }
+    IBM_HIP(copy_d2d(seg_f(se - sb), fbuf(se), pop_bytes, s));
+    for (int64_t t = se - 1; t >= sb; --t) {
+      const int par = (int)((s0 + t) & 1);
+      const int step = (int)(c0 + t);
+      IBM_HIP(copy_d2d(M.x, seg_x(t - sb), x_bytes, s));
+      ibm::launch_fill_u32(&lat->L.ctrl->step, 1, (uint32_t)step, s);
+      ibm::launch_fill_u32(lat->L.g[par], 3 * lat->lay.S, 0u, s);
+      ibm::launch_spread(lat->L, M, par, lat->box_mode & 1, s);  // F(t), g(t)
+      const float *f0 = seg_f(t - sb), *f1 = seg_f(t + 1 - sb);
+      ibm::launch_adj_interp(lat->L, M, A, f1, par, step, s);
+      ibm::launch_adj_velocity(lat->L, A, f1, par, step, cur, s);
+      ibm::launch_adj_collide_stream(lat->L, A, f0, par, step, cur, linear, s);
+      ibm::launch_adj_spread(lat->L, M, A, s);
+      ibm::launch_adj_fem(lat->L, M, A, s);
+      cur ^= 1;
+    }
+  }
+  const long long nparts = couette_start ? ibm::adj_couette_blocks(lat->L) : 0;
+  if (couette_start) ibm::launch_adj_couette_start(lat->L, A, cur, linear ? 1 : 0, part, s);
+
+  // back to the forward state at the end of the run
+  lat->steps = s0 + steps;
+  IBM_HIP(copy_d2d(fbuf(steps), ck_f(al.n_ck - 1), pop_bytes, s));
+  IBM_HIP(copy_d2d(M.x, ck_x(al.n_ck - 1), x_bytes, s));
+  adjoint_reset_fields(lat, (uint32_t)(c0 + steps), s);
+  lat->recenter_every = saved_recenter;
+  lat->since_recenter = 0;
+  lat->have_prev_u = false;
+  invalidate_graph(lat);
+  IBM_HIP(hipGetLastError());
+
+  std::vector<double2> pk(M.nn);
+  std::vector<double> uw(2 * (size_t)lat->nx * lat->ny), parts((size_t)nparts);
+  std::vector<double> obs((size_t)M.n_caps * IBM_OBS_N);
+  IBM_HIP(hipMemcpyAsync(pk.data(), A.pk, pk.size() * sizeof(double2), hipMemcpyDeviceToHost, s));
+  IBM_HIP(hipMemcpyAsync(uw.data(), A.uw_col, uw.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  if (nparts) IBM_HIP(hipMemcpyAsync(parts.data(), part, parts.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  IBM_HIP(hipMemcpyAsync(obs.data(), M.obs, obs.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  rc = check_device(lat);
+  if (rc) return rc;
+  for (int c = 0; c < M.n_caps; ++c) {
+    double a = 0.0, k = 0.0;
+    for (int n = lat->node_off[c]; n < lat->node_off[c + 1]; ++n) {
+      a += pk[n].x;
+      k += pk[n].y;
+    }
+    dD_dks[c] = a;
+    dD_dka[c] = k;
+  }
+  double du = 0.0;
+  for (double v : uw) du += v;
+  for (double v : parts) du += v;
+  *dD_duw = du;
+  *D_out = obs[(size_t)capsule * IBM_OBS_N + IBM_OBS_D];
+  return ok();
+}
+
 int ibm_batch_bytes(int n_runs, ibm_lattice *const *runs, size_t *bytes) {
   if (n_runs < 1 || !runs || !bytes) return fail(IBM_ERR_INVALID_ARG, "need n_runs >= 1 and runs");
   for (int r = 0; r < n_runs; ++r)

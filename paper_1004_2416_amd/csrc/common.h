@@ -103,6 +103,20 @@ struct TanDev {
   float duw;      // d u_w (wall speed)
 };
 
+// Adjoint (reverse-mode) state of the timestep: the derivative of one scalar
+// objective with respect to every quantity of the step being reversed.
+struct AdjDev {
+  float *lf[2];     // adjoints of the populations, same layout as the populations
+  float *lU;        // adjoint of the lattice velocity at stencil nodes [3][S]
+  float *lg;        // adjoint of the force density [3][S]
+  float4 *lx;       // adjoint of the node positions [nn]
+  float4 *lx_tmp;   // partial sums within one reverse step [nn]
+  float4 *lF;       // adjoint of the nodal forces [nn]
+  double2 *pk;      // per node: accumulated d/dk_s, d/dk_alpha of its capsule's moduli
+  double *uw_col;   // per wall column (bottom, top) [2][ny][nx]: accumulated d/du_w
+  int *stamp;       // per tile: the step whose stencils touched it (nonzero weight)
+};
+
 // Independent runs advanced together: every kernel of the step is launched once
 // for all runs, each block working for one run.  Work items map a block to
 // (run, block index within that run's own launch).

@@ -20,6 +20,13 @@ void launch_tangent_init(const LatDev &L, const TanDev &T, int dst, int profile,
                          hipStream_t s);
 void launch_get_tangent_pops(const LatDev &L, const TanDev &T, int src, double *out,
                              hipStream_t s);
+void launch_adj_velocity(const LatDev &L, const AdjDev &A, const float *f1, int par, int step,
+                         int cur, hipStream_t s);
+void launch_adj_collide_stream(const LatDev &L, const AdjDev &A, const float *f0, int par, int step,
+                               int cur, bool linear, hipStream_t s);
+long long adj_couette_blocks(const LatDev &L);
+void launch_adj_couette_start(const LatDev &L, const AdjDev &A, int cur, int linear,
+                              double *partial, hipStream_t s);
 void launch_batch_collide_stream(const BatchDev &B, int fp16, int src, int par, bool linear,
                                  hipStream_t s);
 
@@ -38,6 +45,12 @@ void launch_observables(const MemDev &M, Ctrl *ctrl, hipStream_t s);
 // observables of the mesh x + h dx into obs [n_caps][16]
 void launch_observables_shifted(const MemDev &M, Ctrl *ctrl, const float4 *dx, double h,
                                 double *obs, hipStream_t s);
+void launch_obs_grad(const MemDev &M, int c, int nodes_of_c, double h, float4 *grad,
+                     hipStream_t s);
+void launch_adj_interp(const LatDev &L, const MemDev &M, const AdjDev &A, const float *f1, int par,
+                       int step, hipStream_t s);
+void launch_adj_spread(const LatDev &L, const MemDev &M, const AdjDev &A, hipStream_t s);
+void launch_adj_fem(const LatDev &L, const MemDev &M, const AdjDev &A, hipStream_t s);
 void launch_tangent_spread(const LatDev &L, const MemDev &M, const TanDev &T, int par,
                            hipStream_t s);
 void launch_tangent_interp(const LatDev &L, const MemDev &M, const TanDev &T, int fsrc, int par,

@@ -694,6 +694,209 @@ void launch_get_tangent_pops(const LatDev &L, const TanDev &T, int src, double *
   k_get_tangent_pops<<<g, b, 0, s>>>(L, T, src, out);
 }
 
+// ---- adjoint (reverse mode) of the lattice part of the step -----------------------
+// Reverse of one step t, given the adjoint of f(t+1) (A.lf[cur]) and of the
+// lattice velocity at the stencil nodes (A.lU).  f0 and f1 are the stored
+// populations f(t) and f(t+1) (same layout as the lattice buffers), g(t) is in
+// L.g[par] where the tile is stamped with `step`.
+
+// Lattice velocity U = (j(f1) + g/2) / rho(f1) at the stencil nodes: adds
+// (c_i - U) . lU / rho to the adjoint of f1_i and sets the force-density
+// adjoint lg = lU / (2 rho) (every node of a tile the step's stencils touch,
+// A.stamp, so stale values of an older step are overwritten); clears lU.
+__global__ __launch_bounds__(256) void k_adj_velocity(LatDev L, AdjDev A, const float *f1, int par,
+                                                      int step, int cur) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= L.nx || y >= L.ny) return;
+  if (A.stamp[tile_of(L, x, y, z)] != step) return;
+  const long long S = L.S;
+  const long long row = (long long)z * L.ny + y;
+  const long long n = row * L.nx + x;
+  const float ax = A.lU[n], ay = A.lU[S + n], az = A.lU[2 * S + n];
+  if (ax == 0.0f && ay == 0.0f && az == 0.0f) {
+    A.lg[n] = A.lg[S + n] = A.lg[2 * S + n] = 0.0f;
+    return;
+  }
+  float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float d = f1[pidx(L, i, row, x)];
+    drho += d;
+    if (cx(i)) jx += cx(i) * d;
+    if (cy(i)) jy += cy(i) * d;
+    if (cz(i)) jz += cz(i) * d;
+  }
+  const float inv_rho = 1.0f / (1.0f + drho);
+  const float *g = L.g[par];
+  const float ux = (jx + 0.5f * g[n]) * inv_rho, uy = (jy + 0.5f * g[S + n]) * inv_rho,
+              uz = (jz + 0.5f * g[2 * S + n]) * inv_rho;
+  const float au = ax * ux + ay * uy + az * uz;
+  float *lf = A.lf[cur];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const long long at = pidx(L, i, row, x);
+    lf[at] += (cx(i) * ax + cy(i) * ay + cz(i) * az - au) * inv_rho;
+  }
+  A.lg[n] = 0.5f * ax * inv_rho;
+  A.lg[S + n] = 0.5f * ay * inv_rho;
+  A.lg[2 * S + n] = 0.5f * az * inv_rho;
+  A.lU[n] = A.lU[S + n] = A.lU[2 * S + n] = 0.0f;
+}
+
+void launch_adj_velocity(const LatDev &L, const AdjDev &A, const float *f1, int par, int step,
+                         int cur, hipStream_t s) {
+  dim3 b = lattice_block(L), g = lattice_grid(L, b);
+  k_adj_velocity<<<g, b, 0, s>>>(L, A, f1, par, step, cur);
+}
+
+// Streaming (pulled back from x + c_i, or from the bounce-back partner at a
+// wall), then BGK + Guo reversed at the node: with u = (j + g/2)/rho,
+//   lf_k = (1 - 1/tau) l*_k + lrho + lu . (c_k - u) / rho,
+//   lrho = sum_i l*_i (1/tau) d feq_i / d rho,
+//   lu   = sum_i l*_i [(1/tau) d feq_i / d u + d S_i / d u],
+//   lg  += sum_i l*_i d S_i / d g + lu / (2 rho)     (stencil tiles only),
+// and the wall-speed term of the bounce-back kick into the per-column sums.
+template <bool LINEAR>
+__global__ __launch_bounds__(256) void k_adj_collide_stream(LatDev L, AdjDev A, const float *f0,
+                                                            int par, int step, int cur) {
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  if (x >= L.nx || y >= L.ny) return;
+  const long long S = L.S;
+  const long long row = (long long)z * L.ny + y;
+  const long long n = row * L.nx + x;
+  const float *l1 = A.lf[cur];
+  float *l0 = A.lf[cur ^ 1];
+  const int ym = (y == 0) ? L.ny - 1 : y - 1, yp = (y == L.ny - 1) ? 0 : y + 1;
+  const int xm = (x == 0) ? L.nx - 1 : x - 1, xp = (x == L.nx - 1) ? 0 : x + 1;
+  float ls[Q];
+  float luw = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const int zt = z + cz(i);
+    if (cz(i) != 0 && (zt < 0 || zt >= L.nz)) {
+      const float v = l1[pidx(L, opp(i), row, x)];
+      ls[i] = v;
+      luw += v * (-6.0f * (float)wgt(i) * (float)cx(i) * (zt < 0 ? -1.0f : 1.0f));
+    } else {
+      const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
+      const int xt = cx(i) > 0 ? xp : (cx(i) < 0 ? xm : x);
+      ls[i] = l1[pidx(L, i, (long long)zt * L.ny + yt, xt)];
+    }
+  }
+  if (z == 0 || z == L.nz - 1)
+    A.uw_col[(z == 0 ? 0 : (long long)L.nx * L.ny) + (long long)y * L.nx + x] += (double)luw;
+  float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float d = f0[pidx(L, i, row, x)];
+    drho += d;
+    if (cx(i)) jx += cx(i) * d;
+    if (cy(i)) jy += cy(i) * d;
+    if (cz(i)) jz += cz(i) * d;
+  }
+  // the force density is zero outside the tiles spreading touched; its
+  // adjoint is needed wherever the step's stencils reach
+  const bool stamped = A.stamp[tile_of(L, x, y, z)] == step;
+  const float gx = L.g[par][n], gy = L.g[par][S + n], gz = L.g[par][2 * S + n];
+  const float rho = 1.0f + drho, inv_rho = 1.0f / rho;
+  const float ux = (jx + 0.5f * gx) * inv_rho, uy = (jy + 0.5f * gy) * inv_rho,
+              uz = (jz + 0.5f * gz) * inv_rho;
+  const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
+  const float itau = L.inv_tau, pre = L.guo_pre;
+  float lrho = 0.0f, lux = 0.0f, luy = 0.0f, luz = 0.0f, lgx = 0.0f, lgy = 0.0f, lgz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float w = (float)wgt(i);
+    const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
+    const float Qi = LINEAR ? 3.0f * cu : 3.0f * cu + 4.5f * cu * cu - usq15;
+    lrho += ls[i] * itau * w * (1.0f + Qi);
+    const float a = ls[i] * itau * w * rho;
+    if (LINEAR) {
+      lux += a * 3.0f * cx(i);
+      luy += a * 3.0f * cy(i);
+      luz += a * 3.0f * cz(i);
+    } else {
+      lux += a * (3.0f * cx(i) + 9.0f * cu * cx(i) - 3.0f * ux);
+      luy += a * (3.0f * cy(i) + 9.0f * cu * cy(i) - 3.0f * uy);
+      luz += a * (3.0f * cz(i) + 9.0f * cu * cz(i) - 3.0f * uz);
+    }
+    if (stamped) {
+      const float cg = cx(i) * gx + cy(i) * gy + cz(i) * gz;
+      const float b = ls[i] * pre * w;
+      lux += b * (-3.0f * gx + 9.0f * cg * cx(i));
+      luy += b * (-3.0f * gy + 9.0f * cg * cy(i));
+      luz += b * (-3.0f * gz + 9.0f * cg * cz(i));
+      lgx += b * (3.0f * (cx(i) - ux) + 9.0f * cu * cx(i));
+      lgy += b * (3.0f * (cy(i) - uy) + 9.0f * cu * cy(i));
+      lgz += b * (3.0f * (cz(i) - uz) + 9.0f * cu * cz(i));
+    }
+  }
+  const float luu = lux * ux + luy * uy + luz * uz;
+#pragma unroll
+  for (int k = 0; k < Q; ++k)
+    l0[pidx(L, k, row, x)] =
+        (1.0f - itau) * ls[k] + lrho + (lux * cx(k) + luy * cy(k) + luz * cz(k) - luu) * inv_rho;
+  if (stamped) {
+    A.lg[n] += lgx + 0.5f * lux * inv_rho;
+    A.lg[S + n] += lgy + 0.5f * luy * inv_rho;
+    A.lg[2 * S + n] += lgz + 0.5f * luz * inv_rho;
+  }
+}
+
+void launch_adj_collide_stream(const LatDev &L, const AdjDev &A, const float *f0, int par, int step,
+                               int cur, bool linear, hipStream_t s) {
+  dim3 b = lattice_block(L), g = lattice_grid(L, b);
+  if (linear) k_adj_collide_stream<true><<<g, b, 0, s>>>(L, A, f0, par, step, cur);
+  else k_adj_collide_stream<false><<<g, b, 0, s>>>(L, A, f0, par, step, cur);
+}
+
+// d/du_w through the Couette start f_i(0) = f_i^eq(1, u_w (2z + 1 - nz)/nz):
+// sum over the lattice of lf_i(0) d f_i(0) / d u_w, one partial sum per block.
+__global__ __launch_bounds__(256) void k_adj_couette_start(LatDev L, AdjDev A, int cur, int linear,
+                                                           double *partial) {
+  __shared__ double red[256];
+  const int x = blockIdx.x * blockDim.x + threadIdx.x;
+  const int y = blockIdx.y * blockDim.y + threadIdx.y;
+  const int z = blockIdx.z;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int nt = blockDim.x * blockDim.y;
+  double v = 0.0;
+  if (x < L.nx && y < L.ny) {
+    const long long row = (long long)z * L.ny + y;
+    const double shape = (double)(2 * z + 1 - L.nz) / (double)L.nz;
+    const double ux = (double)L.uw * shape;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double c = cx(i);
+      const double dfi = linear ? wgt(i) * 3.0 * c * shape
+                                : wgt(i) * (3.0 * c + 9.0 * c * c * ux - 3.0 * ux) * shape;
+      v += (double)A.lf[cur][pidx(L, i, row, x)] * dfi;
+    }
+  }
+  red[tid] = v;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (tid < k && tid + k < nt) red[tid] += red[tid + k];
+    __syncthreads();
+  }
+  if (tid == 0) partial[((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = red[0];
+}
+
+long long adj_couette_blocks(const LatDev &L) {
+  dim3 b = lattice_block(L), g = lattice_grid(L, b);
+  return (long long)g.x * g.y * g.z;
+}
+
+void launch_adj_couette_start(const LatDev &L, const AdjDev &A, int cur, int linear,
+                              double *partial, hipStream_t s) {
+  dim3 b = lattice_block(L), g = lattice_grid(L, b);
+  k_adj_couette_start<<<g, b, 0, s>>>(L, A, cur, linear, partial);
+}
+
 // ---- batches of runs -------------------------------------------------------------
 // The lattice update of many independent runs in one launch: block b updates
 // 256 consecutive nodes (one per thread) of run lat_items[b].x.  Runs without

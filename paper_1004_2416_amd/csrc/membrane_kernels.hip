@@ -961,6 +961,181 @@ void launch_tangent_interp(const LatDev &L, const MemDev &M, const TanDev &T, in
   else k_tangent_interp<4><<<grid, block, 0, s>>>(L, M, T, fsrc, par, nblocks);
 }
 
+// ---- adjoint (reverse mode) of the coupling and the membrane forces ---------------
+// With r = X - x_n, Phi(r) = phi(r_x) phi(r_y) phi(r_z) and d Phi / d x_n =
+// -grad Phi(r):
+//   interpolation u_n = sum_X Phi U(X):   lU(X) += Phi lu_n,
+//                                          lx_n  += -sum_X (U(X) . lu_n) grad Phi
+//   spreading g(X) = sum_n Phi F_n:       lF_n   = sum_X Phi lg(X),
+//                                          lx_n  += -sum_X (F_n . lg(X)) grad Phi
+//   forces F = -grad W(x; k_s, k_alpha):   lx    += (dF/dx)^T lF = (dF/dx) lF
+//                                          (the Hessian of W is symmetric, so the
+//                                          tangent kernel's product serves),
+//                                          d/dk_s += (dF/dk_s) . lF, likewise k_alpha.
+// Advection x(t+1) = x(t) + u_n gives lu_n = lx(t+1) and lx(t) = lx(t+1) + ...
+template <int M>
+__global__ __launch_bounds__(256) void k_adj_interp(LatDev L, MemDev Mm, AdjDev A, const float *f1,
+                                                    int par, int step, int nblocks) {
+  constexpr int GS = group_size<M>();
+  const int blk = xcd_block(nblocks);
+  if (blk < 0) return;
+  const int lane = threadIdx.x & (GS - 1);
+  const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
+  if (node >= Mm.nn) return;  // whole groups leave together
+  const float4 lu = A.lx[node];
+  float gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  if (lane < M * M * M) {
+    int lx, ly, lz;
+    float w, dw;
+    const float4 p = Mm.x[node];
+    stencil_weight<M>(p, make_float4(0.0f, 0.0f, 0.0f, 0.0f), lane, lx, ly, lz, w, dw);
+    const int4 o = Mm.origin[Mm.node_cap[node]];
+    const int Z = o.z + lz;
+    if (w != 0.0f && Z >= 0 && Z < L.nz) {
+      const float rx = (float)lx - p.x, ry = (float)ly - p.y, rz = (float)lz - p.z;
+      const float wx = phi<M>(rx), wy = phi<M>(ry), wz = phi<M>(rz);
+      const float dx = dphi<M>(rx) * wy * wz, dy = wx * dphi<M>(ry) * wz, dz = wx * wy * dphi<M>(rz);
+      const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
+      const float3 U = lattice_velocity<float>(L, f1, L.g[par], X, Y, Z);
+      const float su = U.x * lu.x + U.y * lu.y + U.z * lu.z;
+      gx = -su * dx;
+      gy = -su * dy;
+      gz = -su * dz;
+      const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
+      A.stamp[tile_of(L, X, Y, Z)] = step;
+      unsafeAtomicAdd(A.lU + n, w * lu.x);
+      unsafeAtomicAdd(A.lU + L.S + n, w * lu.y);
+      unsafeAtomicAdd(A.lU + 2 * L.S + n, w * lu.z);
+    }
+  }
+  gx = group_sum<GS>(gx);
+  gy = group_sum<GS>(gy);
+  gz = group_sum<GS>(gz);
+  if (lane == 0) A.lx_tmp[node] = make_float4(lu.x + gx, lu.y + gy, lu.z + gz, 0.0f);
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void k_adj_spread(LatDev L, MemDev Mm, AdjDev A, int nblocks) {
+  constexpr int GS = group_size<M>();
+  const int blk = xcd_block(nblocks);
+  if (blk < 0) return;
+  const int lane = threadIdx.x & (GS - 1);
+  const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
+  if (node >= Mm.nn) return;  // whole groups leave together
+  const float4 F = Mm.F[node];
+  float fx = 0.0f, fy = 0.0f, fz = 0.0f, gx = 0.0f, gy = 0.0f, gz = 0.0f;
+  if (lane < M * M * M) {
+    int lx, ly, lz;
+    float w, dw;
+    const float4 p = Mm.x[node];
+    stencil_weight<M>(p, make_float4(0.0f, 0.0f, 0.0f, 0.0f), lane, lx, ly, lz, w, dw);
+    const int4 o = Mm.origin[Mm.node_cap[node]];
+    const int Z = o.z + lz;
+    if (w != 0.0f && Z >= 0 && Z < L.nz) {
+      const float rx = (float)lx - p.x, ry = (float)ly - p.y, rz = (float)lz - p.z;
+      const float wx = phi<M>(rx), wy = phi<M>(ry), wz = phi<M>(rz);
+      const float dx = dphi<M>(rx) * wy * wz, dy = wx * dphi<M>(ry) * wz, dz = wx * wy * dphi<M>(rz);
+      const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
+      const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
+      const float ax = A.lg[n], ay = A.lg[L.S + n], az = A.lg[2 * L.S + n];
+      fx = w * ax;
+      fy = w * ay;
+      fz = w * az;
+      const float sf = F.x * ax + F.y * ay + F.z * az;
+      gx = -sf * dx;
+      gy = -sf * dy;
+      gz = -sf * dz;
+    }
+  }
+  fx = group_sum<GS>(fx);
+  fy = group_sum<GS>(fy);
+  fz = group_sum<GS>(fz);
+  gx = group_sum<GS>(gx);
+  gy = group_sum<GS>(gy);
+  gz = group_sum<GS>(gz);
+  if (lane == 0) {
+    A.lF[node] = make_float4(fx, fy, fz, 0.0f);
+    const float4 t = A.lx_tmp[node];
+    A.lx_tmp[node] = make_float4(t.x + gx, t.y + gy, t.z + gz, 0.0f);
+  }
+}
+
+// Eight lanes per node, one incident face per lane.
+__global__ __launch_bounds__(256) void k_adj_fem(LatDev L, MemDev Mm, AdjDev A, int nblocks) {
+  constexpr int GS = 8;
+  const int blk = xcd_block(nblocks);
+  if (blk < 0) return;
+  const int lane = threadIdx.x & (GS - 1);
+  const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
+  if (node >= Mm.nn) return;  // whole groups leave together
+  const float4 zero = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  float v[9] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
+  const int e1 = Mm.csr_off[node + 1];
+  for (int e = Mm.csr_off[node] + lane; e < e1; e += GS) {
+    const int ent = Mm.csr_ent[e];
+    const int j = ent >> 2, corner = ent & 3;
+    const int4 tj = Mm.tri[j];
+    const float4 rp = Mm.ref_p[j], gh = Mm.ref_ghi[j], gl = Mm.ref_glo[j];
+    const float4 mod = Mm.moduli[tj.w];
+    const FaceRef R{rp.x, rp.y, rp.z, rp.w, gh.x, gh.y, gh.z, gl.x, gl.y, gl.z};
+    const float4 a = Mm.x[tj.x], b = Mm.x[tj.y], c = Mm.x[tj.z];
+    float3 t[3];
+    // Hessian product with the force adjoints at the corners
+    skalak_face_grad_tangent(a, b, c, A.lF[tj.x], A.lF[tj.y], A.lF[tj.z], R, mod.x, mod.y, 0.0f,
+                             0.0f, t[0], t[1], t[2]);
+    v[0] -= t[corner].x;
+    v[1] -= t[corner].y;
+    v[2] -= t[corner].z;
+    // the face's corner force per unit k_s and per unit k_alpha
+    skalak_face_grad_tangent(a, b, c, zero, zero, zero, R, mod.x, mod.y, 1.0f, 0.0f, t[0], t[1], t[2]);
+    v[3] -= t[corner].x;
+    v[4] -= t[corner].y;
+    v[5] -= t[corner].z;
+    skalak_face_grad_tangent(a, b, c, zero, zero, zero, R, mod.x, mod.y, 0.0f, 1.0f, t[0], t[1], t[2]);
+    v[6] -= t[corner].x;
+    v[7] -= t[corner].y;
+    v[8] -= t[corner].z;
+  }
+#pragma unroll
+  for (int q = 0; q < 9; ++q) v[q] = group_sum<GS>(v[q]);
+  if (lane == 0) {
+    const float4 t = A.lx_tmp[node], lF = A.lF[node];
+    A.lx[node] = make_float4(t.x + v[0], t.y + v[1], t.z + v[2], 0.0f);
+    const double2 pk = A.pk[node];
+    A.pk[node] = make_double2(pk.x + (double)(v[3] * lF.x + v[4] * lF.y + v[5] * lF.z),
+                              pk.y + (double)(v[6] * lF.x + v[7] * lF.y + v[8] * lF.z));
+  }
+}
+
+static int lanes_of(int m) {
+  return m == 2 ? group_size<2>() : (m == 3 ? group_size<3>() : group_size<4>());
+}
+
+void launch_adj_interp(const LatDev &L, const MemDev &M, const AdjDev &A, const float *f1, int par,
+                       int step, hipStream_t s) {
+  if (M.nn <= 0) return;
+  const int nblocks = (int)(((long long)M.nn * lanes_of(M.m) + 255) / 256);
+  const dim3 grid(xcd_grid(nblocks)), block(256);
+  if (M.m == 2) k_adj_interp<2><<<grid, block, 0, s>>>(L, M, A, f1, par, step, nblocks);
+  else if (M.m == 3) k_adj_interp<3><<<grid, block, 0, s>>>(L, M, A, f1, par, step, nblocks);
+  else k_adj_interp<4><<<grid, block, 0, s>>>(L, M, A, f1, par, step, nblocks);
+}
+
+void launch_adj_spread(const LatDev &L, const MemDev &M, const AdjDev &A, hipStream_t s) {
+  if (M.nn <= 0) return;
+  const int nblocks = (int)(((long long)M.nn * lanes_of(M.m) + 255) / 256);
+  const dim3 grid(xcd_grid(nblocks)), block(256);
+  if (M.m == 2) k_adj_spread<2><<<grid, block, 0, s>>>(L, M, A, nblocks);
+  else if (M.m == 3) k_adj_spread<3><<<grid, block, 0, s>>>(L, M, A, nblocks);
+  else k_adj_spread<4><<<grid, block, 0, s>>>(L, M, A, nblocks);
+}
+
+void launch_adj_fem(const LatDev &L, const MemDev &M, const AdjDev &A, hipStream_t s) {
+  if (M.nn <= 0) return;
+  const int nblocks = (int)(((long long)M.nn * 8 + 255) / 256);
+  k_adj_fem<<<dim3(xcd_grid(nblocks)), dim3(256), 0, s>>>(L, M, A, nblocks);
+}
+
 // ---- batches of runs -------------------------------------------------------------
 // Spreading (with the Skalak forces) and interpolation of many independent
 // runs, one launch each; a block works for run items[b].x as block items[b].y of that
@@ -1161,24 +1336,47 @@ __device__ void block_sum(double (*red)[256], double *vals) {
 // (divided by V); the ellipsoid with that tensor has
 // r_a^2 = 5/2 (E2 + E3 - E1), r_b^2 = 5/2 (E1 + E3 - E2),
 // r_c^2 = 5/2 (E1 + E2 - E3) for eigenvalues E1 <= E2 <= E3.
-// Node n of the observables: stored coordinates, or x + h dx when dx is given.
-__device__ __forceinline__ double3 obs_node(const MemDev &M, const float4 *dx, double h, int n) {
-  const float4 p = M.x[n];
-  if (!dx) return make_double3(p.x, p.y, p.z);
-  const float4 d = dx[n];
-  return make_double3((double)p.x + h * d.x, (double)p.y + h * d.y, (double)p.z + h * d.z);
-}
+// Node positions of the observables: stored coordinates, or x + h dx along a
+// tangent, or one node moved by h along one axis.
+struct PosShift {
+  const MemDev *M;
+  const float4 *dx;
+  double h;
+  __device__ __forceinline__ double3 operator()(int n) const {
+    const float4 p = M->x[n];
+    if (!dx) return make_double3(p.x, p.y, p.z);
+    const float4 d = dx[n];
+    return make_double3((double)p.x + h * d.x, (double)p.y + h * d.y, (double)p.z + h * d.z);
+  }
+};
 
-__global__ __launch_bounds__(256) void k_observables(MemDev M, Ctrl *ctrl, const float4 *dx,
-                                                     double h, double *obs) {
-  __shared__ double red[7][256];
-  __shared__ double cen[3];
-  const int c = blockIdx.x;
+struct PosPoke {
+  const MemDev *M;
+  int node, axis;
+  double h;
+  __device__ __forceinline__ double3 operator()(int n) const {
+    const float4 p = M->x[n];
+    double3 r = make_double3(p.x, p.y, p.z);
+    if (n == node) {
+      if (axis == 0) r.x += h;
+      else if (axis == 1) r.y += h;
+      else r.z += h;
+    }
+    return r;
+  }
+};
+
+// Observables of capsule c (layout of ibm_observables, capsule-local
+// centroid); all threads of the block call it, thread 0 gets out[] and the
+// return value (all observables finite).
+template <class Pos>
+__device__ bool capsule_obs(const MemDev &M, int c, const Pos &pos, double (*red)[256], double *cen,
+                            double *out) {
   const int f0 = M.cap_face_off[c], f1 = M.cap_face_off[c + 1];
   double v1[4] = {0.0, 0.0, 0.0, 0.0};
   for (int j = f0 + threadIdx.x; j < f1; j += blockDim.x) {
     const int4 t = M.tri[j];
-    const double3 A = obs_node(M, dx, h, t.x), B = obs_node(M, dx, h, t.y), C = obs_node(M, dx, h, t.z);
+    const double3 A = pos(t.x), B = pos(t.y), C = pos(t.z);
     const double ax = A.x, ay = A.y, az = A.z, bx = B.x, by = B.y, bz = B.z;
     const double cx_ = C.x, cy_ = C.y, cz_ = C.z;
     const double vt =
@@ -1199,7 +1397,7 @@ __global__ __launch_bounds__(256) void k_observables(MemDev M, Ctrl *ctrl, const
   double s7[7] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
   for (int j = f0 + threadIdx.x; j < f1; j += blockDim.x) {
     const int4 t = M.tri[j];
-    const double3 A = obs_node(M, dx, h, t.x), B = obs_node(M, dx, h, t.y), C = obs_node(M, dx, h, t.z);
+    const double3 A = pos(t.x), B = pos(t.y), C = pos(t.z);
     const double e1x = B.x - A.x, e1y = B.y - A.y, e1z = B.z - A.z;
     const double e2x = C.x - A.x, e2y = C.y - A.y, e2z = C.z - A.z;
     const double anx = 0.5 * (e1y * e2z - e1z * e2y);
@@ -1219,46 +1417,83 @@ __global__ __launch_bounds__(256) void k_observables(MemDev M, Ctrl *ctrl, const
     s7[6] += sqrt(anx * anx + any * any + anz * anz);
   }
   block_sum<7>(red, s7);
+  bool finite = true;
+  if (threadIdx.x == 0) {
+    const double k = 1.0 / (5.0 * V);
+    double I[6];
+    for (int q = 0; q < 6; ++q) I[q] = s7[q] * k;
+    double a[3][3] = {{I[0], I[3], I[4]}, {I[3], I[1], I[5]}, {I[4], I[5], I[2]}};
+    double vec[3][3];
+    sym3_eigen(a, vec);
+    double e[3] = {a[0][0], a[1][1], a[2][2]};
+    int id[3] = {0, 1, 2};
+    for (int i = 0; i < 3; ++i)
+      for (int j = i + 1; j < 3; ++j)
+        if (e[id[j]] < e[id[i]]) {
+          const int tmp = id[i];
+          id[i] = id[j];
+          id[j] = tmp;
+        }
+    const double E1 = e[id[0]], E2 = e[id[1]], E3 = e[id[2]];
+    const double ra = sqrt(fmax(2.5 * (E2 + E3 - E1), 0.0));
+    const double rb = sqrt(fmax(2.5 * (E1 + E3 - E2), 0.0));
+    const double rc = sqrt(fmax(2.5 * (E1 + E2 - E3), 0.0));
+    double th = atan2(vec[2][id[0]], vec[0][id[0]]);
+    if (th <= -M_PI / 2) th += M_PI;
+    if (th > M_PI / 2) th -= M_PI;
+    if (!((E2 - E1) > 1e-12 * fabs(E3))) th = __longlong_as_double(0x7ff8000000000000LL);
+    out[0] = V;
+    out[1] = cen[0];
+    out[2] = cen[1];
+    out[3] = cen[2];
+    out[4] = (ra - rc) / (ra + rc);
+    out[5] = th;
+    out[6] = ra;
+    out[7] = rb;
+    out[8] = rc;
+    out[9] = s7[6];
+    for (int q = 0; q < 6; ++q) out[10 + q] = I[q];
+    finite = isfinite(V) && isfinite(out[4]);
+    for (int q = 0; q < 6; ++q) finite = finite && isfinite(I[q]);
+  }
+  return finite;
+}
+
+__global__ __launch_bounds__(256) void k_observables(MemDev M, Ctrl *ctrl, const float4 *dx,
+                                                     double h, double *obs) {
+  __shared__ double red[7][256];
+  __shared__ double cen[3];
+  const int c = blockIdx.x;
+  double out[16];
+  const bool finite = capsule_obs(M, c, PosShift{&M, dx, h}, red, cen, out);
   if (threadIdx.x != 0) return;
-  const double k = 1.0 / (5.0 * V);
-  double I[6];
-  for (int q = 0; q < 6; ++q) I[q] = s7[q] * k;
-  double a[3][3] = {{I[0], I[3], I[4]}, {I[3], I[1], I[5]}, {I[4], I[5], I[2]}};
-  double vec[3][3];
-  sym3_eigen(a, vec);
-  double e[3] = {a[0][0], a[1][1], a[2][2]};
-  int id[3] = {0, 1, 2};
-  for (int i = 0; i < 3; ++i)
-    for (int j = i + 1; j < 3; ++j)
-      if (e[id[j]] < e[id[i]]) {
-        const int tmp = id[i];
-        id[i] = id[j];
-        id[j] = tmp;
-      }
-  const double E1 = e[id[0]], E2 = e[id[1]], E3 = e[id[2]];
-  const double ra = sqrt(fmax(2.5 * (E2 + E3 - E1), 0.0));
-  const double rb = sqrt(fmax(2.5 * (E1 + E3 - E2), 0.0));
-  const double rc = sqrt(fmax(2.5 * (E1 + E2 - E3), 0.0));
-  double th = atan2(vec[2][id[0]], vec[0][id[0]]);
-  if (th <= -M_PI / 2) th += M_PI;
-  if (th > M_PI / 2) th -= M_PI;
-  if (!((E2 - E1) > 1e-12 * fabs(E3))) th = __longlong_as_double(0x7ff8000000000000LL);
   const int4 o = M.origin[c];
-  double *out = obs + (size_t)c * 16;
-  out[0] = V;
-  out[1] = cen[0] + o.x;
-  out[2] = cen[1] + o.y;
-  out[3] = cen[2] + o.z;
-  out[4] = (ra - rc) / (ra + rc);
-  out[5] = th;
-  out[6] = ra;
-  out[7] = rb;
-  out[8] = rc;
-  out[9] = s7[6];
-  for (int q = 0; q < 6; ++q) out[10 + q] = I[q];
-  bool finite = isfinite(V) && isfinite(out[4]);
-  for (int q = 0; q < 6; ++q) finite = finite && isfinite(I[q]);
+  out[1] += o.x;
+  out[2] += o.y;
+  out[3] += o.z;
+  for (int q = 0; q < 16; ++q) obs[(size_t)c * 16 + q] = out[q];
   if (!finite) atomicOr(&ctrl->err, ERR_NONFINITE);
+}
+
+// Gradient of the Taylor deformation D of capsule c with respect to its node
+// positions, by FP64 central differences (one block per node and axis),
+// written as FP32 into grad (the capsule's rows; other rows untouched).
+__global__ __launch_bounds__(256) void k_obs_grad(MemDev M, int c, double h, float4 *grad) {
+  __shared__ double red[7][256];
+  __shared__ double cen[3];
+  const int n0 = M.cap_node_off[c];
+  const int node = n0 + (int)blockIdx.x / 3, axis = (int)blockIdx.x % 3;
+  double outp[16], outm[16];
+  capsule_obs(M, c, PosPoke{&M, node, axis, h}, red, cen, outp);
+  __syncthreads();
+  capsule_obs(M, c, PosPoke{&M, node, axis, -h}, red, cen, outm);
+  if (threadIdx.x == 0) reinterpret_cast<float *>(grad + node)[axis] = (float)((outp[4] - outm[4]) / (2.0 * h));
+}
+
+void launch_obs_grad(const MemDev &M, int c, int nodes_of_c, double h, float4 *grad,
+                     hipStream_t s) {
+  if (nodes_of_c <= 0) return;
+  k_obs_grad<<<dim3(3 * nodes_of_c), dim3(256), 0, s>>>(M, c, h, grad);
 }
 
 void launch_observables(const MemDev &M, Ctrl *ctrl, hipStream_t s) {

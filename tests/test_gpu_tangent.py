@@ -100,11 +100,13 @@ def test_tangent_shape_derivative(B, which):
 
 def test_tangent_c5_workload(B):
     """The 64^3 single-capsule workload (r = 8, 1280 faces, 3-point delta,
-    Ca = 0.05) for 500 steps: the three derivatives of D in one pass each,
-    against oracle central differences at full size (six FP64 runs)."""
+    Ca = 0.05) for 500 steps: the three derivatives of D by the tangent model
+    (one pass each) and by the adjoint (one reverse sweep), against oracle
+    central differences at full size (six FP64 runs)."""
     steps = 500
     wl = W.config("c5")
     c = Case(wl)
+    fds = {}
     for which in ("ks", "C", "gamma"):
         p = param_value(c, which)
         fd = (oracle_D(c, which, 1 + H_FD, steps)[0] - oracle_D(c, which, 1 - H_FD, steps)[0]) \
@@ -119,6 +121,19 @@ def test_tangent_c5_workload(B):
         lat.close()
         say("  c5 d D / d %s: tangent %.8e  oracle FD %.8e" % (which, got, fd))
         assert abs(got - fd) < 1e-3 * abs(fd)
+        fds[which] = fd
+    # the reverse sweep gives all three at once
+    lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau)
+    lat.set_shear(wl.u_w, init_profile=True)
+    lat.add_capsules(c.meshes(), c.ks, c.ka, wl.m)
+    g = lat.adjoint_gradient(steps, checkpoint_every=100, couette_start=True)
+    lat.close()
+    C = c.ka[0] / c.ks[0]
+    adj = {"ks": g["dks"][0] + C * g["dka"][0], "C": c.ks[0] * g["dka"][0],
+           "gamma": 0.5 * wl.nz * g["duw"]}
+    for which, fd in fds.items():
+        say("  c5 d D / d %s: adjoint %.8e" % (which, adj[which]))
+        assert abs(adj[which] - fd) < 1e-3 * abs(fd)
 
 
 def test_tangent_one_step_fields(B):
