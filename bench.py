@@ -41,6 +41,14 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
+def collide_stream_kernel(wl, variant: int) -> str:
+    """Which collide-stream kernel the library launches for this lattice and
+    variant: the row-vector form when bit 16 is set and a row of nx nodes
+    splits into nx / 4 lanes that divide a wavefront (IBM_OPT_LBM_VARIANT)."""
+    rows = (variant & 16) and wl.nx % 4 == 0 and wl.nx // 4 <= 64 and 64 % (wl.nx // 4) == 0
+    return "k_collide_stream_rows" if rows else "k_collide_stream"
+
+
 def measured_traffic(workload: str, storage: str):
     """HBM bytes per collide-stream launch from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
@@ -234,7 +242,9 @@ def main():
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(wl.name, args.storage),
-            "kernel": "k_collide_stream", "algorithmic_bytes_per_launch": algo,
+            "kernel": collide_stream_kernel(wl, args.lbm_variant if args.lbm_variant >= 0
+                                            else (tuned or {}).get("lbm_variant", 23)),
+            "algorithmic_bytes_per_launch": algo,
         },
     }
     if not args.no_cpu_baseline:

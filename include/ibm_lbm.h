@@ -294,7 +294,8 @@ int ibm_adjoint_bytes(ibm_lattice *lat, int64_t steps, int checkpoint_every, siz
  * n_caps values, *dD_duw (with couette_start = 1 including the dependence of
  * a linear Couette start, as set by ibm_set_shear(init_profile = 1), on u_w).
  * dev_mem: caller-owned scratch of ibm_adjoint_bytes bytes, 256-byte aligned.
- * The lattice ends at step T as after ibm_step(steps).  Waits. */
+ * The lattice ends at step T as after ibm_step(steps); after an error its
+ * state is unspecified (its options are kept).  Waits. */
 int ibm_adjoint_gradient(ibm_lattice *lat, int64_t steps, int checkpoint_every, int capsule,
                          int couette_start, void *dev_mem, size_t bytes, double *D_out,
                          double *dD_dks, double *dD_dka, double *dD_duw);

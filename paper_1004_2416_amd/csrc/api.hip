@@ -1295,8 +1295,17 @@ int ibm_adjoint_gradient(ibm_lattice *lat, int64_t steps, int checkpoint_every, 
   int c0 = 0;  // the device step counter the stamps refer to
   IBM_HIP(hipMemcpy(&c0, &lat->L.ctrl->step, sizeof(int), hipMemcpyDeviceToHost));
   const int64_t s0 = lat->steps;
-  const int saved_recenter = lat->recenter_every;
-  lat->recenter_every = 0x7fffffff;  // fixed frames: the reverse pass replays the same steps
+  // fixed frames: the reverse pass replays the same steps; restored on every exit
+  struct RecenterGuard {
+    ibm_lattice *lat;
+    int saved;
+    ~RecenterGuard() {
+      lat->recenter_every = saved;
+      lat->since_recenter = 0;
+      invalidate_graph(lat);
+    }
+  } guard{lat, lat->recenter_every};
+  lat->recenter_every = 0x7fffffff;
   invalidate_graph(lat);
   auto fbuf = [&](int64_t t) { return lat->L.f[(s0 + t) & 1]; };
   const bool linear = lat->eq_linear != 0;
@@ -1364,10 +1373,7 @@ int ibm_adjoint_gradient(ibm_lattice *lat, int64_t steps, int checkpoint_every, 
   IBM_HIP(copy_d2d(fbuf(steps), ck_f(al.n_ck - 1), pop_bytes, s));
   IBM_HIP(copy_d2d(M.x, ck_x(al.n_ck - 1), x_bytes, s));
   adjoint_reset_fields(lat, (uint32_t)(c0 + steps), s);
-  lat->recenter_every = saved_recenter;
-  lat->since_recenter = 0;
   lat->have_prev_u = false;
-  invalidate_graph(lat);
   IBM_HIP(hipGetLastError());
 
   std::vector<double2> pk(M.nn);

@@ -922,12 +922,13 @@ __global__ __launch_bounds__(256) void k_batch_collide_stream(BatchDev B, int sr
     L.stamp[0] = L.stamp[1];
     L.stamp[1] = ts;
   }
-  const long long idx = (long long)it.y * 256 + threadIdx.x;
-  if (idx >= (long long)L.nx * L.ny * L.nz) return;
-  const int x = (int)(idx % L.nx);
-  const long long row = idx / L.nx;
-  collide_stream_nodes<T, LINEAR, true, 1, true>(L, 0, 0, x, (int)(row % L.ny),
-                                                 (int)(row / L.ny));
+  // a lattice holds at most 2^31 nodes: unsigned 32-bit index arithmetic suffices
+  const unsigned idx = (unsigned)it.y * 256u + threadIdx.x;
+  if ((long long)idx >= (long long)L.nx * L.ny * L.nz) return;
+  const unsigned nx = (unsigned)L.nx, ny = (unsigned)L.ny;
+  const unsigned row = idx / nx;
+  collide_stream_nodes<T, LINEAR, true, 1, true>(L, 0, 0, (int)(idx - row * nx), (int)(row % ny),
+                                                 (int)(row / ny));
 }
 
 void launch_batch_collide_stream(const BatchDev &B, int fp16, int src, int par, bool linear,
