@@ -41,12 +41,17 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def collide_stream_kernel(wl, variant: int) -> str:
+def collide_stream_kernel(wl, variant: int, storage: str) -> str:
     """Which collide-stream kernel the library launches for this lattice and
-    variant: the row-vector form when bit 16 is set and a row of nx nodes
-    splits into nx / 4 lanes that divide a wavefront (IBM_OPT_LBM_VARIANT)."""
-    rows = (variant & 16) and wl.nx % 4 == 0 and wl.nx // 4 <= 64 and 64 % (wl.nx // 4) == 0
-    return "k_collide_stream_rows" if rows else "k_collide_stream"
+    variant (IBM_OPT_LBM_VARIANT): with FP16 storage and bits 16 and 32 set,
+    the eight-node row-vector form when nx / 8 lanes divide a wavefront; with
+    bit 16 the four-node row-vector form when nx / 4 lanes do; else the
+    per-node form."""
+    def fits(vec):
+        return wl.nx % vec == 0 and wl.nx // vec <= 64 and 64 % (wl.nx // vec) == 0
+    if storage == "fp16" and (variant & 48) == 48 and fits(8):
+        return "k_collide_stream_rows8"
+    return "k_collide_stream_rows" if (variant & 16) and fits(4) else "k_collide_stream"
 
 
 def measured_traffic(workload: str, storage: str):
@@ -243,7 +248,8 @@ def main():
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic(wl.name, args.storage),
             "kernel": collide_stream_kernel(wl, args.lbm_variant if args.lbm_variant >= 0
-                                            else (tuned or {}).get("lbm_variant", 23)),
+                                            else (tuned or {}).get("lbm_variant", 23),
+                                            args.storage),
             "algorithmic_bytes_per_launch": algo,
         },
     }

@@ -105,11 +105,14 @@ extern "C" {
 #define IBM_OPT_RECENTER 3     /* steps between re-centring of the capsule
                                   frames (default 64, >= 1)                 */
 #define IBM_OPT_LBM_VARIANT 4  /* launch variant of the collide-stream kernel,
-                                  0..31 (bit 0: two nodes per thread, bit 1:
+                                  0..63 (bit 0: two nodes per thread, bit 1:
                                   non-temporal accesses, bit 2: 128-thread,
                                   bit 3: 64-thread blocks, bit 4: four nodes
                                   per thread with whole x rows per wavefront,
-                                  used when nx / 4 divides 64; default 23);
+                                  used when nx / 4 divides 64; bit 5 with
+                                  bit 4 and FP16 storage: eight nodes per
+                                  thread, used when nx / 8 divides 64;
+                                  default 23);
                                   results are identical, only the speed
                                   differs                                    */
 #define IBM_OPT_STENCIL_BOX 6  /* bit 0: spreading, bit 1: interpolation of

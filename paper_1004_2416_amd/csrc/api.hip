@@ -564,6 +564,7 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
   L.tnz = lat->lay.tnz;
   L.S = lat->lay.S;
   L.gsh = lat->lay.gsh;
+  for (int i = 0; i < ibm::Q; ++i) L.pst[i] = (long long)i * ((long long)nx << L.gsh);
   for (int k = 0; k < 2; ++k) {
     L.f[k] = lat->base + lat->lay.off_f[k];
     L.g[k] = reinterpret_cast<float *>(lat->base + lat->lay.off_g[k]);
@@ -573,11 +574,14 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
   L.inv_tau = (float)(1.0 / tau);
   L.guo_pre = (float)(1.0 - 0.5 / tau);
   L.uw = 0.0f;
-  for (int i = 0; i < ibm::Q; ++i) L.h_scale[i] = 1.0f;
+  for (int i = 0; i < ibm::Q; ++i) L.h_scale[i] = L.h_inv[i] = 1.0f;
   if (storage == IBM_STORAGE_FP16) {
     // Deviations f_i - w_i scaled by 2^k / w_i keep a shear-flow population
     // (|f_i - w_i| <~ 0.1 w_i) in FP16's normal range with 11 significant bits.
-    for (int i = 0; i < ibm::Q; ++i) L.h_scale[i] = (float)(16.0 / ibm::wgt(i));
+    for (int i = 0; i < ibm::Q; ++i) {
+      L.h_scale[i] = (float)(16.0 / ibm::wgt(i));
+      L.h_inv[i] = 1.0f / L.h_scale[i];
+    }
   }
   reset_force_state(lat, lat->stream);
   for (int k = 0; k < 2; ++k) {
@@ -900,7 +904,7 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
       lat->recenter_every = value;
       break;
     case IBM_OPT_LBM_VARIANT:
-      if (value < 0 || value > 31) return fail(IBM_ERR_INVALID_ARG, "variant is 0..31");
+      if (value < 0 || value > 63) return fail(IBM_ERR_INVALID_ARG, "variant is 0..63");
       lat->lbm_variant = value;
       break;
     case IBM_OPT_STENCIL_BOX:
@@ -958,6 +962,9 @@ int ibm_autotune(ibm_lattice *lat, int steps_per_trial, int *chosen) {
   // accesses, 256- or 128-thread blocks
   std::vector<int> cand;
   const bool rows_ok = lat->nx % 4 == 0 && lat->nx / 4 <= 64 && 64 % (lat->nx / 4) == 0;
+  const bool rows8_ok = lat->storage == IBM_STORAGE_FP16 && lat->nx % 8 == 0 &&
+                        lat->nx / 8 <= 64 && 64 % (lat->nx / 8) == 0;
+  if (rows8_ok) cand.push_back(48);
   if (rows_ok) cand.push_back(16);
   for (int nt : {2, 0})
     for (int v2 : {1, 0})

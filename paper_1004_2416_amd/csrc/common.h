@@ -62,6 +62,8 @@ struct LatDev {
   float guo_pre;          // 1 - 1 / (2 tau)
   float uw;               // wall speed: top +uw, bottom -uw along x
   float h_scale[Q];       // FP16 storage: stored = (f_i - w_i) * h_scale[i]
+  float h_inv[Q];         // 1 / h_scale[i], rounded to FP32
+  long long pst[Q];       // i * pstride: offset of population i within a group
 };
 
 // Membrane arrays (all capsules concatenated).
@@ -189,9 +191,20 @@ __device__ __forceinline__ int stencil_lo(float p) {
 // one contiguous run of G nx values (G chosen so that G nx >= 128 where
 // possible), so an update reads and writes a few contiguous kilobytes per
 // group instead of 19 arrays that are megabytes apart.
-__device__ __forceinline__ long long pidx(const LatDev &L, int i, long long row, int x) {
+// pidx(L, i, row, x) = prow(L, row) + i pstride(L) + x: a per-row offset and
+// a stride between the populations of a group that is the same for all rows.
+__device__ __forceinline__ long long prow(const LatDev &L, long long row) {
   const long long g = row >> L.gsh, r = row - (g << L.gsh);
-  return (((g * Q + i) << L.gsh) + r) * (long long)L.nx + x;
+  return (((g * Q) << L.gsh) + r) * (long long)L.nx;
+}
+__device__ __forceinline__ long long pstride(const LatDev &L) { return (long long)L.nx << L.gsh; }
+__device__ __forceinline__ long long pidx(const LatDev &L, int i, long long row, int x) {
+  return prow(L, row) + i * pstride(L) + x;
+}
+// The same for a compile-time direction i: the offset of population i comes
+// from the table (one 64-bit add per access instead of a multiply).
+__device__ __forceinline__ long long pidx_c(const LatDev &L, int i, long long row, int x) {
+  return prow(L, row) + L.pst[i] + x;
 }
 
 __device__ __forceinline__ int wrap_mod(int a, int n) {

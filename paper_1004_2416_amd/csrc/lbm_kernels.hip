@@ -100,7 +100,45 @@ __device__ __forceinline__ void st_dev(T *p, long long idx, float v, float scale
 //   (sum c_i w_i = 0).  Equilibrium deviation (Eq. equilibrium):
 //   feq_i - w_i = w_i (rho - 1) + w_i rho (3 c.u + 9/2 (c.u)^2 - 3/2 u.u),
 //   or w_i (rho - 1) + 3 w_i rho c.u for the linearised form (Sec. IV.A).
-//   Guo term (Eq. latticeforce) and BGK relaxation (Eq. lbequation).
+//   Guo term (Eq. latticeforce) and BGK relaxation (Eq. lbequation):
+//   d_i' = (1 - 1/tau) d_i + (feq_i - w_i) / tau
+//          + (1 - 1/(2 tau)) w_i (3 (c_i - u).g + 9 (c_i.u)(c_i.g)).
+// Evaluated as d_i' = (1 - 1/tau) d_i + w_i t(c_i.u, c_i.e) with e = 3 (1 -
+// 1/(2 tau)) g and the node scalars of
+//   t(p, q) = C0 + a p + b p^2 + q + 3 p q,
+//   C0 = (rho - 1 - 3/2 rho u.u) / tau - u.e,  a = 3 rho / tau,
+//   b = 9/2 rho / tau (the linearised form: no u.u term, b = 0).
+// A pair of opposite directions has (p, q) and (-p, -q), so each pair costs
+// the even part S = C0 + p (b p + 3 q) and the odd part A = a p + q once:
+// t = S + A and S - A.
+constexpr bool odd_even_pairs_opposite() {
+  for (int i = 1; i < Q; i += 2)
+    if (cx(i + 1) != -cx(i) || cy(i + 1) != -cy(i) || cz(i + 1) != -cz(i) || wgt(i + 1) != wgt(i))
+      return false;
+  return true;
+}
+static_assert(odd_even_pairs_opposite(), "directions 2k-1 and 2k must be opposite");
+
+// c_i . (x, y, z) as a signed sum of the nonzero components only (a product
+// with a zero component is not folded away under IEEE rules; -0 + v is).
+__device__ __forceinline__ float cdot(int i, float x, float y, float z) {
+  float r = -0.0f;
+  if (cx(i) > 0) r = r + x;
+  if (cx(i) < 0) r = r - x;
+  if (cy(i) > 0) r = r + y;
+  if (cy(i) < 0) r = r - y;
+  if (cz(i) > 0) r = r + z;
+  if (cz(i) < 0) r = r - z;
+  return r;
+}
+
+// The moving-wall term of a population that bounces back: 6 w_i (c_i . u_w)
+// with the wall moving along x at -uw (bottom, c_z < 0) or +uw (top).
+__device__ __forceinline__ float wall_kick(int i, float uw) {
+  if (cx(i) == 0) return 0.0f;
+  return 6.0f * (float)wgt(i) * (float)(cx(i) * (cz(i) < 0 ? -1 : 1)) * uw;
+}
+
 template <bool LINEAR, bool FORCE>
 __device__ __forceinline__ void collide(float (&d)[Q], float gx, float gy, float gz,
                                         float inv_tau, float guo_pre) {
@@ -113,25 +151,38 @@ __device__ __forceinline__ void collide(float (&d)[Q], float gx, float gy, float
     if (cz(i)) jz += cz(i) * d[i];
   }
   const float rho = 1.0f + drho;
-  const float inv_rho = 1.0f / rho;
-  const float ux = (jx + 0.5f * gx) * inv_rho;
-  const float uy = (jy + 0.5f * gy) * inv_rho;
-  const float uz = (jz + 0.5f * gz) * inv_rho;
-  const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
-  const float gu = ux * gx + uy * gy + uz * gz;
+  const float inv_rho = __builtin_amdgcn_rcpf(rho);  // 1 ulp; rho is near 1
+  float ux = jx, uy = jy, uz = jz;
+  if (FORCE) {
+    ux += 0.5f * gx;
+    uy += 0.5f * gy;
+    uz += 0.5f * gz;
+  }
+  ux *= inv_rho;
+  uy *= inv_rho;
+  uz *= inv_rho;
+  const float om1 = 1.0f - inv_tau;
+  const float a = 3.0f * inv_tau * rho;
+  const float b = LINEAR ? 0.0f : 1.5f * a;
+  float C0 = LINEAR ? drho * inv_tau : (drho - 1.5f * rho * (ux * ux + uy * uy + uz * uz)) * inv_tau;
+  float ex = 0.0f, ey = 0.0f, ez = 0.0f;
+  if (FORCE) {
+    const float e = 3.0f * guo_pre;
+    ex = e * gx;
+    ey = e * gy;
+    ez = e * gz;
+    C0 -= ux * ex + uy * ey + uz * ez;
+  }
+  d[0] = om1 * d[0] + (float)wgt(0) * C0;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
+  for (int i = 1; i < Q; i += 2) {
     const float w = (float)wgt(i);
-    const float cu = cx(i) * ux + cy(i) * uy + cz(i) * uz;
-    float deq;
-    if (LINEAR) deq = w * (drho + rho * 3.0f * cu);
-    else deq = w * (drho + rho * (3.0f * cu + 4.5f * cu * cu - usq15));
-    float post = d[i] - (d[i] - deq) * inv_tau;
-    if (FORCE) {
-      const float cg = cx(i) * gx + cy(i) * gy + cz(i) * gz;
-      post += guo_pre * w * (3.0f * (cg - gu) + 9.0f * cu * cg);
-    }
-    d[i] = post;
+    const float p = cdot(i, ux, uy, uz);
+    const float q = FORCE ? cdot(i, ex, ey, ez) : 0.0f;
+    const float S = C0 + p * (b * p + 3.0f * q);
+    const float A = a * p + q;
+    d[i] = om1 * d[i] + w * (S + A);
+    d[i + 1] = om1 * d[i + 1] + w * (S - A);
   }
 }
 
@@ -154,8 +205,8 @@ __device__ __forceinline__ void collide_stream_nodes(const LatDev &L, int src, i
   float d[VEC][Q];
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float inv = 1.0f / L.h_scale[i];
-    const long long at = pidx(L, i, row0, x0);
+    const float inv = L.h_inv[i];
+    const long long at = pidx_c(L, i, row0, x0);
     if constexpr (VEC == 2) Pop<T>::template ld2<NT>(fs, at, inv, d[0][i], d[1][i]);
     else d[0][i] = Pop<T>::template ld<NT>(fs, at, inv);
   }
@@ -196,15 +247,14 @@ __device__ __forceinline__ void collide_stream_nodes(const LatDev &L, int src, i
   for (int i = 0; i < Q; ++i) {
     const int zt = z + cz(i);
     if (cz(i) != 0 && (zt < 0 || zt >= L.nz)) {
-      const float uwall = (zt < 0) ? -L.uw : L.uw;
-      const float kick = 6.0f * (float)wgt(i) * (float)cx(i) * uwall;
-      const long long at = pidx(L, opp(i), row0, x0);
+      const float kick = wall_kick(i, L.uw);
+      const long long at = pidx_c(L, opp(i), row0, x0);
       if constexpr (VEC == 2)
         Pop<T>::template st2<NT>(fd, at, d[0][i] - kick, d[1][i] - kick, L.h_scale[opp(i)]);
       else Pop<T>::template st<NT>(fd, at, d[0][i] - kick, L.h_scale[opp(i)]);
     } else {
       const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
-      const long long row = pidx(L, i, (long long)zt * L.ny + yt, 0);
+      const long long row = pidx_c(L, i, (long long)zt * L.ny + yt, 0);
       if (cx(i) == 0) {
         if constexpr (VEC == 2) Pop<T>::template st2<NT>(fd, row + x0, d[0][i], d[1][i], L.h_scale[i]);
         else Pop<T>::template st<NT>(fd, row + x0, d[0][i], L.h_scale[i]);
@@ -314,7 +364,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       float v[4];
-      Pop4<T>::ld(fs, pidx(L, i, row0, x0), 1.0f / L.h_scale[i], v);
+      Pop4<T>::ld(fs, pidx_c(L, i, row0, x0), L.h_inv[i], v);
 #pragma unroll
       for (int k = 0; k < VEC; ++k) d[k][i] = v[k];
     }
@@ -359,18 +409,159 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     if (!live) continue;
     const int zt = z + cz(i);
     if (cz(i) != 0 && (zt < 0 || zt >= L.nz)) {
-      const float uwall = (zt < 0) ? -L.uw : L.uw;
-      const float kick = 6.0f * (float)wgt(i) * (float)cx(i) * uwall;
-      Pop4<T>::st(fd, pidx(L, opp(i), row0, x0), d[0][i] - kick, d[1][i] - kick, d[2][i] - kick,
+      const float kick = wall_kick(i, L.uw);
+      Pop4<T>::st(fd, pidx_c(L, opp(i), row0, x0), d[0][i] - kick, d[1][i] - kick, d[2][i] - kick,
                   d[3][i] - kick, L.h_scale[opp(i)]);
     } else {
       const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
-      const long long at = pidx(L, i, (long long)zt * L.ny + yt, x0);
+      const long long at = pidx_c(L, i, (long long)zt * L.ny + yt, x0);
       if (cx(i) > 0) Pop4<T>::st(fd, at, in, d[0][i], d[1][i], d[2][i], L.h_scale[i]);
       else if (cx(i) < 0) Pop4<T>::st(fd, at, d[1][i], d[2][i], d[3][i], in, L.h_scale[i]);
       else Pop4<T>::st(fd, at, d[0][i], d[1][i], d[2][i], d[3][i], L.h_scale[i]);
     }
   }
+}
+
+// FP16 row-vector form with eight nodes per thread: one aligned 16-byte
+// access per population, as in the FP32 form, instead of eight bytes.  The
+// populations stay packed (two halves per register) between the load and the
+// store: each node is unpacked, collided, and its post-collision values are
+// rounded once into the slots it came from.  The +-x streaming shift moves one
+// half-word across the eight-node segments: the neighbour lane's end word
+// arrives by a lane shuffle and the segment is re-aligned by a 16-bit funnel
+// shift.  Bounce-back rows apply the wall kick before rounding (the scale of
+// a direction equals that of its opposite, both w_i being equal).
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ float half_lo(unsigned int w) {
+  return __half2float(__ushort_as_half((unsigned short)(w & 0xffffu)));
+}
+__device__ __forceinline__ float half_hi(unsigned int w) {
+  return __half2float(__ushort_as_half((unsigned short)(w >> 16)));
+}
+
+template <bool LINEAR, bool FORCE>
+__global__ __launch_bounds__(256) void k_collide_stream_rows8(LatDev L, int src, int par, int tpr) {
+  constexpr int VEC = 8;
+  const int lane = threadIdx.x & 63;
+  const int t = lane % tpr;
+  const int row = (blockIdx.x * (int)blockDim.x + (int)threadIdx.x) / tpr;
+  const bool live = row < L.ny * L.nz;
+  const int y = live ? row % L.ny : 0;
+  const int z = live ? row / L.ny : 0;
+  const int x0 = t * VEC;
+  const long long S = L.S;
+  const long long n0 = ((long long)z * L.ny + y) * (long long)L.nx + x0;
+  const long long row0 = (long long)z * L.ny + y;
+  const unsigned short *__restrict__ fs = static_cast<const unsigned short *>(L.f[src]);
+  unsigned short *__restrict__ fd = static_cast<unsigned short *>(L.f[src ^ 1]);
+  const int row_lane0 = lane - t;
+  const int left = row_lane0 + (t == 0 ? tpr - 1 : t - 1);
+  const int right = row_lane0 + (t == tpr - 1 ? 0 : t + 1);
+  // z walls this row touches: directions leaving through them bounce back
+  const bool wall_lo = z == 0, wall_hi = z == L.nz - 1;
+
+  unsigned int w[Q][4];
+  if (live) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const u32x4 r = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(fs + pidx_c(L, i, row0, x0)));
+      w[i][0] = r.x;
+      w[i][1] = r.y;
+      w[i][2] = r.z;
+      w[i][3] = r.w;
+    }
+    float g[VEC][3];
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) g[k][0] = g[k][1] = g[k][2] = 0.0f;
+    if (FORCE) {
+      // the segment spans two force tiles along x (TILE_X = 4)
+      const int step = L.ctrl->step;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int tile = tile_of(L, x0 + 4 * h, y, z);
+        if (L.stamp[par][tile] == step) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c) {
+            float v[4];
+            Pop4<float>::ld(L.g[par], c * S + n0 + 4 * h, 1.0f, v);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) g[4 * h + k][c] = v[k];
+          }
+        }
+        if (L.stamp[par ^ 1][tile] == step - 1) {
+#pragma unroll
+          for (int c = 0; c < 3; ++c)
+            Pop4<float>::st(L.g[par ^ 1], c * S + n0 + 4 * h, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f);
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < VEC; ++k) {
+      const int j = k >> 1;
+      float d[Q];
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        d[i] = ((k & 1) ? half_hi(w[i][j]) : half_lo(w[i][j])) * (L.h_inv[i]);
+      collide<LINEAR, FORCE>(d, g[k][0], g[k][1], g[k][2], L.inv_tau, L.guo_pre);
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        float v = d[i];
+        if (cz(i) != 0 && (cz(i) < 0 ? wall_lo : wall_hi))
+          v -= wall_kick(i, L.uw);
+        const unsigned int q = (unsigned int)__half_as_ushort(__float2half_rn(v * L.h_scale[i]));
+        w[i][j] = (k & 1) ? ((w[i][j] & 0xffffu) | (q << 16)) : ((w[i][j] & 0xffff0000u) | q);
+      }
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) w[i][0] = w[i][1] = w[i][2] = w[i][3] = 0u;
+  }
+
+  const int ym = (y == 0) ? L.ny - 1 : y - 1;
+  const int yp = (y == L.ny - 1) ? 0 : y + 1;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    unsigned int in = 0u;
+    if (cx(i) > 0) in = (unsigned int)__shfl((int)w[i][3], left);
+    if (cx(i) < 0) in = (unsigned int)__shfl((int)w[i][0], right);
+    if (!live) continue;
+    u32x4 o;
+    long long at;
+    if (cz(i) != 0 && (cz(i) < 0 ? wall_lo : wall_hi)) {
+      at = pidx_c(L, opp(i), row0, x0);
+      o = u32x4{w[i][0], w[i][1], w[i][2], w[i][3]};
+    } else {
+      const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
+      at = pidx_c(L, i, (long long)(z + cz(i)) * L.ny + yt, x0);
+      if (cx(i) > 0)
+        o = u32x4{__builtin_amdgcn_alignbit(w[i][0], in, 16), __builtin_amdgcn_alignbit(w[i][1], w[i][0], 16),
+                  __builtin_amdgcn_alignbit(w[i][2], w[i][1], 16), __builtin_amdgcn_alignbit(w[i][3], w[i][2], 16)};
+      else if (cx(i) < 0)
+        o = u32x4{__builtin_amdgcn_alignbit(w[i][1], w[i][0], 16), __builtin_amdgcn_alignbit(w[i][2], w[i][1], 16),
+                  __builtin_amdgcn_alignbit(w[i][3], w[i][2], 16), __builtin_amdgcn_alignbit(in, w[i][3], 16)};
+      else
+        o = u32x4{w[i][0], w[i][1], w[i][2], w[i][3]};
+    }
+    __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(fd + at));
+  }
+}
+
+static bool launch_cs_rows8(const LatDev &L, int src, int par, bool force, bool linear,
+                            hipStream_t s) {
+  if (L.nx % 8 != 0) return false;
+  const int tpr = L.nx / 8;
+  if (tpr > 64 || 64 % tpr != 0) return false;
+  const long long threads = (long long)L.ny * L.nz * tpr;
+  const dim3 b(256), g((unsigned)((threads + 255) / 256));
+  if (force) {
+    if (linear) k_collide_stream_rows8<true, true><<<g, b, 0, s>>>(L, src, par, tpr);
+    else k_collide_stream_rows8<false, true><<<g, b, 0, s>>>(L, src, par, tpr);
+  } else {
+    if (linear) k_collide_stream_rows8<true, false><<<g, b, 0, s>>>(L, src, par, tpr);
+    else k_collide_stream_rows8<false, false><<<g, b, 0, s>>>(L, src, par, tpr);
+  }
+  return true;
 }
 
 template <typename T>
@@ -425,7 +616,11 @@ static void launch_cs_t(const LatDev &L, int src, int par, bool force, bool line
                         int variant, hipStream_t s) {
   // variant bits: 1 = two nodes per thread, 2 = non-temporal accesses,
   // 4 = 128-thread blocks, 8 = 64-thread blocks, 16 = row-vector kernel
-  // (four nodes per thread, whole rows per wavefront) where the row fits
+  // (four nodes per thread, whole rows per wavefront) where the row fits,
+  // 32 = with FP16 storage, eight nodes per thread in that form (nx / 8
+  // dividing 64)
+  if constexpr (sizeof(T) == 2)
+    if ((variant & 48) == 48 && launch_cs_rows8(L, src, par, force, linear, s)) return;
   if ((variant & 16) && launch_cs_rows<T>(L, src, par, force, linear, s)) return;
   const bool vec2 = (variant & 1) && (L.nx % 2 == 0);
   const bool nt = (variant & 2) != 0;
@@ -497,7 +692,7 @@ __global__ __launch_bounds__(256) void k_get_field(LatDev L, int src, int gpar, 
   double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double d = ld_dev<T>(f, pidx(L, i, (long long)z * L.ny + y, x), 1.0f / L.h_scale[i]);
+    const double d = ld_dev<T>(f, pidx(L, i, (long long)z * L.ny + y, x), L.h_inv[i]);
     if (what == 0) out[i * N + n] = wgt(i) + d;
     drho += d;
     jx += cx(i) * d;

@@ -549,7 +549,7 @@ __device__ __forceinline__ float3 lattice_velocity(const LatDev &L, const T *f, 
   float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float d = ld_pop<T>(f, pidx(L, i, row, X), 1.0f / L.h_scale[i]);
+    const float d = ld_pop<T>(f, pidx(L, i, row, X), L.h_inv[i]);
     drho += d;
     if (cx(i)) jx += cx(i) * d;
     if (cy(i)) jy += cy(i) * d;

@@ -13,7 +13,7 @@ import numpy as np
 import pytest
 
 from paper_1004_2416_amd import workloads as W
-from parity_helpers import Case, WEIGHTS, deformed_mesh, rep_positions, scaled_err
+from parity_helpers import Case, O, WEIGHTS, deformed_mesh, rep_positions, scaled_err
 
 pytestmark = pytest.mark.gpu
 
@@ -81,13 +81,14 @@ def test_fp16_store_is_the_stated_rounding(B):
     assert np.array_equal(got, rep16(sim.f)), float(np.max(np.abs(got - rep16(sim.f))))
 
 
-@pytest.mark.parametrize("m", [2, 4])
-def test_fp16_one_step_error(B, m):
+@pytest.mark.parametrize("m,n", [(2, (30, 20, 16)), (4, (30, 20, 16)), (3, (32, 20, 16))])
+def test_fp16_one_step_error(B, m, n):
     """One coupled step from an identical (FP16-representable) deformed
     state: populations within 2^-11 (+ FP32 slack) of the largest
     deviation, force density as in FP32, node velocities and positions
-    within the error the rounded populations carry."""
-    c = small_case(m=m)
+    within the error the rounded populations carry.  nx = 30 runs the
+    per-node collide-stream form, nx = 32 the eight-node row form."""
+    c = small_case(m=m, n=n)
     sim = c.oracle()
     assert sim.run(40) == 0
     f_s = rep16(sim.f)
@@ -171,3 +172,64 @@ def test_fp16_full_size_step(B):
     assert errs["f_dev"] < 1.05 * HALF_ULP
     assert errs["F"] < 1e-5 and errs["g"] < 1e-5
     assert errs["u_abs"] < ub
+
+
+def collide_stream_form(variant, nx):
+    """The collide-stream form the library runs with FP16 storage for this
+    IBM_OPT_LBM_VARIANT and row length."""
+    def fits(vec):
+        return nx % vec == 0 and nx // vec <= 64 and 64 % (nx // vec) == 0
+    if (variant & 48) == 48 and fits(8):
+        return "rows8"
+    return "rows4" if (variant & 16) and fits(4) else "nodes"
+
+
+def test_fp16_collide_stream_forms_agree(B):
+    """The FP16 collide-stream forms on rows of 8 (one lane per row) to 512
+    nodes (a whole wavefront per row), with and without a capsule's forces,
+    with wall bounce-back.  Each form's first step from an FP16-representable
+    state is within 2^-11 of the largest deviation from the FP64 oracle's.
+    The forms evaluate the same FP32 expressions, but the compiler may
+    contract a product into a sum differently in each, and with a capsule
+    the spreading's FP32 atomics sum in a varying order; a last-bit FP32
+    difference can then round to the neighbouring FP16 value, so after five
+    steps the forms agree within one FP16 ulp (2^-10) of the largest
+    deviation."""
+    forms = (55, 23, 7, 0)
+    shapes = [((32, 20, 16), True), ((64, 12, 10), False), ((8, 6, 5), False),
+              ((16, 10, 9), False), ((256, 6, 4), False), ((512, 4, 3), False)]
+    for n, with_capsule in shapes:
+        if with_capsule:
+            c = small_case(n=n)
+        else:
+            c = Case(W.Workload("rows16", *n, 1.0, 0.03, 3, 0, []), perturb=0.01, seed=n[0])
+            f_s = rep16(c.f0)
+            one = O.lbm_step(f_s, None, c.wl.tau, c.wl.u_w)
+        ref = None
+        for v in forms:
+            lat = c.gpu(storage="fp16", graph=False)
+            lat.set_option(B.OPT_LBM_VARIANT, v)
+            if not with_capsule:
+                lat.set_populations(f_s)
+                lat.step(1)
+                e1 = dev_err(lat.populations().cpu().numpy(), one)
+                assert e1 < 1.05 * HALF_ULP, (n, v, e1)
+            lat.step(5)
+            f = lat.populations().cpu().numpy()
+            x = lat.mesh()[0].cpu().numpy() if with_capsule else None
+            lat.close()
+            form = collide_stream_form(v, n[0])
+            if ref is None:
+                ref = (f, x, form)
+                continue
+            e = dev_err(f, ref[0])
+            say("  fp16 forms n=%s variant %d (%s vs %s): max |df| / max |f - w| %.2e"
+                % (n, v, form, ref[2], e))
+            assert e <= 2 * HALF_ULP, (n, v)
+            if with_capsule:
+                assert np.max(np.abs(x - ref[1])) < 1e-6, (n, v)
+    lat = c.gpu(storage="fp16", graph=False)
+    lat.set_option(B.OPT_LBM_VARIANT, 63)
+    with pytest.raises(B.IBMError):
+        lat.set_option(B.OPT_LBM_VARIANT, 64)
+    lat.close()

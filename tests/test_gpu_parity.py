@@ -202,7 +202,7 @@ def test_autotune_keeps_the_run_on_the_oracle(B):
     chosen = lat.autotune(16)
     n = lat.steps
     say("  autotune chose", chosen, "after", n, "steps")
-    assert 0 <= chosen["lbm_variant"] < 32 and 0 <= chosen["stencil_box"] < 4
+    assert 0 <= chosen["lbm_variant"] < 64 and 0 <= chosen["stencil_box"] < 4
     sim = c.oracle()
     assert sim.run(n) == 0
     f = lat.populations().cpu().numpy()
