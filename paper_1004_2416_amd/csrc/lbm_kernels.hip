@@ -139,17 +139,33 @@ __device__ __forceinline__ float wall_kick(int i, float uw) {
   return 6.0f * (float)wgt(i) * (float)(cx(i) * (cz(i) < 0 ? -1 : 1)) * uw;
 }
 
-template <bool LINEAR, bool FORCE>
+// SCALED: d holds D_i = (f_i - w_i) 16 / w_i, the FP16 storage units, in and
+// out.  The moments take w_i / 16 per weight class, and the update becomes
+// D_i' = (1 - 1/tau) D_i + 16 t(c_i.u, c_i.e): the factor 16 goes into the node
+// scalars, so neither the load nor the store needs a per-direction scale.
+template <bool LINEAR, bool FORCE, bool SCALED = false>
 __device__ __forceinline__ void collide(float (&d)[Q], float gx, float gy, float gz,
                                         float inv_tau, float guo_pre) {
-  float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+  // partial sums per weight class: rest, axis (1-6), diagonal (7-18)
+  float sa = -0.0f, sd = -0.0f, xa = -0.0f, xd = -0.0f, ya = -0.0f, yd = -0.0f, za = -0.0f,
+        zd = -0.0f;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    drho += d[i];
-    if (cx(i)) jx += cx(i) * d[i];
-    if (cy(i)) jy += cy(i) * d[i];
-    if (cz(i)) jz += cz(i) * d[i];
+  for (int i = 1; i < Q; ++i) {
+    float &s = i <= 6 ? sa : sd, &jx = i <= 6 ? xa : xd, &jy = i <= 6 ? ya : yd,
+          &jz = i <= 6 ? za : zd;
+    s = s + d[i];
+    if (cx(i) > 0) jx = jx + d[i];
+    if (cx(i) < 0) jx = jx - d[i];
+    if (cy(i) > 0) jy = jy + d[i];
+    if (cy(i) < 0) jy = jy - d[i];
+    if (cz(i) > 0) jz = jz + d[i];
+    if (cz(i) < 0) jz = jz - d[i];
   }
+  constexpr float k0 = SCALED ? (float)(wgt(0) / 16.0) : 1.0f;
+  constexpr float ka = SCALED ? (float)(wgt(1) / 16.0) : 1.0f;
+  constexpr float kd = SCALED ? (float)(wgt(7) / 16.0) : 1.0f;
+  const float drho = k0 * d[0] + ka * sa + kd * sd;
+  const float jx = ka * xa + kd * xd, jy = ka * ya + kd * yd, jz = ka * za + kd * zd;
   const float rho = 1.0f + drho;
   const float inv_rho = __builtin_amdgcn_rcpf(rho);  // 1 ulp; rho is near 1
   float ux = jx, uy = jy, uz = jz;
@@ -161,29 +177,54 @@ __device__ __forceinline__ void collide(float (&d)[Q], float gx, float gy, float
   ux *= inv_rho;
   uy *= inv_rho;
   uz *= inv_rho;
+  constexpr float sc = SCALED ? 16.0f : 1.0f;
   const float om1 = 1.0f - inv_tau;
-  const float a = 3.0f * inv_tau * rho;
+  const float a = (3.0f * sc) * inv_tau * rho;
   const float b = LINEAR ? 0.0f : 1.5f * a;
-  float C0 = LINEAR ? drho * inv_tau : (drho - 1.5f * rho * (ux * ux + uy * uy + uz * uz)) * inv_tau;
+  float C0 = LINEAR ? drho * (sc * inv_tau)
+                    : (drho - 1.5f * rho * (ux * ux + uy * uy + uz * uz)) * (sc * inv_tau);
   float ex = 0.0f, ey = 0.0f, ez = 0.0f;
   if (FORCE) {
-    const float e = 3.0f * guo_pre;
+    const float e = (3.0f * sc) * guo_pre;
     ex = e * gx;
     ey = e * gy;
     ez = e * gz;
     C0 -= ux * ex + uy * ey + uz * ez;
   }
-  d[0] = om1 * d[0] + (float)wgt(0) * C0;
+  if (SCALED) d[0] = om1 * d[0] + C0;
+  else d[0] = om1 * d[0] + (float)wgt(0) * C0;
 #pragma unroll
   for (int i = 1; i < Q; i += 2) {
-    const float w = (float)wgt(i);
     const float p = cdot(i, ux, uy, uz);
     const float q = FORCE ? cdot(i, ex, ey, ez) : 0.0f;
     const float S = C0 + p * (b * p + 3.0f * q);
     const float A = a * p + q;
-    d[i] = om1 * d[i] + w * (S + A);
-    d[i + 1] = om1 * d[i + 1] + w * (S - A);
+    if (SCALED) {
+      d[i] = om1 * d[i] + (S + A);
+      d[i + 1] = om1 * d[i + 1] + (S - A);
+    } else {
+      const float w = (float)wgt(i);
+      d[i] = om1 * d[i] + w * (S + A);
+      d[i + 1] = om1 * d[i + 1] + w * (S - A);
+    }
   }
+}
+
+// The wall term in FP16 storage units: 6 w_i (c_i . u_w) 16 / w_i.
+__device__ __forceinline__ float wall_kick_scaled(int i, float uw) {
+  if (cx(i) == 0) return 0.0f;
+  return 96.0f * (float)(cx(i) * (cz(i) < 0 ? -1 : 1)) * uw;
+}
+
+// 32-bit form of prow / nx (the group-row index of an x row): row + (Q - 1) G
+// (row / G).  Valid while the padded row count times Q is below 2^32, which
+// the launchers of its users check.
+__device__ __forceinline__ unsigned grow32(const LatDev &L, unsigned row) {
+  return row + (((row >> L.gsh) * (unsigned)(Q - 1)) << L.gsh);
+}
+// Element offset of (row, x) within population 0 of its group.
+__device__ __forceinline__ unsigned long long rowoff(const LatDev &L, unsigned row, int x) {
+  return (unsigned long long)grow32(L, row) * (unsigned)L.nx + (unsigned)x;
 }
 
 // One lattice update of VEC consecutive x nodes (x0 .. x0 + VEC - 1) of buffer
@@ -282,7 +323,7 @@ __global__ __launch_bounds__(256) void k_collide_stream(LatDev L, int src, int p
 // Row-vector form of the same update for rows that fit one wavefront: each
 // thread owns VEC = 4 consecutive x nodes and tpr = nx / 4 threads (a divisor
 // of 64) hold one whole row, so every population is loaded and stored as one
-// aligned 16-byte vector.  The +-x streaming shift moves one value per row
+// aligned vector (16 bytes in FP32, 8 in FP16).  The +-x streaming shift moves one value per row
 // segment to the neighbouring thread with a lane shuffle (the row's ends wrap
 // into each other, which is the periodic boundary along x).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
@@ -351,8 +392,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const long long nxl = L.nx;
   const long long plane = nxl * L.ny;
   const long long n0 = (long long)z * plane + (long long)y * nxl + x0;
-  const long long row0 = (long long)z * L.ny + y;
-  const T *__restrict__ fs = static_cast<const T *>(L.f[src]);
+  // FP16 values are used in their storage units (collide<..., SCALED>)
+  constexpr bool SC = sizeof(T) == 2;
+  const unsigned row0 = (unsigned)(z * L.ny + y);
+  const unsigned long long off0 = rowoff(L, row0, x0);
   T *__restrict__ fd = static_cast<T *>(L.f[src ^ 1]);
   // lanes holding the left and right neighbours of this segment in the row
   const int row_lane0 = lane - t;
@@ -364,7 +407,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       float v[4];
-      Pop4<T>::ld(fs, pidx_c(L, i, row0, x0), L.h_inv[i], v);
+      Pop4<T>::ld(static_cast<const T *>(L.f[src]) + L.pst[i], off0, 1.0f, v);
 #pragma unroll
       for (int k = 0; k < VEC; ++k) d[k][i] = v[k];
     }
@@ -390,7 +433,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
 #pragma unroll
     for (int k = 0; k < VEC; ++k)
-      collide<LINEAR, FORCE>(d[k], g[k][0], g[k][1], g[k][2], L.inv_tau, L.guo_pre);
+      collide<LINEAR, FORCE, SC>(d[k], g[k][0], g[k][1], g[k][2], L.inv_tau, L.guo_pre);
   } else {
 #pragma unroll
     for (int i = 0; i < Q; ++i)
@@ -409,15 +452,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     if (!live) continue;
     const int zt = z + cz(i);
     if (cz(i) != 0 && (zt < 0 || zt >= L.nz)) {
-      const float kick = wall_kick(i, L.uw);
-      Pop4<T>::st(fd, pidx_c(L, opp(i), row0, x0), d[0][i] - kick, d[1][i] - kick, d[2][i] - kick,
-                  d[3][i] - kick, L.h_scale[opp(i)]);
+      const float kick = SC ? wall_kick_scaled(i, L.uw) : wall_kick(i, L.uw);
+      Pop4<T>::st(fd + L.pst[opp(i)], off0, d[0][i] - kick, d[1][i] - kick, d[2][i] - kick,
+                  d[3][i] - kick, 1.0f);
     } else {
       const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
-      const long long at = pidx_c(L, i, (long long)zt * L.ny + yt, x0);
-      if (cx(i) > 0) Pop4<T>::st(fd, at, in, d[0][i], d[1][i], d[2][i], L.h_scale[i]);
-      else if (cx(i) < 0) Pop4<T>::st(fd, at, d[1][i], d[2][i], d[3][i], in, L.h_scale[i]);
-      else Pop4<T>::st(fd, at, d[0][i], d[1][i], d[2][i], d[3][i], L.h_scale[i]);
+      T *base = fd + L.pst[i];
+      const unsigned long long at = rowoff(L, (unsigned)(zt * L.ny + yt), x0);
+      if (cx(i) > 0) Pop4<T>::st(base, at, in, d[0][i], d[1][i], d[2][i], 1.0f);
+      else if (cx(i) < 0) Pop4<T>::st(base, at, d[1][i], d[2][i], d[3][i], in, 1.0f);
+      else Pop4<T>::st(base, at, d[0][i], d[1][i], d[2][i], d[3][i], 1.0f);
     }
   }
 }
@@ -429,8 +473,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // rounded once into the slots it came from.  The +-x streaming shift moves one
 // half-word across the eight-node segments: the neighbour lane's end word
 // arrives by a lane shuffle and the segment is re-aligned by a 16-bit funnel
-// shift.  Bounce-back rows apply the wall kick before rounding (the scale of
-// a direction equals that of its opposite, both w_i being equal).
+// shift.  Values are used in their storage units (collide<..., SCALED>);
+// bounce-back rows apply the wall kick in those units before rounding (a
+// direction and its opposite share w_i, hence their units).
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ float half_lo(unsigned int w) {
@@ -452,7 +497,8 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows8(LatDev L, int src,
   const int x0 = t * VEC;
   const long long S = L.S;
   const long long n0 = ((long long)z * L.ny + y) * (long long)L.nx + x0;
-  const long long row0 = (long long)z * L.ny + y;
+  const unsigned row0 = (unsigned)(z * L.ny + y);
+  const unsigned long long off0 = rowoff(L, row0, x0);
   const unsigned short *__restrict__ fs = static_cast<const unsigned short *>(L.f[src]);
   unsigned short *__restrict__ fd = static_cast<unsigned short *>(L.f[src ^ 1]);
   const int row_lane0 = lane - t;
@@ -465,7 +511,7 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows8(LatDev L, int src,
   if (live) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const u32x4 r = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(fs + pidx_c(L, i, row0, x0)));
+      const u32x4 r = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>((fs + L.pst[i]) + off0));
       w[i][0] = r.x;
       w[i][1] = r.y;
       w[i][2] = r.z;
@@ -502,14 +548,14 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows8(LatDev L, int src,
       float d[Q];
 #pragma unroll
       for (int i = 0; i < Q; ++i)
-        d[i] = ((k & 1) ? half_hi(w[i][j]) : half_lo(w[i][j])) * (L.h_inv[i]);
-      collide<LINEAR, FORCE>(d, g[k][0], g[k][1], g[k][2], L.inv_tau, L.guo_pre);
+        d[i] = (k & 1) ? half_hi(w[i][j]) : half_lo(w[i][j]);
+      collide<LINEAR, FORCE, true>(d, g[k][0], g[k][1], g[k][2], L.inv_tau, L.guo_pre);
 #pragma unroll
       for (int i = 0; i < Q; ++i) {
         float v = d[i];
         if (cz(i) != 0 && (cz(i) < 0 ? wall_lo : wall_hi))
-          v -= wall_kick(i, L.uw);
-        const unsigned int q = (unsigned int)__half_as_ushort(__float2half_rn(v * L.h_scale[i]));
+          v -= wall_kick_scaled(i, L.uw);
+        const unsigned int q = (unsigned int)__half_as_ushort(__float2half_rn(v));
         w[i][j] = (k & 1) ? ((w[i][j] & 0xffffu) | (q << 16)) : ((w[i][j] & 0xffff0000u) | q);
       }
     }
@@ -527,13 +573,13 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows8(LatDev L, int src,
     if (cx(i) < 0) in = (unsigned int)__shfl((int)w[i][0], right);
     if (!live) continue;
     u32x4 o;
-    long long at;
+    unsigned short *at;
     if (cz(i) != 0 && (cz(i) < 0 ? wall_lo : wall_hi)) {
-      at = pidx_c(L, opp(i), row0, x0);
+      at = (fd + L.pst[opp(i)]) + off0;
       o = u32x4{w[i][0], w[i][1], w[i][2], w[i][3]};
     } else {
       const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
-      at = pidx_c(L, i, (long long)(z + cz(i)) * L.ny + yt, x0);
+      at = (fd + L.pst[i]) + rowoff(L, (unsigned)((z + cz(i)) * L.ny + yt), x0);
       if (cx(i) > 0)
         o = u32x4{__builtin_amdgcn_alignbit(w[i][0], in, 16), __builtin_amdgcn_alignbit(w[i][1], w[i][0], 16),
                   __builtin_amdgcn_alignbit(w[i][2], w[i][1], 16), __builtin_amdgcn_alignbit(w[i][3], w[i][2], 16)};
@@ -543,13 +589,21 @@ __global__ __launch_bounds__(256) void k_collide_stream_rows8(LatDev L, int src,
       else
         o = u32x4{w[i][0], w[i][1], w[i][2], w[i][3]};
     }
-    __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(fd + at));
+    __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(at));
   }
+}
+
+// Row kernels index x rows with grow32: the padded row count times Q must stay
+// below 2^32.
+static bool rows_fit_32bit(const LatDev &L) {
+  const long long G = 1LL << L.gsh;
+  const long long rows = ((long long)L.ny * L.nz + G - 1) / G * G;
+  return rows * Q < (1LL << 32);
 }
 
 static bool launch_cs_rows8(const LatDev &L, int src, int par, bool force, bool linear,
                             hipStream_t s) {
-  if (L.nx % 8 != 0) return false;
+  if (L.nx % 8 != 0 || !rows_fit_32bit(L)) return false;
   const int tpr = L.nx / 8;
   if (tpr > 64 || 64 % tpr != 0) return false;
   const long long threads = (long long)L.ny * L.nz * tpr;
@@ -567,7 +621,7 @@ static bool launch_cs_rows8(const LatDev &L, int src, int par, bool force, bool 
 template <typename T>
 static bool launch_cs_rows(const LatDev &L, int src, int par, bool force, bool linear,
                            hipStream_t s) {
-  if (L.nx % 4 != 0) return false;
+  if (L.nx % 4 != 0 || !rows_fit_32bit(L)) return false;
   const int tpr = L.nx / 4;
   if (tpr > 64 || 64 % tpr != 0) return false;
   const long long rows = (long long)L.ny * L.nz;
