@@ -45,13 +45,12 @@ def collide_stream_kernel(wl, variant: int, storage: str) -> str:
     """Which collide-stream kernel the library launches for this lattice and
     variant (IBM_OPT_LBM_VARIANT): with FP16 storage and bits 16 and 32 set,
     the eight-node row-vector form when nx / 8 lanes divide a wavefront; with
-    bit 16 the four-node row-vector form when nx / 4 lanes do; else the
-    per-node form."""
-    def fits(vec):
-        return wl.nx % vec == 0 and wl.nx // vec <= 64 and 64 % (wl.nx // vec) == 0
-    if storage == "fp16" and (variant & 48) == 48 and fits(8):
+    bit 16 the four-node row-vector form when a row padded to a multiple of 4
+    has at most 256 values; else the per-node form."""
+    nx = wl.nx
+    if storage == "fp16" and (variant & 48) == 48 and nx % 8 == 0 and 64 % (nx // 8) == 0:
         return "k_collide_stream_rows8"
-    return "k_collide_stream_rows" if (variant & 16) and fits(4) else "k_collide_stream"
+    return "k_collide_stream_rows" if (variant & 16) and (nx + 3) // 4 <= 64 else "k_collide_stream"
 
 
 def measured_traffic(workload: str, storage: str):

@@ -109,7 +109,7 @@ extern "C" {
                                   non-temporal accesses, bit 2: 128-thread,
                                   bit 3: 64-thread blocks, bit 4: four nodes
                                   per thread with whole x rows per wavefront,
-                                  used when nx / 4 divides 64; bit 5 with
+                                  used when nx <= 256; bit 5 with
                                   bit 4 and FP16 storage: eight nodes per
                                   thread, used when nx / 8 divides 64;
                                   default 23);

@@ -48,6 +48,8 @@ constexpr int GRAPH_STEPS = 16;
 struct LatticeLayout {
   long long N, S;
   int gsh;             // log2 of the rows per population group
+  int nxs;             // population row stride (nx rounded up to a multiple of 4)
+  int tpr;             // lanes per row of the row-form kernels (0: not used)
   long long pop_elems;  // elements of one population buffer
   int tnx, tny, tnz;
   size_t off_ctrl, off_stamp[2], off_g[2], off_f[2], total;
@@ -57,13 +59,18 @@ LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
   LatticeLayout l{};
   l.N = (long long)nx * ny * nz;
   l.S = (long long)round_up((size_t)l.N, 64);
-  // rows per group: the smallest power of two (up to 8) whose group holds at
-  // least 128 values per population, so short rows still fill cache lines
+  // x rows padded to a multiple of 4 values (aligned 4-node vectors); rows per
+  // group: the smallest power of two (up to 8) whose group holds at least 128
+  // values per population, so short rows still fill cache lines
+  l.nxs = (nx + 3) / 4 * 4;
   l.gsh = 0;
-  while (l.gsh < 3 && ((long long)nx << l.gsh) < 128) ++l.gsh;
+  while (l.gsh < 3 && ((long long)l.nxs << l.gsh) < 128) ++l.gsh;
   const long long rows = (long long)ny * nz;
   const long long g = 1LL << l.gsh;
-  l.pop_elems = (long long)ibm::Q * ((rows + g - 1) / g * g) * nx;
+  l.pop_elems = (long long)ibm::Q * ((rows + g - 1) / g * g) * l.nxs;
+  // the row form of the collide-stream kernel: a row in one wavefront, and
+  // 32-bit group-row indices (padded rows times Q below 2^32)
+  l.tpr = (l.nxs / 4 <= 64 && (rows + g - 1) / g * g * ibm::Q < (1LL << 32)) ? l.nxs / 4 : 0;
   l.tnx = (nx + ibm::TILE_X - 1) / ibm::TILE_X;
   l.tny = (ny + ibm::TILE_Y - 1) / ibm::TILE_Y;
   l.tnz = (nz + ibm::TILE_Z - 1) / ibm::TILE_Z;
@@ -399,7 +406,11 @@ void batch_items(const std::vector<ibm_lattice *> &runs, std::vector<int2> &li,
   ni.clear();
   for (size_t r = 0; r < runs.size(); ++r) {
     const ibm_lattice *lat = runs[r];
-    const long long nb = ceil_div((long long)lat->nx * lat->ny * lat->nz, 256);
+    // row form: whole rows per wavefront, four wavefronts per block; else one
+    // node per thread
+    const long long rows = (long long)lat->ny * lat->nz;
+    const long long nb = lat->L.tpr ? ceil_div(ceil_div(rows, lat->L.rpw), 4)
+                                    : ceil_div((long long)lat->nx * lat->ny * lat->nz, 256);
     for (long long b = 0; b < nb; ++b) li.push_back(make_int2((int)r, (int)b));
     if (!lat->has_mem) continue;
     const long long nbn = ceil_div((long long)lat->M.nn * group_lanes(lat->M.m), 256);
@@ -564,7 +575,10 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
   L.tnz = lat->lay.tnz;
   L.S = lat->lay.S;
   L.gsh = lat->lay.gsh;
-  for (int i = 0; i < ibm::Q; ++i) L.pst[i] = (long long)i * ((long long)nx << L.gsh);
+  L.nxs = lat->lay.nxs;
+  L.tpr = lat->lay.tpr;
+  L.rpw = L.tpr ? 64 / L.tpr : 0;
+  for (int i = 0; i < ibm::Q; ++i) L.pst[i] = (long long)i * ((long long)L.nxs << L.gsh);
   for (int k = 0; k < 2; ++k) {
     L.f[k] = lat->base + lat->lay.off_f[k];
     L.g[k] = reinterpret_cast<float *>(lat->base + lat->lay.off_g[k]);
@@ -961,7 +975,7 @@ int ibm_autotune(ibm_lattice *lat, int steps_per_trial, int *chosen) {
   // per-node kernel with or without two nodes per thread, non-temporal
   // accesses, 256- or 128-thread blocks
   std::vector<int> cand;
-  const bool rows_ok = lat->nx % 4 == 0 && lat->nx / 4 <= 64 && 64 % (lat->nx / 4) == 0;
+  const bool rows_ok = lat->L.tpr > 0;
   const bool rows8_ok = lat->storage == IBM_STORAGE_FP16 && lat->nx % 8 == 0 &&
                         lat->nx / 8 <= 64 && 64 % (lat->nx / 8) == 0;
   if (rows8_ok) cand.push_back(48);

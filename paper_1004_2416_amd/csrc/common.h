@@ -54,6 +54,9 @@ struct LatDev {
   int tnx, tny, tnz;      // tile grid
   long long S;            // stride between force-density components (elements)
   int gsh;                // log2 of the x rows per population group
+  int nxs;                // population row stride: nx rounded up to a multiple of 4
+  int tpr, rpw;           // row form: lanes per row (nxs / 4) and rows per
+                          // wavefront (64 / tpr), or 0 where it does not apply
   void *f[2];             // population buffers (float or __half), see pidx
   float *g[2];            // force density [3][S] of even and odd steps
   int *stamp[2];          // per-tile step stamps of the two fields
@@ -187,17 +190,18 @@ __device__ __forceinline__ int stencil_lo(float p) {
 }
 
 // Populations are stored interleaved by groups of G = 2^gsh x rows
-// (row = z ny + y): [row / G][i][row % G][x].  Each population of a group is
-// one contiguous run of G nx values (G chosen so that G nx >= 128 where
-// possible), so an update reads and writes a few contiguous kilobytes per
-// group instead of 19 arrays that are megabytes apart.
+// (row = z ny + y): [row / G][i][row % G][x], each x row padded to nxs (a
+// multiple of 4) values.  Each population of a group is one contiguous run
+// of G nxs values (G chosen so that G nxs >= 128 where possible), so an update
+// reads and writes a few contiguous kilobytes per group instead of 19 arrays
+// that are megabytes apart.  The padding (x >= nx) holds no lattice node.
 // pidx(L, i, row, x) = prow(L, row) + i pstride(L) + x: a per-row offset and
 // a stride between the populations of a group that is the same for all rows.
 __device__ __forceinline__ long long prow(const LatDev &L, long long row) {
   const long long g = row >> L.gsh, r = row - (g << L.gsh);
-  return (((g * Q) << L.gsh) + r) * (long long)L.nx;
+  return (((g * Q) << L.gsh) + r) * (long long)L.nxs;
 }
-__device__ __forceinline__ long long pstride(const LatDev &L) { return (long long)L.nx << L.gsh; }
+__device__ __forceinline__ long long pstride(const LatDev &L) { return (long long)L.nxs << L.gsh; }
 __device__ __forceinline__ long long pidx(const LatDev &L, int i, long long row, int x) {
   return prow(L, row) + i * pstride(L) + x;
 }

@@ -224,7 +224,7 @@ __device__ __forceinline__ unsigned grow32(const LatDev &L, unsigned row) {
 }
 // Element offset of (row, x) within population 0 of its group.
 __device__ __forceinline__ unsigned long long rowoff(const LatDev &L, unsigned row, int x) {
-  return (unsigned long long)grow32(L, row) * (unsigned)L.nx + (unsigned)x;
+  return (unsigned long long)grow32(L, row) * (unsigned)L.nxs + (unsigned)x;
 }
 
 // One lattice update of VEC consecutive x nodes (x0 .. x0 + VEC - 1) of buffer
@@ -321,11 +321,14 @@ __global__ __launch_bounds__(256) void k_collide_stream(LatDev L, int src, int p
 }
 
 // Row-vector form of the same update for rows that fit one wavefront: each
-// thread owns VEC = 4 consecutive x nodes and tpr = nx / 4 threads (a divisor
-// of 64) hold one whole row, so every population is loaded and stored as one
-// aligned vector (16 bytes in FP32, 8 in FP16).  The +-x streaming shift moves one value per row
-// segment to the neighbouring thread with a lane shuffle (the row's ends wrap
-// into each other, which is the periodic boundary along x).
+// thread owns 4 consecutive x nodes of the padded row, tpr = nxs / 4 lanes of
+// one wavefront hold one whole row and a wavefront holds rpw = 64 / tpr rows
+// (lanes beyond rpw tpr idle), so every population is loaded and stored as one
+// aligned vector (16 bytes in FP32, 8 in FP16).  The +-x streaming shift moves
+// one value per row segment to the neighbouring lane with a lane shuffle; the
+// row's ends wrap into each other (the periodic boundary along x), at
+// position e = nx - 1 - 4 (tpr - 1) of the last segment when the row is
+// padded (values at x >= nx are computed and written into the padding only).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
@@ -377,77 +380,101 @@ struct Pop4<__half> {
   }
 };
 
-template <typename T, bool LINEAR, bool FORCE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_collide_stream_rows(
-    LatDev L, int src, int par, int tpr) {
-  constexpr int VEC = 4;
-  const int lane = threadIdx.x & 63;
-  const int t = lane % tpr;                    // thread within its row
-  const int row = (blockIdx.x * (int)blockDim.x + (int)threadIdx.x) / tpr;
-  const bool live = row < L.ny * L.nz;
-  const int y = live ? row % L.ny : 0;
-  const int z = live ? row / L.ny : 0;
-  const int x0 = t * VEC;
-  const long long S = L.S;
-  const long long nxl = L.nx;
-  const long long plane = nxl * L.ny;
-  const long long n0 = (long long)z * plane + (long long)y * nxl + x0;
+// x row `row`, segment t (lane `lane` of its wavefront).  All lanes of the
+// wavefront call this together (the shuffles need every lane); `live` is
+// false for idle lanes and rows beyond the lattice.  PAD: nx is not a
+// multiple of 4.
+template <typename T, bool LINEAR, bool FORCE, bool PAD>
+__device__ __forceinline__ void collide_stream_rowseg(const LatDev &L, int src, int par, int row,
+                                                      int t, int lane, bool live) {
   // FP16 values are used in their storage units (collide<..., SCALED>)
   constexpr bool SC = sizeof(T) == 2;
+  const int tpr = L.tpr, last = tpr - 1;
+  const int y = live ? row % L.ny : 0;
+  const int z = live ? row / L.ny : 0;
+  const int x0 = t * 4;
+  // nodes of this segment inside the row, and the slot of x = nx - 1 in the
+  // last segment
+  const int nval = PAD ? min(4, L.nx - x0) : 4;
+  const int e = PAD ? L.nx - 1 - 4 * last : 3;
+  const long long S = L.S;
+  const long long n0 = ((long long)z * L.ny + y) * L.nx + x0;
   const unsigned row0 = (unsigned)(z * L.ny + y);
   const unsigned long long off0 = rowoff(L, row0, x0);
   T *__restrict__ fd = static_cast<T *>(L.f[src ^ 1]);
   // lanes holding the left and right neighbours of this segment in the row
   const int row_lane0 = lane - t;
-  const int left = row_lane0 + (t == 0 ? tpr - 1 : t - 1);
-  const int right = row_lane0 + (t == tpr - 1 ? 0 : t + 1);
+  const int left = live ? row_lane0 + (t == 0 ? last : t - 1) : lane;
+  const int right = live ? row_lane0 + (t == last ? 0 : t + 1) : lane;
 
-  float d[VEC][Q];
+  float d[4][Q];
   if (live) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       float v[4];
       Pop4<T>::ld(static_cast<const T *>(L.f[src]) + L.pst[i], off0, 1.0f, v);
 #pragma unroll
-      for (int k = 0; k < VEC; ++k) d[k][i] = v[k];
+      for (int k = 0; k < 4; ++k) d[k][i] = v[k];
     }
-    float g[VEC][3];
+    float g[4][3];
 #pragma unroll
-    for (int k = 0; k < VEC; ++k) g[k][0] = g[k][1] = g[k][2] = 0.0f;
+    for (int k = 0; k < 4; ++k) g[k][0] = g[k][1] = g[k][2] = 0.0f;
     if (FORCE) {
+      // the force density is unpadded, [3][S] with x fastest: aligned vectors
+      // only when nx is a multiple of 4
       const int step = L.ctrl->step;
       const int tile = tile_of(L, x0, y, z);
       if (L.stamp[par][tile] == step) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
-          float v[4];
-          Pop4<float>::ld(L.g[par], c * S + n0, 1.0f, v);
+          if (PAD) {
 #pragma unroll
-          for (int k = 0; k < VEC; ++k) g[k][c] = v[k];
+            for (int k = 0; k < 4; ++k)
+              if (k < nval) g[k][c] = L.g[par][c * S + n0 + k];
+          } else {
+            float v[4];
+            Pop4<float>::ld(L.g[par], c * S + n0, 1.0f, v);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) g[k][c] = v[k];
+          }
         }
       }
       if (L.stamp[par ^ 1][tile] == step - 1) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) Pop4<float>::st(L.g[par ^ 1], c * S + n0, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f);
+        for (int c = 0; c < 3; ++c) {
+          if (PAD) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              if (k < nval) L.g[par ^ 1][c * S + n0 + k] = 0.0f;
+          } else {
+            Pop4<float>::st(L.g[par ^ 1], c * S + n0, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f);
+          }
+        }
       }
     }
 #pragma unroll
-    for (int k = 0; k < VEC; ++k)
+    for (int k = 0; k < 4; ++k)
       collide<LINEAR, FORCE, SC>(d[k], g[k][0], g[k][1], g[k][2], L.inv_tau, L.guo_pre);
   } else {
 #pragma unroll
     for (int i = 0; i < Q; ++i)
 #pragma unroll
-      for (int k = 0; k < VEC; ++k) d[k][i] = 0.0f;
+      for (int k = 0; k < 4; ++k) d[k][i] = 0.0f;
   }
 
   const int ym = (y == 0) ? L.ny - 1 : y - 1;
   const int yp = (y == L.ny - 1) ? 0 : y + 1;
+  const bool wrap = PAD && t == last;  // this segment holds x = nx - 1 at slot e
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     // every lane takes part in the shuffles, live or not
     float in = 0.0f;
-    if (cx(i) > 0) in = __shfl(d[VEC - 1][i], left);
+    if (cx(i) > 0) {
+      // the last segment hands x = nx - 1 on to x = 0 of the row
+      float v = d[3][i];
+      if (wrap) v = e == 0 ? d[0][i] : (e == 1 ? d[1][i] : (e == 2 ? d[2][i] : d[3][i]));
+      in = __shfl(v, left);
+    }
     if (cx(i) < 0) in = __shfl(d[0][i], right);
     if (!live) continue;
     const int zt = z + cz(i);
@@ -459,11 +486,35 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
       T *base = fd + L.pst[i];
       const unsigned long long at = rowoff(L, (unsigned)(zt * L.ny + yt), x0);
-      if (cx(i) > 0) Pop4<T>::st(base, at, in, d[0][i], d[1][i], d[2][i], 1.0f);
-      else if (cx(i) < 0) Pop4<T>::st(base, at, d[1][i], d[2][i], d[3][i], in, 1.0f);
-      else Pop4<T>::st(base, at, d[0][i], d[1][i], d[2][i], d[3][i], 1.0f);
+      if (cx(i) > 0) {
+        Pop4<T>::st(base, at, in, d[0][i], d[1][i], d[2][i], 1.0f);
+      } else if (cx(i) < 0) {
+        // slot k takes x0 + k + 1; in the last segment x = nx - 1 (slot e)
+        // takes x = 0 of the row (`in`), slots beyond e are padding
+        float o0 = d[1][i], o1 = d[2][i], o2 = d[3][i];
+        if (wrap) {
+          o0 = e == 0 ? in : o0;
+          o1 = e <= 1 ? in : o1;
+          o2 = e <= 2 ? in : o2;
+        }
+        Pop4<T>::st(base, at, o0, o1, o2, in, 1.0f);
+      } else {
+        Pop4<T>::st(base, at, d[0][i], d[1][i], d[2][i], d[3][i], 1.0f);
+      }
     }
   }
+}
+
+template <typename T, bool LINEAR, bool FORCE, bool PAD>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_collide_stream_rows(
+    LatDev L, int src, int par) {
+  const int lane = threadIdx.x & 63;
+  const int wave = (blockIdx.x * (int)blockDim.x + (int)threadIdx.x) >> 6;
+  const int r = lane / L.tpr;  // row within the wavefront
+  const int t = lane - r * L.tpr;
+  const int row = wave * L.rpw + r;
+  collide_stream_rowseg<T, LINEAR, FORCE, PAD>(L, src, par, row, t, lane,
+                                               r < L.rpw && row < L.ny * L.nz);
 }
 
 // FP16 row-vector form with eight nodes per thread: one aligned 16-byte
@@ -618,22 +669,28 @@ static bool launch_cs_rows8(const LatDev &L, int src, int par, bool force, bool 
   return true;
 }
 
+template <typename T, bool PAD>
+static void launch_cs_rows_p(const LatDev &L, int src, int par, bool force, bool linear, dim3 g,
+                             hipStream_t s) {
+  const dim3 b(256);
+  if (force) {
+    if (linear) k_collide_stream_rows<T, true, true, PAD><<<g, b, 0, s>>>(L, src, par);
+    else k_collide_stream_rows<T, false, true, PAD><<<g, b, 0, s>>>(L, src, par);
+  } else {
+    if (linear) k_collide_stream_rows<T, true, false, PAD><<<g, b, 0, s>>>(L, src, par);
+    else k_collide_stream_rows<T, false, false, PAD><<<g, b, 0, s>>>(L, src, par);
+  }
+}
+
 template <typename T>
 static bool launch_cs_rows(const LatDev &L, int src, int par, bool force, bool linear,
                            hipStream_t s) {
-  if (L.nx % 4 != 0 || !rows_fit_32bit(L)) return false;
-  const int tpr = L.nx / 4;
-  if (tpr > 64 || 64 % tpr != 0) return false;
+  if (L.tpr <= 0) return false;
   const long long rows = (long long)L.ny * L.nz;
-  const long long threads = rows * tpr;
-  const dim3 b(256), g((unsigned)((threads + 255) / 256));
-  if (force) {
-    if (linear) k_collide_stream_rows<T, true, true><<<g, b, 0, s>>>(L, src, par, tpr);
-    else k_collide_stream_rows<T, false, true><<<g, b, 0, s>>>(L, src, par, tpr);
-  } else {
-    if (linear) k_collide_stream_rows<T, true, false><<<g, b, 0, s>>>(L, src, par, tpr);
-    else k_collide_stream_rows<T, false, false><<<g, b, 0, s>>>(L, src, par, tpr);
-  }
+  const long long waves = (rows + L.rpw - 1) / L.rpw;
+  const dim3 g((unsigned)((waves + 3) / 4));
+  if (L.nx % 4) launch_cs_rows_p<T, true>(L, src, par, force, linear, g, s);
+  else launch_cs_rows_p<T, false>(L, src, par, force, linear, g, s);
   return true;
 }
 
@@ -670,7 +727,8 @@ static void launch_cs_t(const LatDev &L, int src, int par, bool force, bool line
                         int variant, hipStream_t s) {
   // variant bits: 1 = two nodes per thread, 2 = non-temporal accesses,
   // 4 = 128-thread blocks, 8 = 64-thread blocks, 16 = row-vector kernel
-  // (four nodes per thread, whole rows per wavefront) where the row fits,
+  // (four nodes per thread, whole rows per wavefront) where a padded row has
+  // at most 256 values,
   // 32 = with FP16 storage, eight nodes per thread in that form (nx / 8
   // dividing 64)
   if constexpr (sizeof(T) == 2)
@@ -855,7 +913,6 @@ __global__ __launch_bounds__(256) void k_tangent_collide_stream(LatDev L, TanDev
   const float vz = (tjz + 0.5f * hz - uz * trho) * inv_rho;
   const float usq15 = 1.5f * (ux * ux + uy * uy + uz * uz);
   const float duu3 = 3.0f * (ux * vx + uy * vy + uz * vz);
-  const float gu = ux * gx + uy * gy + uz * gz;
   const float dgu = vx * gx + vy * gy + vz * gz + ux * hx + uy * hy + uz * hz;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
@@ -1148,7 +1205,9 @@ void launch_adj_couette_start(const LatDev &L, const AdjDev &A, int cur, int lin
 
 // ---- batches of runs -------------------------------------------------------------
 // The lattice update of many independent runs in one launch: block b updates
-// 256 consecutive nodes (one per thread) of run lat_items[b].x.  Runs without
+// part lat_items[b].y of run lat_items[b].x, four wavefronts of whole rows in
+// the row form (runs whose padded rows have at most 256 values), else 256
+// consecutive nodes, one per thread.  Runs without
 // capsules never stamp a tile, so reading the force field only where stamped
 // is correct for them as well.
 template <typename T, bool LINEAR>
@@ -1170,6 +1229,17 @@ __global__ __launch_bounds__(256) void k_batch_collide_stream(BatchDev B, int sr
     int *ts = L.stamp[0];
     L.stamp[0] = L.stamp[1];
     L.stamp[1] = ts;
+  }
+  if (L.tpr > 0) {
+    // row form: four wavefronts of rpw whole rows per block
+    const int lane = threadIdx.x & 63;
+    const int wave = it.y * 4 + (int)(threadIdx.x >> 6);
+    if (wave * L.rpw >= L.ny * L.nz) return;  // the whole wavefront is past the last row
+    const int r = lane / L.tpr;
+    const int t = lane - r * L.tpr;
+    const int row = wave * L.rpw + r;
+    collide_stream_rowseg<T, LINEAR, true, true>(L, 0, 0, row, t, lane, r < L.rpw && row < L.ny * L.nz);
+    return;
   }
   // a lattice holds at most 2^31 nodes: unsigned 32-bit index arithmetic suffices
   const unsigned idx = (unsigned)it.y * 256u + threadIdx.x;

@@ -86,8 +86,8 @@ def test_fp16_one_step_error(B, m, n):
     """One coupled step from an identical (FP16-representable) deformed
     state: populations within 2^-11 (+ FP32 slack) of the largest
     deviation, force density as in FP32, node velocities and positions
-    within the error the rounded populations carry.  nx = 30 runs the
-    per-node collide-stream form, nx = 32 the eight-node row form."""
+    within the error the rounded populations carry.  nx = 30 runs the row
+    form over padded rows, nx = 32 over unpadded ones."""
     c = small_case(m=m, n=n)
     sim = c.oracle()
     assert sim.run(40) == 0
@@ -176,18 +176,16 @@ def test_fp16_full_size_step(B):
 
 def collide_stream_form(variant, nx):
     """The collide-stream form the library runs with FP16 storage for this
-    IBM_OPT_LBM_VARIANT and row length."""
-    def fits(vec):
-        return nx % vec == 0 and nx // vec <= 64 and 64 % (nx // vec) == 0
-    if (variant & 48) == 48 and fits(8):
+    IBM_OPT_LBM_VARIANT and row length (rows padded to a multiple of 4)."""
+    if (variant & 48) == 48 and nx % 8 == 0 and nx // 8 <= 64 and 64 % (nx // 8) == 0:
         return "rows8"
-    return "rows4" if (variant & 16) and fits(4) else "nodes"
+    return "rows4" if (variant & 16) and (nx + 3) // 4 <= 64 else "nodes"
 
 
 def test_fp16_collide_stream_forms_agree(B):
-    """The FP16 collide-stream forms on rows of 8 (one lane per row) to 512
-    nodes (a whole wavefront per row), with and without a capsule's forces,
-    with wall bounce-back.  Each form's first step from an FP16-representable
+    """The FP16 collide-stream forms on rows of 3 to 512 nodes (padded rows
+    of 4 to 256 values run the row form: one lane per row up to a whole
+    wavefront), with and without a capsule's forces, with wall bounce-back.  Each form's first step from an FP16-representable
     state is within 2^-11 of the largest deviation from the FP64 oracle's.
     The forms evaluate the same FP32 expressions, but the compiler may
     contract a product into a sum differently in each, and with a capsule
@@ -196,8 +194,10 @@ def test_fp16_collide_stream_forms_agree(B):
     steps the forms agree within one FP16 ulp (2^-10) of the largest
     deviation."""
     forms = (55, 23, 7, 0)
-    shapes = [((32, 20, 16), True), ((64, 12, 10), False), ((8, 6, 5), False),
-              ((16, 10, 9), False), ((256, 6, 4), False), ((512, 4, 3), False)]
+    shapes = [((32, 20, 16), True), ((30, 20, 16), True), ((64, 12, 10), False),
+              ((8, 6, 5), False), ((16, 10, 9), False), ((256, 6, 4), False),
+              ((512, 4, 3), False), ((21, 9, 7), False), ((253, 4, 3), False),
+              ((6, 5, 4), False), ((3, 4, 3), False)]
     for n, with_capsule in shapes:
         if with_capsule:
             c = small_case(n=n)
