@@ -115,17 +115,22 @@ extern "C" {
                                   default 23);
                                   results are identical, only the speed
                                   differs                                    */
-#define IBM_OPT_STENCIL_BOX 6  /* bit 0: spreading, bit 1: interpolation of
-                                  the per-node kernels go through an LDS box
-                                  spanning the stencils of each block's
-                                  nodes (overlapping stencils are summed,
-                                  or their lattice velocities evaluated,
-                                  once per lattice node).  Default, set when
-                                  the membrane is attached unless chosen
-                                  before: 1 (box spreading) when the
-                                  membrane makes at least 256 blocks of
-                                  work, else 0.  Results agree to FP32
-                                  rounding (see also ibm_autotune)          */
+#define IBM_OPT_STENCIL_BOX 6  /* 0..7.  bit 0: spreading, bit 1:
+                                  interpolation of the per-node kernels go
+                                  through an LDS box spanning the stencils
+                                  of each block's nodes (overlapping
+                                  stencils are summed, or their lattice
+                                  velocities evaluated, once per lattice
+                                  node); bit 2 (over bit 1): interpolation
+                                  reads the lattice velocity from a field
+                                  that one pass evaluates at every node of
+                                  the 4^3 tiles the step's stencils touch.
+                                  Default, set when the membrane is
+                                  attached unless chosen before: 1 (box
+                                  spreading) when the membrane makes at
+                                  least 256 blocks of work, else 0.
+                                  Results agree to FP32 rounding (see also
+                                  ibm_autotune)                             */
 #define IBM_OPT_CHUNK_NODES 5  /* spreading and interpolation work on chunks
                                   of this many consecutive membrane nodes of
                                   one capsule (16, 32, 64, 128 or 256),
@@ -328,10 +333,12 @@ int ibm_batch_create(int n_runs, ibm_lattice *const *runs, void *dev_mem, size_t
 /* Enqueue n timesteps of every run (Sec. II.C, sub-steps 1-5); asynchronous.
  * Device-side errors of a run are reported by that run's next synchronising
  * call.  The per-node coupling kernels are used whatever a run's
- * IBM_OPT_CHUNK_NODES, and the lattice update is the one-node-per-thread
- * form whatever its IBM_OPT_LBM_VARIANT.  The stencil-box mode is the first
- * run's IBM_OPT_STENCIL_BOX if it was set, else box spreading when the
- * batch's membranes make at least 256 blocks of work. */
+ * IBM_OPT_CHUNK_NODES, and the lattice update is the row form (whole x rows
+ * per wavefront) for runs with nx <= 256, else one node per thread, whatever
+ * a run's IBM_OPT_LBM_VARIANT.  The stencil-box mode is the first run's
+ * IBM_OPT_STENCIL_BOX if it was set, else 5 (box spreading, interpolation
+ * from the tile-velocity field) when the batch's membranes make at least 256
+ * blocks of work, else 0. */
 int ibm_batch_step(ibm_batch *b, int64_t n);
 
 /* ibm_profile_step for a batch: n steps of every run with plain launches and

@@ -52,7 +52,7 @@ struct LatticeLayout {
   int tpr;             // lanes per row of the row-form kernels (0: not used)
   long long pop_elems;  // elements of one population buffer
   int tnx, tny, tnz;
-  size_t off_ctrl, off_stamp[2], off_g[2], off_f[2], total;
+  size_t off_ctrl, off_stamp[2], off_U, off_g[2], off_f[2], total;
 };
 
 LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
@@ -83,6 +83,8 @@ LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
     l.off_stamp[k] = off;
     off += round_up(tiles * sizeof(int), ALIGN);
   }
+  l.off_U = off;
+  off += round_up((size_t)l.S * 16, ALIGN);
   for (int k = 0; k < 2; ++k) {
     l.off_g[k] = off;
     off += round_up(3 * (size_t)l.S * sizeof(float), ALIGN);
@@ -153,7 +155,8 @@ struct ibm_lattice {
   // wavefront, else two nodes per thread, non-temporal, 128-thread blocks
   int use_graph = 1, eq_linear = 0, ab2 = 0, recenter_every = 64, lbm_variant = 16 | 7;
   int chunk_nodes = 0;  // membrane nodes per chunk of the coupling kernels (0: none)
-  int box_mode = 0;     // bit 0: spreading, bit 1: interpolation through per-block LDS boxes
+  int box_mode = 0;     // IBM_OPT_STENCIL_BOX: bit 0 box spreading, bit 1 / bit 2
+                        // interpolation through LDS boxes / the tile-velocity field
   bool box_set = false;  // box_mode chosen by the caller (else set with the membrane)
   bool have_prev_u = false;
   int64_t since_recenter = 0;
@@ -183,6 +186,11 @@ void reset_force_state(ibm_lattice *lat, hipStream_t s) {
   }
 }
 
+// Interpolation mode of the coupling kernels (launch_interp_advect) for an
+// IBM_OPT_STENCIL_BOX value: bit 2 (the tile-velocity field) over bit 1 (LDS
+// boxes) over the per-stencil-node evaluation.
+int interp_mode(int box_mode) { return (box_mode & 4) ? 2 : ((box_mode & 2) ? 1 : 0); }
+
 // Enqueue one full timestep on stream s (Sec. II.C, sub-steps 1-5).
 void enqueue_step(ibm_lattice *lat, hipStream_t s, int advect) {
   const int src = (int)(lat->steps & 1);
@@ -199,7 +207,7 @@ void enqueue_step(ibm_lattice *lat, hipStream_t s, int advect) {
       ibm::launch_tangent_interp(lat->L, lat->M, lat->T, src ^ 1, par, s);
     }
     ibm::launch_interp_advect(lat->L, lat->M, lat->storage, src ^ 1,     // 4, 5
-                              par, advect, (lat->box_mode & 2) != 0, s);
+                              par, advect, interp_mode(lat->box_mode), s);
   } else {
     ibm::launch_collide_stream(lat->L, lat->storage, src, par, false, lat->eq_linear != 0,
                                lat->lbm_variant, s);
@@ -469,9 +477,10 @@ int batch_sync_tables(ibm_batch *b) {
   B.node_items = reinterpret_cast<const int2 *>(b->dev + bl.node_items);
   B.n_lat_items = (int)li.size();
   B.n_node_items = (int)ni.size();
-  // the first run's explicit choice, else box spreading once the whole batch
-  // makes at least 256 blocks of coupling work
-  b->box_mode = r0->box_set ? r0->box_mode : (ni.size() >= 256 ? 1 : 0);
+  // the first run's explicit choice, else box spreading and interpolation
+  // from the tile-velocity field once the whole batch makes at least 256
+  // blocks of coupling work
+  b->box_mode = r0->box_set ? r0->box_mode : (ni.size() >= 256 ? 1 | 4 : 0);
   const bool same = img == b->image && std::memcmp(&B, &b->B, sizeof(B)) == 0;
   if (!same) {
     IBM_HIP(hipMemcpyAsync(b->dev, img.data(), img.size(), hipMemcpyHostToDevice, b->stream));
@@ -490,7 +499,7 @@ void enqueue_batch_step(ibm_batch *b, hipStream_t s, int advect) {
   const int src = (int)(r0->steps & 1), par = src;
   ibm::launch_batch_spread(b->B, par, b->box_mode & 1, s);
   ibm::launch_batch_collide_stream(b->B, r0->storage, src, par, r0->eq_linear != 0, s);
-  ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, (b->box_mode & 2) != 0, s);
+  ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, interp_mode(b->box_mode), s);
   for (ibm_lattice *lat : b->runs) {
     lat->steps += 1;
     lat->since_recenter += 1;
@@ -585,6 +594,7 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
     L.stamp[k] = reinterpret_cast<int *>(lat->base + lat->lay.off_stamp[k]);
   }
   L.ctrl = reinterpret_cast<ibm::Ctrl *>(lat->base + lat->lay.off_ctrl);
+  L.U = reinterpret_cast<float4 *>(lat->base + lat->lay.off_U);
   L.inv_tau = (float)(1.0 / tau);
   L.guo_pre = (float)(1.0 - 0.5 / tau);
   L.uw = 0.0f;
@@ -922,7 +932,7 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
       lat->lbm_variant = value;
       break;
     case IBM_OPT_STENCIL_BOX:
-      if (value < 0 || value > 3) return fail(IBM_ERR_INVALID_ARG, "stencil box mode is 0..3");
+      if (value < 0 || value > 7) return fail(IBM_ERR_INVALID_ARG, "stencil box mode is 0..7");
       lat->box_mode = value;
       lat->box_set = true;
       break;
@@ -1001,7 +1011,7 @@ int ibm_autotune(ibm_lattice *lat, int steps_per_trial, int *chosen) {
   invalidate_graph(lat);
   if (!rc && lat->has_mem && lat->chunk_nodes == 0) {
     best = 1e30f;
-    for (int bm = 0; bm < 4 && !rc; ++bm) {
+    for (int bm = 0; bm < 6 && !rc; ++bm) {  // 6, 7 interpolate as 4, 5
       lat->box_mode = bm;
       invalidate_graph(lat);
       float ms = 0.0f;
@@ -1045,7 +1055,7 @@ int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase) {
                                  lat->lbm_variant, s);
       IBM_HIP(hipEventRecord(e[3], s));
       ibm::launch_interp_advect(lat->L, lat->M, lat->storage, src ^ 1, par, advect_mode(lat),
-                                (lat->box_mode & 2) != 0, s);
+                                interp_mode(lat->box_mode), s);
       IBM_HIP(hipEventRecord(e[4], s));
       if (lat->ab2) lat->have_prev_u = true;
     } else {
@@ -1531,7 +1541,7 @@ int ibm_batch_profile_step(ibm_batch *b, int64_t n, double *ms_per_phase) {
     IBM_HIP(hipEventRecord(e[1], s));
     ibm::launch_batch_collide_stream(b->B, r0->storage, src, par, r0->eq_linear != 0, s);
     IBM_HIP(hipEventRecord(e[2], s));
-    ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, (b->box_mode & 2) != 0, s);
+    ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, interp_mode(b->box_mode), s);
     IBM_HIP(hipEventRecord(e[3], s));
     for (ibm_lattice *lat : b->runs) {
       lat->steps += 1;

@@ -60,6 +60,8 @@ struct LatDev {
   void *f[2];             // population buffers (float or __half), see pidx
   float *g[2];            // force density [3][S] of even and odd steps
   int *stamp[2];          // per-tile step stamps of the two fields
+  float4 *U;              // lattice velocity (ux, uy, uz, 0) at the nodes of
+                          // the tiles stamped this step, for interpolation [S]
   Ctrl *ctrl;
   float inv_tau;          // 1 / tau
   float guo_pre;          // 1 - 1 / (2 tau)

@@ -35,11 +35,14 @@ void launch_reference_geometry(const MemDev &M, Ctrl *ctrl, hipStream_t s);
 // box: sum overlapping stencils of each block in an LDS box first
 void launch_spread(const LatDev &L, const MemDev &M, int par, bool box, hipStream_t s);
 // advect: 0 Euler, 1 Adams-Bashforth with the stored velocity of the previous step
+// mode: 0 lattice velocities per stencil node from the populations, 1 per
+// block in an LDS box, 2 from the tile-velocity field (a pass over the
+// stamped tiles first)
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
-                          int advect, bool box, hipStream_t s);
+                          int advect, int mode, hipStream_t s);
 void launch_recenter(const MemDev &M, hipStream_t s);
 void launch_batch_spread(const BatchDev &B, int par, bool box, hipStream_t s);
-void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect, bool box,
+void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect, int mode,
                          hipStream_t s);
 void launch_observables(const MemDev &M, Ctrl *ctrl, hipStream_t s);
 // observables of the mesh x + h dx into obs [n_caps][16]

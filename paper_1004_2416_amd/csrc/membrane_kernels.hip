@@ -241,9 +241,14 @@ __device__ __forceinline__ Box block_box(int gx, int gy, int gz, bool has, int c
   return b;
 }
 
+// Up to SPREAD_BOX lattice nodes per box; its tiles, counted in unwrapped
+// coordinates, number at most (ceil(ex/4) + 1)(ceil(ey/4) + 1)(ceil(ez/4) + 1)
+// <= 1028 for ex ey ez <= 1024.
 constexpr int SPREAD_BOX = 1024;
+constexpr int SPREAD_BOX_TILES = 1032;
 struct SpreadLDS {
   float box[3][SPREAD_BOX];
+  unsigned char tflag[SPREAD_BOX_TILES];
   int bb[6];
 };
 
@@ -316,7 +321,13 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   const bool fits = b.fits;
   const int x0 = b.x0, y0 = b.y0, z0 = b.z0, ex = b.ex, ey = b.ey;
   const int V = b.V;
+  // the box's tiles in unwrapped coordinates (>> 2 floors negative ones too)
+  const int tx0 = x0 >> 2, ty0 = y0 >> 2, tz0 = z0 >> 2;
+  const int ntx = fits ? ((x0 + ex - 1) >> 2) - tx0 + 1 : 0;
+  const int nty = fits ? ((y0 + ey - 1) >> 2) - ty0 + 1 : 0;
+  const int NT = fits ? ntx * nty * (((z0 + b.ez - 1) >> 2) - tz0 + 1) : 0;
   for (int c = threadIdx.x; c < V; c += blockDim.x) sm.box[0][c] = sm.box[1][c] = sm.box[2][c] = 0.0f;
+  for (int q = threadIdx.x; q < NT; q += blockDim.x) sm.tflag[q] = 0;
   __syncthreads();
   if (has) {
     if (fits) {
@@ -324,6 +335,7 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
       atomicAdd(&sm.box[0][c], w * fx);
       atomicAdd(&sm.box[1][c], w * fy);
       atomicAdd(&sm.box[2][c], w * fz);
+      sm.tflag[(((gz >> 2) - tz0) * nty + ((gy >> 2) - ty0)) * ntx + ((gx >> 2) - tx0)] = 1;
     } else {
       const int X = wrap_mod(gx, L.nx), Y = wrap_mod(gy, L.ny);
       const long long n = ((long long)gz * L.ny + Y) * L.nx + X;
@@ -345,7 +357,22 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
     if (vx != 0.0f) unsafeAtomicAdd(g + n, vx);
     if (vy != 0.0f) unsafeAtomicAdd(g + L.S + n, vy);
     if (vz != 0.0f) unsafeAtomicAdd(g + 2 * L.S + n, vz);
-    L.stamp[par][tile_of(L, X, Y, Z)] = step;
+  }
+  // Every tile a nonzero weight touches, once per block.  Where nx or ny is
+  // not a multiple of 4, the four wrapped positions of an unwrapped tile fall
+  // into up to three tiles along that axis: stamp all of them.
+  for (int q = threadIdx.x; q < NT; q += blockDim.x) {
+    if (!sm.tflag[q]) continue;
+    const int ux = tx0 + q % ntx, uy = ty0 + (q / ntx) % nty, uz = tz0 + q / (ntx * nty);
+    int tx[3], ty[3], nxt = 0, nyt = 0;
+#pragma unroll
+    for (int d = 0; d < 4; ++d) {
+      const int a = wrap_mod(4 * ux + d, L.nx) >> 2, c = wrap_mod(4 * uy + d, L.ny) >> 2;
+      if (nxt == 0 || (tx[nxt - 1] != a && tx[0] != a)) tx[nxt < 3 ? nxt++ : 2] = a;
+      if (nyt == 0 || (ty[nyt - 1] != c && ty[0] != c)) ty[nyt < 3 ? nyt++ : 2] = c;
+    }
+    for (int i = 0; i < nyt; ++i)
+      for (int j = 0; j < nxt; ++j) L.stamp[par][(uz * L.tny + ty[i]) * L.tnx + tx[j]] = step;
   }
 }
 
@@ -560,6 +587,48 @@ __device__ __forceinline__ float3 lattice_velocity(const LatDev &L, const T *f, 
                      (jz + 0.5f * g[2 * L.S + n]) * inv_rho);
 }
 
+// The lattice velocity of every node of the tiles stamped by this step's
+// spreading (the tiles of all stencils with a nonzero weight), into L.U.  A
+// block scans tiles [t0, t0 + nt) in chunks of its thread count, gathers the
+// stamped ones of a chunk in LDS and gives each to one wavefront (64 lanes,
+// one per node).  All threads of the block call it.
+template <typename T>
+__device__ __forceinline__ void tile_velocity_block(const LatDev &L, int fsrc, int par, int t0,
+                                                    int nt) {
+  __shared__ int list[256];
+  __shared__ int cnt;
+  const int ntiles = L.tnx * L.tny * L.tnz;
+  const int step = L.ctrl->step;
+  const int lane = threadIdx.x & 63;
+  const T *f = static_cast<const T *>(L.f[fsrc]);
+  const float *g = L.g[par];
+  for (int c0 = 0; c0 < nt; c0 += (int)blockDim.x) {
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    if (c0 + (int)threadIdx.x < nt) {
+      const int tile = t0 + c0 + (int)threadIdx.x;
+      if (tile < ntiles && L.stamp[par][tile] == step) list[atomicAdd(&cnt, 1)] = tile;
+    }
+    __syncthreads();
+    const int n = cnt;
+    for (int k = (int)(threadIdx.x >> 6); k < n; k += (int)(blockDim.x >> 6)) {
+      const int tile = list[k];
+      const int tx = tile % L.tnx, ty = (tile / L.tnx) % L.tny, tz = tile / (L.tnx * L.tny);
+      const int X = 4 * tx + (lane & 3), Y = 4 * ty + ((lane >> 2) & 3), Z = 4 * tz + (lane >> 4);
+      if (X < L.nx && Y < L.ny && Z < L.nz) {
+        const float3 u = lattice_velocity<T>(L, f, g, X, Y, Z);
+        L.U[((long long)Z * L.ny + Y) * L.nx + X] = make_float4(u.x, u.y, u.z, 0.0f);
+      }
+    }
+    __syncthreads();  // list and cnt are reused by the next chunk
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tile_velocity(LatDev L, int fsrc, int par, int nt) {
+  tile_velocity_block<T>(L, fsrc, par, (int)blockIdx.x * nt, nt);
+}
+
 // The lattice velocity is evaluated once per lattice node of the block's
 // stencil box that a stencil touches with nonzero weight (consecutive threads
 // on consecutive x: coalesced population reads; neighbouring nodes share most
@@ -572,7 +641,9 @@ struct InterpLDS {
   int bb[6];
 };
 
-template <typename T, int M, bool BOX>
+// UF: read the lattice velocity from L.U (filled by the tile-velocity pass
+// of this step) instead of evaluating it from the populations.
+template <typename T, int M, bool BOX, bool UF>
 __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, int fsrc, int par,
                                              int advect, int blk, InterpLDS &sm) {
   constexpr int GS = group_size<M>();
@@ -603,12 +674,12 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
   const T *f = static_cast<const T *>(L.f[fsrc]);
   const float *g = L.g[par];
   Box b{0, 0, 0, 1, 1, 1, 0, false};
-  if constexpr (BOX) b = block_box(gx, gy, gz, has, INTERP_BOX, sm.bb);
+  if constexpr (BOX && !UF) b = block_box(gx, gy, gz, has, INTERP_BOX, sm.bb);
   const bool fits = b.fits;
   const int x0 = b.x0, y0 = b.y0, z0 = b.z0, ex = b.ex, ey = b.ey;
   const int V = b.V;
   const int cell = ((gz - z0) * ey + (gy - y0)) * ex + (gx - x0);
-  if constexpr (BOX) {
+  if constexpr (BOX && !UF) {
     for (int c = threadIdx.x; c < V; c += blockDim.x) sm.mark[c] = 0;
     __syncthreads();
     if (has && fits) sm.mark[cell] = 1;
@@ -626,8 +697,14 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
   float ux = 0.0f, uy = 0.0f, uz = 0.0f;
   if (has) {
     float3 u;
-    if (fits) u = make_float3(sm.box[0][cell], sm.box[1][cell], sm.box[2][cell]);
-    else u = lattice_velocity<T>(L, f, g, wrap_mod(gx, L.nx), wrap_mod(gy, L.ny), gz);
+    if constexpr (UF) {
+      const float4 v = L.U[((long long)gz * L.ny + wrap_mod(gy, L.ny)) * L.nx + wrap_mod(gx, L.nx)];
+      u = make_float3(v.x, v.y, v.z);
+    } else if (fits) {
+      u = make_float3(sm.box[0][cell], sm.box[1][cell], sm.box[2][cell]);
+    } else {
+      u = lattice_velocity<T>(L, f, g, wrap_mod(gx, L.nx), wrap_mod(gy, L.ny), gz);
+    }
     ux = w * u.x;
     uy = w * u.y;
     uz = w * u.z;
@@ -657,7 +734,17 @@ __global__ __launch_bounds__(256) void k_interp_advect(LatDev L, MemDev Mm, int 
   __shared__ InterpLDS sm;
   if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
   const int blk = xcd_block(nblocks);
-  if (blk >= 0) interp_lanes<T, M, BOX>(L, Mm, fsrc, par, advect, blk, sm);
+  if (blk >= 0) interp_lanes<T, M, BOX, false>(L, Mm, fsrc, par, advect, blk, sm);
+}
+
+// Interpolation from the tile-velocity field.
+template <typename T, int M>
+__global__ __launch_bounds__(256) void k_interp_field(LatDev L, MemDev Mm, int fsrc, int par,
+                                                      int advect, int nblocks) {
+  __shared__ InterpLDS sm;
+  if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
+  const int blk = xcd_block(nblocks);
+  if (blk >= 0) interp_lanes<T, M, false, true>(L, Mm, fsrc, par, advect, blk, sm);
 }
 
 // ---- chunked interpolation + advection ----------------------------------------
@@ -773,7 +860,7 @@ __global__ __launch_bounds__(256) void k_interp_chunks(LatDev L, MemDev Mm, int 
 }
 
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
-                          int advect, bool box, hipStream_t s) {
+                          int advect, int mode, hipStream_t s) {
   if (M.nn <= 0) return;
   if (M.n_chunks > 0) {
     const dim3 grid(xcd_grid(M.n_chunks)), block(256);
@@ -792,20 +879,39 @@ void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, 
   const long long lanes = (long long)M.nn * gs;
   const int nblocks = (int)((lanes + 255) / 256);
   const dim3 grid(xcd_grid(nblocks)), block(256);
-#define IBM_LAUNCH_INTERP(T, BX)                                                                 \
-  do {                                                                                           \
-    if (M.m == 2) k_interp_advect<T, 2, BX><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks); \
+  if (mode != 2) {
+    // the lattice velocity from the populations, per stencil node or per block
+    // in an LDS box
+#define IBM_LAUNCH_INTERP(T, BX)                                                                    \
+  do {                                                                                              \
+    if (M.m == 2) k_interp_advect<T, 2, BX><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);      \
     else if (M.m == 3) k_interp_advect<T, 3, BX><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks); \
-    else k_interp_advect<T, 4, BX><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);     \
+    else k_interp_advect<T, 4, BX><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);          \
   } while (0)
-  if (fp16) {
-    if (box) IBM_LAUNCH_INTERP(__half, true);
-    else IBM_LAUNCH_INTERP(__half, false);
-  } else {
-    if (box) IBM_LAUNCH_INTERP(float, true);
-    else IBM_LAUNCH_INTERP(float, false);
-  }
+    if (fp16) {
+      if (mode == 1) IBM_LAUNCH_INTERP(__half, true);
+      else IBM_LAUNCH_INTERP(__half, false);
+    } else {
+      if (mode == 1) IBM_LAUNCH_INTERP(float, true);
+      else IBM_LAUNCH_INTERP(float, false);
+    }
 #undef IBM_LAUNCH_INTERP
+    return;
+  }
+  // the lattice velocity of the stamped tiles, then the stencil sums from it
+  const long long tiles = (long long)L.tnx * L.tny * L.tnz;
+  const int vt = 32;  // tiles scanned per block
+  const dim3 vgrid((unsigned)((tiles + vt - 1) / vt));
+#define IBM_LAUNCH_INTERP_FIELD(T)                                                                  \
+  do {                                                                                              \
+    k_tile_velocity<T><<<vgrid, block, 0, s>>>(L, fsrc, par, vt);                                   \
+    if (M.m == 2) k_interp_field<T, 2><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);      \
+    else if (M.m == 3) k_interp_field<T, 3><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks); \
+    else k_interp_field<T, 4><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);             \
+  } while (0)
+  if (fp16) IBM_LAUNCH_INTERP_FIELD(__half);
+  else IBM_LAUNCH_INTERP_FIELD(float);
+#undef IBM_LAUNCH_INTERP_FIELD
 }
 
 // ---- tangent (forward sensitivity) of spreading and interpolation ----------------
@@ -1156,7 +1262,9 @@ __global__ __launch_bounds__(256) void k_batch_spread(BatchDev B, int par) {
 }
 
 // The first block of each run advances that run's device step counter.
-template <typename T, bool BOX>
+// MODE as for launch_interp_advect: 0 per stencil node, 1 per block in LDS,
+// 2 from each run's tile-velocity field (k_batch_tile_velocity first).
+template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_batch_interp(BatchDev B, int fsrc, int par, int advect) {
   __shared__ InterpLDS sm;
   const int b = xcd_block(B.n_node_items);
@@ -1166,9 +1274,24 @@ __global__ __launch_bounds__(256) void k_batch_interp(BatchDev B, int fsrc, int 
   const MemDev &Mm = B.mem[it.x];
   if (it.y == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
   const int m = Mm.m;
-  if (m == 2) interp_lanes<T, 2, BOX>(L, Mm, fsrc, par, advect, it.y, sm);
-  else if (m == 3) interp_lanes<T, 3, BOX>(L, Mm, fsrc, par, advect, it.y, sm);
-  else interp_lanes<T, 4, BOX>(L, Mm, fsrc, par, advect, it.y, sm);
+  if (m == 2) interp_lanes<T, 2, MODE == 1, MODE == 2>(L, Mm, fsrc, par, advect, it.y, sm);
+  else if (m == 3) interp_lanes<T, 3, MODE == 1, MODE == 2>(L, Mm, fsrc, par, advect, it.y, sm);
+  else interp_lanes<T, 4, MODE == 1, MODE == 2>(L, Mm, fsrc, par, advect, it.y, sm);
+}
+
+// The tile-velocity pass of every run, on the lattice work items: the nb
+// blocks of a run scan its tiles in equal ranges.
+template <typename T>
+__global__ __launch_bounds__(256) void k_batch_tile_velocity(BatchDev B, int fsrc, int par) {
+  if ((int)blockIdx.x >= B.n_lat_items) return;
+  const int2 it = B.lat_items[blockIdx.x];
+  const LatDev &L = B.lat[it.x];
+  if (!B.mem[it.x].nn) return;  // no capsule: nothing is stamped
+  const long long rows = (long long)L.ny * L.nz;
+  const long long nb = L.tpr ? ((rows + L.rpw - 1) / L.rpw + 3) / 4 : ((long long)L.nx * rows + 255) / 256;
+  const long long ntiles = (long long)L.tnx * L.tny * L.tnz;
+  const int nt = (int)((ntiles + nb - 1) / nb);
+  tile_velocity_block<T>(L, fsrc, par, it.y * nt, nt);
 }
 
 void launch_batch_spread(const BatchDev &B, int par, bool box, hipStream_t s) {
@@ -1178,17 +1301,24 @@ void launch_batch_spread(const BatchDev &B, int par, bool box, hipStream_t s) {
   else k_batch_spread<false><<<grid, block, 0, s>>>(B, par);
 }
 
-void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect, bool box,
+void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect, int mode,
                          hipStream_t s) {
   if (B.n_node_items <= 0) return;
   const dim3 grid(xcd_grid(B.n_node_items)), block(256);
-  if (fp16) {
-    if (box) k_batch_interp<__half, true><<<grid, block, 0, s>>>(B, fsrc, par, advect);
-    else k_batch_interp<__half, false><<<grid, block, 0, s>>>(B, fsrc, par, advect);
-  } else {
-    if (box) k_batch_interp<float, true><<<grid, block, 0, s>>>(B, fsrc, par, advect);
-    else k_batch_interp<float, false><<<grid, block, 0, s>>>(B, fsrc, par, advect);
-  }
+#define IBM_LAUNCH_BATCH_INTERP(T)                                                            \
+  do {                                                                                        \
+    if (mode == 2) {                                                                          \
+      k_batch_tile_velocity<T><<<dim3(B.n_lat_items), block, 0, s>>>(B, fsrc, par);           \
+      k_batch_interp<T, 2><<<grid, block, 0, s>>>(B, fsrc, par, advect);                      \
+    } else if (mode == 1) {                                                                   \
+      k_batch_interp<T, 1><<<grid, block, 0, s>>>(B, fsrc, par, advect);                      \
+    } else {                                                                                  \
+      k_batch_interp<T, 0><<<grid, block, 0, s>>>(B, fsrc, par, advect);                      \
+    }                                                                                         \
+  } while (0)
+  if (fp16) IBM_LAUNCH_BATCH_INTERP(__half);
+  else IBM_LAUNCH_BATCH_INTERP(float);
+#undef IBM_LAUNCH_BATCH_INTERP
 }
 
 // ---- capsule frame re-centring -------------------------------------------------

@@ -40,11 +40,15 @@ def test_library_exports_every_declared_symbol(B):
 def test_size_queries_and_validation(B):
     n = ctypes.c_size_t()
     assert B.lib.ibm_lattice_bytes(128, 128, 128, 0, ctypes.byref(n)) == 0
-    # two FP32 population copies dominate: 2 * 19 * 4 B per node
-    assert 2 * 19 * 4 * 128 ** 3 < n.value < 1.2 * 2 * 19 * 4 * 128 ** 3
+    # per node: two population copies (2 x 19 x 4 B in FP32, 2 x 19 x 2 B in
+    # FP16), two force-density fields (2 x 3 x 4 B) and the velocity field
+    # interpolation reads (16 B); tile stamps and the control block add little
+    N = 128 ** 3
+    per32, per16 = 2 * 19 * 4 + 24 + 16, 2 * 19 * 2 + 24 + 16
+    assert per32 * N <= n.value < 1.02 * per32 * N
     m = ctypes.c_size_t()
     assert B.lib.ibm_lattice_bytes(128, 128, 128, 1, ctypes.byref(m)) == 0
-    assert m.value < 0.6 * n.value
+    assert per16 * N <= m.value < 1.02 * per16 * N
     assert B.lib.ibm_lattice_bytes(0, 4, 4, 0, ctypes.byref(n)) == -1
     assert "lattice size" in B.lib.ibm_last_error().decode()
     assert B.lib.ibm_lattice_bytes(4, 4, 4, 7, ctypes.byref(n)) == -1

@@ -118,6 +118,24 @@ def test_batch_matches_oracle_per_run(B):
         r.lat.close()
 
 
+@pytest.mark.parametrize("box", [5, 4, 2])
+def test_batch_interpolation_modes(B, box):
+    """The batch's coupling kernels with the first run's stencil-box mode:
+    interpolation from the runs' tile-velocity fields (4, 5, the default of
+    large batches) or through LDS boxes (2), over 40 steps."""
+    runs = [Run(B, spec) for spec in CASES]
+    runs[0].lat.set_option(B.OPT_STENCIL_BOX, box)
+    batch = B.Batch([r.lat for r in runs])
+    batch.step(1)
+    batch.step(39)
+    for r in runs:
+        r.advance_oracle(40)
+    check(runs, 1e-4, 1e-3)
+    batch.close()
+    for r in runs:
+        r.lat.close()
+
+
 def test_batch_adams_bashforth_linear_equilibrium(B):
     runs = [Run(B, spec, ab2=True, linear=True) for spec in CASES[:2]]
     batch = B.Batch([r.lat for r in runs])

@@ -183,10 +183,11 @@ def test_coupling_chunk_sizes(B, chunk):
 
 
 @pytest.mark.parametrize("m", [2, 3, 4])
-@pytest.mark.parametrize("box", [1, 2, 3])
+@pytest.mark.parametrize("box", [1, 2, 3, 4, 5])
 def test_stencil_box_modes(B, m, box):
-    """Spreading and/or interpolation through per-block LDS boxes match the
-    oracle like the direct per-lane form."""
+    """Spreading and/or interpolation through per-block LDS boxes (bits 0, 1)
+    or interpolation from the tile-velocity field (bit 2) match the oracle
+    like the direct per-lane form."""
     say("stencil box", box, "m", m)
     c = small_case(n=(40, 36, 30), m=m, level=3, r=8.0, ca=0.02, uw=0.03)
     f_s, x_s = deformed_state(c, 10)
@@ -202,7 +203,7 @@ def test_autotune_keeps_the_run_on_the_oracle(B):
     chosen = lat.autotune(16)
     n = lat.steps
     say("  autotune chose", chosen, "after", n, "steps")
-    assert 0 <= chosen["lbm_variant"] < 64 and 0 <= chosen["stencil_box"] < 4
+    assert 0 <= chosen["lbm_variant"] < 64 and 0 <= chosen["stencil_box"] < 6
     sim = c.oracle()
     assert sim.run(n) == 0
     f = lat.populations().cpu().numpy()
@@ -212,15 +213,16 @@ def test_autotune_keeps_the_run_on_the_oracle(B):
     assert np.max(np.abs(xg - sim.x)) < 1e-3
 
 
-@pytest.mark.parametrize("chunk", [0, 16, 256])
-def test_coupling_chunk_box_too_large(B, chunk):
+@pytest.mark.parametrize("chunk,box", [(0, 3), (16, 3), (256, 3), (0, 5)])
+def test_coupling_chunk_box_too_large(B, chunk, box):
     """A coarse capsule (42 nodes, radius 14): the stencil box of every block
     (chunk 0) or chunk exceeds the on-chip capacity, so the contributions go
-    to and come from the global fields directly."""
-    say("oversized chunk boxes", chunk)
+    to and come from the global fields directly (with box 5 the tiles for the
+    tile-velocity field are then stamped per stencil node)."""
+    say("oversized chunk boxes", chunk, box)
     c = small_case(n=(40, 40, 40), m=3, level=1, r=14.0, ca=0.02, uw=0.03)
     f_s, x_s = deformed_state(c, 10)
-    compare_one_step(B, c, f_s, x_s, chunk=chunk, opts={B.OPT_STENCIL_BOX: 3})
+    compare_one_step(B, c, f_s, x_s, chunk=chunk, opts={B.OPT_STENCIL_BOX: box})
 
 
 def test_undeformed_capsule_has_zero_force(B):
@@ -236,8 +238,10 @@ def test_undeformed_capsule_has_zero_force(B):
 # ---------------------------------------------------------------------------
 # trajectories
 # ---------------------------------------------------------------------------
-def trajectory(B, c, steps, every, graph=True):
+def trajectory(B, c, steps, every, graph=True, box=-1):
     lat = c.gpu(graph=graph)
+    if box >= 0:
+        lat.set_option(B.OPT_STENCIL_BOX, box)
     sim = c.oracle()
     Dg, Do = [], []
     for k in range(steps // every):
@@ -262,16 +266,19 @@ def test_trajectory_c1(B):
     assert np.max(np.abs(xg - sim.x)) < 1e-3
 
 
-def test_trajectory_drifting_capsule_wraps_and_recentres(B):
+@pytest.mark.parametrize("nx,box", [(24, -1), (23, 5), (24, 4)])
+def test_trajectory_drifting_capsule_wraps_and_recentres(B, nx, box):
     """An off-centre capsule carried 18 lattice spacings along x by the shear
-    flow: crosses the periodic end and has its frame re-centred many times."""
-    say("drifting capsule")
-    nx, ny, nz, uw, r = 24, 16, 24, 0.04, 3.0
+    flow: crosses the periodic end and has its frame re-centred many times;
+    with the tile-velocity field (box 4, 5) also on a lattice whose x extent
+    is not a multiple of the tile size (tiles straddling the periodic end)."""
+    say("drifting capsule", nx, box)
+    ny, nz, uw, r = 16, 24, 0.04, 3.0
     ks = W.ks_from_capillary(0.05, uw, nz, r)
     wl = W.Workload("drift", nx, ny, nz, 1.0, uw, 3, 0,
                     [W.CapsuleSpec(2, r, (12.2, 7.6, 17.0), ks, ks)])
     c = Case(wl)
-    Dg, Do, xg, sim = trajectory(B, c, 1000, 100)
+    Dg, Do, xg, sim = trajectory(B, c, 1000, 100, box=box)
     assert np.mean(sim.x[:, 0]) - np.mean(c.xref[:, 0]) > 12.0
     assert np.max(np.abs(Dg - Do)) < 1e-3 * np.max(np.abs(Do))
     assert np.max(np.abs(xg - sim.x)) < 1e-3
