@@ -23,7 +23,8 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
 METRIC = "IB-LBM step MLUPS, % HBM roofline; batched/FP16/adjoint vs plain FP32"
-KERNEL_SOURCES = ("paper_1004_2416_amd/csrc/lbm_kernels.hip", "paper_1004_2416_amd/csrc/common.h")
+KERNEL_SOURCES = ("paper_1004_2416_amd/csrc/lbm_kernels.hip", "paper_1004_2416_amd/csrc/lbm_device.h",
+                  "paper_1004_2416_amd/csrc/common.h")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "collide_stream_traffic.txt")
 
 
@@ -69,7 +70,7 @@ def measured_traffic(workload: str, storage: str):
 
 
 def setup(workload: str, storage: str, graph: bool, variant: int = -1, chunk: int = -1,
-          box: int = -1):
+          box: int = -1, overlap: int = -1):
     from paper_1004_2416_amd import binding as B
     from paper_1004_2416_amd import workloads as W
 
@@ -85,6 +86,8 @@ def setup(workload: str, storage: str, graph: bool, variant: int = -1, chunk: in
         lat.set_option(B.OPT_CHUNK_NODES, int(chunk))
     if box >= 0:
         lat.set_option(B.OPT_STENCIL_BOX, int(box))
+    if overlap >= 0:
+        lat.set_option(B.OPT_OVERLAP, int(overlap))
     return wl, lat
 
 
@@ -157,6 +160,8 @@ def main():
                          "-1: library default)")
     ap.add_argument("--stencil-box", type=int, default=-1,
                     help="IBM_OPT_STENCIL_BOX bits (-1: library default)")
+    ap.add_argument("--overlap", type=int, default=-1,
+                    help="IBM_OPT_OVERLAP (-1: library default)")
     ap.add_argument("--sensitivity", action="store_true",
                     help="time the tangent-model gradient of D instead of the step")
     ap.add_argument("--autotune", action="store_true",
@@ -187,7 +192,7 @@ def main():
 
     import torch
     wl, lat = setup(args.workload, args.storage, not args.no_graph, args.lbm_variant,
-                    args.chunk_nodes, args.stencil_box)
+                    args.chunk_nodes, args.stencil_box, args.overlap)
     stream = lat.stream
     tuned = lat.autotune(64) if args.autotune else None
     lat.step(args.warmup)
@@ -234,7 +239,7 @@ def main():
             "delta_width": wl.m, "storage": args.storage, "graph": not args.no_graph,
             "u_w": wl.u_w, "tau": wl.tau, "lbm_variant": args.lbm_variant,
             "chunk_nodes": args.chunk_nodes, "stencil_box": args.stencil_box,
-            "autotuned": tuned,
+            "overlap": args.overlap, "autotuned": tuned,
         },
         "membrane_node_updates_per_s": round(wl.n_membrane_nodes * args.steps / (ms * 1e-3), 1),
         "step_pct_hbm_roofline": round(100 * mlups * 1e6 * bytes_per_node(args.storage)

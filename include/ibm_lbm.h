@@ -52,6 +52,10 @@ extern "C" {
 #define IBM_ERR_STENCIL_HITS_WALL (-4)  /* a delta stencil reached z < 0 or z >= nz */
 #define IBM_ERR_NONFINITE (-5)          /* NaN or Inf found in observables      */
 #define IBM_ERR_INVERTED_FACE (-6)      /* a membrane face degenerated or flipped */
+#define IBM_ERR_OUTSIDE_SLAB (-7)       /* IBM_OPT_OVERLAP: a stencil reached the
+                                           part of the lattice updated without
+                                           force; the steps since the last
+                                           check are not valid                  */
 
 /* ---- population storage ------------------------------------------------- */
 /* Populations are stored as deviations f_i - w_i from the lattice weights,
@@ -141,11 +145,30 @@ extern "C" {
                                   Results agree to FP32 rounding
                                   (summation order differs)                 */
 
+#define IBM_OPT_OVERLAP 7      /* 1: split the lattice update of
+                                  graph-replayed steps at the slab of z
+                                  that stencils can reach (the membranes' z
+                                  extent plus a margin of 4 + ceil(2 |u_w|
+                                  IBM_OPT_RECENTER) lu, rounded out to 4):
+                                  the rows outside need no force and run
+                                  inside the launches of the spreading
+                                  (above the slab) and of the previous
+                                  step's interpolation (below), overlapping
+                                  them.  The slab is measured again at
+                                  every re-centring.  A stencil outside it
+                                  makes the next synchronising call fail
+                                  with IBM_ERR_OUTSIDE_SLAB.  Used only
+                                  without a tangent and chunks, with the
+                                  row form (nx <= 256), and when the slab
+                                  holds at most three quarters of the rows.
+                                  0 (default): off.  Results are those of
+                                  the plain step                            */
+
 typedef struct ibm_lattice ibm_lattice;
 
 /* Bytes of device memory the lattice state needs (two population buffers,
- * two force densities and their tile stamps, control words).  storage:
- * IBM_STORAGE_*. */
+ * two force densities and their tile stamps, the interpolation velocity
+ * field, control words).  storage: IBM_STORAGE_*. */
 int ibm_lattice_bytes(int nx, int ny, int nz, int storage, size_t *bytes);
 
 /* Create a lattice of nx * ny * nz nodes with BGK relaxation time tau > 1/2
@@ -226,6 +249,13 @@ int ibm_synchronize(ibm_lattice *lat);
 
 /* Set an option IBM_OPT_* (see above). */
 int ibm_set_option(ibm_lattice *lat, int option, int value);
+
+/* The force box of the split lattice update (IBM_OPT_OVERLAP) that the next
+ * graph-replayed steps use: box[0..3] = zlo, zhi, ylo, yhi, the rows
+ * zlo <= z < zhi, ylo <= y < yhi (y spans the lattice: ylo = 0, yhi = ny);
+ * the whole lattice (0, nz, 0, ny) when the update is not split.  Measures
+ * the membranes' extent first if it is stale (waits). */
+int ibm_split_box(ibm_lattice *lat, int *box);
 
 /* Choose the fastest collide-stream form (IBM_OPT_LBM_VARIANT) and, with
  * capsules, stencil-box mode (IBM_OPT_STENCIL_BOX) by timing whole steps of

@@ -28,7 +28,7 @@ ERRORS = {
 STORAGE = {"fp32": 0, "fp16": 1}
 FIELD_POPS, FIELD_RHO, FIELD_U, FIELD_FORCE = 0, 1, 2, 3
 OPT_GRAPH, OPT_EQUILIBRIUM, OPT_ADVECTION, OPT_RECENTER, OPT_LBM_VARIANT = 0, 1, 2, 3, 4
-OPT_CHUNK_NODES, OPT_STENCIL_BOX = 5, 6
+OPT_CHUNK_NODES, OPT_STENCIL_BOX, OPT_OVERLAP = 5, 6, 7
 PHASES = ("forces", "spread", "lbm", "interp")
 OBS_FIELDS = ("V", "cx", "cy", "cz", "D", "theta", "ra", "rb", "rc", "area",
               "Ixx", "Iyy", "Izz", "Ixy", "Ixz", "Iyz")
@@ -64,6 +64,7 @@ def _load():
         "ibm_observables": ([v, v], i),
         "ibm_synchronize": ([v], i),
         "ibm_set_option": ([v, i, i], i),
+        "ibm_split_box": ([v, ctypes.POINTER(i)], i),
         "ibm_profile_step": ([v, i64, v], i),
         "ibm_autotune": ([v, i, v], i),
         "ibm_destroy": ([v], i),
@@ -181,6 +182,14 @@ class Lattice:
 
     def set_option(self, option: int, value: int):
         _check(lib.ibm_set_option(self._h, int(option), int(value)))
+
+    def split_box(self):
+        """(zlo, zhi, ylo, yhi): the force box of the split lattice update
+        (IBM_OPT_OVERLAP) the next graph steps use; the whole lattice when
+        the update is not split."""
+        box = (ctypes.c_int * 4)()
+        _check(lib.ibm_split_box(self._h, box))
+        return tuple(box)
 
     # -- stepping ------------------------------------------------------------
     def step(self, n: int = 1):

@@ -164,6 +164,12 @@ struct ibm_lattice {
   hipGraphExec_t gexec = nullptr;
   bool graph_valid = false;
 
+  // IBM_OPT_OVERLAP: the lattice update of graph-replayed steps split into the
+  // force slab L.zlo <= z < L.zhi and the rest, which rides along with the
+  // coupling kernels
+  int overlap = 0;
+  bool slab_stale = true;  // the slab must be measured again before the next graph
+
   bool has_tan = false;  // a tangent (forward sensitivity) state is attached
   ibm::TanDev T{};
 };
@@ -174,6 +180,7 @@ void invalidate_graph(ibm_lattice *lat) {
   if (lat->gexec) (void)hipGraphExecDestroy(lat->gexec);
   lat->gexec = nullptr;
   lat->graph_valid = false;
+  lat->slab_stale = true;
 }
 
 // Clear the control words, the tile stamps and both force fields.
@@ -258,13 +265,91 @@ int upload_chunks(ibm_lattice *lat) {
 
 int advect_mode(ibm_lattice *lat) { return (lat->ab2 && lat->have_prev_u) ? 1 : 0; }
 
+bool split_update(const ibm_lattice *lat) {
+  return lat->L.zlo > 0 || lat->L.zhi < lat->nz || lat->L.ylo > 0 || lat->L.yhi < lat->ny;
+}
+
+// IBM_OPT_OVERLAP: measure the membranes' extent (waits) and set the force
+// slab of rows zlo <= z < zhi (all y): stencils reach 1 below and 2 above a
+// node's floor(z); the margin covers the drift until the next re-centring;
+// the slab is rounded out to the 4^3 force tiles.  The whole lattice when the
+// option is off or not applicable (no row form, a tangent, chunks), or when
+// the slab holds more than three quarters of the rows.  (The slab spans all
+// y: rows updated inside the coupling launches cost more than in the
+// lattice kernel, as the coupling kernels' dependent loads then wait behind
+// their traffic, so a narrower box in y measured slower.)
+int refresh_slab(ibm_lattice *lat) {
+  int zlo = 0, zhi = lat->nz, ylo = 0, yhi = lat->ny;
+  if (lat->overlap && lat->has_mem && !lat->has_tan && lat->chunk_nodes == 0 && lat->L.tpr > 0) {
+    ibm::launch_node_range(lat->M, lat->L.ctrl, lat->stream);
+    int r[4] = {0, 0, 0, 0};  // zmin, zmax, ymin, ymax
+    IBM_HIP(hipMemcpyAsync(r, &lat->L.ctrl->zmin, sizeof(r), hipMemcpyDeviceToHost, lat->stream));
+    IBM_HIP(hipStreamSynchronize(lat->stream));
+    const int margin = 4 + (int)std::ceil(2.0 * std::fabs(lat->uw) * lat->recenter_every);
+    const int za = r[0] - 1 - margin, zb = r[1] + 3 + margin;
+    zlo = za <= 0 ? 0 : za / 4 * 4;
+    zhi = zb >= lat->nz ? lat->nz : std::min(lat->nz, (zb + 3) / 4 * 4);
+    if (4LL * (zhi - zlo) > 3LL * lat->nz) {
+      zlo = ylo = 0;
+      zhi = lat->nz;
+      yhi = lat->ny;
+    }
+  }
+  ibm::LatDev &L = lat->L;
+  if (zlo != L.zlo || zhi != L.zhi || ylo != L.ylo || yhi != L.yhi) {
+    L.zlo = zlo;
+    L.zhi = zhi;
+    L.ylo = ylo;
+    L.yhi = yhi;
+    invalidate_graph(lat);
+  }
+  lat->slab_stale = false;
+  return IBM_OK;
+}
+
+// Graph steps with the lattice update split at the force slab (rows with z in
+// [zlo, zhi); the row sets also take a box in y, here the whole lattice): the
+// other rows need no force.  Those above the slab ride along with the
+// spreading of the same step, those below it with the interpolation of the
+// step before (a step's update only needs that step's populations), so only
+// the slab waits for the spreading.  The first step's
+// rows of the second kind go first on their own; the last interpolation
+// carries no rows (the next step is not begun).
+void enqueue_steps_split(ibm_lattice *lat, hipStream_t s, int nsteps, int advect) {
+  const ibm::LatDev &L = lat->L;
+  const bool linear = lat->eq_linear != 0;
+  const int mode = interp_mode(lat->box_mode);
+  const int slab = L.zhi - L.zlo;
+  const ibm::RowSet near{0, 0, L.zlo, L.ylo, L.yhi - L.ylo, slab * (L.yhi - L.ylo)};
+  const ibm::RowSet low{0, L.zlo * L.ny, L.zlo, 0, std::max(1, L.ylo), slab * L.ylo};
+  const ibm::RowSet high{L.zhi * L.ny, (L.nz - L.zhi) * L.ny, L.zlo, L.yhi, std::max(1, L.ny - L.yhi),
+                         slab * (L.ny - L.yhi)};
+  const ibm::RowSet none{0, 0, 0, 0, 1, 0};
+  const int src0 = (int)(lat->steps & 1);
+  ibm::launch_collide_stream_rows(L, lat->storage, src0, src0, false, linear, low, s);
+  for (int k = 0; k < nsteps; ++k) {
+    const int src = (int)(lat->steps & 1);
+    const int par = src;
+    ibm::launch_spread_far(L, lat->M, par, lat->box_mode & 1, lat->storage, linear, src, high, s);
+    ibm::launch_collide_stream_rows(L, lat->storage, src, par, true, linear, near, s);
+    ibm::launch_interp_far(L, lat->M, lat->storage, src ^ 1, par, advect, mode, linear,
+                           k + 1 < nsteps ? low : none, s);
+    lat->steps += 1;
+    lat->since_recenter += 1;
+  }
+}
+
 int capture_graph(ibm_lattice *lat) {
   invalidate_graph(lat);
   if (!lat->cap_stream) IBM_HIP(hipStreamCreateWithFlags(&lat->cap_stream, hipStreamNonBlocking));
   const int64_t saved_steps = lat->steps, saved_since = lat->since_recenter;
   hipGraph_t graph = nullptr;
   IBM_HIP(hipStreamBeginCapture(lat->cap_stream, hipStreamCaptureModeThreadLocal));
-  for (int k = 0; k < GRAPH_STEPS; ++k) enqueue_step(lat, lat->cap_stream, advect_mode(lat));
+  if (split_update(lat)) {
+    enqueue_steps_split(lat, lat->cap_stream, GRAPH_STEPS, advect_mode(lat));
+  } else {
+    for (int k = 0; k < GRAPH_STEPS; ++k) enqueue_step(lat, lat->cap_stream, advect_mode(lat));
+  }
   hipError_t e = hipStreamEndCapture(lat->cap_stream, &graph);
   lat->steps = saved_steps;
   lat->since_recenter = saved_since;
@@ -292,6 +377,8 @@ int check_device(ibm_lattice *lat) {
     if (err & ibm::ERR_FACE)
       return fail(IBM_ERR_INVERTED_FACE, "a membrane face degenerated (det C <= 0)");
     if (err & ibm::ERR_NONFINITE) return fail(IBM_ERR_NONFINITE, "non-finite observables");
+    if (err & ibm::ERR_SLAB)
+      return fail(IBM_ERR_OUTSIDE_SLAB, "a stencil reached outside the force slab of the split update");
   }
   return IBM_OK;
 }
@@ -465,7 +552,11 @@ int batch_sync_tables(ibm_batch *b) {
   const BatchLayout bl = batch_layout(n, b->cap_lat, b->cap_node);
   std::vector<char> img(bl.total, 0);
   for (size_t r = 0; r < n; ++r) {
-    std::memcpy(img.data() + bl.lat + r * sizeof(ibm::LatDev), &b->runs[r]->L, sizeof(ibm::LatDev));
+    ibm::LatDev Lr = b->runs[r]->L;  // batches update the whole lattice
+    Lr.zlo = Lr.ylo = 0;
+    Lr.zhi = Lr.nz;
+    Lr.yhi = Lr.ny;
+    std::memcpy(img.data() + bl.lat + r * sizeof(ibm::LatDev), &Lr, sizeof(ibm::LatDev));
     std::memcpy(img.data() + bl.mem + r * sizeof(ibm::MemDev), &b->runs[r]->M, sizeof(ibm::MemDev));
   }
   std::memcpy(img.data() + bl.lat_items, li.data(), li.size() * sizeof(int2));
@@ -598,6 +689,10 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
   L.inv_tau = (float)(1.0 / tau);
   L.guo_pre = (float)(1.0 - 0.5 / tau);
   L.uw = 0.0f;
+  L.zlo = 0;
+  L.zhi = nz;
+  L.ylo = 0;
+  L.yhi = ny;
   for (int i = 0; i < ibm::Q; ++i) L.h_scale[i] = L.h_inv[i] = 1.0f;
   if (storage == IBM_STORAGE_FP16) {
     // Deviations f_i - w_i scaled by 2^k / w_i keep a shear-flow population
@@ -809,6 +904,19 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
   return ok();
 }
 
+int ibm_split_box(ibm_lattice *lat, int *box) {
+  if (!lat || !box) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  if (lat->slab_stale && (lat->overlap || split_update(lat))) {
+    int rc = refresh_slab(lat);
+    if (rc) return rc;
+  }
+  box[0] = lat->L.zlo;
+  box[1] = lat->L.zhi;
+  box[2] = lat->L.ylo;
+  box[3] = lat->L.yhi;
+  return ok();
+}
+
 int ibm_step(ibm_lattice *lat, int64_t n) {
   if (!lat) return fail(IBM_ERR_INVALID_ARG, "lat is NULL");
   if (n < 0) return fail(IBM_ERR_INVALID_ARG, "negative step count");
@@ -818,6 +926,11 @@ int ibm_step(ibm_lattice *lat, int64_t n) {
     if (lat->has_mem && lat->since_recenter >= lat->recenter_every) {
       ibm::launch_recenter(lat->M, lat->stream);
       lat->since_recenter = 0;
+      if (lat->overlap) lat->slab_stale = true;
+    }
+    if (lat->slab_stale && (lat->overlap || split_update(lat))) {
+      int rc = refresh_slab(lat);
+      if (rc) return rc;
     }
     const bool graph_ok = lat->use_graph && (lat->steps & 1) == 0 && n >= GRAPH_STEPS &&
                           (!lat->has_mem || lat->since_recenter + GRAPH_STEPS <= lat->recenter_every) &&
@@ -886,6 +999,7 @@ int ibm_set_mesh(ibm_lattice *lat, const double *xyz_host) {
   IBM_HIP(hipStreamSynchronize(lat->stream));
   lat->have_prev_u = false;
   lat->since_recenter = 0;
+  lat->slab_stale = true;  // the nodes moved: the force slab is measured again
   return ok();
 }
 
@@ -930,6 +1044,11 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
     case IBM_OPT_LBM_VARIANT:
       if (value < 0 || value > 63) return fail(IBM_ERR_INVALID_ARG, "variant is 0..63");
       lat->lbm_variant = value;
+      break;
+    case IBM_OPT_OVERLAP:
+      if (value < 0 || value > 1) return fail(IBM_ERR_INVALID_ARG, "overlap is 0 or 1");
+      lat->overlap = value;
+      invalidate_graph(lat);
       break;
     case IBM_OPT_STENCIL_BOX:
       if (value < 0 || value > 7) return fail(IBM_ERR_INVALID_ARG, "stencil box mode is 0..7");

@@ -41,11 +41,14 @@ constexpr int TILE_X = 4, TILE_Y = 4, TILE_Z = 4;
 constexpr int ERR_WALL = 1;      // a nonzero stencil weight beyond a wall
 constexpr int ERR_FACE = 2;      // a face with non-positive deformed area
 constexpr int ERR_NONFINITE = 4; // NaN/Inf in the observables
+constexpr int ERR_SLAB = 8;      // a nonzero stencil weight outside [zlo, zhi)
 
 struct alignas(256) Ctrl {
   int step;   // number of completed timesteps (incremented by the last kernel)
   int err;    // ERR_* bits, OR-ed by kernels, cleared by the host
-  int pad[62];
+  int zmin, zmax;  // lattice z and y extents of the membrane nodes (k_node_range)
+  int ymin, ymax;
+  int pad[58];
 };
 
 // Everything the lattice kernels need, passed by value.
@@ -60,6 +63,8 @@ struct LatDev {
   void *f[2];             // population buffers (float or __half), see pidx
   float *g[2];            // force density [3][S] of even and odd steps
   int *stamp[2];          // per-tile step stamps of the two fields
+  int zlo, zhi, ylo, yhi; // rows (z, y) stencils may reach: the whole lattice
+                          // unless the update is split, see IBM_OPT_OVERLAP
   float4 *U;              // lattice velocity (ux, uy, uz, 0) at the nodes of
                           // the tiles stamped this step, for interpolation [S]
   Ctrl *ctrl;
@@ -70,6 +75,19 @@ struct LatDev {
   float h_inv[Q];         // 1 / h_scale[i], rounded to FP32
   long long pst[Q];       // i * pstride: offset of population i within a group
 };
+
+// A set of x rows (row = z ny + y) for the row-form lattice update: the run
+// a0 .. a0 + n0 - 1, then n1 rows of the box z in [bz, ...), y in [by, by + wy)
+// taken y fastest.
+struct RowSet {
+  int a0, n0, bz, by, wy, n1;
+};
+__device__ __forceinline__ int rowset_row(const RowSet &rs, const LatDev &L, int k) {
+  if (k < rs.n0) return rs.a0 + k;
+  k -= rs.n0;
+  const int q = k / rs.wy;
+  return (rs.bz + q) * L.ny + rs.by + (k - q * rs.wy);
+}
 
 // Membrane arrays (all capsules concatenated).
 struct MemDev {

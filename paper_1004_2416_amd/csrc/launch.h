@@ -7,8 +7,14 @@ namespace ibm {
 
 // lbm_kernels.hip
 // variant: tuning bits of the collide-stream kernel (see lbm_kernels.hip)
+// z0, z1: update only the nodes with z0 <= z < z1 (streaming out of the range
+// is included); the default is the whole lattice
 void launch_collide_stream(const LatDev &L, int fp16, int src, int par, bool force,
-                           bool linear, int variant, hipStream_t s);
+                           bool linear, int variant, hipStream_t s, int z0 = 0, int z1 = -1);
+// The row form over the rows of rs; false (nothing launched) where the row
+// form does not apply (L.tpr == 0)
+bool launch_collide_stream_rows(const LatDev &L, int fp16, int src, int par, bool force,
+                                bool linear, const RowSet &rs, hipStream_t s);
 void launch_init_equilibrium(const LatDev &L, int fp16, int dst, double uw, hipStream_t s);
 void launch_get_field(const LatDev &L, int fp16, int src, int gpar, int what, double *out,
                       hipStream_t s);
@@ -41,6 +47,16 @@ void launch_spread(const LatDev &L, const MemDev &M, int par, bool box, hipStrea
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
                           int advect, int mode, hipStream_t s);
 void launch_recenter(const MemDev &M, hipStream_t s);
+// Spreading of step (par), and interpolation of the step whose new
+// populations are in buffer fsrc, each carrying the force-free lattice update
+// of the rows of rs in buffer fsrc (row form)
+void launch_spread_far(const LatDev &L, const MemDev &M, int par, bool box, int fp16, bool linear,
+                       int fsrc, const RowSet &rs, hipStream_t s);
+void launch_interp_far(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par, int advect,
+                       int mode, bool linear, const RowSet &rs, hipStream_t s);
+// min and max over the membrane nodes of floor(lattice z) and floor(lattice
+// y) into ctrl->zmin, zmax, ymin, ymax
+void launch_node_range(const MemDev &M, Ctrl *ctrl, hipStream_t s);
 void launch_batch_spread(const BatchDev &B, int par, bool box, hipStream_t s);
 void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect, int mode,
                          hipStream_t s);

@@ -11,6 +11,7 @@
 
 #include "common.h"
 #include "launch.h"
+#include "lbm_device.h"
 
 namespace ibm {
 
@@ -301,6 +302,12 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
     if (w != 0.0f && (gz < 0 || gz >= L.nz)) {
       atomicOr(&L.ctrl->err, ERR_WALL);
       w = 0.0f;
+    }
+    // a split lattice update assumes no force outside the rows zlo <= z < zhi,
+    // ylo <= y < yhi
+    if (w != 0.0f) {
+      const int Y = wrap_mod(gy, L.ny);
+      if (gz < L.zlo || gz >= L.zhi || Y < L.ylo || Y >= L.yhi) atomicOr(&L.ctrl->err, ERR_SLAB);
     }
   }
   const bool has = w != 0.0f;
@@ -1319,6 +1326,162 @@ void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int adv
   if (fp16) IBM_LAUNCH_BATCH_INTERP(__half);
   else IBM_LAUNCH_BATCH_INTERP(float);
 #undef IBM_LAUNCH_BATCH_INTERP
+}
+
+// ---- coupling kernels carrying part of a split lattice update -------------------
+// IBM_OPT_OVERLAP: the lattice update of the x rows outside the force slab
+// needs no force density, so it rides along with a coupling kernel.  Blocks
+// [0, xcd_grid(nblocks)) of the launch do the coupling kernel's work; the
+// blocks after them update the rows of rs in buffer fsrc into fsrc ^ 1 (row
+// form, four wavefronts of whole rows per block).  The latency-bound coupling
+// blocks and the bandwidth-bound lattice blocks then share the chip within
+// one launch.
+__device__ __forceinline__ int coupling_blocks(int nblocks) { return (nblocks + 7) / 8 * 8; }
+
+template <typename T, bool LINEAR>
+__device__ __forceinline__ void far_rows_block(const LatDev &L, int fsrc, int kb, const RowSet &rs) {
+  const int lane = threadIdx.x & 63;
+  const int wave = kb * 4 + (int)(threadIdx.x >> 6);
+  const int n = rs.n0 + rs.n1;
+  if (wave * L.rpw >= n) return;  // the whole wavefront is past the set
+  const int r = lane / L.tpr;
+  const int t = lane - r * L.tpr;
+  const int k = wave * L.rpw + r;
+  const bool live = r < L.rpw && k < n;
+  collide_stream_rowseg<T, LINEAR, false, true>(L, fsrc, 0, live ? rowset_row(rs, L, k) : 0, t, lane, live);
+}
+
+template <int M, bool BOX, typename T, bool LINEAR>
+__global__ __launch_bounds__(256) void k_spread_far(LatDev L, MemDev Mm, int par, int nblocks,
+                                                    int fsrc, RowSet rs) {
+  __shared__ SpreadLDS sm;
+  const int cb = coupling_blocks(nblocks);
+  if ((int)blockIdx.x < cb) {
+    const int blk = xcd_block(nblocks);
+    if (blk >= 0) spread_lanes<M, BOX>(L, Mm, par, blk, sm);
+    return;
+  }
+  far_rows_block<T, LINEAR>(L, fsrc, (int)blockIdx.x - cb, rs);
+}
+
+template <typename T, int M, int MODE, bool LINEAR>
+__global__ __launch_bounds__(256) void k_interp_far(LatDev L, MemDev Mm, int fsrc, int par,
+                                                    int advect, int nblocks, RowSet rs) {
+  __shared__ InterpLDS sm;
+  const int cb = coupling_blocks(nblocks);
+  if ((int)blockIdx.x < cb) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
+    const int blk = xcd_block(nblocks);
+    if (blk >= 0) interp_lanes<T, M, MODE == 1, MODE == 2>(L, Mm, fsrc, par, advect, blk, sm);
+    return;
+  }
+  far_rows_block<T, LINEAR>(L, fsrc, (int)blockIdx.x - cb, rs);
+}
+
+static unsigned far_blocks(const LatDev &L, const RowSet &rs) {
+  const long long rows = (long long)rs.n0 + rs.n1;
+  if (rows <= 0 || L.tpr <= 0) return 0;
+  return (unsigned)(((rows + L.rpw - 1) / L.rpw + 3) / 4);
+}
+
+template <typename T, bool LINEAR>
+static void launch_spread_far_t(const LatDev &L, const MemDev &M, int par, bool box, int fsrc,
+                                const RowSet &rs, hipStream_t s) {
+  const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
+  const int nblocks = (int)(((long long)M.nn * gs + 255) / 256);
+  const dim3 grid(xcd_grid(nblocks) + far_blocks(L, rs)), block(256);
+#define IBM_LAUNCH_SPREAD_FAR(BX)                                                                        \
+  do {                                                                                                   \
+    if (M.m == 2) k_spread_far<2, BX, T, LINEAR><<<grid, block, 0, s>>>(L, M, par, nblocks, fsrc, rs);      \
+    else if (M.m == 3) k_spread_far<3, BX, T, LINEAR><<<grid, block, 0, s>>>(L, M, par, nblocks, fsrc, rs); \
+    else k_spread_far<4, BX, T, LINEAR><<<grid, block, 0, s>>>(L, M, par, nblocks, fsrc, rs);          \
+  } while (0)
+  if (box) IBM_LAUNCH_SPREAD_FAR(true);
+  else IBM_LAUNCH_SPREAD_FAR(false);
+#undef IBM_LAUNCH_SPREAD_FAR
+}
+
+void launch_spread_far(const LatDev &L, const MemDev &M, int par, bool box, int fp16, bool linear,
+                       int fsrc, const RowSet &rs, hipStream_t s) {
+  if (M.nn <= 0) return;
+  if (fp16) {
+    if (linear) launch_spread_far_t<__half, true>(L, M, par, box, fsrc, rs, s);
+    else launch_spread_far_t<__half, false>(L, M, par, box, fsrc, rs, s);
+  } else {
+    if (linear) launch_spread_far_t<float, true>(L, M, par, box, fsrc, rs, s);
+    else launch_spread_far_t<float, false>(L, M, par, box, fsrc, rs, s);
+  }
+}
+
+template <typename T, bool LINEAR>
+static void launch_interp_far_t(const LatDev &L, const MemDev &M, int fsrc, int par, int advect,
+                                int mode, const RowSet &rs, hipStream_t s) {
+  const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
+  const int nblocks = (int)(((long long)M.nn * gs + 255) / 256);
+  const dim3 grid(xcd_grid(nblocks) + far_blocks(L, rs)), block(256);
+  if (mode == 2) {
+    const long long tiles = (long long)L.tnx * L.tny * L.tnz;
+    k_tile_velocity<T><<<dim3((unsigned)((tiles + 31) / 32)), block, 0, s>>>(L, fsrc, par, 32);
+  }
+#define IBM_LAUNCH_INTERP_FAR(MD)                                                                                \
+  do {                                                                                                           \
+    if (M.m == 2) k_interp_far<T, 2, MD, LINEAR><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks, rs);      \
+    else if (M.m == 3) k_interp_far<T, 3, MD, LINEAR><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks, rs); \
+    else k_interp_far<T, 4, MD, LINEAR><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks, rs);          \
+  } while (0)
+  if (mode == 2) IBM_LAUNCH_INTERP_FAR(2);
+  else if (mode == 1) IBM_LAUNCH_INTERP_FAR(1);
+  else IBM_LAUNCH_INTERP_FAR(0);
+#undef IBM_LAUNCH_INTERP_FAR
+}
+
+void launch_interp_far(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par, int advect,
+                       int mode, bool linear, const RowSet &rs, hipStream_t s) {
+  if (M.nn <= 0) return;
+  if (fp16) {
+    if (linear) launch_interp_far_t<__half, true>(L, M, fsrc, par, advect, mode, rs, s);
+    else launch_interp_far_t<__half, false>(L, M, fsrc, par, advect, mode, rs, s);
+  } else {
+    if (linear) launch_interp_far_t<float, true>(L, M, fsrc, par, advect, mode, rs, s);
+    else launch_interp_far_t<float, false>(L, M, fsrc, par, advect, mode, rs, s);
+  }
+}
+
+// ---- lattice extent of the membrane -------------------------------------------
+__global__ __launch_bounds__(256) void k_node_range(MemDev M, Ctrl *ctrl) {
+  int zlo = 0x7fffffff, zhi = -0x7fffffff, ylo = 0x7fffffff, yhi = -0x7fffffff;
+  for (int n = blockIdx.x * blockDim.x + threadIdx.x; n < M.nn; n += gridDim.x * blockDim.x) {
+    const int4 o = M.origin[M.node_cap[n]];
+    const float4 p = M.x[n];
+    const int z = o.z + (int)floorf(p.z), y = o.y + (int)floorf(p.y);
+    zlo = min(zlo, z);
+    zhi = max(zhi, z);
+    ylo = min(ylo, y);
+    yhi = max(yhi, y);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    zlo = min(zlo, __shfl_xor(zlo, off, 64));
+    zhi = max(zhi, __shfl_xor(zhi, off, 64));
+    ylo = min(ylo, __shfl_xor(ylo, off, 64));
+    yhi = max(yhi, __shfl_xor(yhi, off, 64));
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicMin(&ctrl->zmin, zlo);
+    atomicMax(&ctrl->zmax, zhi);
+    atomicMin(&ctrl->ymin, ylo);
+    atomicMax(&ctrl->ymax, yhi);
+  }
+}
+
+void launch_node_range(const MemDev &M, Ctrl *ctrl, hipStream_t s) {
+  launch_fill_u32(&ctrl->zmin, 1, 0x7fffffffu, s);
+  launch_fill_u32(&ctrl->zmax, 1, 0x80000001u, s);  // -0x7fffffff
+  launch_fill_u32(&ctrl->ymin, 1, 0x7fffffffu, s);
+  launch_fill_u32(&ctrl->ymax, 1, 0x80000001u, s);
+  if (M.nn <= 0) return;
+  const int blocks = (int)std::min<long long>(1024, ((long long)M.nn + 255) / 256);
+  k_node_range<<<dim3(blocks), dim3(256), 0, s>>>(M, ctrl);
 }
 
 // ---- capsule frame re-centring -------------------------------------------------

@@ -284,6 +284,66 @@ def test_trajectory_drifting_capsule_wraps_and_recentres(B, nx, box):
     assert np.max(np.abs(xg - sim.x)) < 1e-3
 
 
+@pytest.mark.parametrize("box", [-1, 5])
+def test_split_update_overlap(B, box):
+    """IBM_OPT_OVERLAP on a tall lattice: the lattice update of graph steps is
+    split into the slab of rows stencils can reach (after spreading) and the
+    other rows (without force, inside the coupling launches).  192 steps with
+    two re-centrings against the oracle, with the default interpolation and
+    with the tile-velocity field (box 5); then the option off goes back to
+    the whole lattice."""
+    nx, ny, nz, uw, r = 24, 40, 64, 0.02, 4.0
+    ks = W.ks_from_capillary(0.05, uw, nz, r)
+    c = Case(W.Workload("tall", nx, ny, nz, 1.0, uw, 3, 0,
+                        [W.CapsuleSpec(2, r, (11.7, 19.6, 31.8), ks, ks)]), perturb=0.01, seed=5)
+    lat = c.gpu(graph=True)
+    if box >= 0:
+        lat.set_option(B.OPT_STENCIL_BOX, box)
+    lat.set_option(B.OPT_OVERLAP, 1)
+    zlo, zhi, ylo, yhi = lat.split_box()
+    say("  force box z", zlo, zhi, "y", ylo, yhi)
+    # the capsule spans z 27.8..35.8; stencils reach 1 below and 2 above, the
+    # margin is 4 + ceil(2 * 0.02 * 64) = 7, rounded out to multiples of 4
+    assert (zlo, zhi, ylo, yhi) == (16, 48, 0, ny)
+    sim = c.oracle()
+    lat.step(192)
+    assert sim.run(192) == 0
+    lat.synchronize()
+    f = lat.populations().cpu().numpy()
+    xg = lat.mesh()[0].cpu().numpy()
+    ef, ex = rel_err(f, sim.f), float(np.max(np.abs(xg - sim.x)))
+    say("  overlap 192 steps: f %.2e  x %.2e" % (ef, ex))
+    assert ef < 1e-5 and ex < 1e-4
+    lat.set_option(B.OPT_OVERLAP, 0)
+    assert lat.split_box() == (0, nz, 0, ny)
+    lat.step(32)
+    assert sim.run(32) == 0
+    assert rel_err(lat.populations().cpu().numpy(), sim.f) < 1e-5
+    lat.close()
+
+
+def test_split_update_falls_back(B):
+    """The whole lattice stays one update where the slab would hold more than
+    three quarters of the rows; a capsule across the periodic y end."""
+    short = small_case(m=3, ca=0.02, uw=0.03).gpu(graph=True)
+    short.set_option(B.OPT_OVERLAP, 1)
+    nz, ny, nx = short.shape
+    assert short.split_box() == (0, nz, 0, ny)
+    short.close()
+    nx, ny, nz, uw, r = 24, 40, 64, 0.02, 4.0
+    ks = W.ks_from_capillary(0.05, uw, nz, r)
+    c = Case(W.Workload("tall", nx, ny, nz, 1.0, uw, 3, 0,
+                        [W.CapsuleSpec(2, r, (11.7, 2.5, 31.8), ks, ks)]))
+    lat = c.gpu(graph=True)
+    lat.set_option(B.OPT_OVERLAP, 1)
+    assert lat.split_box() == (16, 48, 0, ny)
+    sim = c.oracle()
+    lat.step(64)
+    assert sim.run(64) == 0
+    assert rel_err(lat.populations().cpu().numpy(), sim.f) < 1e-5
+    lat.close()
+
+
 def test_adams_bashforth_and_linear_equilibrium(B):
     """The two variants of the method the paper tests: second-order
     advection (Sec. II.C) and the linearised equilibrium (Sec. IV.A)."""
