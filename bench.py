@@ -160,8 +160,9 @@ def main():
                          "-1: library default)")
     ap.add_argument("--stencil-box", type=int, default=-1,
                     help="IBM_OPT_STENCIL_BOX bits (-1: library default)")
-    ap.add_argument("--overlap", type=int, default=-1,
-                    help="IBM_OPT_OVERLAP (-1: library default)")
+    ap.add_argument("--overlap", type=int, default=1,
+                    help="IBM_OPT_OVERLAP: 1 (default) splits the lattice update where it pays, "
+                         "0 off, -1 library default")
     ap.add_argument("--sensitivity", action="store_true",
                     help="time the tangent-model gradient of D instead of the step")
     ap.add_argument("--autotune", action="store_true",
@@ -195,6 +196,7 @@ def main():
                     args.chunk_nodes, args.stencil_box, args.overlap)
     stream = lat.stream
     tuned = lat.autotune(64) if args.autotune else None
+    split_box = lat.split_box()
     lat.step(args.warmup)
     lat.synchronize()
 
@@ -239,7 +241,7 @@ def main():
             "delta_width": wl.m, "storage": args.storage, "graph": not args.no_graph,
             "u_w": wl.u_w, "tau": wl.tau, "lbm_variant": args.lbm_variant,
             "chunk_nodes": args.chunk_nodes, "stencil_box": args.stencil_box,
-            "overlap": args.overlap, "autotuned": tuned,
+            "overlap": args.overlap, "split_box": list(split_box), "autotuned": tuned,
         },
         "membrane_node_updates_per_s": round(wl.n_membrane_nodes * args.steps / (ms * 1e-3), 1),
         "step_pct_hbm_roofline": round(100 * mlups * 1e6 * bytes_per_node(args.storage)

@@ -145,7 +145,7 @@ extern "C" {
                                   Results agree to FP32 rounding
                                   (summation order differs)                 */
 
-#define IBM_OPT_OVERLAP 7      /* 1: split the lattice update of
+#define IBM_OPT_OVERLAP 7      /* 1, 2: split the lattice update of
                                   graph-replayed steps at the slab of z
                                   that stencils can reach (the membranes' z
                                   extent plus a margin of 4 + ceil(2 |u_w|
@@ -160,9 +160,11 @@ extern "C" {
                                   with IBM_ERR_OUTSIDE_SLAB.  Used only
                                   without a tangent and chunks, with the
                                   row form (nx <= 256), and when the slab
-                                  holds at most three quarters of the rows.
-                                  0 (default): off.  Results are those of
-                                  the plain step                            */
+                                  holds at most three quarters of the rows
+                                  (value 2), and with value 1 only when at
+                                  least 2^20 nodes lie outside it (the
+                                  split pays there).  0 (default): off.
+                                  Results are those of the plain step       */
 
 typedef struct ibm_lattice ibm_lattice;
 
@@ -258,8 +260,9 @@ int ibm_set_option(ibm_lattice *lat, int option, int value);
 int ibm_split_box(ibm_lattice *lat, int *box);
 
 /* Choose the fastest collide-stream form (IBM_OPT_LBM_VARIANT) and, with
- * capsules, stencil-box mode (IBM_OPT_STENCIL_BOX) by timing whole steps of
- * this lattice with HIP events: after 4 x steps_per_trial settling steps,
+ * capsules, stencil-box mode (IBM_OPT_STENCIL_BOX) and IBM_OPT_OVERLAP (on
+ * only where it splits the update and is faster; query it with
+ * ibm_split_box) by timing whole steps of this lattice with HIP events: after 4 x steps_per_trial settling steps,
  * each candidate runs 16 steps and is then timed twice over steps_per_trial
  * steps (rounded up to a multiple of 16), keeping the better time.  The run
  * advances by all these steps (the candidates compute the same update, to

@@ -1466,7 +1466,25 @@ __global__ __launch_bounds__(256) void k_node_range(MemDev M, Ctrl *ctrl) {
     ylo = min(ylo, __shfl_xor(ylo, off, 64));
     yhi = max(yhi, __shfl_xor(yhi, off, 64));
   }
+  // across the block's wavefronts, then four atomics per block (few blocks:
+  // thousands of atomics on the same four words serialise)
+  __shared__ int red[4][4];
+  const int w = threadIdx.x >> 6;
   if ((threadIdx.x & 63) == 0) {
+    red[0][w] = zlo;
+    red[1][w] = zhi;
+    red[2][w] = ylo;
+    red[3][w] = yhi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = (int)(blockDim.x >> 6);
+    for (int k = 1; k < nw; ++k) {
+      zlo = min(zlo, red[0][k]);
+      zhi = max(zhi, red[1][k]);
+      ylo = min(ylo, red[2][k]);
+      yhi = max(yhi, red[3][k]);
+    }
     atomicMin(&ctrl->zmin, zlo);
     atomicMax(&ctrl->zmax, zhi);
     atomicMin(&ctrl->ymin, ylo);
@@ -1480,7 +1498,7 @@ void launch_node_range(const MemDev &M, Ctrl *ctrl, hipStream_t s) {
   launch_fill_u32(&ctrl->ymin, 1, 0x7fffffffu, s);
   launch_fill_u32(&ctrl->ymax, 1, 0x80000001u, s);
   if (M.nn <= 0) return;
-  const int blocks = (int)std::min<long long>(1024, ((long long)M.nn + 255) / 256);
+  const int blocks = (int)std::min<long long>(64, ((long long)M.nn + 255) / 256);
   k_node_range<<<dim3(blocks), dim3(256), 0, s>>>(M, ctrl);
 }
 

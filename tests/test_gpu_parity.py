@@ -299,7 +299,7 @@ def test_split_update_overlap(B, box):
     lat = c.gpu(graph=True)
     if box >= 0:
         lat.set_option(B.OPT_STENCIL_BOX, box)
-    lat.set_option(B.OPT_OVERLAP, 1)
+    lat.set_option(B.OPT_OVERLAP, 2)
     zlo, zhi, ylo, yhi = lat.split_box()
     say("  force box z", zlo, zhi, "y", ylo, yhi)
     # the capsule spans z 27.8..35.8; stencils reach 1 below and 2 above, the
@@ -314,6 +314,9 @@ def test_split_update_overlap(B, box):
     ef, ex = rel_err(f, sim.f), float(np.max(np.abs(xg - sim.x)))
     say("  overlap 192 steps: f %.2e  x %.2e" % (ef, ex))
     assert ef < 1e-5 and ex < 1e-4
+    # value 1 splits only with 2^20 nodes outside the slab (here 40 k)
+    lat.set_option(B.OPT_OVERLAP, 1)
+    assert lat.split_box() == (0, nz, 0, ny)
     lat.set_option(B.OPT_OVERLAP, 0)
     assert lat.split_box() == (0, nz, 0, ny)
     lat.step(32)
@@ -326,7 +329,7 @@ def test_split_update_falls_back(B):
     """The whole lattice stays one update where the slab would hold more than
     three quarters of the rows; a capsule across the periodic y end."""
     short = small_case(m=3, ca=0.02, uw=0.03).gpu(graph=True)
-    short.set_option(B.OPT_OVERLAP, 1)
+    short.set_option(B.OPT_OVERLAP, 2)
     nz, ny, nx = short.shape
     assert short.split_box() == (0, nz, 0, ny)
     short.close()
@@ -335,7 +338,7 @@ def test_split_update_falls_back(B):
     c = Case(W.Workload("tall", nx, ny, nz, 1.0, uw, 3, 0,
                         [W.CapsuleSpec(2, r, (11.7, 2.5, 31.8), ks, ks)]))
     lat = c.gpu(graph=True)
-    lat.set_option(B.OPT_OVERLAP, 1)
+    lat.set_option(B.OPT_OVERLAP, 2)
     assert lat.split_box() == (16, 48, 0, ny)
     sim = c.oracle()
     lat.step(64)
