@@ -214,9 +214,11 @@ def main():
     ms_per_step = ms / args.steps
     mlups = wl.n_nodes_lattice * args.steps / (ms * 1e-3) / 1e6
 
-    # per-kernel durations from HIP events on the library's stream
+    # per-phase durations from HIP events between the kernels on the library's
+    # stream, then the collide-stream kernel's own duration from the start and
+    # end timestamps of its dispatches (what rocprofv3 reports for it)
     phases = lat.profile(args.profile_steps)
-    k1_ms = phases["lbm"]
+    k1_ms = lat.lattice_kernel_ms(args.profile_steps)
     algo = bytes_per_node(args.storage) * wl.n_nodes_lattice
     achieved = algo / (k1_ms * 1e-3) / 1e9
     obs = lat.observables()
@@ -257,6 +259,8 @@ def main():
                                             else (tuned or {}).get("lbm_variant", 23),
                                             args.storage),
             "algorithmic_bytes_per_launch": algo,
+            "kernel_us": round(k1_ms * 1e3, 2),
+            "launches_timed": args.profile_steps,
         },
     }
     if not args.no_cpu_baseline:
@@ -372,7 +376,7 @@ def run_batch(args):
     mlups_single = n_lat * k_single / (start.elapsed_time(end) * 1e-3) / 1e6
 
     phases = batch.profile(args.profile_steps)
-    k1_ms = phases["lbm"]
+    k1_ms = batch.lattice_kernel_ms(args.profile_steps)
     algo = bytes_per_node(args.storage) * n_lat
     achieved = algo / (k1_ms * 1e-3) / 1e9
     D = [float(lat.observables()[0, 4]) for lat in lats[:4]]
@@ -411,6 +415,7 @@ def run_batch(args):
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": measured_traffic("batched_sweep_64runs", args.storage),
             "kernel": "k_batch_collide_stream", "algorithmic_bytes_per_launch": algo,
+            "kernel_us": round(k1_ms * 1e3, 2), "launches_timed": args.profile_steps,
         },
     }
     if not args.no_cpu_baseline:

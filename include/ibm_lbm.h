@@ -275,6 +275,15 @@ int ibm_autotune(ibm_lattice *lat, int steps_per_trial, int *chosen);
  * measurement; waits. */
 int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase);
 
+/* Run n timesteps as ibm_profile_step does (plain launches, the whole-lattice
+ * update of step 3, Sec. II.A) and store in *ms the mean execution time of
+ * the collide-stream kernel alone, in milliseconds: the difference of the
+ * start and end timestamps of its own dispatch (hipExtLaunchKernel events),
+ * which is what a kernel tracer reports for it; the IBM_PHASE_LBM phase of
+ * ibm_profile_step also holds the launch gaps before and after it.  For
+ * measurement; waits. */
+int ibm_profile_lattice_kernel(ibm_lattice *lat, int64_t n, double *ms);
+
 /* Release the handle (not the caller's device buffers); waits first. */
 int ibm_destroy(ibm_lattice *lat);
 
@@ -378,6 +387,10 @@ int ibm_batch_step(ibm_batch *b, int64_t n);
  * HIP events between the batched kernels; ms_per_phase[IBM_N_PHASES] gets
  * the mean duration per step of each phase.  For measurement; waits. */
 int ibm_batch_profile_step(ibm_batch *b, int64_t n, double *ms_per_phase);
+
+/* ibm_profile_lattice_kernel for a batch: the mean execution time of the
+ * batched collide-stream kernel over n steps of every run. */
+int ibm_batch_profile_lattice_kernel(ibm_batch *b, int64_t n, double *ms);
 
 /* Release the batch (not the runs or dev_mem); waits first. */
 int ibm_batch_destroy(ibm_batch *b);

@@ -66,6 +66,7 @@ def _load():
         "ibm_set_option": ([v, i, i], i),
         "ibm_split_box": ([v, ctypes.POINTER(i)], i),
         "ibm_profile_step": ([v, i64, v], i),
+        "ibm_profile_lattice_kernel": ([v, i64, v], i),
         "ibm_autotune": ([v, i, v], i),
         "ibm_destroy": ([v], i),
         "ibm_last_error": ([], ctypes.c_char_p),
@@ -83,6 +84,7 @@ def _load():
         "ibm_batch_create": ([i, v, v, sz, ctypes.POINTER(v)], i),
         "ibm_batch_step": ([v, i64], i),
         "ibm_batch_profile_step": ([v, i64, v], i),
+        "ibm_batch_profile_lattice_kernel": ([v, i64, v], i),
         "ibm_batch_destroy": ([v], i),
     }
     for name, (args, res) in sig.items():
@@ -206,6 +208,13 @@ class Lattice:
         out = np.zeros(4)
         _check(lib.ibm_profile_step(self._h, int(n), _ptr(out)))
         return dict(zip(PHASES, out.tolist()))
+
+    def lattice_kernel_ms(self, n: int) -> float:
+        """Mean execution time (ms) of the collide-stream kernel over n plain
+        steps, from its own dispatch timestamps (the run advances by n)."""
+        out = np.zeros(1)
+        _check(lib.ibm_profile_lattice_kernel(self._h, int(n), _ptr(out)))
+        return float(out[0])
 
     def autotune(self, steps_per_trial: int = 64) -> dict:
         """Pick the fastest kernel forms by timing real steps (the run
@@ -350,6 +359,13 @@ class Batch:
         out = np.zeros(4)
         _check(lib.ibm_batch_profile_step(self._h, int(n), _ptr(out)))
         return dict(zip(PHASES, out.tolist()))
+
+    def lattice_kernel_ms(self, n: int) -> float:
+        """Mean execution time (ms) of the batched collide-stream kernel over
+        n plain steps of every run, from its own dispatch timestamps."""
+        out = np.zeros(1)
+        _check(lib.ibm_batch_profile_lattice_kernel(self._h, int(n), _ptr(out)))
+        return float(out[0])
 
     def close(self):
         if getattr(self, "_h", None):

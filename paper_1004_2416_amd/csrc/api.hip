@@ -1172,16 +1172,29 @@ int ibm_autotune(ibm_lattice *lat, int steps_per_trial, int *chosen) {
   return ok();
 }
 
-int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase) {
-  if (!lat || !ms_per_phase) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+// Plain (not captured) steps with marker events around each phase; with
+// kernel_ms, the lattice-update kernel of every step also records its own
+// dispatch's start and end, and *kernel_ms receives their mean difference.
+static int profile_steps(ibm_lattice *lat, int64_t n, double *ms_per_phase, double *kernel_ms) {
   if (lat->has_tan) return fail(IBM_ERR_BAD_STATE, "detach the tangent before profiling");
   if (n < 1 || n > 4096) return fail(IBM_ERR_INVALID_ARG, "profile 1..4096 steps");
   const int ne = lat->has_mem ? 5 : 2;
   std::vector<hipEvent_t> ev((size_t)n * ne);
+  std::vector<ibm::DispatchTimer> kt(kernel_ms ? (size_t)n : 0);
   for (auto &e : ev) IBM_HIP(hipEventCreate(&e));
+  for (auto &t : kt) {
+    IBM_HIP(hipEventCreate(&t.start));
+    IBM_HIP(hipEventCreate(&t.stop));
+  }
   hipStream_t s = lat->stream;
   for (int64_t k = 0; k < n; ++k) {
+    if (lat->has_mem && lat->since_recenter >= lat->recenter_every) {
+      ibm::launch_recenter(lat->M, s);
+      lat->since_recenter = 0;
+      if (lat->overlap) lat->slab_stale = true;
+    }
     hipEvent_t *e = &ev[(size_t)k * ne];
+    const ibm::DispatchTimer *t = kernel_ms ? &kt[(size_t)k] : nullptr;
     const int src = (int)(lat->steps & 1), par = src;
     IBM_HIP(hipEventRecord(e[0], s));
     if (lat->has_mem) {
@@ -1189,7 +1202,7 @@ int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase) {
       ibm::launch_spread(lat->L, lat->M, par, lat->box_mode & 1, s);
       IBM_HIP(hipEventRecord(e[2], s));
       ibm::launch_collide_stream(lat->L, lat->storage, src, par, true, lat->eq_linear != 0,
-                                 lat->lbm_variant, s);
+                                 lat->lbm_variant, s, 0, -1, t);
       IBM_HIP(hipEventRecord(e[3], s));
       ibm::launch_interp_advect(lat->L, lat->M, lat->storage, src ^ 1, par, advect_mode(lat),
                                 interp_mode(lat->box_mode), s);
@@ -1197,7 +1210,7 @@ int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase) {
       if (lat->ab2) lat->have_prev_u = true;
     } else {
       ibm::launch_collide_stream(lat->L, lat->storage, src, par, false, lat->eq_linear != 0,
-                                 lat->lbm_variant, s);
+                                 lat->lbm_variant, s, 0, -1, t);
       IBM_HIP(hipEventRecord(e[1], s));
     }
     lat->steps += 1;
@@ -1205,7 +1218,7 @@ int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase) {
   }
   IBM_HIP(hipGetLastError());
   IBM_HIP(hipStreamSynchronize(s));
-  double acc[IBM_N_PHASES] = {0.0, 0.0, 0.0, 0.0};
+  double acc[IBM_N_PHASES] = {0.0, 0.0, 0.0, 0.0}, kacc = 0.0;
   for (int64_t k = 0; k < n; ++k) {
     hipEvent_t *e = &ev[(size_t)k * ne];
     float ms = 0.0f;
@@ -1218,11 +1231,31 @@ int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase) {
       IBM_HIP(hipEventElapsedTime(&ms, e[0], e[1]));
       acc[IBM_PHASE_LBM] += ms;
     }
+    if (kernel_ms) {
+      IBM_HIP(hipEventElapsedTime(&ms, kt[(size_t)k].start, kt[(size_t)k].stop));
+      kacc += ms;
+    }
   }
   for (auto &e : ev) (void)hipEventDestroy(e);
-  for (int p = 0; p < IBM_N_PHASES; ++p) ms_per_phase[p] = acc[p] / (double)n;
+  for (auto &t : kt) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  if (ms_per_phase)
+    for (int p = 0; p < IBM_N_PHASES; ++p) ms_per_phase[p] = acc[p] / (double)n;
+  if (kernel_ms) *kernel_ms = kacc / (double)n;
   int rc = check_device(lat);
   return rc ? rc : ok();
+}
+
+int ibm_profile_step(ibm_lattice *lat, int64_t n, double *ms_per_phase) {
+  if (!lat || !ms_per_phase) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  return profile_steps(lat, n, ms_per_phase, nullptr);
+}
+
+int ibm_profile_lattice_kernel(ibm_lattice *lat, int64_t n, double *ms) {
+  if (!lat || !ms) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  return profile_steps(lat, n, nullptr, ms);
 }
 
 int ibm_destroy(ibm_lattice *lat) {
@@ -1655,14 +1688,19 @@ int ibm_batch_step(ibm_batch *b, int64_t n) {
   return ok();
 }
 
-int ibm_batch_profile_step(ibm_batch *b, int64_t n, double *ms_per_phase) {
-  if (!b || !ms_per_phase) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+// As profile_steps, over all runs of a batch.
+static int batch_profile_steps(ibm_batch *b, int64_t n, double *ms_per_phase, double *kernel_ms) {
   if (n < 1 || n > 4096) return fail(IBM_ERR_INVALID_ARG, "profile 1..4096 steps");
   int rc = batch_sync_tables(b);
   if (rc) return rc;
   ibm_lattice *r0 = b->runs[0];
   std::vector<hipEvent_t> ev((size_t)n * 4);
+  std::vector<ibm::DispatchTimer> kt(kernel_ms ? (size_t)n : 0);
   for (auto &e : ev) IBM_HIP(hipEventCreate(&e));
+  for (auto &t : kt) {
+    IBM_HIP(hipEventCreate(&t.start));
+    IBM_HIP(hipEventCreate(&t.stop));
+  }
   hipStream_t s = b->stream;
   for (int64_t k = 0; k < n; ++k) {
     for (ibm_lattice *lat : b->runs)
@@ -1676,7 +1714,8 @@ int ibm_batch_profile_step(ibm_batch *b, int64_t n, double *ms_per_phase) {
     IBM_HIP(hipEventRecord(e[0], s));
     ibm::launch_batch_spread(b->B, par, b->box_mode & 1, s);
     IBM_HIP(hipEventRecord(e[1], s));
-    ibm::launch_batch_collide_stream(b->B, r0->storage, src, par, r0->eq_linear != 0, s);
+    ibm::launch_batch_collide_stream(b->B, r0->storage, src, par, r0->eq_linear != 0, s,
+                                     kernel_ms ? &kt[(size_t)k] : nullptr);
     IBM_HIP(hipEventRecord(e[2], s));
     ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, interp_mode(b->box_mode), s);
     IBM_HIP(hipEventRecord(e[3], s));
@@ -1688,7 +1727,7 @@ int ibm_batch_profile_step(ibm_batch *b, int64_t n, double *ms_per_phase) {
   }
   IBM_HIP(hipGetLastError());
   IBM_HIP(hipStreamSynchronize(s));
-  double acc[IBM_N_PHASES] = {0.0, 0.0, 0.0, 0.0};
+  double acc[IBM_N_PHASES] = {0.0, 0.0, 0.0, 0.0}, kacc = 0.0;
   const int phase_of[3] = {IBM_PHASE_SPREAD, IBM_PHASE_LBM, IBM_PHASE_INTERP};
   for (int64_t k = 0; k < n; ++k) {
     hipEvent_t *e = &ev[(size_t)k * 4];
@@ -1697,10 +1736,31 @@ int ibm_batch_profile_step(ibm_batch *b, int64_t n, double *ms_per_phase) {
       IBM_HIP(hipEventElapsedTime(&ms, e[p], e[p + 1]));
       acc[phase_of[p]] += ms;
     }
+    if (kernel_ms) {
+      float ms = 0.0f;
+      IBM_HIP(hipEventElapsedTime(&ms, kt[(size_t)k].start, kt[(size_t)k].stop));
+      kacc += ms;
+    }
   }
   for (auto &e : ev) (void)hipEventDestroy(e);
-  for (int p = 0; p < IBM_N_PHASES; ++p) ms_per_phase[p] = acc[p] / (double)n;
+  for (auto &t : kt) {
+    (void)hipEventDestroy(t.start);
+    (void)hipEventDestroy(t.stop);
+  }
+  if (ms_per_phase)
+    for (int p = 0; p < IBM_N_PHASES; ++p) ms_per_phase[p] = acc[p] / (double)n;
+  if (kernel_ms) *kernel_ms = kacc / (double)n;
   return ok();
+}
+
+int ibm_batch_profile_step(ibm_batch *b, int64_t n, double *ms_per_phase) {
+  if (!b || !ms_per_phase) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  return batch_profile_steps(b, n, ms_per_phase, nullptr);
+}
+
+int ibm_batch_profile_lattice_kernel(ibm_batch *b, int64_t n, double *ms) {
+  if (!b || !ms) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  return batch_profile_steps(b, n, nullptr, ms);
 }
 
 int ibm_batch_destroy(ibm_batch *b) {

@@ -5,12 +5,21 @@
 
 namespace ibm {
 
+// Events that take the start and end timestamps of one kernel's own dispatch
+// (hipExtLaunchKernel), so that their elapsed time is the kernel's execution
+// alone, without the launch gaps that marker events around it include.
+struct DispatchTimer {
+  hipEvent_t start, stop;
+};
+
 // lbm_kernels.hip
 // variant: tuning bits of the collide-stream kernel (see lbm_kernels.hip)
 // z0, z1: update only the nodes with z0 <= z < z1 (streaming out of the range
 // is included); the default is the whole lattice
+// timer: when given, the (single) kernel of this update records its dispatch
 void launch_collide_stream(const LatDev &L, int fp16, int src, int par, bool force,
-                           bool linear, int variant, hipStream_t s, int z0 = 0, int z1 = -1);
+                           bool linear, int variant, hipStream_t s, int z0 = 0, int z1 = -1,
+                           const DispatchTimer *timer = nullptr);
 // The row form over the rows of rs; false (nothing launched) where the row
 // form does not apply (L.tpr == 0)
 bool launch_collide_stream_rows(const LatDev &L, int fp16, int src, int par, bool force,
@@ -34,7 +43,7 @@ long long adj_couette_blocks(const LatDev &L);
 void launch_adj_couette_start(const LatDev &L, const AdjDev &A, int cur, int linear,
                               double *partial, hipStream_t s);
 void launch_batch_collide_stream(const BatchDev &B, int fp16, int src, int par, bool linear,
-                                 hipStream_t s);
+                                 hipStream_t s, const DispatchTimer *timer = nullptr);
 
 // membrane_kernels.hip
 void launch_reference_geometry(const MemDev &M, Ctrl *ctrl, hipStream_t s);

@@ -13,6 +13,8 @@
 #include "launch.h"
 #include "lbm_device.h"
 
+#include <hip/hip_ext.h>
+
 namespace ibm {
 
 // One lattice update of VEC consecutive x nodes (x0 .. x0 + VEC - 1) of buffer
@@ -256,45 +258,53 @@ static bool rows_fit_32bit(const LatDev &L) {
   return rows * Q < (1LL << 32);
 }
 
+// Launch k on (g, b); with a timer, through hipExtLaunchKernel so that the
+// timer's events take this dispatch's own start and end timestamps.
+template <typename K, typename... A>
+static void launch_k(K k, dim3 g, dim3 b, hipStream_t s, const DispatchTimer *t, A... a) {
+  if (t) hipExtLaunchKernelGGL(k, g, b, 0, s, t->start, t->stop, 0, a...);
+  else hipLaunchKernelGGL(k, g, b, 0, s, a...);
+}
+
 static bool launch_cs_rows8(const LatDev &L, int src, int par, bool force, bool linear,
-                            hipStream_t s) {
+                            hipStream_t s, const DispatchTimer *t) {
   if (L.nx % 8 != 0 || !rows_fit_32bit(L)) return false;
   const int tpr = L.nx / 8;
   if (tpr > 64 || 64 % tpr != 0) return false;
   const long long threads = (long long)L.ny * L.nz * tpr;
   const dim3 b(256), g((unsigned)((threads + 255) / 256));
   if (force) {
-    if (linear) k_collide_stream_rows8<true, true><<<g, b, 0, s>>>(L, src, par, tpr);
-    else k_collide_stream_rows8<false, true><<<g, b, 0, s>>>(L, src, par, tpr);
+    if (linear) launch_k(k_collide_stream_rows8<true, true>, g, b, s, t, L, src, par, tpr);
+    else launch_k(k_collide_stream_rows8<false, true>, g, b, s, t, L, src, par, tpr);
   } else {
-    if (linear) k_collide_stream_rows8<true, false><<<g, b, 0, s>>>(L, src, par, tpr);
-    else k_collide_stream_rows8<false, false><<<g, b, 0, s>>>(L, src, par, tpr);
+    if (linear) launch_k(k_collide_stream_rows8<true, false>, g, b, s, t, L, src, par, tpr);
+    else launch_k(k_collide_stream_rows8<false, false>, g, b, s, t, L, src, par, tpr);
   }
   return true;
 }
 
 template <typename T, bool PAD>
 static void launch_cs_rows_p(const LatDev &L, int src, int par, bool force, bool linear, dim3 g,
-                             const RowSet &rs, hipStream_t s) {
+                             const RowSet &rs, hipStream_t s, const DispatchTimer *t) {
   const dim3 b(256);
   if (force) {
-    if (linear) k_collide_stream_rows<T, true, true, PAD><<<g, b, 0, s>>>(L, src, par, rs);
-    else k_collide_stream_rows<T, false, true, PAD><<<g, b, 0, s>>>(L, src, par, rs);
+    if (linear) launch_k(k_collide_stream_rows<T, true, true, PAD>, g, b, s, t, L, src, par, rs);
+    else launch_k(k_collide_stream_rows<T, false, true, PAD>, g, b, s, t, L, src, par, rs);
   } else {
-    if (linear) k_collide_stream_rows<T, true, false, PAD><<<g, b, 0, s>>>(L, src, par, rs);
-    else k_collide_stream_rows<T, false, false, PAD><<<g, b, 0, s>>>(L, src, par, rs);
+    if (linear) launch_k(k_collide_stream_rows<T, true, false, PAD>, g, b, s, t, L, src, par, rs);
+    else launch_k(k_collide_stream_rows<T, false, false, PAD>, g, b, s, t, L, src, par, rs);
   }
 }
 
 template <typename T>
 static bool launch_cs_rows(const LatDev &L, int src, int par, bool force, bool linear,
-                           const RowSet &rs, hipStream_t s) {
+                           const RowSet &rs, hipStream_t s, const DispatchTimer *t = nullptr) {
   if (L.tpr <= 0) return false;
   const long long waves = ((long long)rs.n0 + rs.n1 + L.rpw - 1) / L.rpw;
   if (waves <= 0) return true;
   const dim3 g((unsigned)((waves + 3) / 4));
-  if (L.nx % 4) launch_cs_rows_p<T, true>(L, src, par, force, linear, g, rs, s);
-  else launch_cs_rows_p<T, false>(L, src, par, force, linear, g, rs, s);
+  if (L.nx % 4) launch_cs_rows_p<T, true>(L, src, par, force, linear, g, rs, s, t);
+  else launch_cs_rows_p<T, false>(L, src, par, force, linear, g, rs, s, t);
   return true;
 }
 
@@ -315,21 +325,21 @@ static dim3 lattice_grid(const LatDev &L, dim3 b, int vec = 1) {
 
 template <typename T, int VEC, bool NT>
 static void launch_cs_v(const LatDev &L, int src, int par, bool force, bool linear,
-                        int threads, int z0, int z1, hipStream_t s) {
+                        int threads, int z0, int z1, hipStream_t s, const DispatchTimer *t) {
   dim3 b = lattice_block(L, VEC, threads), g = lattice_grid(L, b, VEC);
   g.z = (unsigned)(z1 - z0);
   if (force) {
-    if (linear) k_collide_stream<T, true, true, VEC, NT><<<g, b, 0, s>>>(L, src, par, z0);
-    else k_collide_stream<T, false, true, VEC, NT><<<g, b, 0, s>>>(L, src, par, z0);
+    if (linear) launch_k(k_collide_stream<T, true, true, VEC, NT>, g, b, s, t, L, src, par, z0);
+    else launch_k(k_collide_stream<T, false, true, VEC, NT>, g, b, s, t, L, src, par, z0);
   } else {
-    if (linear) k_collide_stream<T, true, false, VEC, NT><<<g, b, 0, s>>>(L, src, par, z0);
-    else k_collide_stream<T, false, false, VEC, NT><<<g, b, 0, s>>>(L, src, par, z0);
+    if (linear) launch_k(k_collide_stream<T, true, false, VEC, NT>, g, b, s, t, L, src, par, z0);
+    else launch_k(k_collide_stream<T, false, false, VEC, NT>, g, b, s, t, L, src, par, z0);
   }
 }
 
 template <typename T>
 static void launch_cs_t(const LatDev &L, int src, int par, bool force, bool linear,
-                        int variant, int z0, int z1, hipStream_t s) {
+                        int variant, int z0, int z1, hipStream_t s, const DispatchTimer *t) {
   // variant bits: 1 = two nodes per thread, 2 = non-temporal accesses,
   // 4 = 128-thread blocks, 8 = 64-thread blocks, 16 = row-vector kernel
   // (four nodes per thread, whole rows per wavefront) where a padded row has
@@ -338,18 +348,18 @@ static void launch_cs_t(const LatDev &L, int src, int par, bool force, bool line
   // dividing 64)
   const bool whole = z0 == 0 && z1 == L.nz;
   if constexpr (sizeof(T) == 2)
-    if (whole && (variant & 48) == 48 && launch_cs_rows8(L, src, par, force, linear, s)) return;
+    if (whole && (variant & 48) == 48 && launch_cs_rows8(L, src, par, force, linear, s, t)) return;
   const RowSet rs{z0 * L.ny, (z1 - z0) * L.ny, 0, 0, 1, 0};
-  if ((variant & 16) && launch_cs_rows<T>(L, src, par, force, linear, rs, s)) return;
+  if ((variant & 16) && launch_cs_rows<T>(L, src, par, force, linear, rs, s, t)) return;
   const bool vec2 = (variant & 1) && (L.nx % 2 == 0);
   const bool nt = (variant & 2) != 0;
   const int threads = (variant & 8) ? 64 : ((variant & 4) ? 128 : 256);
   if (vec2) {
-    if (nt) launch_cs_v<T, 2, true>(L, src, par, force, linear, threads, z0, z1, s);
-    else launch_cs_v<T, 2, false>(L, src, par, force, linear, threads, z0, z1, s);
+    if (nt) launch_cs_v<T, 2, true>(L, src, par, force, linear, threads, z0, z1, s, t);
+    else launch_cs_v<T, 2, false>(L, src, par, force, linear, threads, z0, z1, s, t);
   } else {
-    if (nt) launch_cs_v<T, 1, true>(L, src, par, force, linear, threads, z0, z1, s);
-    else launch_cs_v<T, 1, false>(L, src, par, force, linear, threads, z0, z1, s);
+    if (nt) launch_cs_v<T, 1, true>(L, src, par, force, linear, threads, z0, z1, s, t);
+    else launch_cs_v<T, 1, false>(L, src, par, force, linear, threads, z0, z1, s, t);
   }
 }
 
@@ -360,13 +370,14 @@ bool launch_collide_stream_rows(const LatDev &L, int fp16, int src, int par, boo
 }
 
 void launch_collide_stream(const LatDev &L, int fp16, int src, int par, bool force,
-                           bool linear, int variant, hipStream_t s, int z0, int z1) {
+                           bool linear, int variant, hipStream_t s, int z0, int z1,
+                           const DispatchTimer *timer) {
   if (z1 < 0) z1 = L.nz;
   if (z0 < 0) z0 = 0;
   if (z1 > L.nz) z1 = L.nz;
   if (z0 >= z1) return;
-  if (fp16) launch_cs_t<__half>(L, src, par, force, linear, variant, z0, z1, s);
-  else launch_cs_t<float>(L, src, par, force, linear, variant, z0, z1, s);
+  if (fp16) launch_cs_t<__half>(L, src, par, force, linear, variant, z0, z1, s, timer);
+  else launch_cs_t<float>(L, src, par, force, linear, variant, z0, z1, s, timer);
 }
 
 // ---- initialisation: f = feq(rho = 1, u = (uw (2 z + 1 - nz) / nz, 0, 0)) ----
@@ -868,15 +879,15 @@ __global__ __launch_bounds__(256) void k_batch_collide_stream(BatchDev B, int sr
 }
 
 void launch_batch_collide_stream(const BatchDev &B, int fp16, int src, int par, bool linear,
-                                 hipStream_t s) {
+                                 hipStream_t s, const DispatchTimer *t) {
   if (B.n_lat_items <= 0) return;
   const dim3 grid(B.n_lat_items), block(256);
   if (fp16) {
-    if (linear) k_batch_collide_stream<__half, true><<<grid, block, 0, s>>>(B, src, par);
-    else k_batch_collide_stream<__half, false><<<grid, block, 0, s>>>(B, src, par);
+    if (linear) launch_k(k_batch_collide_stream<__half, true>, grid, block, s, t, B, src, par);
+    else launch_k(k_batch_collide_stream<__half, false>, grid, block, s, t, B, src, par);
   } else {
-    if (linear) k_batch_collide_stream<float, true><<<grid, block, 0, s>>>(B, src, par);
-    else k_batch_collide_stream<float, false><<<grid, block, 0, s>>>(B, src, par);
+    if (linear) launch_k(k_batch_collide_stream<float, true>, grid, block, s, t, B, src, par);
+    else launch_k(k_batch_collide_stream<float, false>, grid, block, s, t, B, src, par);
   }
 }
 

@@ -136,6 +136,29 @@ def test_batch_interpolation_modes(B, box):
         r.lat.close()
 
 
+def test_batch_profiling_steps_are_ordinary_steps(B):
+    """ibm_batch_profile_step and ibm_batch_profile_lattice_kernel advance
+    every run by ordinary steps (plain launches; the second times the batched
+    collide-stream from its own dispatch timestamps): interleaved with
+    ordinary steps, every run still follows its oracle, and the kernel's own
+    duration is positive and within the lattice phase measured around it."""
+    runs = [Run(B, spec) for spec in CASES]
+    batch = B.Batch([r.lat for r in runs])
+    batch.step(1)
+    phases = batch.profile(3)
+    kms = batch.lattice_kernel_ms(3)
+    batch.step(3)
+    for r in runs:
+        r.advance_oracle(10)
+    assert all(r.lat.steps == 10 for r in runs)
+    say("batch: lattice phase %.4f ms, kernel %.4f ms" % (phases["lbm"], kms))
+    check(runs, 1e-4, 1e-3)
+    assert 0.0 < kms < phases["lbm"] + 0.02
+    batch.close()
+    for r in runs:
+        r.lat.close()
+
+
 def test_batch_adams_bashforth_linear_equilibrium(B):
     runs = [Run(B, spec, ab2=True, linear=True) for spec in CASES[:2]]
     batch = B.Batch([r.lat for r in runs])

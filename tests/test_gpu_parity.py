@@ -284,6 +284,31 @@ def test_trajectory_drifting_capsule_wraps_and_recentres(B, nx, box):
     assert np.max(np.abs(xg - sim.x)) < 1e-3
 
 
+def test_profiling_steps_are_ordinary_steps(B):
+    """ibm_profile_step and ibm_profile_lattice_kernel advance the run by
+    ordinary steps (plain launches; the second launches the collide-stream
+    through hipExtLaunchKernel so that events take its dispatch's own
+    timestamps): after 1 + 2 + 2 + 1 steps the run matches the oracle's six
+    steps to the per-step bar, and the kernel's own duration is positive and
+    within the lattice phase measured around it."""
+    c = small_case(m=3, perturb=0.01)
+    lat = c.gpu(graph=True)
+    lat.step(1)
+    phases = lat.profile(2)
+    kms = lat.lattice_kernel_ms(2)
+    lat.step(1)
+    sim = c.oracle()
+    assert sim.run(6) == 0
+    f_g = lat.populations().cpu().numpy()
+    xg = lat.mesh()[0].cpu().numpy()
+    assert lat.steps == 6
+    lat.close()
+    say("  profiled steps: f %.2e  x %.2e  lattice phase %.4f ms  kernel %.4f ms"
+        % (rel_err(f_g, sim.f), np.max(np.abs(xg - sim.x)), phases["lbm"], kms))
+    assert rel_err(f_g, sim.f) < 1e-5
+    assert np.max(np.abs(xg - sim.x)) < 1e-5
+    assert 0.0 < kms < phases["lbm"] + 0.02
+
 @pytest.mark.parametrize("box", [-1, 5])
 def test_split_update_overlap(B, box):
     """IBM_OPT_OVERLAP on a tall lattice: the lattice update of graph steps is
