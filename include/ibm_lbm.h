@@ -109,13 +109,15 @@ extern "C" {
 #define IBM_OPT_RECENTER 3     /* steps between re-centring of the capsule
                                   frames (default 64, >= 1)                 */
 #define IBM_OPT_LBM_VARIANT 4  /* launch variant of the collide-stream kernel,
-                                  0..63 (bit 0: two nodes per thread, bit 1:
+                                  0..255 (bit 0: two nodes per thread, bit 1:
                                   non-temporal accesses, bit 2: 128-thread,
                                   bit 3: 64-thread blocks, bit 4: four nodes
                                   per thread with whole x rows per wavefront,
                                   used when nx <= 256; bit 5 with
                                   bit 4 and FP16 storage: eight nodes per
                                   thread, used when nx / 8 divides 64;
+                                  bit 6, bit 7: the four-node row form in
+                                  128- or 64-thread blocks instead of 256;
                                   default 23);
                                   results are identical, only the speed
                                   differs                                    */

@@ -377,3 +377,52 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# -- D(T) as a differentiable torch function --------------------------------
+_DEFORMATION_FN = None
+
+
+def _deformation_fn():
+    global _DEFORMATION_FN
+    if _DEFORMATION_FN is None:
+        torch = _torch()
+
+        class _Deformation(torch.autograd.Function):
+            @staticmethod
+            def forward(ctx, ks, ka, uw, make_lattice, steps, checkpoint_every, capsule):
+                lat = make_lattice(ks.detach().cpu().tolist(), ka.detach().cpu().tolist(),
+                                   float(uw))
+                try:
+                    g = lat.adjoint_gradient(steps, checkpoint_every, capsule, couette_start=True)
+                finally:
+                    lat.close()
+                f64 = dict(dtype=torch.float64)
+                ctx.save_for_backward(torch.as_tensor(g["dks"], **f64),
+                                      torch.as_tensor(g["dka"], **f64),
+                                      torch.tensor(g["duw"], **f64))
+                return torch.tensor(g["D"], **f64)
+
+            @staticmethod
+            def backward(ctx, gD):
+                dks, dka, duw = ctx.saved_tensors
+                gD = gD.detach().to(torch.float64).cpu()
+                return gD * dks, gD * dka, gD * duw, None, None, None, None
+
+        _DEFORMATION_FN = _Deformation
+    return _DEFORMATION_FN
+
+
+def deformation(make_lattice, ks, ka, uw, steps: int, checkpoint_every: int = 100,
+                capsule: int = 0):
+    """D(T) of `capsule` after `steps` steps (Sec. III) as a torch function of
+    the per-capsule moduli ks, ka (1-D float64 CPU tensors) and the wall
+    speed uw (0-D tensor), differentiable by the discrete adjoint.
+
+    make_lattice(ks, ka, uw) must return a new Lattice at t = 0 with its
+    capsules added with these moduli and ibm_set_shear(uw, init_profile=1)
+    applied, so that the start also depends on uw.  The forward call runs
+    ibm_adjoint_gradient once (forward sweep and reverse sweep) and keeps the
+    gradient; backward only scales it."""
+    return _deformation_fn().apply(ks, ka, uw, make_lattice, int(steps), int(checkpoint_every),
+                                   int(capsule))

@@ -1046,7 +1046,7 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
       lat->recenter_every = value;
       break;
     case IBM_OPT_LBM_VARIANT:
-      if (value < 0 || value > 63) return fail(IBM_ERR_INVALID_ARG, "variant is 0..63");
+      if (value < 0 || value > 255) return fail(IBM_ERR_INVALID_ARG, "variant is 0..255");
       lat->lbm_variant = value;
       break;
     case IBM_OPT_OVERLAP:

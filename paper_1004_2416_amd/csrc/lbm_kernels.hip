@@ -285,8 +285,7 @@ static bool launch_cs_rows8(const LatDev &L, int src, int par, bool force, bool 
 
 template <typename T, bool PAD>
 static void launch_cs_rows_p(const LatDev &L, int src, int par, bool force, bool linear, dim3 g,
-                             const RowSet &rs, hipStream_t s, const DispatchTimer *t) {
-  const dim3 b(256);
+                             dim3 b, const RowSet &rs, hipStream_t s, const DispatchTimer *t) {
   if (force) {
     if (linear) launch_k(k_collide_stream_rows<T, true, true, PAD>, g, b, s, t, L, src, par, rs);
     else launch_k(k_collide_stream_rows<T, false, true, PAD>, g, b, s, t, L, src, par, rs);
@@ -296,15 +295,17 @@ static void launch_cs_rows_p(const LatDev &L, int src, int par, bool force, bool
   }
 }
 
+// wpb: wavefronts per block (1, 2 or 4)
 template <typename T>
 static bool launch_cs_rows(const LatDev &L, int src, int par, bool force, bool linear,
-                           const RowSet &rs, hipStream_t s, const DispatchTimer *t = nullptr) {
+                           const RowSet &rs, hipStream_t s, const DispatchTimer *t = nullptr,
+                           int wpb = 4) {
   if (L.tpr <= 0) return false;
   const long long waves = ((long long)rs.n0 + rs.n1 + L.rpw - 1) / L.rpw;
   if (waves <= 0) return true;
-  const dim3 g((unsigned)((waves + 3) / 4));
-  if (L.nx % 4) launch_cs_rows_p<T, true>(L, src, par, force, linear, g, rs, s, t);
-  else launch_cs_rows_p<T, false>(L, src, par, force, linear, g, rs, s, t);
+  const dim3 g((unsigned)((waves + wpb - 1) / wpb)), b((unsigned)(64 * wpb));
+  if (L.nx % 4) launch_cs_rows_p<T, true>(L, src, par, force, linear, g, b, rs, s, t);
+  else launch_cs_rows_p<T, false>(L, src, par, force, linear, g, b, rs, s, t);
   return true;
 }
 
@@ -341,16 +342,18 @@ template <typename T>
 static void launch_cs_t(const LatDev &L, int src, int par, bool force, bool linear,
                         int variant, int z0, int z1, hipStream_t s, const DispatchTimer *t) {
   // variant bits: 1 = two nodes per thread, 2 = non-temporal accesses,
-  // 4 = 128-thread blocks, 8 = 64-thread blocks, 16 = row-vector kernel
+  // 4 = 128-thread blocks, 8 = 64-thread blocks (per-node kernel), 16 = row-vector kernel
   // (four nodes per thread, whole rows per wavefront) where a padded row has
   // at most 256 values,
   // 32 = with FP16 storage, eight nodes per thread in that form (nx / 8
-  // dividing 64)
+  // dividing 64), 64 = row form in 128-thread blocks, 128 = in 64-thread
+  // blocks
   const bool whole = z0 == 0 && z1 == L.nz;
   if constexpr (sizeof(T) == 2)
     if (whole && (variant & 48) == 48 && launch_cs_rows8(L, src, par, force, linear, s, t)) return;
   const RowSet rs{z0 * L.ny, (z1 - z0) * L.ny, 0, 0, 1, 0};
-  if ((variant & 16) && launch_cs_rows<T>(L, src, par, force, linear, rs, s, t)) return;
+  const int wpb = (variant & 128) ? 1 : ((variant & 64) ? 2 : 4);
+  if ((variant & 16) && launch_cs_rows<T>(L, src, par, force, linear, rs, s, t, wpb)) return;
   const bool vec2 = (variant & 1) && (L.nx % 2 == 0);
   const bool nt = (variant & 2) != 0;
   const int threads = (variant & 8) ? 64 : ((variant & 4) ? 128 : 256);

@@ -84,3 +84,47 @@ def test_library_icosphere_matches_oracle_mesh(B, orc, level):
     canon = lambda f: tuple(np.roll(f, -int(np.argmin(f))))
     assert {canon(f) for f in relabel[t]} == {canon(f) for f in to}
     assert B.lib.ibm_icosphere(8, 1.0, 0, 0, 0, B._ptr(x), B._ptr(t)) == -1
+
+
+def test_deformation_function_marshals_the_adjoint_gradient(B):
+    """binding.deformation on the host side: the lattice factory receives the
+    parameter values, the gradient the adjoint call returns reaches the
+    parameters by the chain rule, and the lattice is closed.  A stand-in
+    lattice returns D = a ks^2 + b ka + c uw^3 with its exact gradient (no GPU
+    call)."""
+    import torch
+
+    made = []
+
+    class Stand:
+        def __init__(self, ks, ka, uw):
+            self.p = (np.asarray(ks), np.asarray(ka), uw)
+            self.closed = False
+
+        def adjoint_gradient(self, steps, checkpoint_every, capsule, couette_start):
+            assert (steps, checkpoint_every, capsule, couette_start) == (40, 8, 1, True)
+            ks, ka, uw = self.p
+            D = float(2.0 * np.sum(ks ** 2) + 3.0 * np.sum(ka) + 5.0 * uw ** 3)
+            return {"D": D, "dks": 4.0 * ks, "dka": np.full_like(ka, 3.0), "duw": 15.0 * uw ** 2}
+
+        def close(self):
+            self.closed = True
+
+    def make(ks, ka, uw):
+        made.append(Stand(ks, ka, uw))
+        return made[-1]
+
+    f64 = dict(dtype=torch.float64)
+    s = torch.tensor(1.5, requires_grad=True, **f64)
+    uw = torch.tensor(0.02, requires_grad=True, **f64)
+    ks0 = torch.tensor([0.01, 0.03], **f64)
+    ks = ks0 * s
+    ka = 0.5 * ks
+    D = B.deformation(make, ks, ka, uw, 40, checkpoint_every=8, capsule=1)
+    (7.0 * D).backward()
+    assert len(made) == 1 and made[0].closed
+    assert np.allclose(made[0].p[0], [0.015, 0.045]) and made[0].p[2] == pytest.approx(0.02)
+    # dD/ds = sum(4 ks * ks0) + sum(3 * 0.5 ks0); dD/duw = 15 uw^2
+    want_s = 7.0 * float(torch.sum(4.0 * ks0 * 1.5 * ks0) + torch.sum(1.5 * ks0))
+    assert float(s.grad) == pytest.approx(want_s, rel=1e-12)
+    assert float(uw.grad) == pytest.approx(7.0 * 15.0 * 0.02 ** 2, rel=1e-12)

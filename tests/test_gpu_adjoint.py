@@ -107,3 +107,47 @@ def test_adjoint_rejected_combinations(B):
     with pytest.raises(B.IBMError):
         lat.adjoint_gradient(4, capsule=3)
     lat.close()
+
+
+def test_autograd_function_wraps_the_adjoint(B):
+    """binding.deformation makes D(T) a torch function of (k_s, k_alpha, u_w)
+    whose backward is the adjoint.  A loss built from D through torch
+    operations on the parameters of Sec. III (a common scale s of both
+    moduli, the ratio C, the wall speed) gets the chain-rule gradient of the
+    direct adjoint call, and dD/ds agrees with the oracle's central
+    difference along k_s at fixed C to 1e-3."""
+    import torch
+    steps, target = 150, 0.05
+    c = tangent_case()
+
+    def make(ks, ka, uw):
+        lat = B.Lattice(c.wl.nx, c.wl.ny, c.wl.nz, c.wl.tau)
+        lat.set_shear(uw, init_profile=True)
+        lat.add_capsules(c.meshes(), ks, ka, c.wl.m)
+        return lat
+
+    f64 = dict(dtype=torch.float64)
+    s = torch.tensor(1.0, requires_grad=True, **f64)
+    C = torch.tensor(c.ka[0] / c.ks[0], requires_grad=True, **f64)
+    uw = torch.tensor(c.wl.u_w, requires_grad=True, **f64)
+    ks = torch.as_tensor(np.asarray(c.ks, np.float64)) * s
+    ka = ks * C
+    D = B.deformation(make, ks, ka, uw, steps, checkpoint_every=50)
+    loss = (D - target) ** 2
+    loss.backward()
+
+    lat = make(c.ks, c.ka, c.wl.u_w)
+    g = lat.adjoint_gradient(steps, checkpoint_every=50, couette_start=True)
+    lat.close()
+    ks0, ka0 = float(c.ks[0]), float(c.ka[0])
+    dD = {"s": g["dks"][0] * ks0 + g["dka"][0] * ka0, "C": g["dka"][0] * ks0, "uw": g["duw"]}
+    w = 2.0 * (g["D"] - target)
+    got = {"s": float(s.grad), "C": float(C.grad), "uw": float(uw.grad)}
+    say("  autograd: D %.8f (direct %.8f); grads" % (float(D.detach()), g["D"]),
+        {k: "%.6e / %.6e" % (got[k], w * dD[k]) for k in got})
+    assert abs(float(D.detach()) - g["D"]) < 1e-6 * abs(g["D"])
+    for k in got:
+        assert abs(got[k] - w * dD[k]) < 1e-4 * abs(w * dD[k]), k
+    fd = (oracle_D(c, "ks", 1 + H_FD, steps)[0] - oracle_D(c, "ks", 1 - H_FD, steps)[0]) / (2 * H_FD)
+    say("  dD/ds: adjoint %.8e  oracle FD %.8e" % (dD["s"], fd))
+    assert abs(dD["s"] - fd) < 1e-3 * abs(fd)

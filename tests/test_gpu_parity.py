@@ -124,6 +124,21 @@ def test_coupled_step_parity(B, m):
     compare_one_step(B, c, f_s, x_s)
 
 
+def test_c1_step_parity_at_sampled_steps(B):
+    """The 32^3 single-capsule workload (642 nodes, 3-point delta): one step
+    from the oracle's state after 1, 10, 100 and 999 steps (rounded to the
+    FP32 storage), every population, force and node compared to the per-step
+    bar.  (Step 0, the undeformed capsule, is its own test below.)"""
+    c = Case(W.config("c1"))
+    sim = c.oracle()
+    done = 0
+    for s in (1, 10, 100, 999):
+        assert sim.run(s - done) == 0
+        done = s
+        say("c1 one step from step", s)
+        compare_one_step(B, c, rep_populations(sim.f), rep_positions(sim.x, c.node_counts))
+
+
 def test_coupled_step_parity_periodic_wrap(B):
     """A capsule straddling the periodic x and y ends, ragged lattice."""
     say("periodic wrap")
@@ -443,6 +458,39 @@ def test_full_size_step_parity(B, name):
     assert np.max(np.abs(xg - sim.x)) < 4e-6
 
 
+@pytest.mark.parametrize("name,steps,every", [("c2", 320, 40), ("c3", 96, 32)])
+def test_trajectory_full_size(B, name, steps, every):
+    """The full-size workloads as the benchmark runs them (16-step graphs,
+    IBM_OPT_OVERLAP = 1: on 128^3 the lattice update is split at the force
+    slab, re-centring every 64 steps) against the oracle from the same start:
+    the Taylor deformation of every capsule within 1e-3 of its largest value
+    over the run.  Node positions are FP32 offsets of up to 16 lattice
+    spacings from each capsule's origin, so every step's x += u rounds by up
+    to ~1e-6; they must stay within steps x 1e-6 of the oracle's."""
+    wl = W.config(name)
+    c = Case(wl)
+    lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau)
+    lat.set_shear(wl.u_w, init_profile=True)
+    lat.add_capsules(c.meshes(), c.ks, c.ka, wl.m)
+    lat.set_option(B.OPT_OVERLAP, 1)
+    sim = c.oracle()
+    Dg, Do = [], []
+    for k in range(steps // every):
+        lat.step(every)
+        assert sim.run(every) == 0
+        Dg.append(lat.observables()[:, 4].copy())
+        Do.append([o["D"] for o in c.observables(sim.x)])
+    say("  %s split box %s" % (name, lat.split_box()))
+    xg = lat.mesh()[0].cpu().numpy()
+    lat.close()
+    Dg, Do = np.array(Dg), np.array(Do)
+    eD = np.max(np.abs(Dg - Do), axis=0) / np.max(np.abs(Do), axis=0)
+    ex = float(np.max(np.abs(xg - sim.x)))
+    say("  %s %d steps: worst capsule D error %.2e of its max D, x %.2e" % (name, steps, eD.max(), ex))
+    assert eD.max() < 1e-3
+    assert ex < steps * 1e-6
+
+
 # ---------------------------------------------------------------------------
 # observables
 # ---------------------------------------------------------------------------
@@ -509,12 +557,12 @@ def test_bad_arguments(B):
 
 def test_collide_stream_variants_agree(B):
     """Every launch variant of the collide-stream kernel computes the same
-    update (odd nx falls back to one node per thread, nx not a multiple of 4
-    to the per-node kernels)."""
+    update: the 32 per-node and row forms, and the row form in 128- and
+    64-thread blocks (bits 6, 7), on padded and unpadded rows."""
     for shape in ((32, 20, 16), (30, 20, 16), (27, 19, 18)):
         c = small_case(n=shape, m=3, ca=0.02)
         ref = None
-        for v in range(32):
+        for v in list(range(32)) + [80, 144, 87, 151]:
             lat = c.gpu(graph=False)
             lat.set_option(B.OPT_LBM_VARIANT, v)
             lat.step(6)
