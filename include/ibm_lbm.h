@@ -139,7 +139,8 @@ extern "C" {
                                   ibm_autotune)                             */
 #define IBM_OPT_CHUNK_NODES 5  /* spreading and interpolation work on chunks
                                   of this many consecutive membrane nodes of
-                                  one capsule (16, 32, 64, 128 or 256),
+                                  one capsule (a power of two, 16 to 1024;
+                                  a smaller capsule is one chunk),
                                   summing overlapping stencils
                                   in on-chip memory; 0: one lane group
                                   per node without chunks (the default,

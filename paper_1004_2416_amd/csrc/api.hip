@@ -1061,7 +1061,7 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
       break;
     case IBM_OPT_CHUNK_NODES: {
       if (value != 0 && (value < ibm::CHUNK_MIN || value > ibm::CHUNK_MAX || (value & (value - 1))))
-        return fail(IBM_ERR_INVALID_ARG, "chunk size is 0 or a power of two in 16..256");
+        return fail(IBM_ERR_INVALID_ARG, "chunk size is 0 or a power of two in 16..1024");
       lat->chunk_nodes = value;
       if (lat->has_mem) {
         const int rc = upload_chunks(lat);

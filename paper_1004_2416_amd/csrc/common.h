@@ -154,10 +154,13 @@ struct BatchDev {
 };
 
 // Chunks: runs of at most CHUNK_MAX consecutive (spatially sorted) nodes of one
-// capsule.  Their stencils cover a compact box of lattice nodes that the
-// chunked kernels keep in LDS when it has at most BOX_CELLS nodes.
-constexpr int CHUNK_MIN = 16, CHUNK_MAX = 256;
+// capsule (a whole capsule of up to CHUNK_MAX nodes is one chunk).  Their
+// stencils cover a compact box of lattice nodes that the chunked kernels keep
+// in LDS when it has at most SPREAD_BOX_CELLS (spreading, three force
+// components in a 1024-thread block) or BOX_CELLS (interpolation) nodes.
+constexpr int CHUNK_MIN = 16, CHUNK_MAX = 1024;
 constexpr int BOX_CELLS = 4096;
+constexpr int SPREAD_BOX_CELLS = 9000;
 
 // ---- discrete delta functions, Sec. II.C Eqs. (2point), (3point), (4point) ----
 // Evaluated for |r| inside the stencil; square-root arguments are clamped at 0

@@ -404,24 +404,40 @@ struct Bounds {
 };
 
 // Box of the M-point stencils of the chunk's nb nodes (positions already in
-// sp); all threads of the block must call it.
+// sp); all threads of the block must call it.  Each wavefront reduces its
+// nodes' stencil corners with shuffles, then one lane per wavefront merges
+// them into bb.
 template <int M>
-__device__ __forceinline__ Bounds chunk_bounds(const float4 *sp, int nb, int *bb) {
+__device__ __forceinline__ Bounds chunk_bounds(const float4 *sp, int nb, int *bb, int cells) {
   const int t = threadIdx.x;
   if (t < 3) {
     bb[t] = 0x7fffffff;
     bb[t + 3] = -0x7fffffff;
   }
   __syncthreads();
+  int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
   for (int k = t; k < nb; k += blockDim.x) {
     const float4 p = sp[k];
-    const int lx = stencil_lo<M>(p.x), ly = stencil_lo<M>(p.y), lz = stencil_lo<M>(p.z);
-    atomicMin(&bb[0], lx);
-    atomicMin(&bb[1], ly);
-    atomicMin(&bb[2], lz);
-    atomicMax(&bb[3], lx);
-    atomicMax(&bb[4], ly);
-    atomicMax(&bb[5], lz);
+    const int l[3] = {stencil_lo<M>(p.x), stencil_lo<M>(p.y), stencil_lo<M>(p.z)};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], l[d]);
+      hi[d] = max(hi[d], l[d]);
+    }
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = min(lo[d], __shfl_xor(lo[d], off, 64));
+      hi[d] = max(hi[d], __shfl_xor(hi[d], off, 64));
+    }
+  if ((t & 63) == 0) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      atomicMin(&bb[d], lo[d]);
+      atomicMax(&bb[d + 3], hi[d]);
+    }
   }
   __syncthreads();
   Bounds b;
@@ -431,7 +447,7 @@ __device__ __forceinline__ Bounds chunk_bounds(const float4 *sp, int nb, int *bb
   b.ex = bb[3] - bb[0] + M;
   b.ey = bb[4] - bb[1] + M;
   b.ez = bb[5] - bb[2] + M;
-  b.fits = (long long)b.ex * b.ey * b.ez <= BOX_CELLS;
+  b.fits = (long long)b.ex * b.ey * b.ez <= cells;
   return b;
 }
 
@@ -440,9 +456,9 @@ __device__ __forceinline__ Bounds chunk_bounds(const float4 *sp, int nb, int *bb
 // identical results) and its corner gradients are summed into the chunk's
 // nodes in LDS, so the step needs no separate face kernel.
 template <int M>
-__global__ __launch_bounds__(256) void k_spread_chunks(LatDev L, MemDev Mm, int par) {
+__global__ __launch_bounds__(1024) void k_spread_chunks(LatDev L, MemDev Mm, int par) {
   constexpr int M3 = M * M * M;
-  __shared__ float box[3][BOX_CELLS];
+  __shared__ float box[3][SPREAD_BOX_CELLS];
   __shared__ float4 sp[CHUNK_MAX];
   __shared__ float sfx[CHUNK_MAX], sfy[CHUNK_MAX], sfz[CHUNK_MAX];
   __shared__ int bb[6];
@@ -481,7 +497,7 @@ __global__ __launch_bounds__(256) void k_spread_chunks(LatDev L, MemDev Mm, int 
   }
   __syncthreads();
   for (int k = t; k < nb; k += blockDim.x) Mm.F[a + k] = make_float4(sfx[k], sfy[k], sfz[k], 0.0f);
-  const Bounds b = chunk_bounds<M>(sp, nb, bb);
+  const Bounds b = chunk_bounds<M>(sp, nb, bb, SPREAD_BOX_CELLS);
   const int V = b.fits ? b.ex * b.ey * b.ez : 0;
   for (int c = t; c < V; c += blockDim.x) box[0][c] = box[1][c] = box[2][c] = 0.0f;
   __syncthreads();
@@ -536,7 +552,7 @@ __global__ __launch_bounds__(256) void k_spread_chunks(LatDev L, MemDev Mm, int 
 void launch_spread(const LatDev &L, const MemDev &M, int par, bool box, hipStream_t s) {
   if (M.nn <= 0) return;
   if (M.n_chunks > 0) {
-    const dim3 grid(xcd_grid(M.n_chunks)), block(256);
+    const dim3 grid(xcd_grid(M.n_chunks)), block(1024);
     if (M.m == 2) k_spread_chunks<2><<<grid, block, 0, s>>>(L, M, par);
     else if (M.m == 3) k_spread_chunks<3><<<grid, block, 0, s>>>(L, M, par);
     else k_spread_chunks<4><<<grid, block, 0, s>>>(L, M, par);
@@ -777,7 +793,7 @@ __global__ __launch_bounds__(256) void k_interp_chunks(LatDev L, MemDev Mm, int 
   const int a = range.x, nb = range.y - range.x;
   const int t = threadIdx.x;
   for (int k = t; k < nb; k += blockDim.x) sp[k] = Mm.x[a + k];
-  const Bounds b = chunk_bounds<M>(sp, nb, bb);
+  const Bounds b = chunk_bounds<M>(sp, nb, bb, BOX_CELLS);
   const int V = b.fits ? b.ex * b.ey * b.ez : 0;
   const int4 o = Mm.origin[Mm.node_cap[a]];
   const T *f = static_cast<const T *>(L.f[fsrc]);

@@ -187,10 +187,11 @@ def test_coupled_step_parity_crowded_overlapping_capsules(B):
     compare_one_step(B, c, f_s, x_s)
 
 
-@pytest.mark.parametrize("chunk", [0, 16, 32, 128, 256])
+@pytest.mark.parametrize("chunk", [0, 16, 32, 128, 256, 1024])
 def test_coupling_chunk_sizes(B, chunk):
     """Spreading and interpolation per lane group (0) and per chunk of
-    16..256 nodes (stencils summed in on-chip memory) all match the oracle."""
+    16..1024 nodes (stencils summed in on-chip memory; 1024: the whole
+    642-node capsule is one chunk) all match the oracle."""
     say("chunk size", chunk)
     c = small_case(n=(40, 36, 30), m=4, level=3, r=8.0, ca=0.02, uw=0.03)
     f_s, x_s = deformed_state(c, 10)
