@@ -257,6 +257,7 @@ struct Pop4<float> {
 };
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 
 template <>
 struct Pop4<__half> {
@@ -273,11 +274,17 @@ struct Pop4<__half> {
     v[2] = h(r.y & 0xffffu, inv);
     v[3] = h(r.y >> 16, inv);
   }
+  // two values per conversion: packed float -> half, rounded to nearest even
+  // (one v_cvt_pk_f16_f32 instead of two conversions and a pack)
+  static __device__ __forceinline__ unsigned int pk(float a, float b) {
+    const f32x2 v = {a, b};
+    return __builtin_bit_cast(unsigned int, __builtin_convertvector(v, f16x2));
+  }
   static __device__ __forceinline__ void st(__half *p, long long i, float a, float b, float c,
                                             float d, float scale) {
     u32x2 r;
-    r.x = q(a, scale) | (q(b, scale) << 16);
-    r.y = q(c, scale) | (q(d, scale) << 16);
+    r.x = pk(a * scale, b * scale);
+    r.y = pk(c * scale, d * scale);
     __builtin_nontemporal_store(r, reinterpret_cast<u32x2 *>(p + i));
   }
 };
