@@ -109,7 +109,7 @@ extern "C" {
 #define IBM_OPT_RECENTER 3     /* steps between re-centring of the capsule
                                   frames (default 64, >= 1)                 */
 #define IBM_OPT_LBM_VARIANT 4  /* launch variant of the collide-stream kernel,
-                                  0..255 (bit 0: two nodes per thread, bit 1:
+                                  0..511 (bit 0: two nodes per thread, bit 1:
                                   non-temporal accesses, bit 2: 128-thread,
                                   bit 3: 64-thread blocks, bit 4: four nodes
                                   per thread with whole x rows per wavefront,
@@ -118,7 +118,13 @@ extern "C" {
                                   thread, used when nx / 8 divides 64;
                                   bit 6, bit 7: the four-node row form in
                                   128- or 64-thread blocks instead of 256;
-                                  default 23);
+                                  bit 8: the four-node row form stores the
+                                  new populations with ordinary (cached)
+                                  writes instead of non-temporal ones;
+                                  default 23, plus 256 where one population
+                                  buffer takes 48 to 192 MiB, so that most of
+                                  it stays in the last-level cache until the
+                                  next step reads it);
                                   results are identical, only the speed
                                   differs                                    */
 #define IBM_OPT_STENCIL_BOX 6  /* 0..7.  bit 0: spreading, bit 1:

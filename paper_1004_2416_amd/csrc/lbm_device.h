@@ -236,15 +236,22 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <typename T>
 struct Pop4;
 
+// NT (default): non-temporal accesses, for populations streamed once per
+// step; false: ordinary cached accesses (the row form's stores on lattices
+// whose new population buffer largely stays in the last-level cache until
+// the next step reads it).
 template <>
 struct Pop4<float> {
+  template <bool NT = true>
   static __device__ __forceinline__ void ld(const float *p, long long i, float, float (&v)[4]) {
-    const f32x4 r = __builtin_nontemporal_load(reinterpret_cast<const f32x4 *>(p + i));
+    const f32x4 *q = reinterpret_cast<const f32x4 *>(p + i);
+    const f32x4 r = NT ? __builtin_nontemporal_load(q) : *q;
     v[0] = r.x;
     v[1] = r.y;
     v[2] = r.z;
     v[3] = r.w;
   }
+  template <bool NT = true>
   static __device__ __forceinline__ void st(float *p, long long i, float a, float b, float c,
                                             float d, float) {
     f32x4 r;
@@ -252,7 +259,9 @@ struct Pop4<float> {
     r.y = b;
     r.z = c;
     r.w = d;
-    __builtin_nontemporal_store(r, reinterpret_cast<f32x4 *>(p + i));
+    f32x4 *q = reinterpret_cast<f32x4 *>(p + i);
+    if (NT) __builtin_nontemporal_store(r, q);
+    else *q = r;
   }
 };
 
@@ -267,8 +276,10 @@ struct Pop4<__half> {
   static __device__ __forceinline__ unsigned int q(float v, float scale) {
     return (unsigned int)__half_as_ushort(__float2half_rn(v * scale));
   }
+  template <bool NT = true>
   static __device__ __forceinline__ void ld(const __half *p, long long i, float inv, float (&v)[4]) {
-    const u32x2 r = __builtin_nontemporal_load(reinterpret_cast<const u32x2 *>(p + i));
+    const u32x2 *a = reinterpret_cast<const u32x2 *>(p + i);
+    const u32x2 r = NT ? __builtin_nontemporal_load(a) : *a;
     v[0] = h(r.x & 0xffffu, inv);
     v[1] = h(r.x >> 16, inv);
     v[2] = h(r.y & 0xffffu, inv);
@@ -280,12 +291,15 @@ struct Pop4<__half> {
     const f32x2 v = {a, b};
     return __builtin_bit_cast(unsigned int, __builtin_convertvector(v, f16x2));
   }
+  template <bool NT = true>
   static __device__ __forceinline__ void st(__half *p, long long i, float a, float b, float c,
                                             float d, float scale) {
     u32x2 r;
     r.x = pk(a * scale, b * scale);
     r.y = pk(c * scale, d * scale);
-    __builtin_nontemporal_store(r, reinterpret_cast<u32x2 *>(p + i));
+    u32x2 *q = reinterpret_cast<u32x2 *>(p + i);
+    if (NT) __builtin_nontemporal_store(r, q);
+    else *q = r;
   }
 };
 
@@ -293,9 +307,24 @@ struct Pop4<__half> {
 // wavefront call this together (the shuffles need every lane); `live` is
 // false for idle lanes and rows beyond the lattice.  PAD: nx is not a
 // multiple of 4.
+template <typename T, bool LINEAR, bool FORCE, bool PAD, bool NT>
+__device__ __forceinline__ void collide_stream_rowseg_a(const LatDev &L, int src, int par, int row,
+                                                        int t, int lane, bool live);
+
 template <typename T, bool LINEAR, bool FORCE, bool PAD>
 __device__ __forceinline__ void collide_stream_rowseg(const LatDev &L, int src, int par, int row,
                                                       int t, int lane, bool live) {
+  if (L.cached)
+    collide_stream_rowseg_a<T, LINEAR, FORCE, PAD, false>(L, src, par, row, t, lane, live);
+  else
+    collide_stream_rowseg_a<T, LINEAR, FORCE, PAD, true>(L, src, par, row, t, lane, live);
+}
+
+// NT: non-temporal population stores (see Pop4); the loads are always
+// non-temporal
+template <typename T, bool LINEAR, bool FORCE, bool PAD, bool NT>
+__device__ __forceinline__ void collide_stream_rowseg_a(const LatDev &L, int src, int par, int row,
+                                                        int t, int lane, bool live) {
   // FP16 values are used in their storage units (collide<..., SCALED>)
   constexpr bool SC = sizeof(T) == 2;
   const int tpr = L.tpr, last = tpr - 1;
@@ -321,7 +350,7 @@ __device__ __forceinline__ void collide_stream_rowseg(const LatDev &L, int src, 
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       float v[4];
-      Pop4<T>::ld(static_cast<const T *>(L.f[src]) + L.pst[i], off0, 1.0f, v);
+      Pop4<T>::template ld<true>(static_cast<const T *>(L.f[src]) + L.pst[i], off0, 1.0f, v);
 #pragma unroll
       for (int k = 0; k < 4; ++k) d[k][i] = v[k];
     }
@@ -389,14 +418,14 @@ __device__ __forceinline__ void collide_stream_rowseg(const LatDev &L, int src, 
     const int zt = z + cz(i);
     if (cz(i) != 0 && (zt < 0 || zt >= L.nz)) {
       const float kick = SC ? wall_kick_scaled(i, L.uw) : wall_kick(i, L.uw);
-      Pop4<T>::st(fd + L.pst[opp(i)], off0, d[0][i] - kick, d[1][i] - kick, d[2][i] - kick,
-                  d[3][i] - kick, 1.0f);
+      Pop4<T>::template st<NT>(fd + L.pst[opp(i)], off0, d[0][i] - kick, d[1][i] - kick,
+                               d[2][i] - kick, d[3][i] - kick, 1.0f);
     } else {
       const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
       T *base = fd + L.pst[i];
       const unsigned long long at = rowoff(L, (unsigned)(zt * L.ny + yt), x0);
       if (cx(i) > 0) {
-        Pop4<T>::st(base, at, in, d[0][i], d[1][i], d[2][i], 1.0f);
+        Pop4<T>::template st<NT>(base, at, in, d[0][i], d[1][i], d[2][i], 1.0f);
       } else if (cx(i) < 0) {
         // slot k takes x0 + k + 1; in the last segment x = nx - 1 (slot e)
         // takes x = 0 of the row (`in`), slots beyond e are padding
@@ -406,9 +435,9 @@ __device__ __forceinline__ void collide_stream_rowseg(const LatDev &L, int src, 
           o1 = e <= 1 ? in : o1;
           o2 = e <= 2 ? in : o2;
         }
-        Pop4<T>::st(base, at, o0, o1, o2, in, 1.0f);
+        Pop4<T>::template st<NT>(base, at, o0, o1, o2, in, 1.0f);
       } else {
-        Pop4<T>::st(base, at, d[0][i], d[1][i], d[2][i], d[3][i], 1.0f);
+        Pop4<T>::template st<NT>(base, at, d[0][i], d[1][i], d[2][i], d[3][i], 1.0f);
       }
     }
   }

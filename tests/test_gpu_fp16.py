@@ -193,7 +193,7 @@ def test_fp16_collide_stream_forms_agree(B):
     difference can then round to the neighbouring FP16 value, so after five
     steps the forms agree within one FP16 ulp (2^-10) of the largest
     deviation."""
-    forms = (55, 23, 7, 0, 87, 151)
+    forms = (55, 23, 7, 0, 87, 151, 279)
     shapes = [((32, 20, 16), True), ((30, 20, 16), True), ((64, 12, 10), False),
               ((8, 6, 5), False), ((16, 10, 9), False), ((256, 6, 4), False),
               ((512, 4, 3), False), ((21, 9, 7), False), ((253, 4, 3), False),
@@ -229,7 +229,7 @@ def test_fp16_collide_stream_forms_agree(B):
             if with_capsule:
                 assert np.max(np.abs(x - ref[1])) < 1e-6, (n, v)
     lat = c.gpu(storage="fp16", graph=False)
-    lat.set_option(B.OPT_LBM_VARIANT, 255)
+    lat.set_option(B.OPT_LBM_VARIANT, 511)
     with pytest.raises(B.IBMError):
-        lat.set_option(B.OPT_LBM_VARIANT, 256)
+        lat.set_option(B.OPT_LBM_VARIANT, 512)
     lat.close()

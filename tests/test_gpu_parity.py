@@ -219,7 +219,7 @@ def test_autotune_keeps_the_run_on_the_oracle(B):
     chosen = lat.autotune(16)
     n = lat.steps
     say("  autotune chose", chosen, "after", n, "steps")
-    assert 0 <= chosen["lbm_variant"] < 64 and 0 <= chosen["stencil_box"] < 6
+    assert 0 <= chosen["lbm_variant"] < 512 and 0 <= chosen["stencil_box"] < 6
     sim = c.oracle()
     assert sim.run(n) == 0
     f = lat.populations().cpu().numpy()
@@ -559,11 +559,12 @@ def test_bad_arguments(B):
 def test_collide_stream_variants_agree(B):
     """Every launch variant of the collide-stream kernel computes the same
     update: the 32 per-node and row forms, and the row form in 128- and
-    64-thread blocks (bits 6, 7), on padded and unpadded rows."""
+    64-thread blocks (bits 6, 7) and with cached accesses (bit 8), on padded
+    and unpadded rows."""
     for shape in ((32, 20, 16), (30, 20, 16), (27, 19, 18)):
         c = small_case(n=shape, m=3, ca=0.02)
         ref = None
-        for v in list(range(32)) + [80, 144, 87, 151]:
+        for v in list(range(32)) + [80, 144, 87, 151, 272, 279]:
             lat = c.gpu(graph=False)
             lat.set_option(B.OPT_LBM_VARIANT, v)
             lat.step(6)
