@@ -468,6 +468,58 @@ std::vector<int> morton_order(const double *xyz, int n) {
   return order;
 }
 
+// Order of a capsule's nodes by recursive coordinate bisection: the set is
+// cut across its longest extent, at the multiple of PATCH (in the membrane's
+// global node numbering, the capsule starting at node `base`) nearest to its
+// middle, until a set lies within one run of PATCH global node numbers; each
+// such patch is then taken in Morton order.  So every run of PATCH
+// consecutive nodes from a multiple of PATCH (the nodes of one spreading
+// block, or of 4 or 8 blocks for the wider deltas) holds one compact patch of
+// the surface, except where one capsule ends and the next begins, and a
+// block's stencils span a small box.  A Morton curve alone sometimes joins
+// two distant pieces of the surface in one such run.
+constexpr int PATCH = 32;
+
+void bisect_order(const double *xyz, int *idx, int n, int base, std::vector<int> &out) {
+  const int first = base / PATCH * PATCH + PATCH;  // first patch boundary after base
+  if (base + n <= first) {
+    std::vector<double> sub(3 * (size_t)n);
+    for (int k = 0; k < n; ++k)
+      for (int d = 0; d < 3; ++d) sub[3 * (size_t)k + d] = xyz[3 * (size_t)idx[k] + d];
+    const std::vector<int> o = morton_order(sub.data(), n);
+    for (int k = 0; k < n; ++k) out.push_back(idx[o[k]]);
+    return;
+  }
+  double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+  for (int k = 0; k < n; ++k)
+    for (int d = 0; d < 3; ++d) {
+      lo[d] = std::min(lo[d], xyz[3 * (size_t)idx[k] + d]);
+      hi[d] = std::max(hi[d], xyz[3 * (size_t)idx[k] + d]);
+    }
+  int axis = 0;
+  for (int d = 1; d < 3; ++d)
+    if (hi[d] - lo[d] > hi[axis] - lo[axis]) axis = d;
+  // the patch boundary inside (base, base + n) nearest to the middle
+  const int last = (base + n - 1) / PATCH * PATCH;  // last boundary before the end
+  int cut = (base + n / 2 + PATCH / 2) / PATCH * PATCH;
+  cut = std::max(first, std::min(cut, last));
+  const int left = cut - base;
+  std::nth_element(idx, idx + left, idx + n, [&](int a, int b) {
+    const double xa = xyz[3 * (size_t)a + axis], xb = xyz[3 * (size_t)b + axis];
+    return xa < xb || (xa == xb && a < b);
+  });
+  bisect_order(xyz, idx, left, base, out);
+  bisect_order(xyz, idx + left, n - left, cut, out);
+}
+
+std::vector<int> patch_order(const double *xyz, int n, int base) {
+  std::vector<int> idx(n), out;
+  out.reserve(n);
+  for (int k = 0; k < n; ++k) idx[k] = k;
+  bisect_order(xyz, idx.data(), n, base, out);
+  return out;
+}
+
 }  // namespace
 
 struct ibm_batch {
@@ -801,11 +853,11 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
   const int nn = node_off[n_caps], nf = face_off[n_caps];
   if (!finite_all(xyz, 3 * (size_t)nn)) return fail(IBM_ERR_INVALID_ARG, "non-finite node position");
 
-  // internal node order: each capsule's nodes sorted along a Morton curve
+  // internal node order: each capsule's nodes in compact patches (patch_order)
   std::vector<int> ext_of_int(nn), int_of_ext(nn);
   for (int c = 0; c < n_caps; ++c) {
     const int n0 = node_off[c];
-    const std::vector<int> order = morton_order(xyz + 3 * (size_t)n0, nodes_per_cap[c]);
+    const std::vector<int> order = patch_order(xyz + 3 * (size_t)n0, nodes_per_cap[c], n0);
     for (int k = 0; k < nodes_per_cap[c]; ++k) {
       ext_of_int[n0 + k] = n0 + order[k];
       int_of_ext[n0 + order[k]] = n0 + k;
