@@ -209,9 +209,10 @@ struct Box {
   bool fits;
 };
 
-__device__ __forceinline__ Box block_box(int gx, int gy, int gz, bool has, int capacity, int *bb) {
-  int v[6] = {has ? gx : 0x7fffffff, has ? gy : 0x7fffffff, has ? gz : 0x7fffffff,
-              has ? gx : -0x7fffffff, has ? gy : -0x7fffffff, has ? gz : -0x7fffffff};
+__device__ __forceinline__ Box block_box(int gx0, int gy0, int gz0, int gx1, int gy1, int gz1,
+                                         bool has, int capacity, int *bb) {
+  int v[6] = {has ? gx0 : 0x7fffffff, has ? gy0 : 0x7fffffff, has ? gz0 : 0x7fffffff,
+              has ? gx1 : -0x7fffffff, has ? gy1 : -0x7fffffff, has ? gz1 : -0x7fffffff};
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) {
 #pragma unroll
@@ -253,10 +254,24 @@ struct SpreadLDS {
   int bb[6];
 };
 
-template <int M, bool BOX>
+// Lanes per membrane node in spreading.  With HALF the wider deltas give each
+// lane two stencil nodes (27 or 64 of them on 16 or 32 lanes), which halves
+// the wavefronts of the launch and the idle lanes of the force evaluation; on
+// large membranes that measured 3-6 % faster steps (128^3, the batched
+// sweep), on a single 642-node capsule (300 wavefronts) 4 % slower.
+template <int M, bool HALF>
+__host__ __device__ constexpr int spread_group_size() {
+  return M == 2 ? 8 : (HALF ? group_size<M>() / 2 : group_size<M>());
+}
+// HALF where the full lane groups would make at least this many wavefronts
+constexpr long long SPREAD_HALF_WAVES = 1024;
+
+template <int M, bool BOX, bool HALF = true>
 __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, int par, int blk,
                                              SpreadLDS &sm) {
-  constexpr int GS = group_size<M>();
+  constexpr int GS = spread_group_size<M, HALF>();
+  constexpr int M3 = M * M * M;
+  constexpr int PPL = (M3 + GS - 1) / GS;  // stencil nodes per lane
   const int lane = threadIdx.x & (GS - 1);
   const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
   const bool live = node < Mm.nn;  // whole groups alike
@@ -286,45 +301,73 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   fy = group_sum<GS>(fy);
   fz = group_sum<GS>(fz);
   if (live && lane == 0) Mm.F[node] = make_float4(fx, fy, fz, 0.0f);
-  // this lane's stencil node, in unwrapped lattice coordinates
-  int gx = 0, gy = 0, gz = 0;
-  float w = 0.0f;
-  if (live && lane < M * M * M) {
+  // this lane's stencil nodes lane, lane + GS, ..., in unwrapped lattice
+  // coordinates
+  int gx[PPL], gy[PPL], gz[PPL];
+  float w[PPL];
+#pragma unroll
+  for (int q = 0; q < PPL; ++q) {
+    gx[q] = gy[q] = gz[q] = 0;
+    w[q] = 0.0f;
+  }
+  if (live) {
     const float4 p = Mm.x[node];
-    const int lx = stencil_lo<M>(p.x) + lane % M;
-    const int ly = stencil_lo<M>(p.y) + (lane / M) % M;
-    const int lz = stencil_lo<M>(p.z) + lane / (M * M);
-    w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
     const int4 o = Mm.origin[Mm.node_cap[node]];
-    gx = o.x + lx;
-    gy = o.y + ly;
-    gz = o.z + lz;
-    if (w != 0.0f && (gz < 0 || gz >= L.nz)) {
-      atomicOr(&L.ctrl->err, ERR_WALL);
-      w = 0.0f;
-    }
-    // a split lattice update assumes no force outside the rows zlo <= z < zhi,
-    // ylo <= y < yhi
-    if (w != 0.0f) {
-      const int Y = wrap_mod(gy, L.ny);
-      if (gz < L.zlo || gz >= L.zhi || Y < L.ylo || Y >= L.yhi) atomicOr(&L.ctrl->err, ERR_SLAB);
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      const int sidx = lane + q * GS;
+      if (sidx >= M3) continue;
+      const int lx = stencil_lo<M>(p.x) + sidx % M;
+      const int ly = stencil_lo<M>(p.y) + (sidx / M) % M;
+      const int lz = stencil_lo<M>(p.z) + sidx / (M * M);
+      float wq = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
+      gx[q] = o.x + lx;
+      gy[q] = o.y + ly;
+      gz[q] = o.z + lz;
+      if (wq != 0.0f && (gz[q] < 0 || gz[q] >= L.nz)) {
+        atomicOr(&L.ctrl->err, ERR_WALL);
+        wq = 0.0f;
+      }
+      // a split lattice update assumes no force outside the rows zlo <= z < zhi,
+      // ylo <= y < yhi
+      if (wq != 0.0f) {
+        const int Y = wrap_mod(gy[q], L.ny);
+        if (gz[q] < L.zlo || gz[q] >= L.zhi || Y < L.ylo || Y >= L.yhi)
+          atomicOr(&L.ctrl->err, ERR_SLAB);
+      }
+      w[q] = wq;
     }
   }
-  const bool has = w != 0.0f;
   float *g = L.g[par];
   const int step = L.ctrl->step;
   if constexpr (!BOX) {
-    if (has) {
-      const int X = wrap_mod(gx, L.nx), Y = wrap_mod(gy, L.ny);
-      const long long n = ((long long)gz * L.ny + Y) * L.nx + X;
-      unsafeAtomicAdd(g + n, w * fx);
-      unsafeAtomicAdd(g + L.S + n, w * fy);
-      unsafeAtomicAdd(g + 2 * L.S + n, w * fz);
-      L.stamp[par][tile_of(L, X, Y, gz)] = step;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      if (w[q] == 0.0f) continue;
+      const int X = wrap_mod(gx[q], L.nx), Y = wrap_mod(gy[q], L.ny);
+      const long long n = ((long long)gz[q] * L.ny + Y) * L.nx + X;
+      unsafeAtomicAdd(g + n, w[q] * fx);
+      unsafeAtomicAdd(g + L.S + n, w[q] * fy);
+      unsafeAtomicAdd(g + 2 * L.S + n, w[q] * fz);
+      L.stamp[par][tile_of(L, X, Y, gz[q])] = step;
     }
     return;
   }
-  const Box b = block_box(gx, gy, gz, has, SPREAD_BOX, sm.bb);
+  // the lane's own extent over its nonzero-weight stencil nodes
+  bool has = false;
+  int bx0 = 0, by0 = 0, bz0 = 0, bx1 = 0, by1 = 0, bz1 = 0;
+#pragma unroll
+  for (int q = 0; q < PPL; ++q) {
+    if (w[q] == 0.0f) continue;
+    bx0 = has ? min(bx0, gx[q]) : gx[q];
+    by0 = has ? min(by0, gy[q]) : gy[q];
+    bz0 = has ? min(bz0, gz[q]) : gz[q];
+    bx1 = has ? max(bx1, gx[q]) : gx[q];
+    by1 = has ? max(by1, gy[q]) : gy[q];
+    bz1 = has ? max(bz1, gz[q]) : gz[q];
+    has = true;
+  }
+  const Box b = block_box(bx0, by0, bz0, bx1, by1, bz1, has, SPREAD_BOX, sm.bb);
   const bool fits = b.fits;
   const int x0 = b.x0, y0 = b.y0, z0 = b.z0, ex = b.ex, ey = b.ey;
   const int V = b.V;
@@ -336,20 +379,22 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   for (int c = threadIdx.x; c < V; c += blockDim.x) sm.box[0][c] = sm.box[1][c] = sm.box[2][c] = 0.0f;
   for (int q = threadIdx.x; q < NT; q += blockDim.x) sm.tflag[q] = 0;
   __syncthreads();
-  if (has) {
+#pragma unroll
+  for (int q = 0; q < PPL; ++q) {
+    if (w[q] == 0.0f) continue;
     if (fits) {
-      const int c = ((gz - z0) * ey + (gy - y0)) * ex + (gx - x0);
-      atomicAdd(&sm.box[0][c], w * fx);
-      atomicAdd(&sm.box[1][c], w * fy);
-      atomicAdd(&sm.box[2][c], w * fz);
-      sm.tflag[(((gz >> 2) - tz0) * nty + ((gy >> 2) - ty0)) * ntx + ((gx >> 2) - tx0)] = 1;
+      const int c = ((gz[q] - z0) * ey + (gy[q] - y0)) * ex + (gx[q] - x0);
+      atomicAdd(&sm.box[0][c], w[q] * fx);
+      atomicAdd(&sm.box[1][c], w[q] * fy);
+      atomicAdd(&sm.box[2][c], w[q] * fz);
+      sm.tflag[(((gz[q] >> 2) - tz0) * nty + ((gy[q] >> 2) - ty0)) * ntx + ((gx[q] >> 2) - tx0)] = 1;
     } else {
-      const int X = wrap_mod(gx, L.nx), Y = wrap_mod(gy, L.ny);
-      const long long n = ((long long)gz * L.ny + Y) * L.nx + X;
-      unsafeAtomicAdd(g + n, w * fx);
-      unsafeAtomicAdd(g + L.S + n, w * fy);
-      unsafeAtomicAdd(g + 2 * L.S + n, w * fz);
-      L.stamp[par][tile_of(L, X, Y, gz)] = step;
+      const int X = wrap_mod(gx[q], L.nx), Y = wrap_mod(gy[q], L.ny);
+      const long long n = ((long long)gz[q] * L.ny + Y) * L.nx + X;
+      unsafeAtomicAdd(g + n, w[q] * fx);
+      unsafeAtomicAdd(g + L.S + n, w[q] * fy);
+      unsafeAtomicAdd(g + 2 * L.S + n, w[q] * fz);
+      L.stamp[par][tile_of(L, X, Y, gz[q])] = step;
     }
   }
   if (!fits) return;  // the whole block
@@ -383,11 +428,11 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   }
 }
 
-template <int M, bool BOX>
+template <int M, bool BOX, bool HALF>
 __global__ __launch_bounds__(256) void k_spread(LatDev L, MemDev Mm, int par, int nblocks) {
   __shared__ SpreadLDS sm;
   const int blk = xcd_block(nblocks);
-  if (blk >= 0) spread_lanes<M, BOX>(L, Mm, par, blk, sm);
+  if (blk >= 0) spread_lanes<M, BOX, HALF>(L, Mm, par, blk, sm);
 }
 
 // ---- chunked spreading ----------------------------------------------------------
@@ -558,15 +603,19 @@ void launch_spread(const LatDev &L, const MemDev &M, int par, bool box, hipStrea
     else k_spread_chunks<4><<<grid, block, 0, s>>>(L, M, par);
     return;
   }
-  const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
+  const int full = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
+  const bool half = (long long)M.nn * full / 64 >= SPREAD_HALF_WAVES;
+  const int gs = M.m == 2 ? full : (half ? full / 2 : full);
   const long long lanes = (long long)M.nn * gs;
   const int nblocks = (int)((lanes + 255) / 256);
   const dim3 grid(xcd_grid(nblocks)), block(256);
-#define IBM_LAUNCH_SPREAD(BX)                                                         \
-  do {                                                                                \
-    if (M.m == 2) k_spread<2, BX><<<grid, block, 0, s>>>(L, M, par, nblocks);         \
-    else if (M.m == 3) k_spread<3, BX><<<grid, block, 0, s>>>(L, M, par, nblocks);    \
-    else k_spread<4, BX><<<grid, block, 0, s>>>(L, M, par, nblocks);                  \
+#define IBM_LAUNCH_SPREAD(BX)                                                               \
+  do {                                                                                      \
+    if (M.m == 2) k_spread<2, BX, false><<<grid, block, 0, s>>>(L, M, par, nblocks);        \
+    else if (M.m == 3 && half) k_spread<3, BX, true><<<grid, block, 0, s>>>(L, M, par, nblocks); \
+    else if (M.m == 3) k_spread<3, BX, false><<<grid, block, 0, s>>>(L, M, par, nblocks);   \
+    else if (half) k_spread<4, BX, true><<<grid, block, 0, s>>>(L, M, par, nblocks);        \
+    else k_spread<4, BX, false><<<grid, block, 0, s>>>(L, M, par, nblocks);                 \
   } while (0)
   if (box) IBM_LAUNCH_SPREAD(true);
   else IBM_LAUNCH_SPREAD(false);
@@ -697,7 +746,7 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
   const T *f = static_cast<const T *>(L.f[fsrc]);
   const float *g = L.g[par];
   Box b{0, 0, 0, 1, 1, 1, 0, false};
-  if constexpr (BOX && !UF) b = block_box(gx, gy, gz, has, INTERP_BOX, sm.bb);
+  if constexpr (BOX && !UF) b = block_box(gx, gy, gz, gx, gy, gz, has, INTERP_BOX, sm.bb);
   const bool fits = b.fits;
   const int x0 = b.x0, y0 = b.y0, z0 = b.z0, ex = b.ex, ey = b.ey;
   const int V = b.V;
@@ -1403,7 +1452,8 @@ static unsigned far_blocks(const LatDev &L, const RowSet &rs) {
 template <typename T, bool LINEAR>
 static void launch_spread_far_t(const LatDev &L, const MemDev &M, int par, bool box, int fsrc,
                                 const RowSet &rs, hipStream_t s) {
-  const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
+  const int gs = M.m == 2 ? spread_group_size<2, true>()
+                          : (M.m == 3 ? spread_group_size<3, true>() : spread_group_size<4, true>());
   const int nblocks = (int)(((long long)M.nn * gs + 255) / 256);
   const dim3 grid(xcd_grid(nblocks) + far_blocks(L, rs)), block(256);
 #define IBM_LAUNCH_SPREAD_FAR(BX)                                                                        \
