@@ -715,46 +715,75 @@ struct InterpLDS {
 
 // UF: read the lattice velocity from L.U (filled by the tile-velocity pass
 // of this step) instead of evaluating it from the populations.
-template <typename T, int M, bool BOX, bool UF>
+// HALF: two stencil nodes per lane for the wider deltas, as in spreading.
+template <typename T, int M, bool BOX, bool UF, bool HALF = false>
 __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, int fsrc, int par,
                                              int advect, int blk, InterpLDS &sm) {
-  constexpr int GS = group_size<M>();
+  constexpr int GS = spread_group_size<M, HALF>();
+  constexpr int M3 = M * M * M;
+  constexpr int PPL = (M3 + GS - 1) / GS;  // stencil nodes per lane
   const int lane = threadIdx.x & (GS - 1);
   const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
   const bool live = node < Mm.nn;  // whole groups alike
   float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-  int gx = 0, gy = 0, gz = 0;
-  float w = 0.0f;
+  int gx[PPL], gy[PPL], gz[PPL];
+  float w[PPL];
+#pragma unroll
+  for (int q = 0; q < PPL; ++q) {
+    gx[q] = gy[q] = gz[q] = 0;
+    w[q] = 0.0f;
+  }
   if (live) {
     p = Mm.x[node];
-    if (lane < M * M * M) {
-      const int lx = stencil_lo<M>(p.x) + lane % M;
-      const int ly = stencil_lo<M>(p.y) + (lane / M) % M;
-      const int lz = stencil_lo<M>(p.z) + lane / (M * M);
-      w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
-      const int4 o = Mm.origin[Mm.node_cap[node]];
-      gx = o.x + lx;
-      gy = o.y + ly;
-      gz = o.z + lz;
-      if (w != 0.0f && (gz < 0 || gz >= L.nz)) {
+    const int4 o = Mm.origin[Mm.node_cap[node]];
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      const int sidx = lane + q * GS;
+      if (sidx >= M3) continue;
+      const int lx = stencil_lo<M>(p.x) + sidx % M;
+      const int ly = stencil_lo<M>(p.y) + (sidx / M) % M;
+      const int lz = stencil_lo<M>(p.z) + sidx / (M * M);
+      float wq = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
+      gx[q] = o.x + lx;
+      gy[q] = o.y + ly;
+      gz[q] = o.z + lz;
+      if (wq != 0.0f && (gz[q] < 0 || gz[q] >= L.nz)) {
         atomicOr(&L.ctrl->err, ERR_WALL);
-        w = 0.0f;
+        wq = 0.0f;
       }
+      w[q] = wq;
     }
   }
-  const bool has = w != 0.0f;
   const T *f = static_cast<const T *>(L.f[fsrc]);
   const float *g = L.g[par];
   Box b{0, 0, 0, 1, 1, 1, 0, false};
-  if constexpr (BOX && !UF) b = block_box(gx, gy, gz, gx, gy, gz, has, INTERP_BOX, sm.bb);
+  if constexpr (BOX && !UF) {
+    bool has = false;
+    int bx0 = 0, by0 = 0, bz0 = 0, bx1 = 0, by1 = 0, bz1 = 0;
+#pragma unroll
+    for (int q = 0; q < PPL; ++q) {
+      if (w[q] == 0.0f) continue;
+      bx0 = has ? min(bx0, gx[q]) : gx[q];
+      by0 = has ? min(by0, gy[q]) : gy[q];
+      bz0 = has ? min(bz0, gz[q]) : gz[q];
+      bx1 = has ? max(bx1, gx[q]) : gx[q];
+      by1 = has ? max(by1, gy[q]) : gy[q];
+      bz1 = has ? max(bz1, gz[q]) : gz[q];
+      has = true;
+    }
+    b = block_box(bx0, by0, bz0, bx1, by1, bz1, has, INTERP_BOX, sm.bb);
+  }
   const bool fits = b.fits;
   const int x0 = b.x0, y0 = b.y0, z0 = b.z0, ex = b.ex, ey = b.ey;
   const int V = b.V;
-  const int cell = ((gz - z0) * ey + (gy - y0)) * ex + (gx - x0);
   if constexpr (BOX && !UF) {
     for (int c = threadIdx.x; c < V; c += blockDim.x) sm.mark[c] = 0;
     __syncthreads();
-    if (has && fits) sm.mark[cell] = 1;
+    if (fits) {
+#pragma unroll
+      for (int q = 0; q < PPL; ++q)
+        if (w[q] != 0.0f) sm.mark[((gz[q] - z0) * ey + (gy[q] - y0)) * ex + (gx[q] - x0)] = 1;
+    }
     __syncthreads();
     for (int c = threadIdx.x; c < V; c += blockDim.x) {
       if (!sm.mark[c]) continue;
@@ -767,19 +796,23 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
     __syncthreads();
   }
   float ux = 0.0f, uy = 0.0f, uz = 0.0f;
-  if (has) {
+#pragma unroll
+  for (int q = 0; q < PPL; ++q) {
+    if (w[q] == 0.0f) continue;
     float3 u;
     if constexpr (UF) {
-      const float4 v = L.U[((long long)gz * L.ny + wrap_mod(gy, L.ny)) * L.nx + wrap_mod(gx, L.nx)];
+      const float4 v =
+          L.U[((long long)gz[q] * L.ny + wrap_mod(gy[q], L.ny)) * L.nx + wrap_mod(gx[q], L.nx)];
       u = make_float3(v.x, v.y, v.z);
     } else if (fits) {
+      const int cell = ((gz[q] - z0) * ey + (gy[q] - y0)) * ex + (gx[q] - x0);
       u = make_float3(sm.box[0][cell], sm.box[1][cell], sm.box[2][cell]);
     } else {
-      u = lattice_velocity<T>(L, f, g, wrap_mod(gx, L.nx), wrap_mod(gy, L.ny), gz);
+      u = lattice_velocity<T>(L, f, g, wrap_mod(gx[q], L.nx), wrap_mod(gy[q], L.ny), gz[q]);
     }
-    ux = w * u.x;
-    uy = w * u.y;
-    uz = w * u.z;
+    ux += w[q] * u.x;
+    uy += w[q] * u.y;
+    uz += w[q] * u.z;
   }
   ux = group_sum<GS>(ux);
   uy = group_sum<GS>(uy);
@@ -800,13 +833,13 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
   }
 }
 
-template <typename T, int M, bool BOX>
+template <typename T, int M, bool BOX, bool HALF>
 __global__ __launch_bounds__(256) void k_interp_advect(LatDev L, MemDev Mm, int fsrc, int par,
                                                        int advect, int nblocks) {
   __shared__ InterpLDS sm;
   if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
   const int blk = xcd_block(nblocks);
-  if (blk >= 0) interp_lanes<T, M, BOX, false>(L, Mm, fsrc, par, advect, blk, sm);
+  if (blk >= 0) interp_lanes<T, M, BOX, false, HALF>(L, Mm, fsrc, par, advect, blk, sm);
 }
 
 // Interpolation from the tile-velocity field.
@@ -953,12 +986,19 @@ void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, 
   const dim3 grid(xcd_grid(nblocks)), block(256);
   if (mode != 2) {
     // the lattice velocity from the populations, per stencil node or per block
-    // in an LDS box
-#define IBM_LAUNCH_INTERP(T, BX)                                                                    \
-  do {                                                                                              \
-    if (M.m == 2) k_interp_advect<T, 2, BX><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);      \
-    else if (M.m == 3) k_interp_advect<T, 3, BX><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks); \
-    else k_interp_advect<T, 4, BX><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);          \
+    // in an LDS box; two stencil nodes per lane on large membranes, as in
+    // spreading
+    const bool half = M.m != 2 && lanes / 64 >= SPREAD_HALF_WAVES;
+    const int nb = half ? (int)((lanes / 2 + 255) / 256) : nblocks;
+    const dim3 gr(xcd_grid(nb));
+#define IBM_LAUNCH_INTERP(T, BX)                                                                  \
+  do {                                                                                            \
+    if (M.m == 2) k_interp_advect<T, 2, BX, false><<<gr, block, 0, s>>>(L, M, fsrc, par, advect, nb); \
+    else if (M.m == 3 && half)                                                                     \
+      k_interp_advect<T, 3, BX, true><<<gr, block, 0, s>>>(L, M, fsrc, par, advect, nb);          \
+    else if (M.m == 3) k_interp_advect<T, 3, BX, false><<<gr, block, 0, s>>>(L, M, fsrc, par, advect, nb); \
+    else if (half) k_interp_advect<T, 4, BX, true><<<gr, block, 0, s>>>(L, M, fsrc, par, advect, nb); \
+    else k_interp_advect<T, 4, BX, false><<<gr, block, 0, s>>>(L, M, fsrc, par, advect, nb);      \
   } while (0)
     if (fp16) {
       if (mode == 1) IBM_LAUNCH_INTERP(__half, true);
@@ -1346,9 +1386,9 @@ __global__ __launch_bounds__(256) void k_batch_interp(BatchDev B, int fsrc, int 
   const MemDev &Mm = B.mem[it.x];
   if (it.y == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
   const int m = Mm.m;
-  if (m == 2) interp_lanes<T, 2, MODE == 1, MODE == 2>(L, Mm, fsrc, par, advect, it.y, sm);
-  else if (m == 3) interp_lanes<T, 3, MODE == 1, MODE == 2>(L, Mm, fsrc, par, advect, it.y, sm);
-  else interp_lanes<T, 4, MODE == 1, MODE == 2>(L, Mm, fsrc, par, advect, it.y, sm);
+  if (m == 2) interp_lanes<T, 2, MODE == 1, MODE == 2, true>(L, Mm, fsrc, par, advect, it.y, sm);
+  else if (m == 3) interp_lanes<T, 3, MODE == 1, MODE == 2, true>(L, Mm, fsrc, par, advect, it.y, sm);
+  else interp_lanes<T, 4, MODE == 1, MODE == 2, true>(L, Mm, fsrc, par, advect, it.y, sm);
 }
 
 // The tile-velocity pass of every run, on the lattice work items: the nb
@@ -1437,7 +1477,7 @@ __global__ __launch_bounds__(256) void k_interp_far(LatDev L, MemDev Mm, int fsr
   if ((int)blockIdx.x < cb) {
     if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
     const int blk = xcd_block(nblocks);
-    if (blk >= 0) interp_lanes<T, M, MODE == 1, MODE == 2>(L, Mm, fsrc, par, advect, blk, sm);
+    if (blk >= 0) interp_lanes<T, M, MODE == 1, MODE == 2, true>(L, Mm, fsrc, par, advect, blk, sm);
     return;
   }
   far_rows_block<T, LINEAR>(L, fsrc, (int)blockIdx.x - cb, rs);
@@ -1482,7 +1522,8 @@ void launch_spread_far(const LatDev &L, const MemDev &M, int par, bool box, int 
 template <typename T, bool LINEAR>
 static void launch_interp_far_t(const LatDev &L, const MemDev &M, int fsrc, int par, int advect,
                                 int mode, const RowSet &rs, hipStream_t s) {
-  const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
+  const int gs = M.m == 2 ? spread_group_size<2, true>()
+                          : (M.m == 3 ? spread_group_size<3, true>() : spread_group_size<4, true>());
   const int nblocks = (int)(((long long)M.nn * gs + 255) / 256);
   const dim3 grid(xcd_grid(nblocks) + far_blocks(L, rs)), block(256);
   if (mode == 2) {
