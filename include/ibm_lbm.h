@@ -138,9 +138,10 @@ extern "C" {
                                   that one pass evaluates at every node of
                                   the 4^3 tiles the step's stencils touch.
                                   Default, set when the membrane is
-                                  attached unless chosen before: 1 (box
-                                  spreading) when the membrane makes at
-                                  least 256 blocks of work, else 0.
+                                  attached unless chosen before: 3 (box
+                                  spreading and box interpolation) when the
+                                  membrane makes at least 256 blocks of
+                                  work, else 0.
                                   Results agree to FP32 rounding (see also
                                   ibm_autotune)                             */
 #define IBM_OPT_CHUNK_NODES 5  /* spreading and interpolation work on chunks

@@ -966,10 +966,12 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
     return rc;
   }
   // Box spreading pays once there are enough blocks for atomic conflicts
-  // between overlapping stencils to dominate (measured: 256+ blocks).
+  // between overlapping stencils to dominate (measured: 256+ blocks); box
+  // interpolation on such membranes too, now that each block's nodes form a
+  // compact patch (measured: 128^3 +1.3 %, the dense suspension +2.2 %).
   if (!lat->box_set) {
     const int gs = m == 2 ? ibm::group_size<2>() : (m == 3 ? ibm::group_size<3>() : ibm::group_size<4>());
-    lat->box_mode = (long long)nn * gs >= 256LL * 256 ? 1 : 0;
+    lat->box_mode = (long long)nn * gs >= 256LL * 256 ? 3 : 0;
   }
   // the force bookkeeping restarts with the membrane
   reset_force_state(lat, s);
