@@ -387,7 +387,8 @@ int ibm_batch_create(int n_runs, ibm_lattice *const *runs, void *dev_mem, size_t
  * call.  The per-node coupling kernels are used whatever a run's
  * IBM_OPT_CHUNK_NODES, and the lattice update is the row form (whole x rows
  * per wavefront) for runs with nx <= 256, else one node per thread, whatever
- * a run's IBM_OPT_LBM_VARIANT.  The stencil-box mode is the first run's
+ * a run's IBM_OPT_LBM_VARIANT; the row form stores the first quarter of each
+ * run's rows with cached writes and the rest non-temporally.  The stencil-box mode is the first run's
  * IBM_OPT_STENCIL_BOX if it was set, else 5 (box spreading, interpolation
  * from the tile-velocity field) when the batch's membranes make at least 256
  * blocks of work, else 0. */

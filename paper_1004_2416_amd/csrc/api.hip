@@ -185,10 +185,10 @@ namespace {
 // the batched sweep); 20 MB (64^3 FP32) 12 % slower, 2.5 MB 2 % faster.
 constexpr long long CACHED_POP_MIN = 48LL << 20, CACHED_POP_MAX = 192LL << 20;
 
-// IBM_OPT_LBM_VARIANT and the device flag of its bit 8
+// IBM_OPT_LBM_VARIANT and the device rows of its bit 8 (all rows)
 void set_variant(ibm_lattice *lat, int v) {
   lat->lbm_variant = v;
-  lat->L.cached = (v & 256) ? 1 : 0;
+  lat->L.cached_rows = (v & 256) ? lat->ny * lat->nz : 0;
 }
 
 void invalidate_graph(ibm_lattice *lat) {
@@ -624,7 +624,10 @@ int batch_sync_tables(ibm_batch *b) {
   std::vector<char> img(bl.total, 0);
   for (size_t r = 0; r < n; ++r) {
     ibm::LatDev Lr = b->runs[r]->L;  // batches update the whole lattice
-    Lr.cached = 0;  // the runs together outgrow the last-level cache (measured slower)
+    // the runs together outgrow the last-level cache: only the first quarter
+    // of each run's rows is stored cached (measured on the 64-run sweep:
+    // +4.6 % FP32, +2.4 % FP16; half or all of the rows: slower)
+    Lr.cached_rows = Lr.ny * Lr.nz / 4;
     Lr.zlo = Lr.ylo = 0;
     Lr.zhi = Lr.nz;
     Lr.yhi = Lr.ny;

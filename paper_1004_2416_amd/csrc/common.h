@@ -60,8 +60,9 @@ struct LatDev {
   int nxs;                // population row stride: nx rounded up to a multiple of 4
   int tpr, rpw;           // row form: lanes per row (nxs / 4) and rows per
                           // wavefront (64 / tpr), or 0 where it does not apply
-  int cached;             // 1: the row form writes the new populations with
-                          // ordinary (cached) stores, 0: non-temporal ones
+  int cached_rows;        // the row form writes the new populations of rows
+                          // z ny + y below this with ordinary (cached) stores,
+                          // the others with non-temporal ones
   void *f[2];             // population buffers (float or __half), see pidx
   float *g[2];            // force density [3][S] of even and odd steps
   int *stamp[2];          // per-tile step stamps of the two fields

@@ -311,10 +311,11 @@ template <typename T, bool LINEAR, bool FORCE, bool PAD, bool NT>
 __device__ __forceinline__ void collide_stream_rowseg_a(const LatDev &L, int src, int par, int row,
                                                         int t, int lane, bool live);
 
+// cached: this wavefront stores with cached writes (uniform across it)
 template <typename T, bool LINEAR, bool FORCE, bool PAD>
 __device__ __forceinline__ void collide_stream_rowseg(const LatDev &L, int src, int par, int row,
-                                                      int t, int lane, bool live) {
-  if (L.cached)
+                                                      int t, int lane, bool live, bool cached) {
+  if (cached)
     collide_stream_rowseg_a<T, LINEAR, FORCE, PAD, false>(L, src, par, row, t, lane, live);
   else
     collide_stream_rowseg_a<T, LINEAR, FORCE, PAD, true>(L, src, par, row, t, lane, live);

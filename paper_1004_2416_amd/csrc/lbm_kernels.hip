@@ -120,7 +120,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int t = lane - r * L.tpr;
   const int k = wave * L.rpw + r;
   const bool live = r < L.rpw && k < rs.n0 + rs.n1;
-  collide_stream_rowseg<T, LINEAR, FORCE, PAD>(L, src, par, live ? rowset_row(rs, L, k) : 0, t, lane, live);
+  // a single lattice stores all rows or none with cached writes
+  collide_stream_rowseg<T, LINEAR, FORCE, PAD>(L, src, par, live ? rowset_row(rs, L, k) : 0, t, lane,
+                                               live, L.cached_rows != 0);
 }
 
 // FP16 row-vector form with eight nodes per thread: one aligned 16-byte
@@ -869,7 +871,9 @@ __global__ __launch_bounds__(256) void k_batch_collide_stream(BatchDev B, int sr
     const int r = lane / L.tpr;
     const int t = lane - r * L.tpr;
     const int row = wave * L.rpw + r;
-    collide_stream_rowseg<T, LINEAR, true, true>(L, 0, 0, row, t, lane, r < L.rpw && row < L.ny * L.nz);
+    // cached writes for the rows of a run below cached_rows, per wavefront
+    collide_stream_rowseg<T, LINEAR, true, true>(L, 0, 0, row, t, lane, r < L.rpw && row < L.ny * L.nz,
+                                                 __builtin_amdgcn_readfirstlane(row) < L.cached_rows);
     return;
   }
   // a lattice holds at most 2^31 nodes: unsigned 32-bit index arithmetic suffices

@@ -1453,7 +1453,8 @@ __device__ __forceinline__ void far_rows_block(const LatDev &L, int fsrc, int kb
   const int t = lane - r * L.tpr;
   const int k = wave * L.rpw + r;
   const bool live = r < L.rpw && k < n;
-  collide_stream_rowseg<T, LINEAR, false, true>(L, fsrc, 0, live ? rowset_row(rs, L, k) : 0, t, lane, live);
+  collide_stream_rowseg<T, LINEAR, false, true>(L, fsrc, 0, live ? rowset_row(rs, L, k) : 0, t, lane,
+                                                live, L.cached_rows != 0);
 }
 
 template <int M, bool BOX, typename T, bool LINEAR>
