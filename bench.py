@@ -177,8 +177,10 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
-              "multi-GPU path; see DESIGN.md for how the timestep would shard.", flush=True)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no "
+              "multi-GPU path (the lattice would split into x-slabs with a 5-population halo "
+              "exchange per cut face, capsules owned by the GPU holding their centre).",
+              flush=True)
         sys.exit(2)
     if args.copy_calibration_mib:
         copy_calibration(args.copy_calibration_mib)
