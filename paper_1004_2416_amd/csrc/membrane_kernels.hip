@@ -254,6 +254,19 @@ struct SpreadLDS {
   int bb[6];
 };
 
+// The capsule holding most of a block's nodes [first, first + count): a block
+// that straddles the end of one capsule holds two compact patches far apart,
+// so only the larger one goes through the block's LDS box (the other lanes
+// work directly on the global fields).  Uniform across the block.
+__device__ __forceinline__ int block_major_capsule(const MemDev &Mm, int first, int count) {
+  if (first >= Mm.nn) return -1;
+  const int last = min(first + count, Mm.nn) - 1;
+  const int c0 = Mm.node_cap[first];
+  const int end0 = Mm.cap_node_off[c0 + 1];
+  if (end0 > last) return c0;
+  return (end0 - first) >= (last + 1 - end0) ? c0 : Mm.node_cap[end0];
+}
+
 // Lanes per membrane node in spreading.  With HALF the wider deltas give each
 // lane two stencil nodes (27 or 64 of them on 16 or 32 lanes), which halves
 // the wavefronts of the launch and the idle lanes of the force evaluation; on
@@ -310,9 +323,10 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
     gx[q] = gy[q] = gz[q] = 0;
     w[q] = 0.0f;
   }
+  const int cap = live ? Mm.node_cap[node] : -1;
   if (live) {
     const float4 p = Mm.x[node];
-    const int4 o = Mm.origin[Mm.node_cap[node]];
+    const int4 o = Mm.origin[cap];
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
       const int sidx = lane + q * GS;
@@ -353,12 +367,15 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
     }
     return;
   }
-  // the lane's own extent over its nonzero-weight stencil nodes
+  // the lane's own extent over its nonzero-weight stencil nodes, if its
+  // capsule is the block's major one
+  const int npb = (int)blockDim.x / GS;
+  const bool inbox = Mm.n_caps == 1 || cap == block_major_capsule(Mm, blk * npb, npb);
   bool has = false;
   int bx0 = 0, by0 = 0, bz0 = 0, bx1 = 0, by1 = 0, bz1 = 0;
 #pragma unroll
   for (int q = 0; q < PPL; ++q) {
-    if (w[q] == 0.0f) continue;
+    if (w[q] == 0.0f || !inbox) continue;
     bx0 = has ? min(bx0, gx[q]) : gx[q];
     by0 = has ? min(by0, gy[q]) : gy[q];
     bz0 = has ? min(bz0, gz[q]) : gz[q];
@@ -382,7 +399,7 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
 #pragma unroll
   for (int q = 0; q < PPL; ++q) {
     if (w[q] == 0.0f) continue;
-    if (fits) {
+    if (fits && inbox) {
       const int c = ((gz[q] - z0) * ey + (gy[q] - y0)) * ex + (gx[q] - x0);
       atomicAdd(&sm.box[0][c], w[q] * fx);
       atomicAdd(&sm.box[1][c], w[q] * fy);
@@ -733,9 +750,10 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
     gx[q] = gy[q] = gz[q] = 0;
     w[q] = 0.0f;
   }
+  const int cap = live ? Mm.node_cap[node] : -1;
   if (live) {
     p = Mm.x[node];
-    const int4 o = Mm.origin[Mm.node_cap[node]];
+    const int4 o = Mm.origin[cap];
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
       const int sidx = lane + q * GS;
@@ -757,12 +775,17 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
   const T *f = static_cast<const T *>(L.f[fsrc]);
   const float *g = L.g[par];
   Box b{0, 0, 0, 1, 1, 1, 0, false};
+  // the LDS box covers the stencils of the block's major capsule only (see
+  // block_major_capsule); the other lanes read the populations themselves
+  bool inbox = false;
   if constexpr (BOX && !UF) {
+    const int npb = (int)blockDim.x / GS;
+    inbox = Mm.n_caps == 1 || cap == block_major_capsule(Mm, blk * npb, npb);
     bool has = false;
     int bx0 = 0, by0 = 0, bz0 = 0, bx1 = 0, by1 = 0, bz1 = 0;
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
-      if (w[q] == 0.0f) continue;
+      if (w[q] == 0.0f || !inbox) continue;
       bx0 = has ? min(bx0, gx[q]) : gx[q];
       by0 = has ? min(by0, gy[q]) : gy[q];
       bz0 = has ? min(bz0, gz[q]) : gz[q];
@@ -779,7 +802,7 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
   if constexpr (BOX && !UF) {
     for (int c = threadIdx.x; c < V; c += blockDim.x) sm.mark[c] = 0;
     __syncthreads();
-    if (fits) {
+    if (fits && inbox) {
 #pragma unroll
       for (int q = 0; q < PPL; ++q)
         if (w[q] != 0.0f) sm.mark[((gz[q] - z0) * ey + (gy[q] - y0)) * ex + (gx[q] - x0)] = 1;
@@ -804,7 +827,7 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
       const float4 v =
           L.U[((long long)gz[q] * L.ny + wrap_mod(gy[q], L.ny)) * L.nx + wrap_mod(gx[q], L.nx)];
       u = make_float3(v.x, v.y, v.z);
-    } else if (fits) {
+    } else if (fits && inbox) {
       const int cell = ((gz[q] - z0) * ey + (gy[q] - y0)) * ex + (gx[q] - x0);
       u = make_float3(sm.box[0][cell], sm.box[1][cell], sm.box[2][cell]);
     } else {
