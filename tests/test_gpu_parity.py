@@ -43,7 +43,8 @@ def small_case(n=(30, 20, 16), m=3, level=2, r=4.0, center=None, ca=0.05, uw=0.0
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("shape,tau,linear", [((30, 20, 12), 1.0, False), ((64, 8, 6), 0.8, False),
                                               ((33, 7, 5), 1.7, True), ((1, 1, 2), 1.0, False),
-                                              ((256, 4, 4), 0.6, False)])
+                                              ((256, 4, 4), 0.6, False), ((300, 3, 4), 1.1, False),
+                                              ((257, 2, 3), 0.9, True)])
 def test_lbm_step_parity(B, shape, tau, linear):
     nx, ny, nz = shape
     say("lbm parity", shape, tau, linear)
