@@ -66,6 +66,15 @@ def test_size_queries_and_validation(B):
     assert n.value > 2 * (642 * 3 * 16 + 1280 * 64)
     bad = np.array([2, 642], dtype=np.int32)
     assert B.lib.ibm_membrane_bytes(2, B._ptr(bad), B._ptr(faces), ctypes.byref(n)) == -1
+    # an empty membrane, a lattice beyond 2^31 nodes and a grid beyond the
+    # launch limits are refused by the size queries themselves
+    assert B.lib.ibm_membrane_bytes(0, B._ptr(nodes), B._ptr(faces), ctypes.byref(n)) == -1
+    assert "n_caps" in B.lib.ibm_last_error().decode()
+    assert B.lib.ibm_lattice_bytes(2048, 1024, 1025, 0, ctypes.byref(n)) == -1
+    assert "2^31" in B.lib.ibm_last_error().decode()
+    assert B.lib.ibm_lattice_bytes(4, 4, 65536, 0, ctypes.byref(n)) == -1
+    assert B.lib.ibm_lattice_bytes(1024, 1024, 2048, 0, ctypes.byref(n)) == 0
+    assert n.value > 2 * 19 * 4 * 2 ** 31
 
 
 @pytest.mark.parametrize("level", [0, 1, 2, 3, 4])
