@@ -20,13 +20,23 @@ def rep_populations(f):
 
 def rep_positions(x, node_counts):
     """Round node positions to the library's frame: per capsule the integer
-    origin floor(mean of its nodes) plus FP32 offsets."""
+    origin floor(mean of its nodes) plus FP32 offsets.  The library takes
+    that origin from the positions it is given, so the result must give back
+    its own origin: a capsule centred on an integer has its mean within
+    rounding of that integer, and rounding the offsets can move the mean
+    across it; then the nodes are rounded again in the new frame."""
     out = np.empty_like(x)
     n0 = 0
     for n in node_counts:
-        sl = slice(n0, n0 + n)
-        o = np.floor(x[sl].sum(axis=0) / n)
-        out[sl] = o + (x[sl] - o).astype(np.float32).astype(np.float64)
+        y = x[n0:n0 + n]
+        for _ in range(8):
+            o = np.floor(y.sum(axis=0) / n)
+            y = o + (y - o).astype(np.float32).astype(np.float64)
+            if np.array_equal(np.floor(y.sum(axis=0) / n), o):
+                break
+        else:
+            raise RuntimeError("no FP32 frame reproduces its own origin")
+        out[n0:n0 + n] = y
         n0 += n
     return out
 

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_1004_2416_amd import workloads as W
-from parity_helpers import Case, O, rel_err, rep_positions, scaled_err
+from parity_helpers import Case, O, deformed_mesh, rel_err, rep_positions, scaled_err
 
 pytestmark = pytest.mark.gpu
 
@@ -208,3 +208,62 @@ def test_batch_rejects_inconsistent_runs(B):
     half.close()
     for r in runs:
         r.lat.close()
+
+
+def test_full_size_batched_sweep(B):
+    """The 64-run sweep at its full sizes (6.67 M lattice nodes, 78 k membrane
+    nodes, delta widths 2-4) in the launch configuration the benchmark times:
+    one batch with its default stencil-box mode (box spreading, interpolation
+    from the tile-velocity field), cached stores for the first quarter of each
+    run's rows, 16-step graphs.  Every capsule is deformed by ~2 % and
+    injected.  After one step every run's populations, forces, node
+    velocities and positions meet the per-step bar against its own oracle.
+    After 16 more (one graph) the populations and positions are compared
+    along the trajectory (positions within one FP32 rounding per step); then
+    each run's state is handed to a fresh oracle and the next step is held to
+    the per-step bar again.  (Forces and node velocities are not compared
+    along the trajectory: the fine meshes' forces move by ~1e-4 of their
+    scale per FP32 rounding of a node position.)"""
+    wls = W.sweep_workloads()
+    say("full-size sweep: %d runs, %d lattice nodes" % (len(wls), sum(w.n_nodes_lattice for w in wls)))
+    cases = [Case(wl) for wl in wls]
+    lats, sims = [], []
+    for k, c in enumerate(cases):
+        lat = c.gpu(graph=True)
+        x_s = deformed_mesh(c, 0.02, 300 + k)
+        lat.set_mesh(x_s)
+        lats.append(lat)
+        sims.append(c.oracle(x=x_s))
+    batch = B.Batch(lats)
+
+    def compare(sims, steps, per_step, since_start=0):
+        worst = dict(f=0.0, F=0.0, u=0.0, x=0.0)
+        for k, (lat, sim) in enumerate(zip(lats, sims)):
+            assert sim.run(steps) == 0
+            xg, Fg, ug = [a.cpu().numpy() for a in lat.mesh()]
+            e = dict(f=rel_err(lat.populations().cpu().numpy(), sim.f),
+                     x=float(np.max(np.abs(xg - sim.x))),
+                     F=scaled_err(Fg, sim.F) if per_step else 0.0,
+                     u=scaled_err(ug, sim.un) if per_step else 0.0)
+            worst = {q: max(worst[q], e[q]) for q in worst}
+            assert e["f"] < 1e-5, (k, e)
+            if per_step:
+                assert e["F"] < 1e-5 and e["u"] < 1e-5 and e["x"] < 2e-6, (k, e)
+            else:
+                assert e["x"] < since_start * 1e-6, (k, e)
+        say("   %d step(s), worst run:" % steps, {q: "%.2e" % v for q, v in worst.items()})
+
+    batch.step(1)
+    compare(sims, 1, True)
+    batch.step(16)
+    compare(sims, 16, False, since_start=17)
+    state = [(lat.populations().cpu().numpy(), lat.mesh()[0].cpu().numpy()) for lat in lats]
+    sims = [c.oracle(f=f, x=x) for c, (f, x) in zip(cases, state)]
+    del state
+    batch.step(1)
+    compare(sims, 1, True)
+    assert all(lat.steps == 18 for lat in lats)
+    batch.close()
+    for lat in lats:
+        lat.synchronize()
+        lat.close()
