@@ -2,12 +2,20 @@
 IB-LB-FEM timestep on one MI355X, with the HBM roofline fraction of the
 collide-stream kernel and the FP64 CPU oracle timed on the host beside it.
 
-    python bench.py [--steps K] [--warmup W] [--workload c2] [--storage fp32]
+    python bench.py [--steps K] [--warmup W] [--workload c3] [--storage fp32]
 
 One step = Skalak forces, spreading, collide-stream with walls, interpolation
-and advection (Sec. II.C) over the whole lattice and every capsule.  Inputs
-are synthetic (the shear-flow workloads of paper_1004_2416_amd.workloads) and
-resident in HBM before timing.  Prints one JSON line.
+and advection (Sec. II.C) over the whole lattice and every capsule.  The
+default workload is the largest single-GPU one: the dense suspension of 200
+capsules on a 256 x 128 x 128 lattice (2-point delta), FP32 populations.  W
+warm-up steps and the capture of the library's step graphs come before the
+timed region, which holds exactly K steps between HIP events on the
+library's stream.  The same line carries, timed the same way, FP16
+population storage on the same workload and the 64-run batched sweep with
+FP32 and FP16 storage ("legs"), and the FP64 oracle on the host's cores
+(all threads and one thread).  Inputs are synthetic (the shear-flow
+workloads of paper_1004_2416_amd.workloads) and resident in HBM before
+timing.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -40,18 +48,6 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, p), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
-
-
-def collide_stream_kernel(wl, variant: int, storage: str) -> str:
-    """Which collide-stream kernel the library launches for this lattice and
-    variant (IBM_OPT_LBM_VARIANT): with FP16 storage and bits 16 and 32 set,
-    the eight-node row-vector form when nx / 8 lanes divide a wavefront; with
-    bit 16 the four-node row-vector form when a row padded to a multiple of 4
-    has at most 256 values; else the per-node form."""
-    nx = wl.nx
-    if storage == "fp16" and (variant & 48) == 48 and nx % 8 == 0 and 64 % (nx // 8) == 0:
-        return "k_collide_stream_rows8"
-    return "k_collide_stream_rows" if (variant & 16) and (nx + 3) // 4 <= 64 else "k_collide_stream"
 
 
 def measured_traffic(workload: str, storage: str):
@@ -91,9 +87,45 @@ def setup(workload: str, storage: str, graph: bool, variant: int = -1, chunk: in
     return wl, lat
 
 
-def cpu_baseline(wl, seconds: float):
-    """The FP64 oracle on the host cores: whole coupled steps of the same
-    workload from the same initial state, until `seconds` have passed."""
+def prime(stepper, warmup: int):
+    """Warm-up steps, then the steps that make the library capture and
+    instantiate its 16-step graphs for both parities of the step count (a
+    graph is captured on the host the first time it is needed), so that the
+    timed region holds steady-state steps only."""
+    stepper.step(warmup)
+    stepper.step(16)
+    stepper.step(1)
+    stepper.step(16)
+
+
+def timed(stream, stepper, steps: int) -> float:
+    """Milliseconds of `steps` steps between HIP events on the library's
+    stream, device synchronised before and after."""
+    import torch
+    start = torch.cuda.Event(enable_timing=True)
+    end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    stepper.step(steps)
+    end.record(stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(end)
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_leg(wl, seconds: float, nthreads: int):
+    """The FP64 oracle: whole coupled steps of the same workload from the same
+    initial state, after one untimed step (first touch of its arrays), until
+    `seconds` have passed."""
     import numpy as np
     from oracle import oracle as O
 
@@ -111,18 +143,32 @@ def cpu_baseline(wl, seconds: float):
     for z in range(wl.nz):
         ux = wl.u_w * (2 * z + 1 - wl.nz) / wl.nz
         f[:, z] = O.equilibrium(1.0, [ux, 0.0, 0.0])[:, None, None]
-    sim = O.Simulation(f, x, x, np.concatenate(ts), ks, ka, wl.tau, wl.u_w, wl.m)
-    sim.run(1)  # first touch of the arrays
+    sim = O.Simulation(f, x, x, np.concatenate(ts), ks, ka, wl.tau, wl.u_w, wl.m,
+                       nthreads=nthreads)
+    sim.run(1)
     steps, t0 = 0, time.perf_counter()
     while True:
         sim.run(1)
         steps += 1
         dt = time.perf_counter() - t0
-        if dt >= seconds and steps >= 2:
+        if dt >= seconds:
             break
+    threads = nthreads if nthreads > 0 else O.max_threads()
     return {"value": round(wl.n_nodes_lattice * steps / dt / 1e6, 3), "unit": "MLUPS",
-            "cores": O.max_threads(), "kind": "oracle",
-            "sample": f"{steps} full FP64 coupled steps of {wl.name} in {dt:.1f} s"}
+            "cores": threads, "kind": "oracle",
+            "sample": f"{steps} full FP64 coupled steps of {wl.name} in {dt:.1f} s "
+                      f"on {threads} thread(s)"}
+
+
+def cpu_baseline(wl, seconds: float):
+    """The oracle on all host threads (the reported value) and on one thread,
+    each on a bounded sample of the workload's steps."""
+    allt = cpu_leg(wl, seconds, 0)
+    one = cpu_leg(wl, seconds, 1)
+    allt["single_thread"] = {"value": one["value"], "unit": one["unit"], "cores": 1,
+                             "sample": one["sample"]}
+    allt["cpu_model"] = cpu_model()
+    return allt
 
 
 def copy_calibration(mib: int):
@@ -146,12 +192,96 @@ def copy_calibration(mib: int):
                       "copy_ms": round(ms, 4), "copy_GBps": round(2 * n * 4 / (ms * 1e-3) / 1e9, 1)}))
 
 
+def single_leg(args, workload: str, storage: str, roofline: bool):
+    """One lattice workload in the benchmark's launch configuration: warm-up
+    and graph capture, then exactly args.steps timed steps."""
+    wl, lat = setup(workload, storage, not args.no_graph, args.lbm_variant,
+                    args.chunk_nodes, args.stencil_box, args.overlap)
+    tuned = lat.autotune(64) if args.autotune else None
+    split_box = lat.split_box()
+    prime(lat, args.warmup)
+    ms = timed(lat.stream, lat, args.steps)
+    lat.synchronize()
+    mlups = wl.n_nodes_lattice * args.steps / (ms * 1e-3) / 1e6
+    leg = {"workload": wl.name, "storage": storage, "value": round(mlups, 1), "unit": "MLUPS",
+           "ms_per_step": round(ms / args.steps, 5),
+           "step_pct_hbm_roofline": round(100 * mlups * 1e6 * bytes_per_node(storage)
+                                          / (HBM_PEAK_GBS * 1e9), 2),
+           "membrane_node_updates_per_s": round(wl.n_membrane_nodes * args.steps / (ms * 1e-3), 1)}
+    extra = {"wl": wl, "split_box": list(split_box), "tuned": tuned}
+    if roofline:
+        # per-phase durations from HIP events between the kernels on the
+        # library's stream, then the collide-stream kernel's own duration
+        # from the start and end timestamps of its dispatches
+        extra["phases"] = lat.profile(args.profile_steps)
+        extra["k1_ms"] = lat.lattice_kernel_ms(args.profile_steps)
+        extra["D"] = lat.observables()[:4, 4]
+    lat.close()
+    return leg, extra
+
+
+def batch_leg(args, storage: str, with_single: bool = False):
+    """The batched sweep: 64 independent single-capsule runs of uneven size,
+    capillary number and delta width advanced together (one launch per kernel
+    of the step for all runs)."""
+    import torch
+    from paper_1004_2416_amd import binding as B
+    from paper_1004_2416_amd import workloads as W
+
+    wls = W.sweep_workloads()
+    lats = []
+    for wl in wls:
+        lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau, storage=storage)
+        lat.set_shear(wl.u_w, init_profile=True)
+        c = wl.capsules[0]
+        lat.add_capsules([B.icosphere(c.level, c.r, c.center)], [c.ks], [c.ka], wl.m)
+        if args.stencil_box >= 0:
+            lat.set_option(B.OPT_STENCIL_BOX, args.stencil_box)
+        lats.append(lat)
+    batch = B.Batch(lats)
+    stream = lats[0].stream
+    n_lat = sum(w.n_nodes_lattice for w in wls)
+    n_mem = sum(w.n_membrane_nodes for w in wls)
+    prime(batch, args.warmup)
+    ms = timed(stream, batch, args.steps)
+    mlups = n_lat * args.steps / (ms * 1e-3) / 1e6
+    leg = {"workload": "batched_sweep_64runs", "storage": storage, "value": round(mlups, 1),
+           "unit": "MLUPS", "ms_per_step": round(ms / args.steps, 5),
+           "step_pct_hbm_roofline": round(100 * mlups * 1e6 * bytes_per_node(storage)
+                                          / (HBM_PEAK_GBS * 1e9), 2),
+           "membrane_node_updates_per_s": round(n_mem * args.steps / (ms * 1e-3), 1)}
+    extra = {"wls": wls, "n_lat": n_lat, "n_mem": n_mem}
+    if with_single:
+        # the same runs, each stepped on its own (its own graphs, captured
+        # before the timed region) for comparison
+        for lat in lats:
+            prime(lat, 0)
+        torch.cuda.synchronize()
+        k_single = max(16, (args.steps // 10) // 16 * 16)
+        import torch as _t
+        e0, e1 = _t.cuda.Event(enable_timing=True), _t.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for lat in lats:
+            lat.step(k_single)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        leg["unbatched_mlups"] = round(n_lat * k_single / (e0.elapsed_time(e1) * 1e-3) / 1e6, 1)
+        leg["batched_speedup"] = round(mlups / leg["unbatched_mlups"], 3)
+        extra["phases"] = batch.profile(args.profile_steps)
+        extra["k1_ms"] = batch.lattice_kernel_ms(args.profile_steps)
+        extra["D"] = [float(lat.observables()[0, 4]) for lat in lats[:4]]
+    batch.close()
+    for lat in lats:
+        lat.close()
+    return leg, extra
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10000)
-    ap.add_argument("--warmup", type=int, default=1000)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"],
+    ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--warmup", type=int, default=400)
+    ap.add_argument("--workload", default="c3", choices=["c1", "c2", "c3", "c4", "c5"],
                     help="c4: the batched sweep of 64 independent runs")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
     ap.add_argument("--no-graph", action="store_true")
@@ -171,8 +301,10 @@ def main():
                     help="collide-stream launch variant (IBM_OPT_LBM_VARIANT bits; "
                          "-1: the library default)")
     ap.add_argument("--profile-steps", type=int, default=400)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="time only the chosen workload (no FP16 / batched comparison legs)")
     ap.add_argument("--copy-calibration-mib", type=int, default=0)
     args = ap.parse_args()
 
@@ -185,88 +317,80 @@ def main():
     if args.copy_calibration_mib:
         copy_calibration(args.copy_calibration_mib)
         return
-
-    if args.workload == "c4":
-        run_batch(args)
-        return
     if args.sensitivity:
         run_sensitivity(args)
         return
 
-    import torch
-    wl, lat = setup(args.workload, args.storage, not args.no_graph, args.lbm_variant,
-                    args.chunk_nodes, args.stencil_box, args.overlap)
-    stream = lat.stream
-    tuned = lat.autotune(64) if args.autotune else None
-    split_box = lat.split_box()
-    lat.step(args.warmup)
-    lat.synchronize()
-
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    start.record(stream)
-    lat.step(args.steps)
-    end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    lat.synchronize()
-    ms = start.elapsed_time(end)
-    ms_per_step = ms / args.steps
-    mlups = wl.n_nodes_lattice * args.steps / (ms * 1e-3) / 1e6
-
-    # per-phase durations from HIP events between the kernels on the library's
-    # stream, then the collide-stream kernel's own duration from the start and
-    # end timestamps of its dispatches (what rocprofv3 reports for it)
-    phases = lat.profile(args.profile_steps)
-    k1_ms = lat.lattice_kernel_ms(args.profile_steps)
-    algo = bytes_per_node(args.storage) * wl.n_nodes_lattice
-    achieved = algo / (k1_ms * 1e-3) / 1e9
-    obs = lat.observables()
-    lat.close()
-
+    t_wall = time.perf_counter()
+    if args.workload == "c4":
+        head, ex = batch_leg(args, args.storage, with_single=True)
+        n_nodes = ex["n_lat"]
+        config = {"workload": "batched_sweep_64runs", "runs": len(ex["wls"]),
+                  "lattice_nodes": ex["n_lat"], "membrane_nodes": ex["n_mem"],
+                  "storage": args.storage, "run_sizes": sorted({w.nx for w in ex["wls"]}),
+                  "delta_widths": sorted({w.m for w in ex["wls"]}),
+                  "stencil_box": args.stencil_box}
+        kernel = "k_batch_collide_stream"
+        traffic_key = "batched_sweep_64runs"
+    else:
+        head, ex = single_leg(args, args.workload, args.storage, roofline=True)
+        wl = ex["wl"]
+        n_nodes = wl.n_nodes_lattice
+        config = {"workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz,
+                  "capsules": len(wl.capsules), "membrane_nodes": wl.n_membrane_nodes,
+                  "delta_width": wl.m, "storage": args.storage, "graph": not args.no_graph,
+                  "u_w": wl.u_w, "tau": wl.tau, "lbm_variant": args.lbm_variant,
+                  "chunk_nodes": args.chunk_nodes, "stencil_box": args.stencil_box,
+                  "overlap": args.overlap, "split_box": ex["split_box"],
+                  "autotuned": ex["tuned"]}
+        kernel = "k_collide_stream_rows"
+        traffic_key = wl.name
+    algo = bytes_per_node(args.storage) * n_nodes
+    achieved = algo / (ex["k1_ms"] * 1e-3) / 1e9
     out = {
         "metric": METRIC,
-        "value": round(mlups, 1),
+        "value": head["value"],
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 5),
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {
-            "workload": wl.name, "nx": wl.nx, "ny": wl.ny, "nz": wl.nz,
-            "capsules": len(wl.capsules), "membrane_nodes": wl.n_membrane_nodes,
-            "delta_width": wl.m, "storage": args.storage, "graph": not args.no_graph,
-            "u_w": wl.u_w, "tau": wl.tau, "lbm_variant": args.lbm_variant,
-            "chunk_nodes": args.chunk_nodes, "stencil_box": args.stencil_box,
-            "overlap": args.overlap, "split_box": list(split_box), "autotuned": tuned,
-        },
-        "membrane_node_updates_per_s": round(wl.n_membrane_nodes * args.steps / (ms * 1e-3), 1),
-        "step_pct_hbm_roofline": round(100 * mlups * 1e6 * bytes_per_node(args.storage)
-                                       / (HBM_PEAK_GBS * 1e9), 2),
-        "phase_ms": {k: round(v, 5) for k, v in phases.items()},
-        "wall_s": round(wall, 3),
-        "D_final": [round(float(d), 6) for d in obs[:4, 4]],
+        "config": config,
+        "membrane_node_updates_per_s": head["membrane_node_updates_per_s"],
+        "step_pct_hbm_roofline": head["step_pct_hbm_roofline"],
+        "phase_ms": {k: round(v, 5) for k, v in ex["phases"].items()},
+        "D_final": [round(float(d), 6) for d in ex["D"]],
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(wl.name, args.storage),
-            "kernel": collide_stream_kernel(wl, args.lbm_variant if args.lbm_variant >= 0
-                                            else (tuned or {}).get("lbm_variant", 23),
-                                            args.storage),
+            "traffic": measured_traffic(traffic_key, args.storage),
+            "kernel": kernel,
             "algorithmic_bytes_per_launch": algo,
-            "kernel_us": round(k1_ms * 1e3, 2),
+            "kernel_us": round(ex["k1_ms"] * 1e3, 2),
             "launches_timed": args.profile_steps,
         },
     }
+    for k in ("unbatched_mlups", "batched_speedup"):
+        if k in head:
+            out[k] = head[k]
+    if not args.no_legs and args.workload == "c3" and args.storage == "fp32":
+        # the comparisons the metric names, timed the same way: FP16
+        # population storage on the same workload, and the batched sweep with
+        # FP32 and FP16 storage (aggregate over its 64 runs)
+        legs = {}
+        legs["c3_fp16"], _ = single_leg(args, "c3", "fp16", roofline=False)
+        legs["c4_batched_fp32"], _ = batch_leg(args, "fp32")
+        legs["c4_batched_fp16"], _ = batch_leg(args, "fp16")
+        out["legs"] = legs
+    out["wall_s"] = round(time.perf_counter() - t_wall, 1)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_seconds)
+        base_wl = ex["wls"][0] if args.workload == "c4" else ex["wl"]
+        out["cpu_baseline"] = cpu_baseline(base_wl, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 
@@ -326,102 +450,6 @@ def run_sensitivity(args):
                                "cores": base["cores"], "kind": "oracle",
                                "sample": "six FP64 oracle runs of %d steps (central differences), "
                                          "scaled from %s" % (args.steps, base["sample"])}
-    print(json.dumps(out), flush=True)
-
-
-def run_batch(args):
-    """The batched sweep: 64 independent single-capsule runs of uneven size,
-    capillary number and delta width advanced together (one launch per
-    kernel of the step for all runs), against the same runs stepped one
-    after another."""
-    import torch
-    from paper_1004_2416_amd import binding as B
-    from paper_1004_2416_amd import workloads as W
-
-    wls = W.sweep_workloads()
-    lats = []
-    for wl in wls:
-        lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau, storage=args.storage)
-        lat.set_shear(wl.u_w, init_profile=True)
-        c = wl.capsules[0]
-        lat.add_capsules([B.icosphere(c.level, c.r, c.center)], [c.ks], [c.ka], wl.m)
-        if args.stencil_box >= 0:
-            lat.set_option(B.OPT_STENCIL_BOX, args.stencil_box)
-        lats.append(lat)
-    batch = B.Batch(lats)
-    stream = lats[0].stream
-    n_lat = sum(w.n_nodes_lattice for w in wls)
-    n_mem = sum(w.n_membrane_nodes for w in wls)
-    batch.step(args.warmup)
-    torch.cuda.synchronize()
-
-    start = torch.cuda.Event(enable_timing=True)
-    end = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    start.record(stream)
-    batch.step(args.steps)
-    end.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    for lat in lats:
-        lat.synchronize()
-    ms = start.elapsed_time(end)
-    mlups = n_lat * args.steps / (ms * 1e-3) / 1e6
-
-    # the same runs, each stepped on its own (its own graphs), for comparison
-    k_single = max(16, (args.steps // 10) // 16 * 16)
-    start.record(stream)
-    for lat in lats:
-        lat.step(k_single)
-    end.record(stream)
-    torch.cuda.synchronize()
-    mlups_single = n_lat * k_single / (start.elapsed_time(end) * 1e-3) / 1e6
-
-    phases = batch.profile(args.profile_steps)
-    k1_ms = batch.lattice_kernel_ms(args.profile_steps)
-    algo = bytes_per_node(args.storage) * n_lat
-    achieved = algo / (k1_ms * 1e-3) / 1e9
-    D = [float(lat.observables()[0, 4]) for lat in lats[:4]]
-    batch.close()
-    for lat in lats:
-        lat.close()
-    out = {
-        "metric": METRIC,
-        "value": round(mlups, 1),
-        "unit": "MLUPS",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms / args.steps, 5),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {
-            "workload": "batched_sweep_64runs", "runs": len(wls), "lattice_nodes": n_lat,
-            "membrane_nodes": n_mem, "storage": args.storage,
-            "run_sizes": sorted({w.nx for w in wls}), "delta_widths": sorted({w.m for w in wls}),
-            "stencil_box": args.stencil_box,
-        },
-        "unbatched_mlups": round(mlups_single, 1),
-        "batched_speedup": round(mlups / mlups_single, 3),
-        "membrane_node_updates_per_s": round(n_mem * args.steps / (ms * 1e-3), 1),
-        "step_pct_hbm_roofline": round(100 * mlups * 1e6 * bytes_per_node(args.storage)
-                                       / (HBM_PEAK_GBS * 1e9), 2),
-        "phase_ms": {k: round(v, 5) for k, v in phases.items()},
-        "wall_s": round(wall, 3),
-        "D_final": [round(d, 6) for d in D],
-        "roofline": {
-            "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic("batched_sweep_64runs", args.storage),
-            "kernel": "k_batch_collide_stream", "algorithmic_bytes_per_launch": algo,
-            "kernel_us": round(k1_ms * 1e3, 2), "launches_timed": args.profile_steps,
-        },
-    }
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wls[0], args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

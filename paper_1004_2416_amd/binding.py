@@ -42,6 +42,11 @@ class IBMError(RuntimeError):
 
 
 def _load():
+    # PyTorch ships its own HIP runtime; the library must bind to that same
+    # runtime (one per process), so torch is imported before the library is
+    # loaded.  Loaded the other way round (the system runtime first), the
+    # library's first call on the device failed with "no ROCm-capable device".
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python paper_1004_2416_amd/build.py` "

@@ -162,8 +162,9 @@ struct ibm_lattice {
   bool have_prev_u = false;
   int64_t since_recenter = 0;
 
-  hipGraphExec_t gexec = nullptr;
-  bool graph_valid = false;
+  // 16-step graphs, one per parity of the step count at which they start
+  // (the buffer each step reads is fixed in the captured launches)
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
 
   // IBM_OPT_OVERLAP: the lattice update of graph-replayed steps split into the
   // force slab L.zlo <= z < L.zhi and the rest, which rides along with the
@@ -192,20 +193,27 @@ void set_variant(ibm_lattice *lat, int v) {
 }
 
 void invalidate_graph(ibm_lattice *lat) {
-  if (lat->gexec) (void)hipGraphExecDestroy(lat->gexec);
-  lat->gexec = nullptr;
-  lat->graph_valid = false;
+  for (hipGraphExec_t &g : lat->gexec) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
   lat->slab_stale = true;
 }
 
-// Clear the control words, the tile stamps and both force fields.
-void reset_force_state(ibm_lattice *lat, hipStream_t s) {
-  ibm::launch_fill_u32(lat->base + lat->lay.off_ctrl, sizeof(ibm::Ctrl) / 4, 0u, s);
+// Clear the tile stamps and both force fields (they hold nothing between
+// steps that the next step needs: its spreading writes its own field).
+void clear_force_fields(ibm_lattice *lat, hipStream_t s) {
   const long long tiles = (long long)lat->lay.tnx * lat->lay.tny * lat->lay.tnz;
   for (int k = 0; k < 2; ++k) {
     ibm::launch_fill_u32(lat->L.stamp[k], tiles, (uint32_t)(-100), s);
     ibm::launch_fill_u32(lat->L.g[k], 3 * lat->lay.S, 0u, s);
   }
+}
+
+// Clear the control words, the tile stamps and both force fields.
+void reset_force_state(ibm_lattice *lat, hipStream_t s) {
+  ibm::launch_fill_u32(lat->base + lat->lay.off_ctrl, sizeof(ibm::Ctrl) / 4, 0u, s);
+  clear_force_fields(lat, s);
 }
 
 // Interpolation mode of the coupling kernels (launch_interp_advect) for an
@@ -321,6 +329,11 @@ int refresh_slab(ibm_lattice *lat) {
     L.ylo = ylo;
     L.yhi = yhi;
     invalidate_graph(lat);
+    // Rows outside a slab take the force-free update, which neither reads
+    // nor clears the force field.  A tile the last step stamped outside the
+    // new slab would keep its force under that stamp, and a later spreading
+    // into it would add onto it: start the fields afresh.
+    clear_force_fields(lat, lat->stream);
   }
   lat->slab_stale = false;
   return IBM_OK;
@@ -358,8 +371,11 @@ void enqueue_steps_split(ibm_lattice *lat, hipStream_t s, int nsteps, int advect
   }
 }
 
+// Capture the graph for the current parity of the step count.
 int capture_graph(ibm_lattice *lat) {
-  invalidate_graph(lat);
+  const int p = (int)(lat->steps & 1);
+  if (lat->gexec[p]) (void)hipGraphExecDestroy(lat->gexec[p]);
+  lat->gexec[p] = nullptr;
   if (!lat->cap_stream) IBM_HIP(hipStreamCreateWithFlags(&lat->cap_stream, hipStreamNonBlocking));
   const int64_t saved_steps = lat->steps, saved_since = lat->since_recenter;
   hipGraph_t graph = nullptr;
@@ -373,13 +389,12 @@ int capture_graph(ibm_lattice *lat) {
   lat->steps = saved_steps;
   lat->since_recenter = saved_since;
   if (e != hipSuccess) return fail(IBM_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&lat->gexec, graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&lat->gexec[p], graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
-    lat->gexec = nullptr;
+    lat->gexec[p] = nullptr;
     return fail(IBM_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
   }
-  lat->graph_valid = true;
   return IBM_OK;
 }
 
@@ -531,9 +546,10 @@ struct ibm_batch {
   size_t cap_lat = 0, cap_node = 0;  // work-item capacities
   ibm::BatchDev B{};
   std::vector<char> image;  // host copy of the device tables last uploaded
-  hipGraphExec_t gexec = nullptr;
-  bool graph_valid = false;
-  int graph_advect = -1, graph_linear = -1, graph_box = -1;  // options the graph was captured with
+  // 16-step graphs per parity of the step count, and the options each was
+  // captured with
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  int graph_advect[2] = {-1, -1}, graph_linear[2] = {-1, -1}, graph_box[2] = {-1, -1};
   int box_mode = 0;  // stencil-box mode of the batched coupling kernels
 };
 
@@ -593,9 +609,10 @@ bool batch_prev_u(const ibm_batch *b) {
 }
 
 void batch_invalidate_graph(ibm_batch *b) {
-  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
-  b->gexec = nullptr;
-  b->graph_valid = false;
+  for (hipGraphExec_t &g : b->gexec) {
+    if (g) (void)hipGraphExecDestroy(g);
+    g = nullptr;
+  }
 }
 
 // Check that the runs can step together and bring the device tables up to
@@ -673,7 +690,9 @@ void enqueue_batch_step(ibm_batch *b, hipStream_t s, int advect) {
 }
 
 int batch_capture_graph(ibm_batch *b, int advect) {
-  batch_invalidate_graph(b);
+  const int p = (int)(b->runs[0]->steps & 1);
+  if (b->gexec[p]) (void)hipGraphExecDestroy(b->gexec[p]);
+  b->gexec[p] = nullptr;
   if (!b->cap_stream) IBM_HIP(hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking));
   std::vector<int64_t> steps, since;
   for (ibm_lattice *lat : b->runs) {
@@ -689,16 +708,15 @@ int batch_capture_graph(ibm_batch *b, int advect) {
     b->runs[r]->since_recenter = since[r];
   }
   if (e != hipSuccess) return fail(IBM_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
-  e = hipGraphInstantiate(&b->gexec, graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(&b->gexec[p], graph, nullptr, nullptr, 0);
   (void)hipGraphDestroy(graph);
   if (e != hipSuccess) {
-    b->gexec = nullptr;
+    b->gexec[p] = nullptr;
     return fail(IBM_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
   }
-  b->graph_valid = true;
-  b->graph_advect = advect;
-  b->graph_linear = b->runs[0]->eq_linear;
-  b->graph_box = b->box_mode;
+  b->graph_advect[p] = advect;
+  b->graph_linear[p] = b->runs[0]->eq_linear;
+  b->graph_box[p] = b->box_mode;
   return IBM_OK;
 }
 
@@ -1004,7 +1022,13 @@ int ibm_step(ibm_lattice *lat, int64_t n) {
   if (lat->has_tan && lat->ab2)
     return fail(IBM_ERR_BAD_STATE, "the tangent model follows Euler advection only");
   while (n > 0) {
-    if (lat->has_mem && lat->since_recenter >= lat->recenter_every) {
+    const bool want_graph = lat->use_graph && n >= GRAPH_STEPS && (!lat->ab2 || lat->have_prev_u);
+    // Re-centre when due, or early when the next graph would run past the
+    // interval (re-centring only changes the frame, so earlier is harmless):
+    // every graph launch then fits.
+    if (lat->has_mem && (lat->since_recenter >= lat->recenter_every ||
+                         (want_graph && lat->since_recenter > 0 &&
+                          lat->since_recenter + GRAPH_STEPS > lat->recenter_every))) {
       ibm::launch_recenter(lat->M, lat->stream);
       lat->since_recenter = 0;
       if (lat->overlap) lat->slab_stale = true;
@@ -1013,15 +1037,15 @@ int ibm_step(ibm_lattice *lat, int64_t n) {
       int rc = refresh_slab(lat);
       if (rc) return rc;
     }
-    const bool graph_ok = lat->use_graph && (lat->steps & 1) == 0 && n >= GRAPH_STEPS &&
-                          (!lat->has_mem || lat->since_recenter + GRAPH_STEPS <= lat->recenter_every) &&
-                          (!lat->ab2 || lat->have_prev_u);
+    const bool graph_ok =
+        want_graph && (!lat->has_mem || lat->since_recenter + GRAPH_STEPS <= lat->recenter_every);
     if (graph_ok) {
-      if (!lat->graph_valid) {
+      const int p = (int)(lat->steps & 1);
+      if (!lat->gexec[p]) {
         int rc = capture_graph(lat);
         if (rc) return rc;
       }
-      IBM_HIP(hipGraphLaunch(lat->gexec, lat->stream));
+      IBM_HIP(hipGraphLaunch(lat->gexec[p], lat->stream));
       lat->steps += GRAPH_STEPS;
       lat->since_recenter += GRAPH_STEPS;
       n -= GRAPH_STEPS;
@@ -1733,24 +1757,30 @@ int ibm_batch_step(ibm_batch *b, int64_t n) {
   if (rc) return rc;
   ibm_lattice *r0 = b->runs[0];
   while (n > 0) {
+    const bool prev = batch_prev_u(b);
+    const bool want_graph = n >= GRAPH_STEPS && (!r0->ab2 || prev);
     bool room = true;
     for (ibm_lattice *lat : b->runs) {
-      if (lat->has_mem && lat->since_recenter >= lat->recenter_every) {
+      // due, or early so that the next graph fits (as in ibm_step)
+      if (lat->has_mem && (lat->since_recenter >= lat->recenter_every ||
+                           (want_graph && lat->since_recenter > 0 &&
+                            lat->since_recenter + GRAPH_STEPS > lat->recenter_every))) {
         ibm::launch_recenter(lat->M, b->stream);
         lat->since_recenter = 0;
+        if (lat->overlap) lat->slab_stale = true;  // for the run's own later steps
       }
       if (lat->has_mem && lat->since_recenter + GRAPH_STEPS > lat->recenter_every) room = false;
     }
-    const bool prev = batch_prev_u(b);
     const int advect = (r0->ab2 && prev) ? 1 : 0;
-    const bool graph_ok = (r0->steps & 1) == 0 && n >= GRAPH_STEPS && room && (!r0->ab2 || prev);
+    const bool graph_ok = want_graph && room;
     if (graph_ok) {
-      if (!b->graph_valid || b->graph_advect != advect || b->graph_linear != r0->eq_linear ||
-          b->graph_box != b->box_mode) {
+      const int p = (int)(r0->steps & 1);
+      if (!b->gexec[p] || b->graph_advect[p] != advect || b->graph_linear[p] != r0->eq_linear ||
+          b->graph_box[p] != b->box_mode) {
         rc = batch_capture_graph(b, advect);
         if (rc) return rc;
       }
-      IBM_HIP(hipGraphLaunch(b->gexec, b->stream));
+      IBM_HIP(hipGraphLaunch(b->gexec[p], b->stream));
       for (ibm_lattice *lat : b->runs) {
         lat->steps += GRAPH_STEPS;
         lat->since_recenter += GRAPH_STEPS;
@@ -1787,6 +1817,7 @@ static int batch_profile_steps(ibm_batch *b, int64_t n, double *ms_per_phase, do
       if (lat->has_mem && lat->since_recenter >= lat->recenter_every) {
         ibm::launch_recenter(lat->M, s);
         lat->since_recenter = 0;
+        if (lat->overlap) lat->slab_stale = true;
       }
     hipEvent_t *e = &ev[(size_t)k * 4];
     const int src = (int)(r0->steps & 1), par = src;

@@ -389,6 +389,39 @@ def test_split_update_falls_back(B):
     lat.close()
 
 
+def test_split_update_after_the_mesh_moves(B):
+    """The split update with the membrane moved by ibm_set_mesh far enough
+    that the force slab changes: the rows outside the new slab take the
+    force-free update, so tiles the previous step stamped there must not keep
+    their force field.  Move up by 14 lattice spacings, step, move back,
+    step; the oracle makes the same moves."""
+    nx, ny, nz, uw, r = 24, 40, 64, 0.02, 4.0
+    ks = W.ks_from_capillary(0.05, uw, nz, r)
+    c = Case(W.Workload("tall", nx, ny, nz, 1.0, uw, 3, 0,
+                        [W.CapsuleSpec(2, r, (11.7, 19.6, 31.8), ks, ks)]), perturb=0.01, seed=5)
+    lat = c.gpu(graph=True)
+    lat.set_option(B.OPT_OVERLAP, 2)
+    sim = c.oracle()
+    lat.step(33)
+    assert sim.run(33) == 0
+    boxes = [lat.split_box()]
+    for dz in (14.0, -14.0):
+        xn = rep_positions(sim.x + np.array([0.0, 0.0, dz]), c.node_counts)
+        lat.set_mesh(xn)
+        sim.x[:] = xn
+        lat.step(40)
+        assert sim.run(40) == 0
+        boxes.append(lat.split_box())
+        f = lat.populations().cpu().numpy()
+        xg = lat.mesh()[0].cpu().numpy()
+        ef, ex = rel_err(f, sim.f), float(np.max(np.abs(xg - sim.x)))
+        say("  moved by %+g: slab %s  f %.2e  x %.2e" % (dz, boxes[-1], ef, ex))
+        assert ef < 1e-5 and ex < 1e-4
+    # the slab did follow the membrane up and back
+    assert boxes[1][0] > boxes[0][0] and boxes[2][0] < boxes[1][0]
+    lat.close()
+
+
 def test_adams_bashforth_and_linear_equilibrium(B):
     """The two variants of the method the paper tests: second-order
     advection (Sec. II.C) and the linearised equilibrium (Sec. IV.A)."""
