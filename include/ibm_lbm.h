@@ -256,6 +256,21 @@ int ibm_set_mesh(ibm_lattice *lat, const double *xyz_host);
  * FP64, from FP64 reductions on the device; waits. */
 int ibm_observables(ibm_lattice *lat, double *out_host);
 
+/* FP64 totals of the current populations over the whole lattice
+ * (Sec. II.A, Eqs. lbmmomenta0/1 summed over all nodes):
+ *   out_dev[0] = sum_X sum_i f_i(X)          (mass)
+ *   out_dev[1..3] = sum_X sum_i c_i f_i(X)   (momentum of the populations,
+ *                                              without the half-force term)
+ * The stored FP32 (or FP16) values are converted exactly and summed in FP64
+ * in a fixed order, so the same state gives the same bits.  out_dev is a
+ * caller device buffer of 4 doubles (8-byte aligned); work_dev a caller
+ * device buffer of at least ibm_totals_bytes bytes (32-byte aligned) for the
+ * partial sums, free again when the stream has run the call.  Enqueued on the
+ * lattice's stream; does not wait.  Errors: IBM_ERR_INVALID_ARG for NULL,
+ * misaligned or too small buffers. */
+int ibm_totals_bytes(const ibm_lattice *lat, size_t *bytes);
+int ibm_lattice_totals(ibm_lattice *lat, void *work_dev, size_t work_bytes, double *out_dev);
+
 /* Wait for the stream; report device-side error flags. */
 int ibm_synchronize(ibm_lattice *lat);
 

@@ -68,6 +68,8 @@ def _load():
         "ibm_set_mesh": ([v, v], i),
         "ibm_observables": ([v, v], i),
         "ibm_synchronize": ([v], i),
+        "ibm_totals_bytes": ([v, ctypes.POINTER(sz)], i),
+        "ibm_lattice_totals": ([v, v, sz, v], i),
         "ibm_set_option": ([v, i, i], i),
         "ibm_split_box": ([v, ctypes.POINTER(i)], i),
         "ibm_profile_step": ([v, i64, v], i),
@@ -268,6 +270,19 @@ class Lattice:
         xyz = np.ascontiguousarray(xyz, dtype=np.float64)
         assert xyz.shape == (self.nn, 3)
         _check(lib.ibm_set_mesh(self._h, _ptr(xyz)))
+
+    def totals(self) -> np.ndarray:
+        """FP64 (mass, momentum x, y, z) of the current populations, summed on
+        the device (ibm_lattice_totals)."""
+        torch = _torch()
+        nb = ctypes.c_size_t()
+        _check(lib.ibm_totals_bytes(self._h, ctypes.byref(nb)))
+        work = torch.empty(max(nb.value // 8, 1), dtype=torch.float64, device=self.device)
+        out = torch.empty(4, dtype=torch.float64, device=self.device)
+        _check(lib.ibm_lattice_totals(self._h, ctypes.c_void_p(work.data_ptr()), nb.value,
+                                      ctypes.c_void_p(out.data_ptr())))
+        self.synchronize()
+        return out.cpu().numpy()
 
     def observables(self) -> np.ndarray:
         out = np.zeros((self.n_caps, OBS_N))

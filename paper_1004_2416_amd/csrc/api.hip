@@ -1119,6 +1119,25 @@ int ibm_observables(ibm_lattice *lat, double *out_host) {
   return rc ? rc : ok();
 }
 
+int ibm_totals_bytes(const ibm_lattice *lat, size_t *bytes) {
+  if (!lat || !bytes) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  *bytes = (size_t)ibm::totals_parts(lat->L) * sizeof(double4);
+  return ok();
+}
+
+int ibm_lattice_totals(ibm_lattice *lat, void *work_dev, size_t work_bytes, double *out_dev) {
+  if (!lat || !work_dev || !out_dev) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  const size_t need = (size_t)ibm::totals_parts(lat->L) * sizeof(double4);
+  if (work_bytes < need)
+    return fail(IBM_ERR_INVALID_ARG, "work_dev has %zu bytes, %zu needed", work_bytes, need);
+  if (((uintptr_t)work_dev) % 32 || ((uintptr_t)out_dev) % 8)
+    return fail(IBM_ERR_INVALID_ARG, "work_dev must be 32-byte and out_dev 8-byte aligned");
+  ibm::launch_totals(lat->L, lat->storage, (int)(lat->steps & 1), static_cast<double4 *>(work_dev),
+                     out_dev, lat->stream);
+  IBM_HIP(hipGetLastError());
+  return ok();
+}
+
 int ibm_synchronize(ibm_lattice *lat) {
   if (!lat) return fail(IBM_ERR_INVALID_ARG, "lat is NULL");
   int rc = check_device(lat);

@@ -162,6 +162,10 @@ struct BatchDev {
 // in LDS when it has at most SPREAD_BOX_CELLS (spreading, three force
 // components in a 1024-thread block) or BOX_CELLS (interpolation) nodes.
 constexpr int CHUNK_MIN = 16, CHUNK_MAX = 1024;
+
+// Lattice totals (ibm_lattice_totals): one FP64 partial sum (mass deviation,
+// momentum) per TOTALS_NODES consecutive lattice nodes.
+constexpr int TOTALS_NODES = 4096;
 constexpr int BOX_CELLS = 4096;
 constexpr int SPREAD_BOX_CELLS = 9000;
 

@@ -29,6 +29,10 @@ void launch_get_field(const LatDev &L, int fp16, int src, int gpar, int what, do
                       hipStream_t s);
 void launch_set_pops(const LatDev &L, int fp16, int dst, const double *in, hipStream_t s);
 void launch_fill_u32(void *p, long long n, uint32_t v, hipStream_t s);
+// FP64 mass and momentum of the populations in buffer src into out[4] (device),
+// with totals_parts(L) partial sums in part (device)
+int totals_parts(const LatDev &L);
+void launch_totals(const LatDev &L, int fp16, int src, double4 *part, double *out, hipStream_t s);
 void launch_tangent_collide_stream(const LatDev &L, const TanDev &T, int src, int par, bool linear,
                                    hipStream_t s);
 void launch_tangent_init(const LatDev &L, const TanDev &T, int dst, int profile, int linear,

@@ -898,6 +898,99 @@ void launch_batch_collide_stream(const BatchDev &B, int fp16, int src, int par, 
   }
 }
 
+// ---- FP64 lattice totals, Eqs. (lbmmomenta0/1) summed over all nodes ---------
+// Mass sum_X sum_i f_i and momentum sum_X sum_i c_i f_i of the populations in
+// buffer src.  Block b sums nodes [b TOTALS_NODES, (b + 1) TOTALS_NODES) of
+// the lattice order n = (z ny + y) nx + x in FP64 and writes its partial
+// (sum of the deviations f_i - w_i, momentum) to part[b]; one block then adds
+// the partials.  Every sum runs in a fixed order, so a state always gives the
+// same bits.  The stored values are converted exactly: FP32 deviations, or
+// FP16 values divided by their power-of-two-times-integer scale in FP64.
+template <typename T>
+__device__ __forceinline__ double stored_deviation(const T *f, long long idx, float scale);
+template <>
+__device__ __forceinline__ double stored_deviation<float>(const float *f, long long idx, float) {
+  return (double)f[idx];
+}
+template <>
+__device__ __forceinline__ double stored_deviation<__half>(const __half *f, long long idx,
+                                                           float scale) {
+  return (double)__half2float(f[idx]) / (double)scale;
+}
+
+__device__ __forceinline__ void block_sum4(double (&v)[4]) {
+  __shared__ double red[4][256];
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) red[c][t] = v[c];
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) red[c][t] += red[c][t + h];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) v[c] = red[c][0];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_totals_partial(LatDev L, int src, double4 *part) {
+  const long long N = (long long)L.nx * L.ny * L.nz;
+  const long long n0 = (long long)blockIdx.x * TOTALS_NODES;
+  const T *f = static_cast<const T *>(L.f[src]);
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < TOTALS_NODES; k += blockDim.x) {
+    const long long n = n0 + k;
+    if (n >= N) break;
+    const long long row = n / L.nx;
+    const int x = (int)(n - row * L.nx);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const double d = stored_deviation<T>(f, pidx_c(L, i, row, x), L.h_scale[i]);
+      v[0] += d;
+      if (cx(i)) v[1] += cx(i) * d;
+      if (cy(i)) v[2] += cy(i) * d;
+      if (cz(i)) v[3] += cz(i) * d;
+    }
+  }
+  block_sum4(v);
+  if (threadIdx.x == 0) part[blockIdx.x] = make_double4(v[0], v[1], v[2], v[3]);
+}
+
+// out[0] = N + sum of the partial mass deviations (sum_i w_i = 1 per node),
+// out[1..3] = momentum (sum_i c_i w_i = 0)
+__global__ __launch_bounds__(256) void k_totals_final(const double4 *part, int nparts, long long N,
+                                                      double *out) {
+  double v[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < nparts; k += blockDim.x) {
+    const double4 p = part[k];
+    v[0] += p.x;
+    v[1] += p.y;
+    v[2] += p.z;
+    v[3] += p.w;
+  }
+  block_sum4(v);
+  if (threadIdx.x == 0) {
+    out[0] = (double)N + v[0];
+    out[1] = v[1];
+    out[2] = v[2];
+    out[3] = v[3];
+  }
+}
+
+int totals_parts(const LatDev &L) {
+  const long long N = (long long)L.nx * L.ny * L.nz;
+  return (int)((N + TOTALS_NODES - 1) / TOTALS_NODES);
+}
+
+void launch_totals(const LatDev &L, int fp16, int src, double4 *part, double *out, hipStream_t s) {
+  const int np = totals_parts(L);
+  if (fp16) k_totals_partial<__half><<<dim3(np), dim3(256), 0, s>>>(L, src, part);
+  else k_totals_partial<float><<<dim3(np), dim3(256), 0, s>>>(L, src, part);
+  k_totals_final<<<dim3(1), dim3(256), 0, s>>>(part, np, (long long)L.nx * L.ny * L.nz, out);
+}
+
 // ---- fills (no hipMemset, so that the same code can be captured) --------------
 __global__ __launch_bounds__(256) void k_fill_u32(uint32_t *p, long long n, uint32_t v) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;

@@ -132,11 +132,15 @@ def test_fp16_trajectory_c1(B):
     Dg, Do = np.array(Dg), np.array(Do)
     xg = lat.mesh()[0].cpu().numpy()
     f_g = lat.populations().cpu().numpy()
+    # the mass from the library's own FP64 reduction on the device, which
+    # must also agree with the sum of the downloaded populations
+    mass = float(lat.totals()[0])
     lat.close()
+    assert abs(mass - float(np.sum(f_g))) < 1e-10 * m0
     eD = float(np.max(np.abs(Dg - Do)) / np.max(np.abs(Do)))
     ex = float(np.max(np.abs(xg - sim.x)))
     ef = dev_err(f_g, sim.f)
-    em = abs(float(np.sum(f_g)) - m0) / m0
+    em = abs(mass - m0) / m0
     say("  fp16 c1 1000 steps: D %.2e (D_end %.4f vs %.4f)  x %.2e  f_dev %.2e  mass %.2e"
         % (eD, Dg[-1], Do[-1], ex, ef, em))
     assert eD < 1e-2

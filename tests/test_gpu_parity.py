@@ -545,6 +545,56 @@ def test_observables_match_oracle(B):
     lat.close()
 
 
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_lattice_totals(B, storage):
+    """FP64 mass and momentum reductions on the device (Eqs. lbmmomenta0/1
+    summed over the lattice): equal to the FP64 sums of the downloaded
+    populations, and to the oracle's after 24 coupled steps (mass within
+    rounding: walls and forces conserve it; momentum within the per-step
+    parity of the populations)."""
+    c = small_case(n=(37, 21, 18), m=3, ca=0.02, perturb=0.02)
+    lat = c.gpu(storage=storage, graph=True)
+    f_start = lat.populations().cpu().numpy()
+    sim = c.oracle(f=f_start)
+    cvec, _, _ = O.lattice_constants()
+    for steps in (0, 1, 23):
+        lat.step(steps)
+        assert sim.run(steps) == 0
+        tot = lat.totals()
+        f = lat.populations().cpu().numpy()
+        own = np.array([f.sum()] + [np.tensordot(cvec[:, a], f, axes=(0, 0)).sum()
+                                    for a in range(3)])
+        ref = np.array([sim.f.sum()] + [np.tensordot(cvec[:, a], sim.f, axes=(0, 0)).sum()
+                                        for a in range(3)])
+        N = f[0].size
+        say("  %s after %d: mass %.15g (own %.3e, oracle %.3e)  momentum err %.2e" % (
+            storage, steps, tot[0], abs(tot[0] - own[0]) / N, abs(tot[0] - ref[0]) / N,
+            np.max(np.abs(tot[1:] - ref[1:])) / N))
+        assert abs(tot[0] - own[0]) < 1e-13 * N
+        assert np.max(np.abs(tot[1:] - own[1:])) < 1e-13 * N
+        tol = 1e-12 if storage == "fp32" else 1e-6
+        assert abs(tot[0] - ref[0]) < tol * N
+        assert np.max(np.abs(tot[1:] - ref[1:])) < (1e-9 if storage == "fp32" else 1e-4) * N
+    lat.close()
+
+
+def test_lattice_totals_full_size(B):
+    """The dense-suspension lattice (4.2 M nodes, 1024 partial sums): the
+    device totals of the Couette start equal the FP64 sums of the
+    downloaded populations; the momentum of the linear profile vanishes."""
+    wl = W.config("c3")
+    lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau)
+    lat.set_shear(wl.u_w, init_profile=True)
+    tot = lat.totals()
+    f = lat.populations()
+    own = float(f.sum())
+    N = wl.nx * wl.ny * wl.nz
+    lat.close()
+    say("  c3 totals", tot, "own mass", own)
+    assert abs(tot[0] - own) < 1e-12 * N and abs(tot[0] - N) < 1e-6 * N
+    assert np.max(np.abs(tot[1:])) < 1e-9 * N
+
+
 # ---------------------------------------------------------------------------
 # errors
 # ---------------------------------------------------------------------------
