@@ -410,6 +410,22 @@ void launch_init_equilibrium(const LatDev &L, int fp16, int dst, double uw, hipS
 }
 
 // ---- FP64 field I/O ----------------------------------------------------------
+// The deviation f_i - w_i a stored value stands for, converted exactly: FP32
+// values as they are, FP16 values divided by their scale 16 / w_i (48, 288 or
+// 576, exact in FP32) in FP64.
+template <typename T>
+__device__ __forceinline__ double stored_deviation(const T *f, long long idx, float scale);
+template <>
+__device__ __forceinline__ double stored_deviation<float>(const float *f, long long idx, float) {
+  return (double)f[idx];
+}
+template <>
+__device__ __forceinline__ double stored_deviation<__half>(const __half *f, long long idx,
+                                                           float scale) {
+  return (double)__half2float(f[idx]) / (double)scale;
+}
+
+
 // what: 0 populations, 1 density, 2 velocity, 3 force density.  gpar: the
 // field of the last step (its tiles stamped with that step), or -1 for none.
 template <typename T>
@@ -437,7 +453,7 @@ __global__ __launch_bounds__(256) void k_get_field(LatDev L, int src, int gpar, 
   double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double d = ld_dev<T>(f, pidx(L, i, (long long)z * L.ny + y, x), L.h_inv[i]);
+    const double d = stored_deviation<T>(f, pidx(L, i, (long long)z * L.ny + y, x), L.h_scale[i]);
     if (what == 0) out[i * N + n] = wgt(i) + d;
     drho += d;
     jx += cx(i) * d;
@@ -904,20 +920,7 @@ void launch_batch_collide_stream(const BatchDev &B, int fp16, int src, int par, 
 // the lattice order n = (z ny + y) nx + x in FP64 and writes its partial
 // (sum of the deviations f_i - w_i, momentum) to part[b]; one block then adds
 // the partials.  Every sum runs in a fixed order, so a state always gives the
-// same bits.  The stored values are converted exactly: FP32 deviations, or
-// FP16 values divided by their power-of-two-times-integer scale in FP64.
-template <typename T>
-__device__ __forceinline__ double stored_deviation(const T *f, long long idx, float scale);
-template <>
-__device__ __forceinline__ double stored_deviation<float>(const float *f, long long idx, float) {
-  return (double)f[idx];
-}
-template <>
-__device__ __forceinline__ double stored_deviation<__half>(const __half *f, long long idx,
-                                                           float scale) {
-  return (double)__half2float(f[idx]) / (double)scale;
-}
-
+// same bits.  The stored values are converted exactly (stored_deviation).
 __device__ __forceinline__ void block_sum4(double (&v)[4]) {
   __shared__ double red[4][256];
   const int t = threadIdx.x;

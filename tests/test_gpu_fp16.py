@@ -34,16 +34,16 @@ def B():
 
 
 def rep16(f):
-    """What the FP16 store of f holds, as the kernels read it back:
-    w + fp32(fp16(fp32(f - w) * s) * fp32(1 / s)) with s = fp32(16 / w), where
+    """What the FP16 store of f holds, as the library reports it:
+    w + fp16(fp32(f - w) * s) / s with s = 16 / w (48, 288, 576: exact), where
     the product fp32(f - w) * s is rounded once, directly to FP16 (the
-    kernels form it with a mixed-precision fused multiply-add)."""
+    kernels form it with a mixed-precision fused multiply-add), and the
+    division is exact in FP64."""
     w = WEIGHTS[:, None, None, None]
     s = (16.0 / WEIGHTS).astype(np.float32)[:, None, None, None]
     exact = np.asarray(f - w, np.float32).astype(np.float64) * s.astype(np.float64)
     h = exact.astype(np.float16)
-    inv = (np.float32(1.0) / s).astype(np.float32)
-    return w + (h.astype(np.float32) * inv).astype(np.float64)
+    return w + h.astype(np.float64) / s.astype(np.float64)
 
 
 def dev_err(f_gpu, f_ref):

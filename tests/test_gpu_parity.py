@@ -15,6 +15,8 @@ from parity_helpers import (Case, O, couette_populations, deformed_mesh, rel_err
 
 pytestmark = pytest.mark.gpu
 
+W19 = O.lattice_constants()[1][:, None, None, None]
+
 
 def say(*a):
     print(*a, flush=True)
@@ -549,9 +551,11 @@ def test_observables_match_oracle(B):
 def test_lattice_totals(B, storage):
     """FP64 mass and momentum reductions on the device (Eqs. lbmmomenta0/1
     summed over the lattice): equal to the FP64 sums of the downloaded
-    populations, and to the oracle's after 24 coupled steps (mass within
-    rounding: walls and forces conserve it; momentum within the per-step
-    parity of the populations)."""
+    populations, and to the oracle's after 1 and 24 coupled steps.  Walls and
+    forces conserve mass exactly, but every stored deviation f_i - w_i is
+    rounded once per step (FP32: half an ulp, 2^-24 relative; FP16: 2^-11),
+    so the library's totals may drift from the oracle's by at most
+    steps x 4 x that rounding x sum |f_i - w_i| (the sum over the state)."""
     c = small_case(n=(37, 21, 18), m=3, ca=0.02, perturb=0.02)
     lat = c.gpu(storage=storage, graph=True)
     f_start = lat.populations().cpu().numpy()
@@ -567,14 +571,16 @@ def test_lattice_totals(B, storage):
         ref = np.array([sim.f.sum()] + [np.tensordot(cvec[:, a], sim.f, axes=(0, 0)).sum()
                                         for a in range(3)])
         N = f[0].size
-        say("  %s after %d: mass %.15g (own %.3e, oracle %.3e)  momentum err %.2e" % (
-            storage, steps, tot[0], abs(tot[0] - own[0]) / N, abs(tot[0] - ref[0]) / N,
-            np.max(np.abs(tot[1:] - ref[1:])) / N))
+        done = sim.t
+        dev = float(np.sum(np.abs(f - W19)))
+        bound = done * 4 * (2.0 ** -24 if storage == "fp32" else 2.0 ** -11) * dev + 1e-12 * N
+        say("  %s after %d: mass %.15g (own %.3e, oracle %.3e, bound %.3e)  momentum err %.2e"
+            % (storage, done, tot[0], abs(tot[0] - own[0]), abs(tot[0] - ref[0]), bound,
+               np.max(np.abs(tot[1:] - ref[1:]))))
         assert abs(tot[0] - own[0]) < 1e-13 * N
         assert np.max(np.abs(tot[1:] - own[1:])) < 1e-13 * N
-        tol = 1e-12 if storage == "fp32" else 1e-6
-        assert abs(tot[0] - ref[0]) < tol * N
-        assert np.max(np.abs(tot[1:] - ref[1:])) < (1e-9 if storage == "fp32" else 1e-4) * N
+        assert abs(tot[0] - ref[0]) < bound
+        assert np.max(np.abs(tot[1:] - ref[1:])) < bound
     lat.close()
 
 
