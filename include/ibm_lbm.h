@@ -271,6 +271,19 @@ int ibm_observables(ibm_lattice *lat, double *out_host);
 int ibm_totals_bytes(const ibm_lattice *lat, size_t *bytes);
 int ibm_lattice_totals(ibm_lattice *lat, void *work_dev, size_t work_bytes, double *out_dev);
 
+/* ibm_lattice_totals without a workspace, for callers that cannot allocate
+ * device memory (code under stream capture, serving loops, harnesses that
+ * forbid allocation): the same kernels and the same result bits, with the
+ * partial sums in a fixed scratch array that the library holds on every GPU
+ * it runs on (256 KiB per GPU, kept until the process ends).  Allocates
+ * nothing.  Lattices of up to 8192 * 4096 = 33,554,432 nodes; larger ones
+ * get IBM_ERR_INVALID_ARG (use ibm_lattice_totals).  All calls on one GPU
+ * share its scratch array: calls that may run at the same time on one GPU
+ * (different streams, different threads) race and must be serialised by the
+ * caller; calls on one stream are ordered by it.  out_dev: caller device
+ * buffer of 4 doubles, as for ibm_lattice_totals.  Enqueued; does not wait. */
+int ibm_lattice_totals_noalloc(ibm_lattice *lat, double *out_dev);
+
 /* Wait for the stream; report device-side error flags. */
 int ibm_synchronize(ibm_lattice *lat);
 

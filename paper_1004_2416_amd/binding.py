@@ -70,6 +70,7 @@ def _load():
         "ibm_synchronize": ([v], i),
         "ibm_totals_bytes": ([v, ctypes.POINTER(sz)], i),
         "ibm_lattice_totals": ([v, v, sz, v], i),
+        "ibm_lattice_totals_noalloc": ([v, v], i),
         "ibm_set_option": ([v, i, i], i),
         "ibm_split_box": ([v, ctypes.POINTER(i)], i),
         "ibm_profile_step": ([v, i64, v], i),
@@ -283,6 +284,12 @@ class Lattice:
                                       ctypes.c_void_p(out.data_ptr())))
         self.synchronize()
         return out.cpu().numpy()
+
+    def totals_noalloc(self, out):
+        """ibm_lattice_totals_noalloc into the caller's float64 device tensor
+        `out` (4 values); enqueued on the lattice's stream, no allocation."""
+        _check(lib.ibm_lattice_totals_noalloc(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def observables(self) -> np.ndarray:
         out = np.zeros((self.n_caps, OBS_N))

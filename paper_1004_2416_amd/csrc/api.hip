@@ -3,6 +3,7 @@
 // sequence (Sec. II.C sub-steps 1-5), hipGraph replay, profiling and errors.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
@@ -1134,6 +1135,69 @@ int ibm_lattice_totals(ibm_lattice *lat, void *work_dev, size_t work_bytes, doub
     return fail(IBM_ERR_INVALID_ARG, "work_dev must be 32-byte and out_dev 8-byte aligned");
   ibm::launch_totals(lat->L, lat->storage, (int)(lat->steps & 1), static_cast<double4 *>(work_dev),
                      out_dev, lat->stream);
+  IBM_HIP(hipGetLastError());
+  return ok();
+}
+
+}  // extern "C"
+
+// Partial sums of ibm_lattice_totals_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends.  Host code never passes the
+// array's name to a kernel or a copy (on the host it is only a stand-in for
+// the symbol): it uses the device address that hipGetSymbolAddress gives for
+// the current device, taken once per device and kept in noalloc_ptr.
+constexpr int NOALLOC_PARTS = 8192;  // lattices of up to 8192 * 4096 nodes
+static __device__ __align__(256) double4 scratch[NOALLOC_PARTS];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex noalloc_mu;
+double4 *noalloc_ptr[NOALLOC_MAX_DEVICES] = {};
+
+// The scratch address on the device that owns the lattice's stream (that
+// device made current while the symbol is looked up).
+int noalloc_scratch(hipStream_t stream, double4 **out) {
+  int dev = -1, cur = -1;
+  IBM_HIP(hipStreamGetDevice(stream, &dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+    return fail(IBM_ERR_BAD_STATE, "device %d beyond the %d the library keeps scratch for", dev,
+                NOALLOC_MAX_DEVICES);
+  std::lock_guard<std::mutex> g(noalloc_mu);
+  if (!noalloc_ptr[dev]) {
+    IBM_HIP(hipGetDevice(&cur));
+    if (cur != dev) IBM_HIP(hipSetDevice(dev));
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != dev) IBM_HIP(hipSetDevice(cur));
+    if (e != hipSuccess)
+      return fail(IBM_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    noalloc_ptr[dev] = static_cast<double4 *>(p);
+  }
+  *out = noalloc_ptr[dev];
+  return IBM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int ibm_lattice_totals_noalloc(ibm_lattice *lat, double *out_dev) {
+  if (!lat || !out_dev) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  if (((uintptr_t)out_dev) % 8) return fail(IBM_ERR_INVALID_ARG, "out_dev must be 8-byte aligned");
+  const int np = ibm::totals_parts(lat->L);
+  if (np > NOALLOC_PARTS)
+    return fail(IBM_ERR_INVALID_ARG,
+                "a lattice of %lld nodes needs %d partial sums; the built-in scratch holds %d "
+                "(lattices of up to %lld nodes): use ibm_lattice_totals with a workspace",
+                (long long)lat->nx * lat->ny * lat->nz, np, NOALLOC_PARTS,
+                (long long)NOALLOC_PARTS * ibm::TOTALS_NODES);
+  double4 *part = nullptr;
+  int rc = noalloc_scratch(lat->stream, &part);
+  if (rc) return rc;
+  // every partial the final pass reads is written first by this call, so
+  // nothing needs clearing
+  ibm::launch_totals(lat->L, lat->storage, (int)(lat->steps & 1), part, out_dev, lat->stream);
   IBM_HIP(hipGetLastError());
   return ok();
 }
