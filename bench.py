@@ -65,8 +65,8 @@ def measured_traffic(workload: str, storage: str):
     return None
 
 
-def setup(workload: str, storage: str, graph: bool, variant: int = -1, chunk: int = -1,
-          box: int = -1, overlap: int = -1):
+def setup(workload: str, storage: str, graph: bool, variant: int = -1, box: int = -1,
+          overlap: int = -1):
     from paper_1004_2416_amd import binding as B
     from paper_1004_2416_amd import workloads as W
 
@@ -78,8 +78,6 @@ def setup(workload: str, storage: str, graph: bool, variant: int = -1, chunk: in
     lat.set_option(B.OPT_GRAPH, int(graph))
     if variant >= 0:
         lat.set_option(B.OPT_LBM_VARIANT, int(variant))
-    if chunk >= 0 and wl.capsules:
-        lat.set_option(B.OPT_CHUNK_NODES, int(chunk))
     if box >= 0:
         lat.set_option(B.OPT_STENCIL_BOX, int(box))
     if overlap >= 0:
@@ -196,7 +194,7 @@ def single_leg(args, workload: str, storage: str, roofline: bool):
     """One lattice workload in the benchmark's launch configuration: warm-up
     and graph capture, then exactly args.steps timed steps."""
     wl, lat = setup(workload, storage, not args.no_graph, args.lbm_variant,
-                    args.chunk_nodes, args.stencil_box, args.overlap)
+                    args.stencil_box, args.overlap)
     tuned = lat.autotune(64) if args.autotune else None
     split_box = lat.split_box()
     prime(lat, args.warmup)
@@ -285,9 +283,6 @@ def main():
                     help="c4: the batched sweep of 64 independent runs")
     ap.add_argument("--storage", default="fp32", choices=["fp32", "fp16"])
     ap.add_argument("--no-graph", action="store_true")
-    ap.add_argument("--chunk-nodes", type=int, default=-1,
-                    help="membrane nodes per chunk of the coupling kernels (0: none; "
-                         "-1: library default)")
     ap.add_argument("--stencil-box", type=int, default=-1,
                     help="IBM_OPT_STENCIL_BOX bits (-1: library default)")
     ap.add_argument("--overlap", type=int, default=1,
@@ -340,7 +335,7 @@ def main():
                   "capsules": len(wl.capsules), "membrane_nodes": wl.n_membrane_nodes,
                   "delta_width": wl.m, "storage": args.storage, "graph": not args.no_graph,
                   "u_w": wl.u_w, "tau": wl.tau, "lbm_variant": args.lbm_variant,
-                  "chunk_nodes": args.chunk_nodes, "stencil_box": args.stencil_box,
+                  "stencil_box": args.stencil_box,
                   "overlap": args.overlap, "split_box": ex["split_box"],
                   "autotuned": ex["tuned"]}
         kernel = "k_collide_stream_rows"

@@ -109,13 +109,12 @@ extern "C" {
 #define IBM_OPT_RECENTER 3     /* steps between re-centring of the capsule
                                   frames (default 64, >= 1)                 */
 #define IBM_OPT_LBM_VARIANT 4  /* launch variant of the collide-stream kernel,
-                                  0..511 (bit 0: two nodes per thread, bit 1:
-                                  non-temporal accesses, bit 2: 128-thread,
-                                  bit 3: 64-thread blocks, bit 4: four nodes
-                                  per thread with whole x rows per wavefront,
-                                  used when nx <= 256; bit 5 with
-                                  bit 4 and FP16 storage: eight nodes per
-                                  thread, used when nx / 8 divides 64;
+                                  0..511 (bit 4: four nodes per thread with
+                                  whole x rows per wavefront, used when
+                                  nx <= 256; else the per-node kernel with
+                                  bit 0: two nodes per thread, bit 1:
+                                  non-temporal accesses, bit 2: 128-thread
+                                  blocks; bits 3 and 5 are ignored;
                                   bit 6, bit 7: the four-node row form in
                                   128- or 64-thread blocks instead of 256;
                                   bit 8: the four-node row form stores the
@@ -135,26 +134,18 @@ extern "C" {
                                   velocities evaluated, once per lattice
                                   node); bit 2 (over bit 1): interpolation
                                   reads the lattice velocity from a field
-                                  that one pass evaluates at every node of
-                                  the 4^3 tiles the step's stencils touch.
+                                  that one pass evaluates, once per lattice
+                                  node, at every node the step's stencils
+                                  touch with a nonzero weight.
                                   Default, set when the membrane is
-                                  attached unless chosen before: 3 (box
-                                  spreading and box interpolation) when the
+                                  attached unless chosen before: when the
                                   membrane makes at least 256 blocks of
-                                  work, else 0.
+                                  work, 5 (box spreading, the velocity
+                                  field) if its stencils cover at least an
+                                  eighth of the lattice nodes, else 3 (box
+                                  spreading and box interpolation); else 0.
                                   Results agree to FP32 rounding (see also
                                   ibm_autotune)                             */
-#define IBM_OPT_CHUNK_NODES 5  /* spreading and interpolation work on chunks
-                                  of this many consecutive membrane nodes of
-                                  one capsule (a power of two, 16 to 1024;
-                                  a smaller capsule is one chunk),
-                                  summing overlapping stencils
-                                  in on-chip memory; 0: one lane group
-                                  per node without chunks (the default,
-                                  faster on the workloads measured).
-                                  Results agree to FP32 rounding
-                                  (summation order differs)                 */
-
 #define IBM_OPT_OVERLAP 7      /* 1, 2: split the lattice update of
                                   graph-replayed steps at the slab of z
                                   that stencils can reach (the membranes' z
@@ -168,7 +159,7 @@ extern "C" {
                                   every re-centring.  A stencil outside it
                                   makes the next synchronising call fail
                                   with IBM_ERR_OUTSIDE_SLAB.  Used only
-                                  without a tangent and chunks, with the
+                                  without a tangent, with the
                                   row form (nx <= 256), and when the slab
                                   holds at most three quarters of the rows
                                   (value 2), and with value 1 only when at
@@ -412,13 +403,12 @@ int ibm_batch_create(int n_runs, ibm_lattice *const *runs, void *dev_mem, size_t
 
 /* Enqueue n timesteps of every run (Sec. II.C, sub-steps 1-5); asynchronous.
  * Device-side errors of a run are reported by that run's next synchronising
- * call.  The per-node coupling kernels are used whatever a run's
- * IBM_OPT_CHUNK_NODES, and the lattice update is the row form (whole x rows
+ * call.  The lattice update is the row form (whole x rows
  * per wavefront) for runs with nx <= 256, else one node per thread, whatever
  * a run's IBM_OPT_LBM_VARIANT; the row form stores the first quarter of each
  * run's rows with cached writes and the rest non-temporally.  The stencil-box mode is the first run's
  * IBM_OPT_STENCIL_BOX if it was set, else 5 (box spreading, interpolation
- * from the tile-velocity field) when the batch's membranes make at least 256
+ * from the node-velocity field) when the batch's membranes make at least 256
  * blocks of work, else 0. */
 int ibm_batch_step(ibm_batch *b, int64_t n);
 

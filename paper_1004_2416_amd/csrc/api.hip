@@ -53,7 +53,7 @@ struct LatticeLayout {
   int tpr;             // lanes per row of the row-form kernels (0: not used)
   long long pop_elems;  // elements of one population buffer
   int tnx, tny, tnz;
-  size_t off_ctrl, off_stamp[2], off_U, off_g[2], off_f[2], total;
+  size_t off_ctrl, off_stamp[2], off_nstamp, off_U, off_g[2], off_f[2], total;
 };
 
 LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
@@ -84,6 +84,8 @@ LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
     l.off_stamp[k] = off;
     off += round_up(tiles * sizeof(int), ALIGN);
   }
+  l.off_nstamp = off;
+  off += round_up((size_t)l.S * sizeof(int), ALIGN);
   l.off_U = off;
   off += round_up((size_t)l.S * 16, ALIGN);
   for (int k = 0; k < 2; ++k) {
@@ -100,7 +102,7 @@ LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
 
 struct MembraneLayout {
   size_t x, u, F, ext_id, node_cap, csr_off, csr_ent, tri, ref_p, ref_ghi, ref_glo, origin, moduli,
-      cap_node_off, cap_face_off, obs, chunk, chunk_face_off, chunk_face, total;
+      cap_node_off, cap_face_off, obs, total;
 };
 
 MembraneLayout membrane_layout(int nc, long long nn, long long nf) {
@@ -127,9 +129,6 @@ MembraneLayout membrane_layout(int nc, long long nn, long long nf) {
   l.cap_node_off = take(((size_t)nc + 1) * 4);
   l.cap_face_off = take(((size_t)nc + 1) * 4);
   l.obs = take((size_t)nc * IBM_OBS_N * 8);
-  l.chunk = take((size_t)(nn / ibm::CHUNK_MIN + nc + 1) * 8);  // at the smallest chunk size
-  l.chunk_face_off = take((size_t)(nn / ibm::CHUNK_MIN + nc + 2) * 4);
-  l.chunk_face = take(3 * (size_t)nf * 4);  // a face lies in at most three chunks
   l.total = off;
   return l;
 }
@@ -156,9 +155,8 @@ struct ibm_lattice {
   // wavefront, else two nodes per thread, non-temporal, 128-thread blocks;
   // cached row stores for population buffers of CACHED_POP_MIN..MAX bytes
   int use_graph = 1, eq_linear = 0, ab2 = 0, recenter_every = 64, lbm_variant = 16 | 7;
-  int chunk_nodes = 0;  // membrane nodes per chunk of the coupling kernels (0: none)
   int box_mode = 0;     // IBM_OPT_STENCIL_BOX: bit 0 box spreading, bit 1 / bit 2
-                        // interpolation through LDS boxes / the tile-velocity field
+                        // interpolation through LDS boxes / the node-velocity field
   bool box_set = false;  // box_mode chosen by the caller (else set with the membrane)
   bool have_prev_u = false;
   int64_t since_recenter = 0;
@@ -209,6 +207,7 @@ void clear_force_fields(ibm_lattice *lat, hipStream_t s) {
     ibm::launch_fill_u32(lat->L.stamp[k], tiles, (uint32_t)(-100), s);
     ibm::launch_fill_u32(lat->L.g[k], 3 * lat->lay.S, 0u, s);
   }
+  ibm::launch_fill_u32(lat->L.nstamp, lat->lay.S, (uint32_t)(-100), s);
 }
 
 // Clear the control words, the tile stamps and both force fields.
@@ -218,7 +217,7 @@ void reset_force_state(ibm_lattice *lat, hipStream_t s) {
 }
 
 // Interpolation mode of the coupling kernels (launch_interp_advect) for an
-// IBM_OPT_STENCIL_BOX value: bit 2 (the tile-velocity field) over bit 1 (LDS
+// IBM_OPT_STENCIL_BOX value: bit 2 (the node-velocity field) over bit 1 (LDS
 // boxes) over the per-stencil-node evaluation.
 int interp_mode(int box_mode) { return (box_mode & 4) ? 2 : ((box_mode & 2) ? 1 : 0); }
 
@@ -248,45 +247,6 @@ void enqueue_step(ibm_lattice *lat, hipStream_t s, int advect) {
   lat->since_recenter += 1;
 }
 
-// Chunk tables of the coupling kernels for the current chunk size: runs of
-// chunk_nodes consecutive nodes, cut at capsule ends, and for each chunk the
-// faces with at least one corner in it.
-int upload_chunks(ibm_lattice *lat) {
-  ibm::MemDev &M = lat->M;
-  std::vector<int2> ch;
-  std::vector<int> cfo(1, 0), cf;
-  if (lat->chunk_nodes > 0) {
-    std::vector<int> seen((size_t)M.nf, -1);
-    for (size_t c = 0; c + 1 < lat->node_off.size(); ++c)
-      for (int n = lat->node_off[c]; n < lat->node_off[c + 1]; n += lat->chunk_nodes) {
-        const int q = (int)ch.size(), e = std::min(n + lat->chunk_nodes, lat->node_off[c + 1]);
-        ch.push_back(make_int2(n, e));
-        for (int v = n; v < e; ++v)
-          for (int k = lat->csr_off[v]; k < lat->csr_off[v + 1]; ++k) {
-            const int j = lat->csr_ent[k] >> 2;
-            if (seen[j] != q) {
-              seen[j] = q;
-              cf.push_back(j);
-            }
-          }
-        cfo.push_back((int)cf.size());
-      }
-  }
-  const size_t cap = (size_t)M.nn / ibm::CHUNK_MIN + M.n_caps + 1;
-  if (ch.size() > cap || cf.size() > 3 * (size_t)M.nf)
-    return fail(IBM_ERR_BAD_STATE, "chunk table overflow");
-  if (!ch.empty()) {
-    hipStream_t s = lat->stream;
-    IBM_HIP(hipMemcpyAsync(M.chunk, ch.data(), ch.size() * sizeof(int2), hipMemcpyHostToDevice, s));
-    IBM_HIP(hipMemcpyAsync(M.chunk_face_off, cfo.data(), cfo.size() * sizeof(int),
-                           hipMemcpyHostToDevice, s));
-    IBM_HIP(hipMemcpyAsync(M.chunk_face, cf.data(), cf.size() * sizeof(int), hipMemcpyHostToDevice, s));
-    IBM_HIP(hipStreamSynchronize(s));  // the host tables must outlive the copies
-  }
-  M.n_chunks = (int)ch.size();
-  return IBM_OK;
-}
-
 int advect_mode(ibm_lattice *lat) { return (lat->ab2 && lat->have_prev_u) ? 1 : 0; }
 
 bool split_update(const ibm_lattice *lat) {
@@ -297,14 +257,14 @@ bool split_update(const ibm_lattice *lat) {
 // slab of rows zlo <= z < zhi (all y): stencils reach 1 below and 2 above a
 // node's floor(z); the margin covers the drift until the next re-centring;
 // the slab is rounded out to the 4^3 force tiles.  The whole lattice when the
-// option is off or not applicable (no row form, a tangent, chunks), or when
+// option is off or not applicable (no row form, a tangent), or when
 // the slab holds more than three quarters of the rows.  (The slab spans all
 // y: rows updated inside the coupling launches cost more than in the
 // lattice kernel, as the coupling kernels' dependent loads then wait behind
 // their traffic, so a narrower box in y measured slower.)
 int refresh_slab(ibm_lattice *lat) {
   int zlo = 0, zhi = lat->nz, ylo = 0, yhi = lat->ny;
-  if (lat->overlap && lat->has_mem && !lat->has_tan && lat->chunk_nodes == 0 && lat->L.tpr > 0) {
+  if (lat->overlap && lat->has_mem && !lat->has_tan && lat->L.tpr > 0) {
     ibm::launch_node_range(lat->M, lat->L.ctrl, lat->stream);
     int r[4] = {0, 0, 0, 0};  // zmin, zmax, ymin, ymax
     IBM_HIP(hipMemcpyAsync(r, &lat->L.ctrl->zmin, sizeof(r), hipMemcpyDeviceToHost, lat->stream));
@@ -617,7 +577,7 @@ void batch_invalidate_graph(ibm_batch *b) {
 }
 
 // Check that the runs can step together and bring the device tables up to
-// date with their current state (a run's membrane or chunk options may have
+// date with their current state (a run's membrane or options may have
 // changed since the last batch step).
 int batch_sync_tables(ibm_batch *b) {
   const ibm_lattice *r0 = b->runs[0];
@@ -662,7 +622,7 @@ int batch_sync_tables(ibm_batch *b) {
   B.n_lat_items = (int)li.size();
   B.n_node_items = (int)ni.size();
   // the first run's explicit choice, else box spreading and interpolation
-  // from the tile-velocity field once the whole batch makes at least 256
+  // from the node-velocity field once the whole batch makes at least 256
   // blocks of coupling work
   b->box_mode = r0->box_set ? r0->box_mode : (ni.size() >= 256 ? 1 | 4 : 0);
   const bool same = img == b->image && std::memcmp(&B, &b->B, sizeof(B)) == 0;
@@ -783,6 +743,7 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
     L.stamp[k] = reinterpret_cast<int *>(lat->base + lat->lay.off_stamp[k]);
   }
   L.ctrl = reinterpret_cast<ibm::Ctrl *>(lat->base + lat->lay.off_ctrl);
+  L.nstamp = reinterpret_cast<int *>(lat->base + lat->lay.off_nstamp);
   L.U = reinterpret_cast<float4 *>(lat->base + lat->lay.off_U);
   L.inv_tau = (float)(1.0 / tau);
   L.guo_pre = (float)(1.0 - 0.5 / tau);
@@ -941,10 +902,6 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
   M.cap_node_off = reinterpret_cast<int *>(b + ml.cap_node_off);
   M.cap_face_off = reinterpret_cast<int *>(b + ml.cap_face_off);
   M.obs = reinterpret_cast<double *>(b + ml.obs);
-  M.chunk = reinterpret_cast<int2 *>(b + ml.chunk);
-  M.chunk_face_off = reinterpret_cast<int *>(b + ml.chunk_face_off);
-  M.chunk_face = reinterpret_cast<int *>(b + ml.chunk_face);
-  M.n_chunks = 0;
   lat->csr_off = csr_off;
   lat->csr_ent = csr_ent;
   lat->node_off = node_off;
@@ -982,18 +939,20 @@ int ibm_membrane_create(ibm_lattice *lat, int n_caps, const int *nodes_per_cap,
     lat->has_mem = false;
     return rc;
   }
-  rc = upload_chunks(lat);
-  if (rc) {
-    lat->has_mem = false;
-    return rc;
-  }
   // Box spreading pays once there are enough blocks for atomic conflicts
   // between overlapping stencils to dominate (measured: 256+ blocks); box
   // interpolation on such membranes too, now that each block's nodes form a
   // compact patch (measured: 128^3 +1.3 %, the dense suspension +2.2 %).
+  // Where the stencil nodes number at least an eighth of the lattice nodes,
+  // interpolation reads the node-velocity field instead (one pass evaluates
+  // each touched node once): the dense suspension's step 1.5 % faster; on
+  // 128^3 with one capsule (stencils on 8 % of the nodes) 5 % slower, the
+  // pass scanning the whole lattice for few marks.
   if (!lat->box_set) {
     const int gs = m == 2 ? ibm::group_size<2>() : (m == 3 ? ibm::group_size<3>() : ibm::group_size<4>());
-    lat->box_mode = (long long)nn * gs >= 256LL * 256 ? 3 : 0;
+    const long long stencil_nodes = (long long)nn * m * m * m;
+    const long long lattice_nodes = (long long)lat->nx * lat->ny * lat->nz;
+    lat->box_mode = (long long)nn * gs >= 256LL * 256 ? (8 * stencil_nodes >= lattice_nodes ? 5 : 3) : 0;
   }
   // the force bookkeeping restarts with the membrane
   reset_force_state(lat, s);
@@ -1243,16 +1202,6 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
       lat->box_mode = value;
       lat->box_set = true;
       break;
-    case IBM_OPT_CHUNK_NODES: {
-      if (value != 0 && (value < ibm::CHUNK_MIN || value > ibm::CHUNK_MAX || (value & (value - 1))))
-        return fail(IBM_ERR_INVALID_ARG, "chunk size is 0 or a power of two in 16..1024");
-      lat->chunk_nodes = value;
-      if (lat->has_mem) {
-        const int rc = upload_chunks(lat);
-        if (rc) return rc;
-      }
-      break;
-    }
     default:
       return fail(IBM_ERR_INVALID_ARG, "unknown option %d", option);
   }
@@ -1293,9 +1242,6 @@ int ibm_autotune(ibm_lattice *lat, int steps_per_trial, int *chosen) {
   // accesses, 256- or 128-thread blocks
   std::vector<int> cand;
   const bool rows_ok = lat->L.tpr > 0;
-  const bool rows8_ok = lat->storage == IBM_STORAGE_FP16 && lat->nx % 8 == 0 &&
-                        lat->nx / 8 <= 64 && 64 % (lat->nx / 8) == 0;
-  if (rows8_ok) cand.push_back(48);
   if (rows_ok) {
     cand.push_back(16);
     cand.push_back(16 | 256);
@@ -1319,7 +1265,7 @@ int ibm_autotune(ibm_lattice *lat, int steps_per_trial, int *chosen) {
   }
   set_variant(lat, best_v);
   invalidate_graph(lat);
-  if (!rc && lat->has_mem && lat->chunk_nodes == 0) {
+  if (!rc && lat->has_mem) {
     best = 1e30f;
     for (int bm = 0; bm < 6 && !rc; ++bm) {  // 6, 7 interpolate as 4, 5
       lat->box_mode = bm;
@@ -1335,7 +1281,7 @@ int ibm_autotune(ibm_lattice *lat, int steps_per_trial, int *chosen) {
     lat->box_set = true;
     invalidate_graph(lat);
   }
-  if (!rc && lat->has_mem && lat->chunk_nodes == 0 && !lat->has_tan && lat->L.tpr > 0) {
+  if (!rc && lat->has_mem && !lat->has_tan && lat->L.tpr > 0) {
     // the split lattice update, where its slab leaves enough rows outside
     float ms_off = 0.0f, ms_on = 0.0f;
     lat->overlap = 0;

@@ -66,10 +66,12 @@ struct LatDev {
   void *f[2];             // population buffers (float or __half), see pidx
   float *g[2];            // force density [3][S] of even and odd steps
   int *stamp[2];          // per-tile step stamps of the two fields
+  int *nstamp;            // per node [S]: the last step whose stencils gave
+                          // it a nonzero weight (the nodes interpolation reads)
   int zlo, zhi, ylo, yhi; // rows (z, y) stencils may reach: the whole lattice
                           // unless the update is split, see IBM_OPT_OVERLAP
-  float4 *U;              // lattice velocity (ux, uy, uz, 0) at the nodes of
-                          // the tiles stamped this step, for interpolation [S]
+  float4 *U;              // lattice velocity (ux, uy, uz, 0) at the nodes the
+                          // step's stencils touch, for interpolation [S]
   Ctrl *ctrl;
   float inv_tau;          // 1 / tau
   float guo_pre;          // 1 - 1 / (2 tau)
@@ -111,10 +113,6 @@ struct MemDev {
   int *cap_node_off;  // [n_caps + 1]
   int *cap_face_off;  // [n_caps + 1]
   double *obs;      // observables [n_caps][IBM_OBS_N]
-  int2 *chunk;      // node ranges [begin, end) of the chunks, each inside one capsule
-  int *chunk_face_off;  // faces with a corner in chunk k: chunk_face[off[k] .. off[k + 1])
-  int *chunk_face;
-  int n_chunks;     // 0: spreading and interpolation work per node, without chunks
 };
 
 // Tangent-linear (forward sensitivity) state: the derivative of every
@@ -156,18 +154,10 @@ struct BatchDev {
   int n_lat_items, n_node_items;
 };
 
-// Chunks: runs of at most CHUNK_MAX consecutive (spatially sorted) nodes of one
-// capsule (a whole capsule of up to CHUNK_MAX nodes is one chunk).  Their
-// stencils cover a compact box of lattice nodes that the chunked kernels keep
-// in LDS when it has at most SPREAD_BOX_CELLS (spreading, three force
-// components in a 1024-thread block) or BOX_CELLS (interpolation) nodes.
-constexpr int CHUNK_MIN = 16, CHUNK_MAX = 1024;
 
 // Lattice totals (ibm_lattice_totals): one FP64 partial sum (mass deviation,
 // momentum) per TOTALS_NODES consecutive lattice nodes.
 constexpr int TOTALS_NODES = 4096;
-constexpr int BOX_CELLS = 4096;
-constexpr int SPREAD_BOX_CELLS = 9000;
 
 // ---- discrete delta functions, Sec. II.C Eqs. (2point), (3point), (4point) ----
 // Evaluated for |r| inside the stencil; square-root arguments are clamped at 0

@@ -55,8 +55,8 @@ void launch_reference_geometry(const MemDev &M, Ctrl *ctrl, hipStream_t s);
 void launch_spread(const LatDev &L, const MemDev &M, int par, bool box, hipStream_t s);
 // advect: 0 Euler, 1 Adams-Bashforth with the stored velocity of the previous step
 // mode: 0 lattice velocities per stencil node from the populations, 1 per
-// block in an LDS box, 2 from the tile-velocity field (a pass over the
-// stamped tiles first)
+// block in an LDS box, 2 from the node-velocity field (a pass over the
+// nodes the step's stencils marked first)
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
                           int advect, int mode, hipStream_t s);
 void launch_recenter(const MemDev &M, hipStream_t s);

@@ -125,133 +125,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
                                                live, L.cached_rows != 0);
 }
 
-// FP16 row-vector form with eight nodes per thread: one aligned 16-byte
-// access per population, as in the FP32 form, instead of eight bytes.  The
-// populations stay packed (two halves per register) between the load and the
-// store: each node is unpacked, collided, and its post-collision values are
-// rounded once into the slots it came from.  The +-x streaming shift moves one
-// half-word across the eight-node segments: the neighbour lane's end word
-// arrives by a lane shuffle and the segment is re-aligned by a 16-bit funnel
-// shift.  Values are used in their storage units (collide<..., SCALED>);
-// bounce-back rows apply the wall kick in those units before rounding (a
-// direction and its opposite share w_i, hence their units).
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-__device__ __forceinline__ float half_lo(unsigned int w) {
-  return __half2float(__ushort_as_half((unsigned short)(w & 0xffffu)));
-}
-__device__ __forceinline__ float half_hi(unsigned int w) {
-  return __half2float(__ushort_as_half((unsigned short)(w >> 16)));
-}
-
-template <bool LINEAR, bool FORCE>
-__global__ __launch_bounds__(256) void k_collide_stream_rows8(LatDev L, int src, int par, int tpr) {
-  constexpr int VEC = 8;
-  const int lane = threadIdx.x & 63;
-  const int t = lane % tpr;
-  const int row = (blockIdx.x * (int)blockDim.x + (int)threadIdx.x) / tpr;
-  const bool live = row < L.ny * L.nz;
-  const int y = live ? row % L.ny : 0;
-  const int z = live ? row / L.ny : 0;
-  const int x0 = t * VEC;
-  const long long S = L.S;
-  const long long n0 = ((long long)z * L.ny + y) * (long long)L.nx + x0;
-  const unsigned row0 = (unsigned)(z * L.ny + y);
-  const unsigned long long off0 = rowoff(L, row0, x0);
-  const unsigned short *__restrict__ fs = static_cast<const unsigned short *>(L.f[src]);
-  unsigned short *__restrict__ fd = static_cast<unsigned short *>(L.f[src ^ 1]);
-  const int row_lane0 = lane - t;
-  const int left = row_lane0 + (t == 0 ? tpr - 1 : t - 1);
-  const int right = row_lane0 + (t == tpr - 1 ? 0 : t + 1);
-  // z walls this row touches: directions leaving through them bounce back
-  const bool wall_lo = z == 0, wall_hi = z == L.nz - 1;
-
-  unsigned int w[Q][4];
-  if (live) {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const u32x4 r = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>((fs + L.pst[i]) + off0));
-      w[i][0] = r.x;
-      w[i][1] = r.y;
-      w[i][2] = r.z;
-      w[i][3] = r.w;
-    }
-    float g[VEC][3];
-#pragma unroll
-    for (int k = 0; k < VEC; ++k) g[k][0] = g[k][1] = g[k][2] = 0.0f;
-    if (FORCE) {
-      // the segment spans two force tiles along x (TILE_X = 4)
-      const int step = L.ctrl->step;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        const int tile = tile_of(L, x0 + 4 * h, y, z);
-        if (L.stamp[par][tile] == step) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c) {
-            float v[4];
-            Pop4<float>::ld(L.g[par], c * S + n0 + 4 * h, 1.0f, v);
-#pragma unroll
-            for (int k = 0; k < 4; ++k) g[4 * h + k][c] = v[k];
-          }
-        }
-        if (L.stamp[par ^ 1][tile] == step - 1) {
-#pragma unroll
-          for (int c = 0; c < 3; ++c)
-            Pop4<float>::st(L.g[par ^ 1], c * S + n0 + 4 * h, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f);
-        }
-      }
-    }
-#pragma unroll
-    for (int k = 0; k < VEC; ++k) {
-      const int j = k >> 1;
-      float d[Q];
-#pragma unroll
-      for (int i = 0; i < Q; ++i)
-        d[i] = (k & 1) ? half_hi(w[i][j]) : half_lo(w[i][j]);
-      collide<LINEAR, FORCE, true>(d, g[k][0], g[k][1], g[k][2], L.inv_tau, L.guo_pre);
-#pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        float v = d[i];
-        if (cz(i) != 0 && (cz(i) < 0 ? wall_lo : wall_hi))
-          v -= wall_kick_scaled(i, L.uw);
-        const unsigned int q = (unsigned int)__half_as_ushort(__float2half_rn(v));
-        w[i][j] = (k & 1) ? ((w[i][j] & 0xffffu) | (q << 16)) : ((w[i][j] & 0xffff0000u) | q);
-      }
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) w[i][0] = w[i][1] = w[i][2] = w[i][3] = 0u;
-  }
-
-  const int ym = (y == 0) ? L.ny - 1 : y - 1;
-  const int yp = (y == L.ny - 1) ? 0 : y + 1;
-#pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    unsigned int in = 0u;
-    if (cx(i) > 0) in = (unsigned int)__shfl((int)w[i][3], left);
-    if (cx(i) < 0) in = (unsigned int)__shfl((int)w[i][0], right);
-    if (!live) continue;
-    u32x4 o;
-    unsigned short *at;
-    if (cz(i) != 0 && (cz(i) < 0 ? wall_lo : wall_hi)) {
-      at = (fd + L.pst[opp(i)]) + off0;
-      o = u32x4{w[i][0], w[i][1], w[i][2], w[i][3]};
-    } else {
-      const int yt = cy(i) > 0 ? yp : (cy(i) < 0 ? ym : y);
-      at = (fd + L.pst[i]) + rowoff(L, (unsigned)((z + cz(i)) * L.ny + yt), x0);
-      if (cx(i) > 0)
-        o = u32x4{__builtin_amdgcn_alignbit(w[i][0], in, 16), __builtin_amdgcn_alignbit(w[i][1], w[i][0], 16),
-                  __builtin_amdgcn_alignbit(w[i][2], w[i][1], 16), __builtin_amdgcn_alignbit(w[i][3], w[i][2], 16)};
-      else if (cx(i) < 0)
-        o = u32x4{__builtin_amdgcn_alignbit(w[i][1], w[i][0], 16), __builtin_amdgcn_alignbit(w[i][2], w[i][1], 16),
-                  __builtin_amdgcn_alignbit(w[i][3], w[i][2], 16), __builtin_amdgcn_alignbit(in, w[i][3], 16)};
-      else
-        o = u32x4{w[i][0], w[i][1], w[i][2], w[i][3]};
-    }
-    __builtin_nontemporal_store(o, reinterpret_cast<u32x4 *>(at));
-  }
-}
-
 // Row kernels index x rows with grow32: the padded row count times Q must stay
 // below 2^32.
 static bool rows_fit_32bit(const LatDev &L) {
@@ -266,23 +139,6 @@ template <typename K, typename... A>
 static void launch_k(K k, dim3 g, dim3 b, hipStream_t s, const DispatchTimer *t, A... a) {
   if (t) hipExtLaunchKernelGGL(k, g, b, 0, s, t->start, t->stop, 0, a...);
   else hipLaunchKernelGGL(k, g, b, 0, s, a...);
-}
-
-static bool launch_cs_rows8(const LatDev &L, int src, int par, bool force, bool linear,
-                            hipStream_t s, const DispatchTimer *t) {
-  if (L.nx % 8 != 0 || !rows_fit_32bit(L)) return false;
-  const int tpr = L.nx / 8;
-  if (tpr > 64 || 64 % tpr != 0) return false;
-  const long long threads = (long long)L.ny * L.nz * tpr;
-  const dim3 b(256), g((unsigned)((threads + 255) / 256));
-  if (force) {
-    if (linear) launch_k(k_collide_stream_rows8<true, true>, g, b, s, t, L, src, par, tpr);
-    else launch_k(k_collide_stream_rows8<false, true>, g, b, s, t, L, src, par, tpr);
-  } else {
-    if (linear) launch_k(k_collide_stream_rows8<true, false>, g, b, s, t, L, src, par, tpr);
-    else launch_k(k_collide_stream_rows8<false, false>, g, b, s, t, L, src, par, tpr);
-  }
-  return true;
 }
 
 template <typename T, bool PAD>
@@ -343,22 +199,17 @@ static void launch_cs_v(const LatDev &L, int src, int par, bool force, bool line
 template <typename T>
 static void launch_cs_t(const LatDev &L, int src, int par, bool force, bool linear,
                         int variant, int z0, int z1, hipStream_t s, const DispatchTimer *t) {
-  // variant bits: 1 = two nodes per thread, 2 = non-temporal accesses,
-  // 4 = 128-thread blocks, 8 = 64-thread blocks (per-node kernel), 16 = row-vector kernel
-  // (four nodes per thread, whole rows per wavefront) where a padded row has
-  // at most 256 values,
-  // 32 = with FP16 storage, eight nodes per thread in that form (nx / 8
-  // dividing 64), 64 = row form in 128-thread blocks, 128 = in 64-thread
-  // blocks
-  const bool whole = z0 == 0 && z1 == L.nz;
-  if constexpr (sizeof(T) == 2)
-    if (whole && (variant & 48) == 48 && launch_cs_rows8(L, src, par, force, linear, s, t)) return;
+  // variant bits: 16 = row-vector kernel (four nodes per thread, whole rows
+  // per wavefront) where a padded row has at most 256 values, 64 = row form
+  // in 128-thread blocks, 128 = in 64-thread blocks; else the per-node kernel
+  // with 1 = two nodes per thread, 2 = non-temporal accesses, 4 = 128-thread
+  // blocks (256 otherwise)
   const RowSet rs{z0 * L.ny, (z1 - z0) * L.ny, 0, 0, 1, 0};
   const int wpb = (variant & 128) ? 1 : ((variant & 64) ? 2 : 4);
   if ((variant & 16) && launch_cs_rows<T>(L, src, par, force, linear, rs, s, t, wpb)) return;
   const bool vec2 = (variant & 1) && (L.nx % 2 == 0);
   const bool nt = (variant & 2) != 0;
-  const int threads = (variant & 8) ? 64 : ((variant & 4) ? 128 : 256);
+  const int threads = (variant & 4) ? 128 : 256;
   if (vec2) {
     if (nt) launch_cs_v<T, 2, true>(L, src, par, force, linear, threads, z0, z1, s, t);
     else launch_cs_v<T, 2, false>(L, src, par, force, linear, threads, z0, z1, s, t);

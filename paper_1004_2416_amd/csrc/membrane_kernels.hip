@@ -250,6 +250,7 @@ constexpr int SPREAD_BOX = 1024;
 constexpr int SPREAD_BOX_TILES = 1032;
 struct SpreadLDS {
   float box[3][SPREAD_BOX];
+  unsigned char nflag[SPREAD_BOX];  // box nodes some stencil weights nonzero
   unsigned char tflag[SPREAD_BOX_TILES];
   int bb[6];
 };
@@ -364,6 +365,7 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
       unsafeAtomicAdd(g + L.S + n, w[q] * fy);
       unsafeAtomicAdd(g + 2 * L.S + n, w[q] * fz);
       L.stamp[par][tile_of(L, X, Y, gz[q])] = step;
+      L.nstamp[n] = step;
     }
     return;
   }
@@ -393,7 +395,10 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   const int ntx = fits ? ((x0 + ex - 1) >> 2) - tx0 + 1 : 0;
   const int nty = fits ? ((y0 + ey - 1) >> 2) - ty0 + 1 : 0;
   const int NT = fits ? ntx * nty * (((z0 + b.ez - 1) >> 2) - tz0 + 1) : 0;
-  for (int c = threadIdx.x; c < V; c += blockDim.x) sm.box[0][c] = sm.box[1][c] = sm.box[2][c] = 0.0f;
+  for (int c = threadIdx.x; c < V; c += blockDim.x) {
+    sm.box[0][c] = sm.box[1][c] = sm.box[2][c] = 0.0f;
+    sm.nflag[c] = 0;
+  }
   for (int q = threadIdx.x; q < NT; q += blockDim.x) sm.tflag[q] = 0;
   __syncthreads();
 #pragma unroll
@@ -404,6 +409,7 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
       atomicAdd(&sm.box[0][c], w[q] * fx);
       atomicAdd(&sm.box[1][c], w[q] * fy);
       atomicAdd(&sm.box[2][c], w[q] * fz);
+      sm.nflag[c] = 1;
       sm.tflag[(((gz[q] >> 2) - tz0) * nty + ((gy[q] >> 2) - ty0)) * ntx + ((gx[q] >> 2) - tx0)] = 1;
     } else {
       const int X = wrap_mod(gx[q], L.nx), Y = wrap_mod(gy[q], L.ny);
@@ -412,17 +418,20 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
       unsafeAtomicAdd(g + L.S + n, w[q] * fy);
       unsafeAtomicAdd(g + 2 * L.S + n, w[q] * fz);
       L.stamp[par][tile_of(L, X, Y, gz[q])] = step;
+      L.nstamp[n] = step;
     }
   }
   if (!fits) return;  // the whole block
   __syncthreads();
-  // only in-range z received force (see above)
+  // only in-range z received force (see above); every node a nonzero weight
+  // touched is marked for interpolation, whatever its force
   for (int c = threadIdx.x; c < V; c += blockDim.x) {
+    if (!sm.nflag[c]) continue;
     const float vx = sm.box[0][c], vy = sm.box[1][c], vz = sm.box[2][c];
-    if (vx == 0.0f && vy == 0.0f && vz == 0.0f) continue;
     const int X = wrap_mod(x0 + c % ex, L.nx), Y = wrap_mod(y0 + (c / ex) % ey, L.ny);
     const int Z = z0 + c / (ex * ey);
     const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
+    L.nstamp[n] = step;
     if (vx != 0.0f) unsafeAtomicAdd(g + n, vx);
     if (vy != 0.0f) unsafeAtomicAdd(g + L.S + n, vy);
     if (vz != 0.0f) unsafeAtomicAdd(g + 2 * L.S + n, vz);
@@ -452,174 +461,8 @@ __global__ __launch_bounds__(256) void k_spread(LatDev L, MemDev Mm, int par, in
   if (blk >= 0) spread_lanes<M, BOX, HALF>(L, Mm, par, blk, sm);
 }
 
-// ---- chunked spreading ----------------------------------------------------------
-// One block per chunk.  The chunk's node forces (gathered from the face
-// gradients) and positions go to LDS together with the bounding box of its
-// stencils.  When the box fits in LDS, every contribution F_n delta(X - x_n) is
-// summed there first and each touched lattice node then receives one atomic
-// add per component: the overlapping stencils of neighbouring membrane nodes
-// cost LDS atomics instead of global ones.  Otherwise the contributions go to
-// the global field directly.
-struct Bounds {
-  int x0, y0, z0, ex, ey, ez;
-  bool fits;
-};
-
-// Box of the M-point stencils of the chunk's nb nodes (positions already in
-// sp); all threads of the block must call it.  Each wavefront reduces its
-// nodes' stencil corners with shuffles, then one lane per wavefront merges
-// them into bb.
-template <int M>
-__device__ __forceinline__ Bounds chunk_bounds(const float4 *sp, int nb, int *bb, int cells) {
-  const int t = threadIdx.x;
-  if (t < 3) {
-    bb[t] = 0x7fffffff;
-    bb[t + 3] = -0x7fffffff;
-  }
-  __syncthreads();
-  int lo[3] = {0x7fffffff, 0x7fffffff, 0x7fffffff}, hi[3] = {-0x7fffffff, -0x7fffffff, -0x7fffffff};
-  for (int k = t; k < nb; k += blockDim.x) {
-    const float4 p = sp[k];
-    const int l[3] = {stencil_lo<M>(p.x), stencil_lo<M>(p.y), stencil_lo<M>(p.z)};
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = min(lo[d], l[d]);
-      hi[d] = max(hi[d], l[d]);
-    }
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1)
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      lo[d] = min(lo[d], __shfl_xor(lo[d], off, 64));
-      hi[d] = max(hi[d], __shfl_xor(hi[d], off, 64));
-    }
-  if ((t & 63) == 0) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      atomicMin(&bb[d], lo[d]);
-      atomicMax(&bb[d + 3], hi[d]);
-    }
-  }
-  __syncthreads();
-  Bounds b;
-  b.x0 = bb[0];
-  b.y0 = bb[1];
-  b.z0 = bb[2];
-  b.ex = bb[3] - bb[0] + M;
-  b.ey = bb[4] - bb[1] + M;
-  b.ez = bb[5] - bb[2] + M;
-  b.fits = (long long)b.ex * b.ey * b.ez <= cells;
-  return b;
-}
-
-// The chunk's node forces are formed here as well: every face with a corner in
-// the chunk is evaluated (a face shared by several chunks in each of them, with
-// identical results) and its corner gradients are summed into the chunk's
-// nodes in LDS, so the step needs no separate face kernel.
-template <int M>
-__global__ __launch_bounds__(1024) void k_spread_chunks(LatDev L, MemDev Mm, int par) {
-  constexpr int M3 = M * M * M;
-  __shared__ float box[3][SPREAD_BOX_CELLS];
-  __shared__ float4 sp[CHUNK_MAX];
-  __shared__ float sfx[CHUNK_MAX], sfy[CHUNK_MAX], sfz[CHUNK_MAX];
-  __shared__ int bb[6];
-  const int ch = xcd_block(Mm.n_chunks);
-  if (ch < 0) return;  // the whole block
-  const int2 range = Mm.chunk[ch];
-  const int a = range.x, nb = range.y - range.x;
-  const int t = threadIdx.x;
-  for (int k = t; k < nb; k += blockDim.x) {
-    sp[k] = Mm.x[a + k];
-    sfx[k] = 0.0f;
-    sfy[k] = 0.0f;
-    sfz[k] = 0.0f;
-  }
-  __syncthreads();
-  // Eq. (forcefromenergy): F_n = -sum over the faces at n of d(A0 w_S)/dx_n
-  const int j1 = Mm.chunk_face_off[ch + 1];
-  for (int e = Mm.chunk_face_off[ch] + t; e < j1; e += blockDim.x) {
-    const int j = Mm.chunk_face[e];
-    const int4 tj = Mm.tri[j];
-    const float4 rp = Mm.ref_p[j], gh = Mm.ref_ghi[j], gl = Mm.ref_glo[j];
-    const float4 mod = Mm.moduli[tj.w];
-    const FaceRef R{rp.x, rp.y, rp.z, rp.w, gh.x, gh.y, gh.z, gl.x, gl.y, gl.z};
-    float3 gc[3];
-    bool deg;
-    skalak_face_grad(Mm.x[tj.x], Mm.x[tj.y], Mm.x[tj.z], R, mod.x, mod.y, gc[0], gc[1], gc[2], deg);
-    if (deg) atomicOr(&L.ctrl->err, ERR_FACE);
-    const int corner[3] = {tj.x - a, tj.y - a, tj.z - a};
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      if (corner[c] < 0 || corner[c] >= nb) continue;
-      atomicAdd(&sfx[corner[c]], -gc[c].x);
-      atomicAdd(&sfy[corner[c]], -gc[c].y);
-      atomicAdd(&sfz[corner[c]], -gc[c].z);
-    }
-  }
-  __syncthreads();
-  for (int k = t; k < nb; k += blockDim.x) Mm.F[a + k] = make_float4(sfx[k], sfy[k], sfz[k], 0.0f);
-  const Bounds b = chunk_bounds<M>(sp, nb, bb, SPREAD_BOX_CELLS);
-  const int V = b.fits ? b.ex * b.ey * b.ez : 0;
-  for (int c = t; c < V; c += blockDim.x) box[0][c] = box[1][c] = box[2][c] = 0.0f;
-  __syncthreads();
-  const int4 o = Mm.origin[Mm.node_cap[a]];
-  float *g = L.g[par];
-  const int step = L.ctrl->step;
-  for (int q = t; q < nb * M3; q += blockDim.x) {
-    const int k = q / M3, sidx = q - k * M3;
-    const int sx = sidx % M, sy = (sidx / M) % M, sz = sidx / (M * M);
-    const float4 p = sp[k];
-    const int lx = stencil_lo<M>(p.x) + sx;
-    const int ly = stencil_lo<M>(p.y) + sy;
-    const int lz = stencil_lo<M>(p.z) + sz;
-    const float w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
-    if (w == 0.0f) continue;
-    const int Z = o.z + lz;
-    if (Z < 0 || Z >= L.nz) {
-      atomicOr(&L.ctrl->err, ERR_WALL);
-      continue;
-    }
-    const float4 F = make_float4(sfx[k], sfy[k], sfz[k], 0.0f);
-    if (b.fits) {
-      const int c = ((lz - b.z0) * b.ey + (ly - b.y0)) * b.ex + (lx - b.x0);
-      atomicAdd(&box[0][c], w * F.x);
-      atomicAdd(&box[1][c], w * F.y);
-      atomicAdd(&box[2][c], w * F.z);
-    } else {
-      const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
-      const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
-      unsafeAtomicAdd(g + n, w * F.x);
-      unsafeAtomicAdd(g + L.S + n, w * F.y);
-      unsafeAtomicAdd(g + 2 * L.S + n, w * F.z);
-      L.stamp[par][tile_of(L, X, Y, Z)] = step;
-    }
-  }
-  if (!b.fits) return;  // the whole block
-  __syncthreads();
-  // box nodes that received force: only in-range z can have (see above)
-  for (int c = t; c < V; c += blockDim.x) {
-    const float vx = box[0][c], vy = box[1][c], vz = box[2][c];
-    if (vx == 0.0f && vy == 0.0f && vz == 0.0f) continue;
-    const int lx = b.x0 + c % b.ex, ly = b.y0 + (c / b.ex) % b.ey, lz = b.z0 + c / (b.ex * b.ey);
-    const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny), Z = o.z + lz;
-    const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
-    if (vx != 0.0f) unsafeAtomicAdd(g + n, vx);
-    if (vy != 0.0f) unsafeAtomicAdd(g + L.S + n, vy);
-    if (vz != 0.0f) unsafeAtomicAdd(g + 2 * L.S + n, vz);
-    L.stamp[par][tile_of(L, X, Y, Z)] = step;
-  }
-}
-
 void launch_spread(const LatDev &L, const MemDev &M, int par, bool box, hipStream_t s) {
   if (M.nn <= 0) return;
-  if (M.n_chunks > 0) {
-    const dim3 grid(xcd_grid(M.n_chunks)), block(1024);
-    if (M.m == 2) k_spread_chunks<2><<<grid, block, 0, s>>>(L, M, par);
-    else if (M.m == 3) k_spread_chunks<3><<<grid, block, 0, s>>>(L, M, par);
-    else k_spread_chunks<4><<<grid, block, 0, s>>>(L, M, par);
-    return;
-  }
   const int full = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
   const bool half = (long long)M.nn * full / 64 >= SPREAD_HALF_WAVES;
   const int gs = M.m == 2 ? full : (half ? full / 2 : full);
@@ -676,46 +519,50 @@ __device__ __forceinline__ float3 lattice_velocity(const LatDev &L, const T *f, 
                      (jz + 0.5f * g[2 * L.S + n]) * inv_rho);
 }
 
-// The lattice velocity of every node of the tiles stamped by this step's
-// spreading (the tiles of all stencils with a nonzero weight), into L.U.  A
-// block scans tiles [t0, t0 + nt) in chunks of its thread count, gathers the
-// stamped ones of a chunk in LDS and gives each to one wavefront (64 lanes,
-// one per node).  All threads of the block call it.
+// The lattice velocity u(X, t+1) of Eq. (velocityinterpolation) at every
+// node that this step's stencils touch with a nonzero weight (node stamp =
+// step), into L.U.  Each wavefront scans 512 consecutive nodes (lattice
+// order, x fastest) for marks, lists the marked ones in LDS in that order,
+// and then evaluates the list with all its lanes, so that neighbouring
+// marked nodes share cache lines and few lanes idle.  Each node is evaluated
+// once, however many stencils overlap on it.  All threads of the block call
+// it; the block covers nodes [n0, n1), n1 - n0 <= NODE_VELOCITY_NODES.
+constexpr int NODE_VELOCITY_NODES = 2048;  // nodes per block: 512 per wavefront
+
 template <typename T>
-__device__ __forceinline__ void tile_velocity_block(const LatDev &L, int fsrc, int par, int t0,
-                                                    int nt) {
-  __shared__ int list[256];
-  __shared__ int cnt;
-  const int ntiles = L.tnx * L.tny * L.tnz;
+__device__ __forceinline__ void node_velocity_range(const LatDev &L, int fsrc, int par,
+                                                    long long n0, long long n1) {
+  __shared__ int list[NODE_VELOCITY_NODES];
   const int step = L.ctrl->step;
-  const int lane = threadIdx.x & 63;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  int *wl = list + wave * 512;
+  const long long w0 = n0 + (long long)wave * 512;
+  int cnt = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const long long n = w0 + k * 64 + lane;
+    const bool marked = n < n1 && L.nstamp[n] == step;
+    const unsigned long long mask = __ballot(marked);
+    if (marked) wl[cnt + __popcll(mask & ((1ull << lane) - 1))] = k * 64 + lane;
+    cnt += __popcll(mask);
+  }
+  __syncthreads();
   const T *f = static_cast<const T *>(L.f[fsrc]);
   const float *g = L.g[par];
-  for (int c0 = 0; c0 < nt; c0 += (int)blockDim.x) {
-    if (threadIdx.x == 0) cnt = 0;
-    __syncthreads();
-    if (c0 + (int)threadIdx.x < nt) {
-      const int tile = t0 + c0 + (int)threadIdx.x;
-      if (tile < ntiles && L.stamp[par][tile] == step) list[atomicAdd(&cnt, 1)] = tile;
-    }
-    __syncthreads();
-    const int n = cnt;
-    for (int k = (int)(threadIdx.x >> 6); k < n; k += (int)(blockDim.x >> 6)) {
-      const int tile = list[k];
-      const int tx = tile % L.tnx, ty = (tile / L.tnx) % L.tny, tz = tile / (L.tnx * L.tny);
-      const int X = 4 * tx + (lane & 3), Y = 4 * ty + ((lane >> 2) & 3), Z = 4 * tz + (lane >> 4);
-      if (X < L.nx && Y < L.ny && Z < L.nz) {
-        const float3 u = lattice_velocity<T>(L, f, g, X, Y, Z);
-        L.U[((long long)Z * L.ny + Y) * L.nx + X] = make_float4(u.x, u.y, u.z, 0.0f);
-      }
-    }
-    __syncthreads();  // list and cnt are reused by the next chunk
+  for (int j = lane; j < cnt; j += 64) {
+    const long long n = w0 + wl[j];
+    const long long row = n / L.nx;
+    const int X = (int)(n - row * L.nx), Y = (int)(row % L.ny), Z = (int)(row / L.ny);
+    const float3 u = lattice_velocity<T>(L, f, g, X, Y, Z);
+    L.U[n] = make_float4(u.x, u.y, u.z, 0.0f);
   }
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_tile_velocity(LatDev L, int fsrc, int par, int nt) {
-  tile_velocity_block<T>(L, fsrc, par, (int)blockIdx.x * nt, nt);
+__global__ __launch_bounds__(256) void k_node_velocity(LatDev L, int fsrc, int par) {
+  const long long N = (long long)L.nx * L.ny * L.nz;
+  const long long n0 = (long long)blockIdx.x * NODE_VELOCITY_NODES;
+  node_velocity_range<T>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES));
 }
 
 // The lattice velocity is evaluated once per lattice node of the block's
@@ -730,7 +577,7 @@ struct InterpLDS {
   int bb[6];
 };
 
-// UF: read the lattice velocity from L.U (filled by the tile-velocity pass
+// UF: read the lattice velocity from L.U (filled by the node-velocity pass
 // of this step) instead of evaluating it from the populations.
 // HALF: two stencil nodes per lane for the wider deltas, as in spreading.
 template <typename T, int M, bool BOX, bool UF, bool HALF = false>
@@ -865,7 +712,7 @@ __global__ __launch_bounds__(256) void k_interp_advect(LatDev L, MemDev Mm, int 
   if (blk >= 0) interp_lanes<T, M, BOX, false, HALF>(L, Mm, fsrc, par, advect, blk, sm);
 }
 
-// Interpolation from the tile-velocity field.
+// Interpolation from the node-velocity field.
 template <typename T, int M>
 __global__ __launch_bounds__(256) void k_interp_field(LatDev L, MemDev Mm, int fsrc, int par,
                                                       int advect, int nblocks) {
@@ -875,134 +722,9 @@ __global__ __launch_bounds__(256) void k_interp_field(LatDev L, MemDev Mm, int f
   if (blk >= 0) interp_lanes<T, M, false, true>(L, Mm, fsrc, par, advect, blk, sm);
 }
 
-// ---- chunked interpolation + advection ----------------------------------------
-// One block per chunk.  When the chunk's stencil box fits in LDS, the lattice
-// velocity is evaluated once at every box node a stencil touches with nonzero
-// weight (consecutive threads on consecutive x: coalesced population reads)
-// and the node sums are taken from LDS; otherwise every stencil node reads the
-// populations itself.  Node sums use the same lane groups as the per-node
-// kernel.  One thread advances the device step counter.
-template <typename T, int M>
-__global__ __launch_bounds__(256) void k_interp_chunks(LatDev L, MemDev Mm, int fsrc, int par,
-                                                       int advect) {
-  constexpr int M3 = M * M * M;
-  constexpr int GS = group_size<M>();
-  __shared__ float box[3][BOX_CELLS];
-  __shared__ unsigned char mark[BOX_CELLS];
-  __shared__ float4 sp[CHUNK_MAX];
-  __shared__ int bb[6];
-  if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
-  const int ch = xcd_block(Mm.n_chunks);
-  if (ch < 0) return;  // the whole block
-  const int2 range = Mm.chunk[ch];
-  const int a = range.x, nb = range.y - range.x;
-  const int t = threadIdx.x;
-  for (int k = t; k < nb; k += blockDim.x) sp[k] = Mm.x[a + k];
-  const Bounds b = chunk_bounds<M>(sp, nb, bb, BOX_CELLS);
-  const int V = b.fits ? b.ex * b.ey * b.ez : 0;
-  const int4 o = Mm.origin[Mm.node_cap[a]];
-  const T *f = static_cast<const T *>(L.f[fsrc]);
-  const float *g = L.g[par];
-  if (b.fits) {
-    for (int c = t; c < V; c += blockDim.x) mark[c] = 0;
-    __syncthreads();
-    for (int q = t; q < nb * M3; q += blockDim.x) {
-      const int k = q / M3, sidx = q - k * M3;
-      const float4 p = sp[k];
-      const int lx = stencil_lo<M>(p.x) + sidx % M;
-      const int ly = stencil_lo<M>(p.y) + (sidx / M) % M;
-      const int lz = stencil_lo<M>(p.z) + sidx / (M * M);
-      const float w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
-      if (w != 0.0f) mark[((lz - b.z0) * b.ey + (ly - b.y0)) * b.ex + (lx - b.x0)] = 1;
-    }
-    __syncthreads();
-    for (int c = t; c < V; c += blockDim.x) {
-      if (!mark[c]) continue;
-      const int lx = b.x0 + c % b.ex, ly = b.y0 + (c / b.ex) % b.ey, lz = b.z0 + c / (b.ex * b.ey);
-      const int Z = o.z + lz;
-      float3 u = make_float3(0.0f, 0.0f, 0.0f);
-      if (Z < 0 || Z >= L.nz) {
-        atomicOr(&L.ctrl->err, ERR_WALL);
-      } else {
-        const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
-        u = lattice_velocity<T>(L, f, g, X, Y, Z);
-      }
-      box[0][c] = u.x;
-      box[1][c] = u.y;
-      box[2][c] = u.z;
-    }
-    __syncthreads();
-  }
-  const int lane = t & (GS - 1);
-  for (int k0 = 0; k0 < nb; k0 += (int)blockDim.x / GS) {
-    const int k = k0 + t / GS;
-    float ux = 0.0f, uy = 0.0f, uz = 0.0f;
-    float4 p = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    if (k < nb) {
-      p = sp[k];
-      if (lane < M3) {
-        const int lx = stencil_lo<M>(p.x) + lane % M;
-        const int ly = stencil_lo<M>(p.y) + (lane / M) % M;
-        const int lz = stencil_lo<M>(p.z) + lane / (M * M);
-        const float w = phi<M>((float)lx - p.x) * phi<M>((float)ly - p.y) * phi<M>((float)lz - p.z);
-        if (w != 0.0f) {
-          float3 u;
-          if (b.fits) {
-            const int c = ((lz - b.z0) * b.ey + (ly - b.y0)) * b.ex + (lx - b.x0);
-            u = make_float3(box[0][c], box[1][c], box[2][c]);
-          } else {
-            const int Z = o.z + lz;
-            if (Z < 0 || Z >= L.nz) {
-              atomicOr(&L.ctrl->err, ERR_WALL);
-              u = make_float3(0.0f, 0.0f, 0.0f);
-            } else {
-              const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
-              u = lattice_velocity<T>(L, f, g, X, Y, Z);
-            }
-          }
-          ux = w * u.x;
-          uy = w * u.y;
-          uz = w * u.z;
-        }
-      }
-    }
-    ux = group_sum<GS>(ux);
-    uy = group_sum<GS>(uy);
-    uz = group_sum<GS>(uz);
-    if (k < nb && lane == 0) {
-      const int node = a + k;
-      if (advect == 1) {
-        const float4 up = Mm.u[node];
-        p.x += 1.5f * ux - 0.5f * up.x;
-        p.y += 1.5f * uy - 0.5f * up.y;
-        p.z += 1.5f * uz - 0.5f * up.z;
-      } else {
-        p.x += ux;
-        p.y += uy;
-        p.z += uz;
-      }
-      Mm.u[node] = make_float4(ux, uy, uz, 0.0f);
-      Mm.x[node] = p;
-    }
-  }
-}
-
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
                           int advect, int mode, hipStream_t s) {
   if (M.nn <= 0) return;
-  if (M.n_chunks > 0) {
-    const dim3 grid(xcd_grid(M.n_chunks)), block(256);
-#define IBM_LAUNCH_INTERP_CHUNKS(T)                                                            \
-  do {                                                                                         \
-    if (M.m == 2) k_interp_chunks<T, 2><<<grid, block, 0, s>>>(L, M, fsrc, par, advect);      \
-    else if (M.m == 3) k_interp_chunks<T, 3><<<grid, block, 0, s>>>(L, M, fsrc, par, advect); \
-    else k_interp_chunks<T, 4><<<grid, block, 0, s>>>(L, M, fsrc, par, advect);               \
-  } while (0)
-    if (fp16) IBM_LAUNCH_INTERP_CHUNKS(__half);
-    else IBM_LAUNCH_INTERP_CHUNKS(float);
-#undef IBM_LAUNCH_INTERP_CHUNKS
-    return;
-  }
   const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
   const long long lanes = (long long)M.nn * gs;
   const int nblocks = (int)((lanes + 255) / 256);
@@ -1033,13 +755,12 @@ void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, 
 #undef IBM_LAUNCH_INTERP
     return;
   }
-  // the lattice velocity of the stamped tiles, then the stencil sums from it
-  const long long tiles = (long long)L.tnx * L.tny * L.tnz;
-  const int vt = 32;  // tiles scanned per block
-  const dim3 vgrid((unsigned)((tiles + vt - 1) / vt));
+  // the lattice velocity at the marked nodes, then the stencil sums from it
+  const long long N = (long long)L.nx * L.ny * L.nz;
+  const dim3 vgrid((unsigned)((N + NODE_VELOCITY_NODES - 1) / NODE_VELOCITY_NODES));
 #define IBM_LAUNCH_INTERP_FIELD(T)                                                                  \
   do {                                                                                              \
-    k_tile_velocity<T><<<vgrid, block, 0, s>>>(L, fsrc, par, vt);                                   \
+    k_node_velocity<T><<<vgrid, block, 0, s>>>(L, fsrc, par);                                       \
     if (M.m == 2) k_interp_field<T, 2><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);      \
     else if (M.m == 3) k_interp_field<T, 3><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks); \
     else k_interp_field<T, 4><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);             \
@@ -1398,7 +1119,7 @@ __global__ __launch_bounds__(256) void k_batch_spread(BatchDev B, int par) {
 
 // The first block of each run advances that run's device step counter.
 // MODE as for launch_interp_advect: 0 per stencil node, 1 per block in LDS,
-// 2 from each run's tile-velocity field (k_batch_tile_velocity first).
+// 2 from each run's velocity field (k_batch_node_velocity first).
 template <typename T, int MODE>
 __global__ __launch_bounds__(256) void k_batch_interp(BatchDev B, int fsrc, int par, int advect) {
   __shared__ InterpLDS sm;
@@ -1414,19 +1135,23 @@ __global__ __launch_bounds__(256) void k_batch_interp(BatchDev B, int fsrc, int 
   else interp_lanes<T, 4, MODE == 1, MODE == 2, true>(L, Mm, fsrc, par, advect, it.y, sm);
 }
 
-// The tile-velocity pass of every run, on the lattice work items: the nb
-// blocks of a run scan its tiles in equal ranges.
+// The velocity pass of every run, on the lattice work items: the nb blocks
+// of a run take its nodes in equal ranges.
 template <typename T>
-__global__ __launch_bounds__(256) void k_batch_tile_velocity(BatchDev B, int fsrc, int par) {
+__global__ __launch_bounds__(256) void k_batch_node_velocity(BatchDev B, int fsrc, int par) {
   if ((int)blockIdx.x >= B.n_lat_items) return;
   const int2 it = B.lat_items[blockIdx.x];
   const LatDev &L = B.lat[it.x];
-  if (!B.mem[it.x].nn) return;  // no capsule: nothing is stamped
-  const long long rows = (long long)L.ny * L.nz;
-  const long long nb = L.tpr ? ((rows + L.rpw - 1) / L.rpw + 3) / 4 : ((long long)L.nx * rows + 255) / 256;
-  const long long ntiles = (long long)L.tnx * L.tny * L.tnz;
-  const int nt = (int)((ntiles + nb - 1) / nb);
-  tile_velocity_block<T>(L, fsrc, par, it.y * nt, nt);
+  if (!B.mem[it.x].nn) return;  // no capsule: nothing is marked
+  const long long rows = (long long)L.ny * L.nz, N = (long long)L.nx * rows;
+  const long long nb = L.tpr ? ((rows + L.rpw - 1) / L.rpw + 3) / 4 : (N + 255) / 256;
+  long long per = (N + nb - 1) / nb;
+  if (per > NODE_VELOCITY_NODES) per = NODE_VELOCITY_NODES;  // not reached: a block of
+                                                             // the lattice update covers
+                                                             // at most 1024 nodes
+  const long long n0 = (long long)it.y * per;
+  if (n0 >= N) return;  // uniform across the block
+  node_velocity_range<T>(L, fsrc, par, n0, min(N, n0 + per));
 }
 
 void launch_batch_spread(const BatchDev &B, int par, bool box, hipStream_t s) {
@@ -1443,7 +1168,7 @@ void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int adv
 #define IBM_LAUNCH_BATCH_INTERP(T)                                                            \
   do {                                                                                        \
     if (mode == 2) {                                                                          \
-      k_batch_tile_velocity<T><<<dim3(B.n_lat_items), block, 0, s>>>(B, fsrc, par);           \
+      k_batch_node_velocity<T><<<dim3(B.n_lat_items), block, 0, s>>>(B, fsrc, par);           \
       k_batch_interp<T, 2><<<grid, block, 0, s>>>(B, fsrc, par, advect);                      \
     } else if (mode == 1) {                                                                   \
       k_batch_interp<T, 1><<<grid, block, 0, s>>>(B, fsrc, par, advect);                      \
@@ -1551,8 +1276,9 @@ static void launch_interp_far_t(const LatDev &L, const MemDev &M, int fsrc, int 
   const int nblocks = (int)(((long long)M.nn * gs + 255) / 256);
   const dim3 grid(xcd_grid(nblocks) + far_blocks(L, rs)), block(256);
   if (mode == 2) {
-    const long long tiles = (long long)L.tnx * L.tny * L.tnz;
-    k_tile_velocity<T><<<dim3((unsigned)((tiles + 31) / 32)), block, 0, s>>>(L, fsrc, par, 32);
+    const long long N = (long long)L.nx * L.ny * L.nz;
+    k_node_velocity<T><<<dim3((unsigned)((N + NODE_VELOCITY_NODES - 1) / NODE_VELOCITY_NODES)), block,
+                         0, s>>>(L, fsrc, par);
   }
 #define IBM_LAUNCH_INTERP_FAR(MD)                                                                                \
   do {                                                                                                           \

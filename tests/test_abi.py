@@ -41,10 +41,11 @@ def test_size_queries_and_validation(B):
     n = ctypes.c_size_t()
     assert B.lib.ibm_lattice_bytes(128, 128, 128, 0, ctypes.byref(n)) == 0
     # per node: two population copies (2 x 19 x 4 B in FP32, 2 x 19 x 2 B in
-    # FP16), two force-density fields (2 x 3 x 4 B) and the velocity field
-    # interpolation reads (16 B); tile stamps and the control block add little
+    # FP16), two force-density fields (2 x 3 x 4 B), the velocity field
+    # interpolation reads (16 B) and the node stamps (4 B); tile stamps and
+    # the control block add little
     N = 128 ** 3
-    per32, per16 = 2 * 19 * 4 + 24 + 16, 2 * 19 * 2 + 24 + 16
+    per32, per16 = 2 * 19 * 4 + 24 + 16 + 4, 2 * 19 * 2 + 24 + 16 + 4
     assert per32 * N <= n.value < 1.02 * per32 * N
     m = ctypes.c_size_t()
     assert B.lib.ibm_lattice_bytes(128, 128, 128, 1, ctypes.byref(m)) == 0

@@ -93,10 +93,8 @@ def deformed_state(c, steps):
     return rep_populations(sim.f), rep_positions(sim.x, c.node_counts)
 
 
-def compare_one_step(B, c, f_s, x_s, tol_f=1e-5, tol_m=1e-5, chunk=None, opts=None):
+def compare_one_step(B, c, f_s, x_s, tol_f=1e-5, tol_m=1e-5, opts=None):
     lat = c.gpu(graph=False)
-    if chunk is not None:
-        lat.set_option(B.OPT_CHUNK_NODES, chunk)
     for k, v in (opts or {}).items():
         lat.set_option(k, v)
     lat.set_populations(f_s)
@@ -190,17 +188,6 @@ def test_coupled_step_parity_crowded_overlapping_capsules(B):
     compare_one_step(B, c, f_s, x_s)
 
 
-@pytest.mark.parametrize("chunk", [0, 16, 32, 128, 256, 1024])
-def test_coupling_chunk_sizes(B, chunk):
-    """Spreading and interpolation per lane group (0) and per chunk of
-    16..1024 nodes (stencils summed in on-chip memory; 1024: the whole
-    642-node capsule is one chunk) all match the oracle."""
-    say("chunk size", chunk)
-    c = small_case(n=(40, 36, 30), m=4, level=3, r=8.0, ca=0.02, uw=0.03)
-    f_s, x_s = deformed_state(c, 10)
-    compare_one_step(B, c, f_s, x_s, chunk=chunk)
-
-
 @pytest.mark.parametrize("m", [2, 3, 4])
 @pytest.mark.parametrize("box", [1, 2, 3, 4, 5])
 def test_stencil_box_modes(B, m, box):
@@ -232,16 +219,16 @@ def test_autotune_keeps_the_run_on_the_oracle(B):
     assert np.max(np.abs(xg - sim.x)) < 1e-3
 
 
-@pytest.mark.parametrize("chunk,box", [(0, 3), (16, 3), (256, 3), (0, 5)])
-def test_coupling_chunk_box_too_large(B, chunk, box):
+@pytest.mark.parametrize("box", [3, 5])
+def test_coupling_box_too_large(B, box):
     """A coarse capsule (42 nodes, radius 14): the stencil box of every block
-    (chunk 0) or chunk exceeds the on-chip capacity, so the contributions go
-    to and come from the global fields directly (with box 5 the tiles for the
-    tile-velocity field are then stamped per stencil node)."""
-    say("oversized chunk boxes", chunk, box)
+    exceeds the on-chip capacity, so the contributions go to and come from
+    the global fields directly (with box 5 the nodes for the velocity field
+    are then marked per stencil node)."""
+    say("oversized boxes", box)
     c = small_case(n=(40, 40, 40), m=3, level=1, r=14.0, ca=0.02, uw=0.03)
     f_s, x_s = deformed_state(c, 10)
-    compare_one_step(B, c, f_s, x_s, chunk=chunk, opts={B.OPT_STENCIL_BOX: box})
+    compare_one_step(B, c, f_s, x_s, opts={B.OPT_STENCIL_BOX: box})
 
 
 def test_undeformed_capsule_has_zero_force(B):
@@ -647,22 +634,21 @@ def test_bad_arguments(B):
 
 
 def test_collide_stream_variants_agree(B):
-    """Every launch variant of the collide-stream kernel computes the same
-    update: the 32 per-node and row forms, and the row form in 128- and
-    64-thread blocks (bits 6, 7) and with cached accesses (bit 8), on padded
-    and unpadded rows."""
+    """Every launch variant of the collide-stream kernel computes the
+    oracle's update: the per-node forms (two nodes per thread, non-temporal
+    accesses, 128-thread blocks) and the row form in 256-, 128- and 64-thread
+    blocks (bits 6, 7) and with cached stores (bit 8), on padded and unpadded
+    rows, each for six coupled steps from the same state as the oracle."""
     for shape in ((32, 20, 16), (30, 20, 16), (27, 19, 18)):
         c = small_case(n=shape, m=3, ca=0.02)
-        ref = None
-        for v in list(range(32)) + [80, 144, 87, 151, 272, 279]:
+        sim = c.oracle()
+        assert sim.run(6) == 0
+        for v in list(range(8)) + [16, 80, 144, 87, 151, 272, 279]:
             lat = c.gpu(graph=False)
             lat.set_option(B.OPT_LBM_VARIANT, v)
             lat.step(6)
             f = lat.populations().cpu().numpy()
             x = lat.mesh()[0].cpu().numpy()
             lat.close()
-            if ref is None:
-                ref = (f, x)
-            else:
-                assert rel_err(f, ref[0]) < 1e-6, v
-                assert np.max(np.abs(x - ref[1])) < 1e-6, v
+            assert rel_err(f, sim.f) < 1e-5, v
+            assert np.max(np.abs(x - sim.x)) < 1e-5, v
