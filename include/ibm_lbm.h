@@ -247,6 +247,16 @@ int ibm_set_mesh(ibm_lattice *lat, const double *xyz_host);
  * FP64, from FP64 reductions on the device; waits. */
 int ibm_observables(ibm_lattice *lat, double *out_host);
 
+/* Gradient of the Taylor deformation D of one capsule (Sec. III: D from the
+ * semiaxes of the ellipsoid with the capsule's inertia tensor) with respect
+ * to its node positions, at the current positions, by reverse
+ * differentiation of the FP64 observables (eigenvalue derivatives
+ * dE_k = v_k^T dI v_k; the eigenvalues must be distinct, which fails for a
+ * sphere).  Writes dD/dx as FP64 [nn][3] rows (caller's node order) of the
+ * capsule's nodes into the device buffer grad_dev; rows of other capsules are
+ * left untouched.  Waits. */
+int ibm_deformation_gradient(ibm_lattice *lat, int capsule, double *grad_dev);
+
 /* FP64 totals of the current populations over the whole lattice
  * (Sec. II.A, Eqs. lbmmomenta0/1 summed over all nodes):
  *   out_dev[0] = sum_X sum_i f_i(X)          (mass)

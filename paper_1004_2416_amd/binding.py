@@ -69,6 +69,7 @@ def _load():
         "ibm_observables": ([v, v], i),
         "ibm_synchronize": ([v], i),
         "ibm_totals_bytes": ([v, ctypes.POINTER(sz)], i),
+        "ibm_deformation_gradient": ([v, i, v], i),
         "ibm_lattice_totals": ([v, v, sz, v], i),
         "ibm_lattice_totals_noalloc": ([v, v], i),
         "ibm_set_option": ([v, i, i], i),
@@ -272,6 +273,14 @@ class Lattice:
         assert xyz.shape == (self.nn, 3)
         _check(lib.ibm_set_mesh(self._h, _ptr(xyz)))
 
+    def deformation_gradient(self, capsule: int = 0) -> np.ndarray:
+        """dD/dx [nn][3] of one capsule's Taylor deformation at the current
+        node positions (zero rows for the other capsules)."""
+        torch = _torch()
+        out = torch.zeros((self.nn, 3), dtype=torch.float64, device=self.device)
+        _check(lib.ibm_deformation_gradient(self._h, int(capsule), ctypes.c_void_p(out.data_ptr())))
+        return out.cpu().numpy()
+
     def totals(self) -> np.ndarray:
         """FP64 (mass, momentum x, y, z) of the current populations, summed on
         the device (ibm_lattice_totals)."""
@@ -420,11 +429,15 @@ def _deformation_fn():
             def forward(ctx, ks, ka, uw, make_lattice, steps, checkpoint_every, capsule):
                 lat = make_lattice(ks.detach().cpu().tolist(), ka.detach().cpu().tolist(),
                                    float(uw))
+                f64 = dict(dtype=torch.float64)
                 try:
+                    if not any(ctx.needs_input_grad[:3]):
+                        # no gradient wanted: the forward run alone
+                        lat.step(steps)
+                        return torch.tensor(float(lat.observables()[capsule, 4]), **f64)
                     g = lat.adjoint_gradient(steps, checkpoint_every, capsule, couette_start=True)
                 finally:
                     lat.close()
-                f64 = dict(dtype=torch.float64)
                 ctx.save_for_backward(torch.as_tensor(g["dks"], **f64),
                                       torch.as_tensor(g["dka"], **f64),
                                       torch.tensor(g["duw"], **f64))
@@ -448,8 +461,10 @@ def deformation(make_lattice, ks, ka, uw, steps: int, checkpoint_every: int = 10
 
     make_lattice(ks, ka, uw) must return a new Lattice at t = 0 with its
     capsules added with these moduli and ibm_set_shear(uw, init_profile=1)
-    applied, so that the start also depends on uw.  The forward call runs
-    ibm_adjoint_gradient once (forward sweep and reverse sweep) and keeps the
-    gradient; backward only scales it."""
+    applied, so that the start also depends on uw.  When a gradient is
+    needed (an input requires grad and grad mode is on), the forward call
+    runs ibm_adjoint_gradient once (forward sweep and reverse sweep) and
+    keeps the gradient, and backward only scales it; otherwise it runs the
+    steps alone."""
     return _deformation_fn().apply(ks, ka, uw, make_lattice, int(steps), int(checkpoint_every),
                                    int(capsule))

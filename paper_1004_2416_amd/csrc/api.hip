@@ -1079,6 +1079,17 @@ int ibm_observables(ibm_lattice *lat, double *out_host) {
   return rc ? rc : ok();
 }
 
+int ibm_deformation_gradient(ibm_lattice *lat, int capsule, double *grad_dev) {
+  if (!lat || !grad_dev) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  if (!lat->has_mem) return fail(IBM_ERR_BAD_STATE, "no membrane attached");
+  if (capsule < 0 || capsule >= lat->M.n_caps)
+    return fail(IBM_ERR_INVALID_ARG, "capsule %d out of range", capsule);
+  ibm::launch_obs_grad64(lat->M, capsule, grad_dev, lat->stream);
+  IBM_HIP(hipGetLastError());
+  int rc = check_device(lat);
+  return rc ? rc : ok();
+}
+
 int ibm_totals_bytes(const ibm_lattice *lat, size_t *bytes) {
   if (!lat || !bytes) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
   *bytes = (size_t)ibm::totals_parts(lat->L) * sizeof(double4);
@@ -1658,8 +1669,7 @@ int ibm_adjoint_gradient(ibm_lattice *lat, int64_t steps, int checkpoint_every, 
   // objective D(T) of the capsule and its gradient with respect to x(T)
   ibm::launch_observables(M, lat->L.ctrl, s);
   for (void *p : {(void *)A.lx, (void *)A.pk}) ibm::launch_fill_u32(p, 4LL * M.nn, 0u, s);
-  ibm::launch_obs_grad(M, capsule, lat->node_off[capsule + 1] - lat->node_off[capsule], 1e-5,
-                       A.lx, s);
+  ibm::launch_obs_grad(M, capsule, A.lx, s);
   for (int k = 0; k < 2; ++k) ibm::launch_fill_u32(A.lf[k], al.pop, 0u, s);
   ibm::launch_fill_u32(A.lU, 3 * lat->lay.S, 0u, s);
   ibm::launch_fill_u32(A.lg, 3 * lat->lay.S, 0u, s);

@@ -77,8 +77,11 @@ void launch_observables(const MemDev &M, Ctrl *ctrl, hipStream_t s);
 // observables of the mesh x + h dx into obs [n_caps][16]
 void launch_observables_shifted(const MemDev &M, Ctrl *ctrl, const float4 *dx, double h,
                                 double *obs, hipStream_t s);
-void launch_obs_grad(const MemDev &M, int c, int nodes_of_c, double h, float4 *grad,
-                     hipStream_t s);
+// dD/dx of capsule c (reverse differentiation of the observables) into the
+// capsule's rows of grad (FP32, internal node order; other rows untouched),
+// or as FP64 [nn][3] rows in the caller's node order
+void launch_obs_grad(const MemDev &M, int c, float4 *grad, hipStream_t s);
+void launch_obs_grad64(const MemDev &M, int c, double *grad, hipStream_t s);
 void launch_adj_interp(const LatDev &L, const MemDev &M, const AdjDev &A, const float *f1, int par,
                        int step, hipStream_t s);
 void launch_adj_spread(const LatDev &L, const MemDev &M, const AdjDev &A, hipStream_t s);

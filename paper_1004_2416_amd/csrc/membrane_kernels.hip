@@ -1537,9 +1537,13 @@ struct PosPoke {
 // Observables of capsule c (layout of ibm_observables, capsule-local
 // centroid); all threads of the block call it, thread 0 gets out[] and the
 // return value (all observables finite).
+// aux (nullable, thread 0): the intermediates the derivative of D needs:
+// [0] V, [1..6] the face sums S of I = S / (5 V) (xx, yy, zz, xy, xz, yz),
+// [7..9] the eigenvalues E1 <= E2 <= E3, [10..18] their unit eigenvectors
+// (v_k at 10 + 3k).
 template <class Pos>
 __device__ bool capsule_obs(const MemDev &M, int c, const Pos &pos, double (*red)[256], double *cen,
-                            double *out) {
+                            double *out, double *aux = nullptr) {
   const int f0 = M.cap_face_off[c], f1 = M.cap_face_off[c + 1];
   double v1[4] = {0.0, 0.0, 0.0, 0.0};
   for (int j = f0 + threadIdx.x; j < f1; j += blockDim.x) {
@@ -1621,6 +1625,14 @@ __device__ bool capsule_obs(const MemDev &M, int c, const Pos &pos, double (*red
     out[8] = rc;
     out[9] = s7[6];
     for (int q = 0; q < 6; ++q) out[10 + q] = I[q];
+    if (aux) {
+      aux[0] = V;
+      for (int q = 0; q < 6; ++q) aux[1 + q] = s7[q];
+      for (int k = 0; k < 3; ++k) {
+        aux[7 + k] = e[id[k]];
+        for (int d = 0; d < 3; ++d) aux[10 + 3 * k + d] = vec[d][id[k]];
+      }
+    }
     finite = isfinite(V) && isfinite(out[4]);
     for (int q = 0; q < 6; ++q) finite = finite && isfinite(I[q]);
   }
@@ -1643,25 +1655,179 @@ __global__ __launch_bounds__(256) void k_observables(MemDev M, Ctrl *ctrl, const
   if (!finite) atomicOr(&ctrl->err, ERR_NONFINITE);
 }
 
-// Gradient of the Taylor deformation D of capsule c with respect to its node
-// positions, by FP64 central differences (one block per node and axis),
-// written as FP32 into grad (the capsule's rows; other rows untouched).
-__global__ __launch_bounds__(256) void k_obs_grad(MemDev M, int c, double h, float4 *grad) {
-  __shared__ double red[7][256];
-  __shared__ double cen[3];
-  const int n0 = M.cap_node_off[c];
-  const int node = n0 + (int)blockIdx.x / 3, axis = (int)blockIdx.x % 3;
-  double outp[16], outm[16];
-  capsule_obs(M, c, PosPoke{&M, node, axis, h}, red, cen, outp);
-  __syncthreads();
-  capsule_obs(M, c, PosPoke{&M, node, axis, -h}, red, cen, outm);
-  if (threadIdx.x == 0) reinterpret_cast<float *>(grad + node)[axis] = (float)((outp[4] - outm[4]) / (2.0 * h));
+// dD/dx of capsule c at the stored node positions (Sec. III), by reverse
+// differentiation of the observables:
+//   D = (r_a - r_c)/(r_a + r_c), r_a^2 = 5/2 (E2 + E3 - E1),
+//   r_c^2 = 5/2 (E1 + E2 - E3);
+//   dE_k = v_k^T dI v_k for the eigenpairs of I (distinct eigenvalues), so
+//   dD/dI = sum_k dD/dE_k v_k v_k^T;
+//   I = S / (5 V) with the face sums S = sum_f Q(r_f) (r_f . a_f),
+//   Q(r) = |r|^2 1 - r r^T, r_f the face centroid relative to the volume
+//   centroid c and a_f = (x2 - x1) x (x3 - x1) / 2 the area normal;
+//   V = sum_f x1 . (x2 x x3) / 6 and c = sum_f v_f (x1 + x2 + x3) / (4 V).
+// Thread 0 forms the capsule-level adjoints (of S, V and of the centroid's
+// numerator, the latter after a block sum of -sum_f dD/dr_f); then every
+// node gathers the contributions of its incident faces (deterministic sums)
+// and writes FP64 (out64) or FP32 (out32, xyz of a float4) at its internal
+// index.  One block per call.
+struct FaceAdj {
+  double Sb[6];   // dD/dS
+  double Vb;      // dD/dV through I and the centroid
+  double Pb[3];   // dD/d(sum_f v_f (x1 + x2 + x3) / 4)
+};
+
+__device__ __forceinline__ void face_r_adjoint(const double3 A, const double3 B, const double3 C,
+                                               const double *cen, const double *Sb, double3 &r,
+                                               double3 &an, double3 &rb, double &P) {
+  const double3 e1 = make_double3(B.x - A.x, B.y - A.y, B.z - A.z);
+  const double3 e2 = make_double3(C.x - A.x, C.y - A.y, C.z - A.z);
+  an = make_double3(0.5 * (e1.y * e2.z - e1.z * e2.y), 0.5 * (e1.z * e2.x - e1.x * e2.z),
+                    0.5 * (e1.x * e2.y - e1.y * e2.x));
+  r = make_double3((A.x + B.x + C.x) / 3.0 - cen[0], (A.y + B.y + C.y) / 3.0 - cen[1],
+                   (A.z + B.z + C.z) / 3.0 - cen[2]);
+  const double rn = r.x * an.x + r.y * an.y + r.z * an.z;
+  // sum_q Sb_q Q_q(r) = r^T K r with K = [[Sb1 + Sb2, -Sb3/2, -Sb4/2], ...]
+  const double k00 = Sb[1] + Sb[2], k11 = Sb[0] + Sb[2], k22 = Sb[0] + Sb[1];
+  const double k01 = -0.5 * Sb[3], k02 = -0.5 * Sb[4], k12 = -0.5 * Sb[5];
+  const double kx = k00 * r.x + k01 * r.y + k02 * r.z;
+  const double ky = k01 * r.x + k11 * r.y + k12 * r.z;
+  const double kz = k02 * r.x + k12 * r.y + k22 * r.z;
+  P = r.x * kx + r.y * ky + r.z * kz;
+  rb = make_double3(2.0 * rn * kx + P * an.x, 2.0 * rn * ky + P * an.y, 2.0 * rn * kz + P * an.z);
 }
 
-void launch_obs_grad(const MemDev &M, int c, int nodes_of_c, double h, float4 *grad,
-                     hipStream_t s) {
-  if (nodes_of_c <= 0) return;
-  k_obs_grad<<<dim3(3 * nodes_of_c), dim3(256), 0, s>>>(M, c, h, grad);
+template <typename O>
+__device__ void obs_grad_D(const MemDev &M, int c, O out) {
+  __shared__ double red[7][256];
+  __shared__ double cen[3];
+  __shared__ double aux[19];
+  __shared__ FaceAdj fa;
+  const PosShift pos{&M, nullptr, 0.0};
+  double o[16];
+  capsule_obs(M, c, pos, red, cen, o, threadIdx.x == 0 ? aux : nullptr);
+  if (threadIdx.x == 0) {
+    const double V = aux[0];
+    const double E1 = aux[7], E2 = aux[8], E3 = aux[9];
+    const double ra = sqrt(fmax(2.5 * (E2 + E3 - E1), 0.0));
+    const double rc = sqrt(fmax(2.5 * (E1 + E2 - E3), 0.0));
+    const double den = (ra + rc) * (ra + rc);
+    const double dra = 2.0 * rc / den, drc = -2.0 * ra / den;
+    const double ga = ra > 0.0 ? 1.25 / ra : 0.0, gc = rc > 0.0 ? 1.25 / rc : 0.0;
+    const double gE[3] = {-dra * ga + drc * gc, dra * ga + drc * gc, dra * ga - drc * gc};
+    double Ib[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int k = 0; k < 3; ++k)
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) Ib[i][j] += gE[k] * aux[10 + 3 * k + i] * aux[10 + 3 * k + j];
+    // I_q = S_q / (5 V); the off-diagonal I_q sits twice in the matrix
+    const double dI[6] = {Ib[0][0], Ib[1][1], Ib[2][2], 2.0 * Ib[0][1], 2.0 * Ib[0][2],
+                          2.0 * Ib[1][2]};
+    double vb = 0.0;
+    for (int q = 0; q < 6; ++q) {
+      fa.Sb[q] = dI[q] / (5.0 * V);
+      vb -= dI[q] * aux[1 + q] / (5.0 * V * V);
+    }
+    fa.Vb = vb;
+  }
+  __syncthreads();
+  // dD/dc = -sum_f dD/dr_f
+  const int f0 = M.cap_face_off[c], f1 = M.cap_face_off[c + 1];
+  double cb[3] = {0.0, 0.0, 0.0};
+  for (int j = f0 + threadIdx.x; j < f1; j += blockDim.x) {
+    const int4 t = M.tri[j];
+    double3 r, an, rb;
+    double P;
+    face_r_adjoint(pos(t.x), pos(t.y), pos(t.z), cen, fa.Sb, r, an, rb, P);
+    cb[0] -= rb.x;
+    cb[1] -= rb.y;
+    cb[2] -= rb.z;
+  }
+  block_sum<3>(red, cb);
+  if (threadIdx.x == 0) {
+    const double V = aux[0];
+    // c = Pnum / V: dD/dPnum = cb / V, and V gains -cb . c / V
+    for (int d = 0; d < 3; ++d) fa.Pb[d] = cb[d] / V;
+    fa.Vb -= (cb[0] * cen[0] + cb[1] * cen[1] + cb[2] * cen[2]) / V;
+  }
+  __syncthreads();
+  const int n0 = M.cap_node_off[c], n1 = M.cap_node_off[c + 1];
+  for (int n = n0 + threadIdx.x; n < n1; n += blockDim.x) {
+    double gx = 0.0, gy = 0.0, gz = 0.0;
+    for (int e = M.csr_off[n]; e < M.csr_off[n + 1]; ++e) {
+      const int ent = M.csr_ent[e];
+      const int4 t = M.tri[ent >> 2];
+      const int corner = ent & 3;
+      const double3 A = pos(t.x), B = pos(t.y), C = pos(t.z);
+      double3 r, an, rb;
+      double P;
+      face_r_adjoint(A, B, C, cen, fa.Sb, r, an, rb, P);
+      // the face centroid moves by a third of each corner's motion
+      double g[3] = {rb.x / 3.0, rb.y / 3.0, rb.z / 3.0};
+      // the area normal a = (B - A) x (C - A) / 2 with adjoint P r:
+      // dB = (C - A) x (P r) / 2, dC = (P r) x (B - A) / 2, dA = -(dB + dC)
+      const double3 ab = make_double3(P * r.x, P * r.y, P * r.z);
+      const double3 e1 = make_double3(B.x - A.x, B.y - A.y, B.z - A.z);
+      const double3 e2 = make_double3(C.x - A.x, C.y - A.y, C.z - A.z);
+      const double bB[3] = {0.5 * (e2.y * ab.z - e2.z * ab.y), 0.5 * (e2.z * ab.x - e2.x * ab.z),
+                            0.5 * (e2.x * ab.y - e2.y * ab.x)};
+      const double bC[3] = {0.5 * (ab.y * e1.z - ab.z * e1.y), 0.5 * (ab.z * e1.x - ab.x * e1.z),
+                            0.5 * (ab.x * e1.y - ab.y * e1.x)};
+      // volume v = A . (B x C) / 6 (adjoint w = Vb + Pb . (A + B + C) / 4)
+      // and the centroid numerator v (A + B + C) / 4
+      const double vt = (A.x * (B.y * C.z - B.z * C.y) + A.y * (B.z * C.x - B.x * C.z) +
+                         A.z * (B.x * C.y - B.y * C.x)) / 6.0;
+      const double w = fa.Vb + 0.25 * (fa.Pb[0] * (A.x + B.x + C.x) + fa.Pb[1] * (A.y + B.y + C.y) +
+                                       fa.Pb[2] * (A.z + B.z + C.z));
+      double cr[3];
+      if (corner == 0) {
+        cr[0] = B.y * C.z - B.z * C.y; cr[1] = B.z * C.x - B.x * C.z; cr[2] = B.x * C.y - B.y * C.x;
+        for (int d = 0; d < 3; ++d) g[d] -= bB[d] + bC[d];
+      } else if (corner == 1) {
+        cr[0] = C.y * A.z - C.z * A.y; cr[1] = C.z * A.x - C.x * A.z; cr[2] = C.x * A.y - C.y * A.x;
+        for (int d = 0; d < 3; ++d) g[d] += bB[d];
+      } else {
+        cr[0] = A.y * B.z - A.z * B.y; cr[1] = A.z * B.x - A.x * B.z; cr[2] = A.x * B.y - A.y * B.x;
+        for (int d = 0; d < 3; ++d) g[d] += bC[d];
+      }
+      for (int d = 0; d < 3; ++d) g[d] += w * cr[d] / 6.0 + 0.25 * vt * fa.Pb[d];
+      gx += g[0];
+      gy += g[1];
+      gz += g[2];
+    }
+    out(n, gx, gy, gz);
+  }
+}
+
+struct GradOut32 {
+  float4 *g;
+  __device__ void operator()(int n, double x, double y, double z) const {
+    g[n] = make_float4((float)x, (float)y, (float)z, 0.0f);
+  }
+};
+// FP64 rows in the caller's node order
+struct GradOut64 {
+  const int *ext;
+  double *g;
+  __device__ void operator()(int n, double x, double y, double z) const {
+    const int r = ext[n];
+    g[3 * (long long)r] = x;
+    g[3 * (long long)r + 1] = y;
+    g[3 * (long long)r + 2] = z;
+  }
+};
+
+__global__ __launch_bounds__(256) void k_obs_grad32(MemDev M, int c, float4 *grad) {
+  obs_grad_D(M, c, GradOut32{grad});
+}
+__global__ __launch_bounds__(256) void k_obs_grad64(MemDev M, int c, double *grad) {
+  obs_grad_D(M, c, GradOut64{M.ext_id, grad});
+}
+
+void launch_obs_grad(const MemDev &M, int c, float4 *grad, hipStream_t s) {
+  k_obs_grad32<<<dim3(1), dim3(256), 0, s>>>(M, c, grad);
+}
+
+void launch_obs_grad64(const MemDev &M, int c, double *grad, hipStream_t s) {
+  k_obs_grad64<<<dim3(1), dim3(256), 0, s>>>(M, c, grad);
 }
 
 void launch_observables(const MemDev &M, Ctrl *ctrl, hipStream_t s) {

@@ -151,3 +151,48 @@ def test_autograd_function_wraps_the_adjoint(B):
     fd = (oracle_D(c, "ks", 1 + H_FD, steps)[0] - oracle_D(c, "ks", 1 - H_FD, steps)[0]) / (2 * H_FD)
     say("  dD/ds: adjoint %.8e  oracle FD %.8e" % (dD["s"], fd))
     assert abs(dD["s"] - fd) < 1e-3 * abs(fd)
+
+    # without a gradient requested the forward run alone gives the same D
+    with torch.no_grad():
+        D_plain = B.deformation(make, ks.detach(), ka.detach(), uw.detach(), steps,
+                                checkpoint_every=50)
+    say("  no-grad D %.8f" % float(D_plain))
+    assert abs(float(D_plain) - g["D"]) < 1e-6 * abs(g["D"])
+
+
+@pytest.mark.parametrize("level,sample", [(2, None), (3, 60)])
+def test_deformation_gradient_matches_oracle_differences(B, level, sample):
+    """dD/dx by reverse differentiation of the observables (Sec. III:
+    eigenvalue derivatives of the inertia tensor, then the face sums, the
+    volume and the centroid) against FP64 central differences of the
+    oracle's D (h = 1e-4: the quotient's truncation error is ~1e-9 relative
+    there and its rounding noise grows as 1/h) at the same node positions: a capsule stretched
+    by a random symmetric map with node noise, every node (162-node mesh) or
+    60 sampled nodes (642-node mesh)."""
+    from parity_helpers import O, deformed_mesh
+    from test_gpu_parity import small_case
+    c = small_case(n=(40, 36, 30), m=3, level=level, r=8.0, ca=0.02, uw=0.03)
+    x = deformed_mesh(c, 0.08, 21 + level)
+    lat = c.gpu(graph=False)
+    lat.set_mesh(x)
+    g = lat.deformation_gradient(0)
+    lat.close()
+    t = c.tri_local[0]
+    nodes = np.arange(len(x)) if sample is None else \
+        np.random.default_rng(level).choice(len(x), sample, replace=False)
+    h = 1e-4
+    fd = np.zeros((len(nodes), 3))
+    for k, n in enumerate(nodes):
+        for a in range(3):
+            xp, xm = x.copy(), x.copy()
+            xp[n, a] += h
+            xm[n, a] -= h
+            fd[k, a] = (O.capsule_observables(xp, t)["D"] - O.capsule_observables(xm, t)["D"]) / (2 * h)
+    err = np.max(np.abs(g[nodes] - fd)) / np.max(np.abs(fd))
+    D = O.capsule_observables(x, t)["D"]
+    say("  level %d: D %.5f  max |dD/dx| %.3e  error vs oracle FD %.2e" % (level, D,
+                                                                          np.max(np.abs(fd)), err))
+    assert err < 1e-6
+    # translation invariance: the gradient sums to zero over the nodes
+    if sample is None:
+        assert np.max(np.abs(g.sum(axis=0))) < 1e-9 * np.max(np.abs(g))
