@@ -240,6 +240,9 @@ def batch_leg(args, storage: str, with_single: bool = False):
     stream = lats[0].stream
     n_lat = sum(w.n_nodes_lattice for w in wls)
     n_mem = sum(w.n_membrane_nodes for w in wls)
+    tuned = batch.autotune(64) if args.autotune else None
+    if args.persistent:
+        batch.set_persistent(True)
     prime(batch, args.warmup)
     ms = timed(stream, batch, args.steps)
     mlups = n_lat * args.steps / (ms * 1e-3) / 1e6
@@ -248,7 +251,9 @@ def batch_leg(args, storage: str, with_single: bool = False):
            "step_pct_hbm_roofline": round(100 * mlups * 1e6 * bytes_per_node(storage)
                                           / (HBM_PEAK_GBS * 1e9), 2),
            "membrane_node_updates_per_s": round(n_mem * args.steps / (ms * 1e-3), 1)}
-    extra = {"wls": wls, "n_lat": n_lat, "n_mem": n_mem}
+    if tuned:
+        leg["autotuned"] = tuned
+    extra = {"wls": wls, "n_lat": n_lat, "n_mem": n_mem, "tuned": tuned}
     if with_single:
         # the same runs, each stepped on its own (its own graphs, captured
         # before the timed region) for comparison
@@ -292,6 +297,8 @@ def main():
                     help="time the tangent-model gradient of D instead of the step")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library time its kernel forms during warm-up")
+    ap.add_argument("--persistent", action="store_true",
+                    help="c4: each batched step as one persistent (cooperative) launch")
     ap.add_argument("--lbm-variant", type=int, default=-1,
                     help="collide-stream launch variant (IBM_OPT_LBM_VARIANT bits; "
                          "-1: the library default)")
@@ -324,7 +331,7 @@ def main():
                   "lattice_nodes": ex["n_lat"], "membrane_nodes": ex["n_mem"],
                   "storage": args.storage, "run_sizes": sorted({w.nx for w in ex["wls"]}),
                   "delta_widths": sorted({w.m for w in ex["wls"]}),
-                  "stencil_box": args.stencil_box}
+                  "stencil_box": args.stencil_box, "autotuned": ex["tuned"]}
         kernel = "k_batch_collide_stream"
         traffic_key = "batched_sweep_64runs"
     else:

@@ -422,6 +422,32 @@ int ibm_batch_create(int n_runs, ibm_lattice *const *runs, void *dev_mem, size_t
  * blocks of work, else 0. */
 int ibm_batch_step(ibm_batch *b, int64_t n);
 
+/* Tune the batch on its live runs by timing whole batched steps with HIP
+ * events (each candidate: its graphs captured and replayed, then the better
+ * of two timings over steps_per_trial steps, rounded up to a multiple of
+ * 16): first the row-form lattice update's block shape (4, 2 or 1 wavefronts
+ * of whole rows per block) and the fraction of each run's rows stored with
+ * cached writes (1/4, 1/2 or none), then, for each delta width present, the
+ * stencil-box mode of that width's runs (0, 1, 3 or 5, see
+ * IBM_OPT_STENCIL_BOX), and last the persistent launch of
+ * ibm_batch_set_persistent against the graphs of per-phase launches.  The
+ * runs advance by all these steps (every candidate computes the same update,
+ * to FP32 rounding).  chosen (nullable, 6 ints) receives the wavefronts per
+ * block at index 0, the denominator of the cached fraction (0: none) at
+ * index 1, the modes of delta widths 2, 3 and 4 at indices 2, 3 and 4 (-1 for
+ * a width no run uses), and 1 at index 5 if the persistent launch was kept.
+ * Waits. */
+int ibm_batch_autotune(ibm_batch *b, int steps_per_trial, int *chosen);
+
+/* on = 1: ibm_batch_step runs each step as one persistent launch (a
+ * cooperative launch of as many blocks as the GPU holds at once, every phase
+ * of every run in it, grid-wide barriers between spreading, the lattice
+ * update, the velocity field and interpolation) instead of replaying graphs
+ * of one launch per phase; used only when every run's rows fit the row form
+ * (nx <= 256).  on = 0 (default): the per-phase launches.  Same results to
+ * FP32 rounding. */
+int ibm_batch_set_persistent(ibm_batch *b, int on);
+
 /* ibm_profile_step for a batch: n steps of every run with plain launches and
  * HIP events between the batched kernels; ms_per_phase[IBM_N_PHASES] gets
  * the mean duration per step of each phase.  For measurement; waits. */

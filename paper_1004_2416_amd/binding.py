@@ -77,6 +77,8 @@ def _load():
         "ibm_profile_step": ([v, i64, v], i),
         "ibm_profile_lattice_kernel": ([v, i64, v], i),
         "ibm_autotune": ([v, i, v], i),
+        "ibm_batch_autotune": ([v, i, v], i),
+        "ibm_batch_set_persistent": ([v, i], i),
         "ibm_destroy": ([v], i),
         "ibm_last_error": ([], ctypes.c_char_p),
         "ibm_icosphere_size": ([i, ctypes.POINTER(i), ctypes.POINTER(i)], i),
@@ -390,6 +392,17 @@ class Batch:
 
     def step(self, n: int = 1):
         _check(lib.ibm_batch_step(self._h, int(n)))
+
+    def autotune(self, steps_per_trial: int = 64) -> dict:
+        """ibm_batch_autotune: block shape, cached rows and the stencil-box
+        mode per delta width, timed on the live batch."""
+        out = (ctypes.c_int * 6)()
+        _check(lib.ibm_batch_autotune(self._h, int(steps_per_trial), out))
+        return {"waves_per_block": out[0], "cached_rows_div": out[1],
+                "stencil_box": {m: out[m] for m in (2, 3, 4)}, "persistent": out[5]}
+
+    def set_persistent(self, on: bool = True):
+        _check(lib.ibm_batch_set_persistent(self._h, int(on)))
 
     def profile(self, n: int) -> dict:
         out = np.zeros(4)

@@ -510,8 +510,16 @@ struct ibm_batch {
   // 16-step graphs per parity of the step count, and the options each was
   // captured with
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
-  int graph_advect[2] = {-1, -1}, graph_linear[2] = {-1, -1}, graph_box[2] = {-1, -1};
-  int box_mode = 0;  // stencil-box mode of the batched coupling kernels
+  int graph_advect[2] = {-1, -1}, graph_linear[2] = {-1, -1};
+  int box_mode = 0;  // default stencil-box mode of the batched coupling kernels
+  // ibm_batch_autotune's choices: stencil-box mode per delta width (index m,
+  // -1: box_mode), wavefronts per block of the row-form lattice update, and
+  // the fraction 1 / cached_div of each run's rows stored with cached writes
+  // (0: none)
+  int class_mode[5] = {-1, -1, -1, -1, -1};
+  int wpb = 4, cached_div = 4;
+  int persistent = 0;  // one cooperative launch per step instead of graphs of
+                       // per-phase launches (where every run uses the row form)
 };
 
 namespace {
@@ -542,18 +550,15 @@ int group_lanes(int m) {
   return m == 2 ? ibm::group_size<2>() : (m == 3 ? ibm::group_size<3>() : ibm::group_size<4>());
 }
 
-// Work items of the batched kernels for the runs' current state.
-void batch_items(const std::vector<ibm_lattice *> &runs, std::vector<int2> &li,
+// Work items of the batched kernels for the runs' current state, with wpb
+// wavefronts per block of the lattice update (batch_lat_blocks).
+void batch_items(const std::vector<ibm_lattice *> &runs, int wpb, std::vector<int2> &li,
                  std::vector<int2> &ni) {
   li.clear();
   ni.clear();
   for (size_t r = 0; r < runs.size(); ++r) {
     const ibm_lattice *lat = runs[r];
-    // row form: whole rows per wavefront, four wavefronts per block; else one
-    // node per thread
-    const long long rows = (long long)lat->ny * lat->nz;
-    const long long nb = lat->L.tpr ? ceil_div(ceil_div(rows, lat->L.rpw), 4)
-                                    : ceil_div((long long)lat->nx * lat->ny * lat->nz, 256);
+    const long long nb = ibm::batch_lat_blocks(lat->L, wpb);
     for (long long b = 0; b < nb; ++b) li.push_back(make_int2((int)r, (int)b));
     if (!lat->has_mem) continue;
     const long long nbn = ceil_div((long long)lat->M.nn * group_lanes(lat->M.m), 256);
@@ -594,9 +599,14 @@ int batch_sync_tables(ibm_batch *b) {
       return fail(IBM_ERR_BAD_STATE, "batched runs differ in their stored node velocities");
   }
   std::vector<int2> li, ni;
-  batch_items(b->runs, li, ni);
+  batch_items(b->runs, b->wpb, li, ni);
   if (li.size() > b->cap_lat || ni.size() > b->cap_node)
     return fail(IBM_ERR_BAD_STATE, "the runs' membranes grew since the batch was created");
+  // the first run's explicit choice, else box spreading and interpolation
+  // from the node-velocity field once the whole batch makes at least 256
+  // blocks of coupling work; ibm_batch_autotune's per-width choices first
+  b->box_mode = r0->box_set ? r0->box_mode : (ni.size() >= 256 ? 1 | 4 : 0);
+  bool any_field = false;
   const size_t n = b->runs.size();
   const BatchLayout bl = batch_layout(n, b->cap_lat, b->cap_node);
   std::vector<char> img(bl.total, 0);
@@ -605,12 +615,16 @@ int batch_sync_tables(ibm_batch *b) {
     // the runs together outgrow the last-level cache: only the first quarter
     // of each run's rows is stored cached (measured on the 64-run sweep:
     // +4.6 % FP32, +2.4 % FP16; half or all of the rows: slower)
-    Lr.cached_rows = Lr.ny * Lr.nz / 4;
+    Lr.cached_rows = b->cached_div ? Lr.ny * Lr.nz / b->cached_div : 0;
     Lr.zlo = Lr.ylo = 0;
     Lr.zhi = Lr.nz;
     Lr.yhi = Lr.ny;
     std::memcpy(img.data() + bl.lat + r * sizeof(ibm::LatDev), &Lr, sizeof(ibm::LatDev));
-    std::memcpy(img.data() + bl.mem + r * sizeof(ibm::MemDev), &b->runs[r]->M, sizeof(ibm::MemDev));
+    ibm::MemDev Mr = b->runs[r]->M;
+    const int cm = b->runs[r]->has_mem ? b->class_mode[Mr.m] : -1;
+    Mr.cmode = cm >= 0 ? cm : b->box_mode;
+    any_field = any_field || (b->runs[r]->has_mem && (Mr.cmode & 4));
+    std::memcpy(img.data() + bl.mem + r * sizeof(ibm::MemDev), &Mr, sizeof(ibm::MemDev));
   }
   std::memcpy(img.data() + bl.lat_items, li.data(), li.size() * sizeof(int2));
   std::memcpy(img.data() + bl.node_items, ni.data(), ni.size() * sizeof(int2));
@@ -621,10 +635,8 @@ int batch_sync_tables(ibm_batch *b) {
   B.node_items = reinterpret_cast<const int2 *>(b->dev + bl.node_items);
   B.n_lat_items = (int)li.size();
   B.n_node_items = (int)ni.size();
-  // the first run's explicit choice, else box spreading and interpolation
-  // from the node-velocity field once the whole batch makes at least 256
-  // blocks of coupling work
-  b->box_mode = r0->box_set ? r0->box_mode : (ni.size() >= 256 ? 1 | 4 : 0);
+  B.wpb = b->wpb;
+  B.any_field = any_field ? 1 : 0;
   const bool same = img == b->image && std::memcmp(&B, &b->B, sizeof(B)) == 0;
   if (!same) {
     IBM_HIP(hipMemcpyAsync(b->dev, img.data(), img.size(), hipMemcpyHostToDevice, b->stream));
@@ -641,9 +653,9 @@ int batch_sync_tables(ibm_batch *b) {
 void enqueue_batch_step(ibm_batch *b, hipStream_t s, int advect) {
   const ibm_lattice *r0 = b->runs[0];
   const int src = (int)(r0->steps & 1), par = src;
-  ibm::launch_batch_spread(b->B, par, b->box_mode & 1, s);
+  ibm::launch_batch_spread(b->B, par, s);
   ibm::launch_batch_collide_stream(b->B, r0->storage, src, par, r0->eq_linear != 0, s);
-  ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, interp_mode(b->box_mode), s);
+  ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, s);
   for (ibm_lattice *lat : b->runs) {
     lat->steps += 1;
     lat->since_recenter += 1;
@@ -677,7 +689,6 @@ int batch_capture_graph(ibm_batch *b, int advect) {
   }
   b->graph_advect[p] = advect;
   b->graph_linear[p] = b->runs[0]->eq_linear;
-  b->graph_box[p] = b->box_mode;
   return IBM_OK;
 }
 
@@ -1752,7 +1763,7 @@ int ibm_batch_bytes(int n_runs, ibm_lattice *const *runs, size_t *bytes) {
     if (!runs[r]) return fail(IBM_ERR_INVALID_ARG, "run %d is NULL", r);
   std::vector<ibm_lattice *> v(runs, runs + n_runs);
   std::vector<int2> li, ni;
-  batch_items(v, li, ni);
+  batch_items(v, 1, li, ni);  // the most lattice items: one wavefront per block
   *bytes = batch_layout(v.size(), li.size(), ni.size()).total;
   return ok();
 }
@@ -1772,7 +1783,7 @@ int ibm_batch_create(int n_runs, ibm_lattice *const *runs, void *dev_mem, size_t
     for (int q = 0; q < r; ++q)
       if (v[q] == v[r]) return fail(IBM_ERR_INVALID_ARG, "run %d appears twice", r);
   std::vector<int2> li, ni;
-  batch_items(v, li, ni);
+  batch_items(v, 1, li, ni);
   ibm_batch *b = new ibm_batch();
   b->runs = v;
   b->stream = v[0]->stream;
@@ -1795,6 +1806,28 @@ int ibm_batch_step(ibm_batch *b, int64_t n) {
   int rc = batch_sync_tables(b);
   if (rc) return rc;
   ibm_lattice *r0 = b->runs[0];
+  bool rows_only = true;
+  for (const ibm_lattice *lat : b->runs) rows_only = rows_only && lat->L.tpr > 0;
+  while (n > 0 && b->persistent && rows_only) {
+    for (ibm_lattice *lat : b->runs)
+      if (lat->has_mem && lat->since_recenter >= lat->recenter_every) {
+        ibm::launch_recenter(lat->M, b->stream);
+        lat->since_recenter = 0;
+        if (lat->overlap) lat->slab_stale = true;
+      }
+    const int src = (int)(r0->steps & 1);
+    const int advect = (r0->ab2 && batch_prev_u(b)) ? 1 : 0;
+    if (ibm::launch_batch_persistent(b->B, r0->storage, src, src, advect, r0->eq_linear != 0,
+                                     b->stream))
+      return fail(IBM_ERR_HIP, "the persistent batched step could not be launched: %s",
+                  hipGetErrorString(hipGetLastError()));
+    for (ibm_lattice *lat : b->runs) {
+      lat->steps += 1;
+      lat->since_recenter += 1;
+      if (lat->ab2 && lat->has_mem) lat->have_prev_u = true;
+    }
+    n -= 1;
+  }
   while (n > 0) {
     const bool prev = batch_prev_u(b);
     const bool want_graph = n >= GRAPH_STEPS && (!r0->ab2 || prev);
@@ -1814,8 +1847,7 @@ int ibm_batch_step(ibm_batch *b, int64_t n) {
     const bool graph_ok = want_graph && room;
     if (graph_ok) {
       const int p = (int)(r0->steps & 1);
-      if (!b->gexec[p] || b->graph_advect[p] != advect || b->graph_linear[p] != r0->eq_linear ||
-          b->graph_box[p] != b->box_mode) {
+      if (!b->gexec[p] || b->graph_advect[p] != advect || b->graph_linear[p] != r0->eq_linear) {
         rc = batch_capture_graph(b, advect);
         if (rc) return rc;
       }
@@ -1834,6 +1866,113 @@ int ibm_batch_step(ibm_batch *b, int64_t n) {
     }
   }
   IBM_HIP(hipGetLastError());
+  return ok();
+}
+
+int ibm_batch_set_persistent(ibm_batch *b, int on) {
+  if (!b) return fail(IBM_ERR_INVALID_ARG, "batch is NULL");
+  if (on != 0 && on != 1) return fail(IBM_ERR_INVALID_ARG, "persistent is 0 or 1");
+  b->persistent = on;
+  return ok();
+}
+
+int ibm_batch_autotune(ibm_batch *b, int steps_per_trial, int *chosen) {
+  if (!b) return fail(IBM_ERR_INVALID_ARG, "batch is NULL");
+  if (steps_per_trial < GRAPH_STEPS || steps_per_trial > 65536)
+    return fail(IBM_ERR_INVALID_ARG, "steps_per_trial must be in %d..65536", GRAPH_STEPS);
+  const int n = (steps_per_trial + GRAPH_STEPS - 1) / GRAPH_STEPS * GRAPH_STEPS;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  IBM_HIP(hipEventCreate(&e0));
+  IBM_HIP(hipEventCreate(&e1));
+  // the better of two timings of n steps, after the graphs of the candidate
+  // are captured and replayed once
+  auto trial = [&](float &ms) -> int {
+    batch_invalidate_graph(b);
+    int r = ibm_batch_step(b, GRAPH_STEPS);
+    if (!r) r = ibm_batch_step(b, 1);
+    if (!r) r = ibm_batch_step(b, GRAPH_STEPS);
+    if (r) return r;
+    ms = 1e30f;
+    for (int rep = 0; rep < 2; ++rep) {
+      IBM_HIP(hipEventRecord(e0, b->stream));
+      r = ibm_batch_step(b, n);
+      if (r) return r;
+      IBM_HIP(hipEventRecord(e1, b->stream));
+      IBM_HIP(hipEventSynchronize(e1));
+      float t = 0.0f;
+      IBM_HIP(hipEventElapsedTime(&t, e0, e1));
+      ms = std::min(ms, t);
+    }
+    for (ibm_lattice *lat : b->runs) {
+      r = check_device(lat);
+      if (r) return r;
+    }
+    return IBM_OK;
+  };
+  int rc = ibm_batch_step(b, 4 * n);  // clocks and caches settle before the first trial
+  // 1. the row-form block shape and the fraction of rows stored cached
+  int best_w = b->wpb, best_c = b->cached_div;
+  float best = 1e30f;
+  for (int w : {4, 2, 1})
+    for (int cd : {4, 2, 0}) {
+      if (rc) break;
+      b->wpb = w;
+      b->cached_div = cd;
+      float ms = 0.0f;
+      rc = trial(ms);
+      if (!rc && ms < best) {
+        best = ms;
+        best_w = w;
+        best_c = cd;
+      }
+    }
+  b->wpb = best_w;
+  b->cached_div = best_c;
+  // 2. the stencil-box mode of each delta width present, one width at a time
+  bool present[5] = {false, false, false, false, false};
+  for (const ibm_lattice *lat : b->runs)
+    if (lat->has_mem) present[lat->M.m] = true;
+  for (int m = 2; m <= 4 && !rc; ++m) {
+    if (!present[m]) continue;
+    int best_m = b->class_mode[m];
+    best = 1e30f;
+    for (int mode : {0, 1, 3, 5}) {
+      b->class_mode[m] = mode;
+      float ms = 0.0f;
+      rc = trial(ms);
+      if (rc) break;
+      if (ms < best) {
+        best = ms;
+        best_m = mode;
+      }
+    }
+    b->class_mode[m] = best_m;
+  }
+  // 3. one persistent launch per step against the graphs of per-phase launches
+  if (!rc) {
+    bool rows_only = true;
+    for (const ibm_lattice *lat : b->runs) rows_only = rows_only && lat->L.tpr > 0;
+    if (rows_only) {
+      float ms_graph = 0.0f, ms_pers = 0.0f;
+      b->persistent = 0;
+      rc = trial(ms_graph);
+      if (!rc) {
+        b->persistent = 1;
+        rc = trial(ms_pers);
+      }
+      b->persistent = (!rc && ms_pers < ms_graph) ? 1 : 0;
+    }
+  }
+  batch_invalidate_graph(b);
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  if (chosen) {
+    chosen[0] = b->wpb;
+    chosen[1] = b->cached_div;
+    for (int m = 2; m <= 4; ++m) chosen[m] = b->class_mode[m];
+    chosen[5] = b->persistent;
+  }
   return ok();
 }
 
@@ -1862,12 +2001,12 @@ static int batch_profile_steps(ibm_batch *b, int64_t n, double *ms_per_phase, do
     const int src = (int)(r0->steps & 1), par = src;
     const int advect = (r0->ab2 && batch_prev_u(b)) ? 1 : 0;
     IBM_HIP(hipEventRecord(e[0], s));
-    ibm::launch_batch_spread(b->B, par, b->box_mode & 1, s);
+    ibm::launch_batch_spread(b->B, par, s);
     IBM_HIP(hipEventRecord(e[1], s));
     ibm::launch_batch_collide_stream(b->B, r0->storage, src, par, r0->eq_linear != 0, s,
                                      kernel_ms ? &kt[(size_t)k] : nullptr);
     IBM_HIP(hipEventRecord(e[2], s));
-    ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, interp_mode(b->box_mode), s);
+    ibm::launch_batch_interp(b->B, r0->storage, src ^ 1, par, advect, s);
     IBM_HIP(hipEventRecord(e[3], s));
     for (ibm_lattice *lat : b->runs) {
       lat->steps += 1;

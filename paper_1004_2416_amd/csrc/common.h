@@ -113,6 +113,8 @@ struct MemDev {
   int *cap_node_off;  // [n_caps + 1]
   int *cap_face_off;  // [n_caps + 1]
   double *obs;      // observables [n_caps][IBM_OBS_N]
+  int cmode;        // batched runs: the coupling kernels' stencil-box mode
+                    // (bits as IBM_OPT_STENCIL_BOX) chosen for this run
 };
 
 // Tangent-linear (forward sensitivity) state: the derivative of every
@@ -152,7 +154,17 @@ struct BatchDev {
   const int2 *lat_items;   // lattice update: 256 nodes per block, one per thread
   const int2 *node_items;  // spreading / interpolation: 256 / group_size lanes
   int n_lat_items, n_node_items;
+  int wpb;                 // wavefronts per block of the row-form lattice update
+  int any_field;           // some run interpolates from the node-velocity field
 };
+
+// Blocks of one run's batched lattice update (64 wpb threads each): the row
+// form with wpb wavefronts of rpw whole rows each, else one node per thread.
+__host__ __device__ inline long long batch_lat_blocks(const LatDev &L, int wpb) {
+  const long long rows = (long long)L.ny * L.nz;
+  if (L.tpr > 0) return ((rows + L.rpw - 1) / L.rpw + wpb - 1) / wpb;
+  return ((long long)L.nx * rows + 64 * wpb - 1) / (64 * wpb);
+}
 
 
 // Lattice totals (ibm_lattice_totals): one FP64 partial sum (mass deviation,

@@ -70,9 +70,15 @@ void launch_interp_far(const LatDev &L, const MemDev &M, int fp16, int fsrc, int
 // min and max over the membrane nodes of floor(lattice z) and floor(lattice
 // y) into ctrl->zmin, zmax, ymin, ymax
 void launch_node_range(const MemDev &M, Ctrl *ctrl, hipStream_t s);
-void launch_batch_spread(const BatchDev &B, int par, bool box, hipStream_t s);
-void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect, int mode,
-                         hipStream_t s);
+// batched coupling kernels: each run's stencil-box mode from its MemDev cmode
+void launch_batch_spread(const BatchDev &B, int par, hipStream_t s);
+void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect, hipStream_t s);
+// The whole batched step (all four phases, every run) as one cooperative
+// launch of co-resident blocks with grid barriers between the phases; only
+// for batches whose runs all use the row form (L.tpr > 0).  Returns 0, or -1
+// if the launch was refused.
+int launch_batch_persistent(const BatchDev &B, int fp16, int src, int par, int advect, bool linear,
+                            hipStream_t s);
 void launch_observables(const MemDev &M, Ctrl *ctrl, hipStream_t s);
 // observables of the mesh x + h dx into obs [n_caps][16]
 void launch_observables_shifted(const MemDev &M, Ctrl *ctrl, const float4 *dx, double h,

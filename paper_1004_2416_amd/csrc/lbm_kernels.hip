@@ -731,9 +731,9 @@ __global__ __launch_bounds__(256) void k_batch_collide_stream(BatchDev B, int sr
     L.stamp[1] = ts;
   }
   if (L.tpr > 0) {
-    // row form: four wavefronts of rpw whole rows per block
+    // row form: B.wpb wavefronts of rpw whole rows per block
     const int lane = threadIdx.x & 63;
-    const int wave = it.y * 4 + (int)(threadIdx.x >> 6);
+    const int wave = it.y * B.wpb + (int)(threadIdx.x >> 6);
     if (wave * L.rpw >= L.ny * L.nz) return;  // the whole wavefront is past the last row
     const int r = lane / L.tpr;
     const int t = lane - r * L.tpr;
@@ -744,7 +744,7 @@ __global__ __launch_bounds__(256) void k_batch_collide_stream(BatchDev B, int sr
     return;
   }
   // a lattice holds at most 2^31 nodes: unsigned 32-bit index arithmetic suffices
-  const unsigned idx = (unsigned)it.y * 256u + threadIdx.x;
+  const unsigned idx = (unsigned)it.y * blockDim.x + threadIdx.x;
   if ((long long)idx >= (long long)L.nx * L.ny * L.nz) return;
   const unsigned nx = (unsigned)L.nx, ny = (unsigned)L.ny;
   const unsigned row = idx / nx;
@@ -755,7 +755,7 @@ __global__ __launch_bounds__(256) void k_batch_collide_stream(BatchDev B, int sr
 void launch_batch_collide_stream(const BatchDev &B, int fp16, int src, int par, bool linear,
                                  hipStream_t s, const DispatchTimer *t) {
   if (B.n_lat_items <= 0) return;
-  const dim3 grid(B.n_lat_items), block(256);
+  const dim3 grid(B.n_lat_items), block(64 * B.wpb);
   if (fp16) {
     if (linear) launch_k(k_batch_collide_stream<__half, true>, grid, block, s, t, B, src, par);
     else launch_k(k_batch_collide_stream<__half, false>, grid, block, s, t, B, src, par);

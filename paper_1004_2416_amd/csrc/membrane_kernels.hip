@@ -13,6 +13,8 @@
 #include "launch.h"
 #include "lbm_device.h"
 
+#include <hip/hip_cooperative_groups.h>
+
 namespace ibm {
 
 // ---- finite-element forces ----------------------------------------------------
@@ -1103,7 +1105,7 @@ void launch_adj_fem(const LatDev &L, const MemDev &M, const AdjDev &A, hipStream
 // runs, one launch each; a block works for run items[b].x as block items[b].y of that
 // run's own launch (so a block never mixes runs).  The delta width is chosen
 // per block.
-template <bool BOX>
+// Each run's spreading box (bit 0 of its cmode) is chosen per block.
 __global__ __launch_bounds__(256) void k_batch_spread(BatchDev B, int par) {
   __shared__ SpreadLDS sm;
   const int b = xcd_block(B.n_node_items);
@@ -1112,15 +1114,30 @@ __global__ __launch_bounds__(256) void k_batch_spread(BatchDev B, int par) {
   const LatDev &L = B.lat[it.x];
   const MemDev &Mm = B.mem[it.x];
   const int m = Mm.m;
-  if (m == 2) spread_lanes<2, BOX>(L, Mm, par, it.y, sm);
-  else if (m == 3) spread_lanes<3, BOX>(L, Mm, par, it.y, sm);
-  else spread_lanes<4, BOX>(L, Mm, par, it.y, sm);
+  if (Mm.cmode & 1) {
+    if (m == 2) spread_lanes<2, true>(L, Mm, par, it.y, sm);
+    else if (m == 3) spread_lanes<3, true>(L, Mm, par, it.y, sm);
+    else spread_lanes<4, true>(L, Mm, par, it.y, sm);
+  } else {
+    if (m == 2) spread_lanes<2, false>(L, Mm, par, it.y, sm);
+    else if (m == 3) spread_lanes<3, false>(L, Mm, par, it.y, sm);
+    else spread_lanes<4, false>(L, Mm, par, it.y, sm);
+  }
 }
 
-// The first block of each run advances that run's device step counter.
-// MODE as for launch_interp_advect: 0 per stencil node, 1 per block in LDS,
-// 2 from each run's velocity field (k_batch_node_velocity first).
-template <typename T, int MODE>
+// The first block of each run advances that run's device step counter.  Each
+// run's interpolation mode follows its cmode as for launch_interp_advect: per
+// stencil node, per block in an LDS box (bit 1), or from the run's velocity
+// field (bit 2; k_batch_node_velocity first).
+template <typename T, int M>
+__device__ __forceinline__ void batch_interp_m(const LatDev &L, const MemDev &Mm, int fsrc, int par,
+                                               int advect, int blk, InterpLDS &sm) {
+  if (Mm.cmode & 4) interp_lanes<T, M, false, true, true>(L, Mm, fsrc, par, advect, blk, sm);
+  else if (Mm.cmode & 2) interp_lanes<T, M, true, false, true>(L, Mm, fsrc, par, advect, blk, sm);
+  else interp_lanes<T, M, false, false, true>(L, Mm, fsrc, par, advect, blk, sm);
+}
+
+template <typename T>
 __global__ __launch_bounds__(256) void k_batch_interp(BatchDev B, int fsrc, int par, int advect) {
   __shared__ InterpLDS sm;
   const int b = xcd_block(B.n_node_items);
@@ -1130,9 +1147,9 @@ __global__ __launch_bounds__(256) void k_batch_interp(BatchDev B, int fsrc, int 
   const MemDev &Mm = B.mem[it.x];
   if (it.y == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
   const int m = Mm.m;
-  if (m == 2) interp_lanes<T, 2, MODE == 1, MODE == 2, true>(L, Mm, fsrc, par, advect, it.y, sm);
-  else if (m == 3) interp_lanes<T, 3, MODE == 1, MODE == 2, true>(L, Mm, fsrc, par, advect, it.y, sm);
-  else interp_lanes<T, 4, MODE == 1, MODE == 2, true>(L, Mm, fsrc, par, advect, it.y, sm);
+  if (m == 2) batch_interp_m<T, 2>(L, Mm, fsrc, par, advect, it.y, sm);
+  else if (m == 3) batch_interp_m<T, 3>(L, Mm, fsrc, par, advect, it.y, sm);
+  else batch_interp_m<T, 4>(L, Mm, fsrc, par, advect, it.y, sm);
 }
 
 // The velocity pass of every run, on the lattice work items: the nb blocks
@@ -1142,9 +1159,10 @@ __global__ __launch_bounds__(256) void k_batch_node_velocity(BatchDev B, int fsr
   if ((int)blockIdx.x >= B.n_lat_items) return;
   const int2 it = B.lat_items[blockIdx.x];
   const LatDev &L = B.lat[it.x];
-  if (!B.mem[it.x].nn) return;  // no capsule: nothing is marked
-  const long long rows = (long long)L.ny * L.nz, N = (long long)L.nx * rows;
-  const long long nb = L.tpr ? ((rows + L.rpw - 1) / L.rpw + 3) / 4 : (N + 255) / 256;
+  // no capsule (nothing is marked), or a run interpolating otherwise
+  if (!B.mem[it.x].nn || !(B.mem[it.x].cmode & 4)) return;
+  const long long N = (long long)L.nx * L.ny * L.nz;
+  const long long nb = batch_lat_blocks(L, B.wpb);
   long long per = (N + nb - 1) / nb;
   if (per > NODE_VELOCITY_NODES) per = NODE_VELOCITY_NODES;  // not reached: a block of
                                                              // the lattice update covers
@@ -1154,31 +1172,137 @@ __global__ __launch_bounds__(256) void k_batch_node_velocity(BatchDev B, int fsr
   node_velocity_range<T>(L, fsrc, par, n0, min(N, n0 + per));
 }
 
-void launch_batch_spread(const BatchDev &B, int par, bool box, hipStream_t s) {
+void launch_batch_spread(const BatchDev &B, int par, hipStream_t s) {
   if (B.n_node_items <= 0) return;
   const dim3 grid(xcd_grid(B.n_node_items)), block(256);
-  if (box) k_batch_spread<true><<<grid, block, 0, s>>>(B, par);
-  else k_batch_spread<false><<<grid, block, 0, s>>>(B, par);
+  k_batch_spread<<<grid, block, 0, s>>>(B, par);
 }
 
-void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect, int mode,
-                         hipStream_t s) {
+void launch_batch_interp(const BatchDev &B, int fp16, int fsrc, int par, int advect, hipStream_t s) {
   if (B.n_node_items <= 0) return;
   const dim3 grid(xcd_grid(B.n_node_items)), block(256);
-#define IBM_LAUNCH_BATCH_INTERP(T)                                                            \
-  do {                                                                                        \
-    if (mode == 2) {                                                                          \
-      k_batch_node_velocity<T><<<dim3(B.n_lat_items), block, 0, s>>>(B, fsrc, par);           \
-      k_batch_interp<T, 2><<<grid, block, 0, s>>>(B, fsrc, par, advect);                      \
-    } else if (mode == 1) {                                                                   \
-      k_batch_interp<T, 1><<<grid, block, 0, s>>>(B, fsrc, par, advect);                      \
-    } else {                                                                                  \
-      k_batch_interp<T, 0><<<grid, block, 0, s>>>(B, fsrc, par, advect);                      \
-    }                                                                                         \
-  } while (0)
-  if (fp16) IBM_LAUNCH_BATCH_INTERP(__half);
-  else IBM_LAUNCH_BATCH_INTERP(float);
-#undef IBM_LAUNCH_BATCH_INTERP
+  if (fp16) {
+    if (B.any_field) k_batch_node_velocity<__half><<<dim3(B.n_lat_items), block, 0, s>>>(B, fsrc, par);
+    k_batch_interp<__half><<<grid, block, 0, s>>>(B, fsrc, par, advect);
+  } else {
+    if (B.any_field) k_batch_node_velocity<float><<<dim3(B.n_lat_items), block, 0, s>>>(B, fsrc, par);
+    k_batch_interp<float><<<grid, block, 0, s>>>(B, fsrc, par, advect);
+  }
+}
+
+// ---- the batched step as one persistent launch ------------------------------------
+// One launch of co-resident blocks per step of every run (cooperative launch):
+// the four phases (spreading, lattice update, velocity field, interpolation)
+// each take all runs' work items, strided over the blocks, and grid-wide
+// barriers separate them.  Only batches whose runs all use the row form.
+// A grid barrier makes every block's writes visible across the XCDs' L2
+// caches (an agent-scope release and acquire per block), the price of this
+// form against separate launches.
+template <typename T, bool LINEAR>
+__device__ __forceinline__ void batch_cs_item(const BatchDev &B, int2 it, int src, int par) {
+  LatDev L = B.lat[it.x];
+  if (src) {
+    void *t = L.f[0];
+    L.f[0] = L.f[1];
+    L.f[1] = t;
+  }
+  if (par) {
+    float *tg = L.g[0];
+    L.g[0] = L.g[1];
+    L.g[1] = tg;
+    int *ts = L.stamp[0];
+    L.stamp[0] = L.stamp[1];
+    L.stamp[1] = ts;
+  }
+  const int lane = threadIdx.x & 63;
+  const int wave = it.y * B.wpb + (int)(threadIdx.x >> 6);
+  if (wave * L.rpw >= L.ny * L.nz) return;  // the whole wavefront is past the last row
+  const int r = lane / L.tpr;
+  const int t = lane - r * L.tpr;
+  const int row = wave * L.rpw + r;
+  collide_stream_rowseg<T, LINEAR, true, true>(L, 0, 0, row, t, lane, r < L.rpw && row < L.ny * L.nz,
+                                               __builtin_amdgcn_readfirstlane(row) < L.cached_rows);
+}
+
+template <typename T, bool LINEAR>
+__global__ __launch_bounds__(256) void k_batch_persistent(BatchDev B, int src, int par, int advect) {
+  __shared__ SpreadLDS ss;
+  __shared__ InterpLDS si;
+  cooperative_groups::grid_group grid = cooperative_groups::this_grid();
+  for (int b = blockIdx.x; b < B.n_node_items; b += gridDim.x) {
+    const int2 it = B.node_items[b];
+    const LatDev &L = B.lat[it.x];
+    const MemDev &Mm = B.mem[it.x];
+    const int m = Mm.m;
+    if (Mm.cmode & 1) {
+      if (m == 2) spread_lanes<2, true>(L, Mm, par, it.y, ss);
+      else if (m == 3) spread_lanes<3, true>(L, Mm, par, it.y, ss);
+      else spread_lanes<4, true>(L, Mm, par, it.y, ss);
+    } else {
+      if (m == 2) spread_lanes<2, false>(L, Mm, par, it.y, ss);
+      else if (m == 3) spread_lanes<3, false>(L, Mm, par, it.y, ss);
+      else spread_lanes<4, false>(L, Mm, par, it.y, ss);
+    }
+    __syncthreads();  // the LDS box is reused by the next item
+  }
+  grid.sync();
+  for (int b = blockIdx.x; b < B.n_lat_items; b += gridDim.x)
+    batch_cs_item<T, LINEAR>(B, B.lat_items[b], src, par);
+  grid.sync();
+  if (B.any_field) {
+    for (int b = blockIdx.x; b < B.n_lat_items; b += gridDim.x) {
+      const int2 it = B.lat_items[b];
+      const LatDev &L = B.lat[it.x];
+      if (!B.mem[it.x].nn || !(B.mem[it.x].cmode & 4)) continue;  // uniform across the block
+      const long long N = (long long)L.nx * L.ny * L.nz;
+      const long long nb = batch_lat_blocks(L, B.wpb);
+      const long long per = (N + nb - 1) / nb;
+      const long long n0 = (long long)it.y * per;
+      if (n0 >= N) continue;
+      node_velocity_range<T>(L, src ^ 1, par, n0, min(N, n0 + per));
+      __syncthreads();  // the node list is reused by the next item
+    }
+    grid.sync();
+  }
+  for (int b = blockIdx.x; b < B.n_node_items; b += gridDim.x) {
+    const int2 it = B.node_items[b];
+    const LatDev &L = B.lat[it.x];
+    const MemDev &Mm = B.mem[it.x];
+    if (it.y == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
+    const int m = Mm.m;
+    if (m == 2) batch_interp_m<T, 2>(L, Mm, src ^ 1, par, advect, it.y, si);
+    else if (m == 3) batch_interp_m<T, 3>(L, Mm, src ^ 1, par, advect, it.y, si);
+    else batch_interp_m<T, 4>(L, Mm, src ^ 1, par, advect, it.y, si);
+    __syncthreads();
+  }
+}
+
+template <typename T, bool LINEAR>
+static int launch_batch_persistent_t(const BatchDev &B, int src, int par, int advect, hipStream_t s) {
+  static int blocks = 0;  // co-resident blocks of this instantiation (per process)
+  if (!blocks) {
+    int per_cu = 0, cus = 0, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent<T, LINEAR>, 256, 0) !=
+            hipSuccess || per_cu < 1)
+      return -1;
+    blocks = per_cu * cus;
+  }
+  BatchDev b = B;
+  void *args[] = {&b, &src, &par, &advect};
+  return hipLaunchCooperativeKernel(reinterpret_cast<void *>(k_batch_persistent<T, LINEAR>),
+                                    dim3(blocks), dim3(256), args, 0, s) == hipSuccess ? 0 : -1;
+}
+
+int launch_batch_persistent(const BatchDev &B, int fp16, int src, int par, int advect, bool linear,
+                            hipStream_t s) {
+  if (fp16) {
+    if (linear) return launch_batch_persistent_t<__half, true>(B, src, par, advect, s);
+    return launch_batch_persistent_t<__half, false>(B, src, par, advect, s);
+  }
+  if (linear) return launch_batch_persistent_t<float, true>(B, src, par, advect, s);
+  return launch_batch_persistent_t<float, false>(B, src, par, advect, s);
 }
 
 // ---- coupling kernels carrying part of a split lattice update -------------------

@@ -77,18 +77,69 @@ class Run:
                     u=scaled_err(ug, self.sim.un), x=float(np.max(np.abs(xg - self.sim.x))))
 
 
-def check(runs, tol_x, tol_F=1e-5):
+def check(runs, tol_x, tol_F=1e-5, tol_u=1e-5):
     """Per-run errors.  After one step from identical states the bar is 1e-5;
     over several steps the FP32 positions drift by ~1e-6 lattice spacings,
     which moves the strain-sensitive nodal forces by ~1e-4 of their scale, so
-    forces get tol_F there (populations and velocities keep 1e-5)."""
+    forces get tol_F there (populations and velocities keep 1e-5; over more
+    than a thousand steps the velocities, which depend on the drifted
+    positions, get tol_u)."""
     for k, r in enumerate(runs):
         e = r.errors()
         say("   run", k, {q: "%.2e" % v for q, v in e.items()})
         assert e["f"] < 1e-5, k
         if r.has_caps:
-            assert e["F"] < tol_F and e["u"] < 1e-5, k
+            assert e["F"] < tol_F and e["u"] < tol_u, k
             assert e["x"] < tol_x, k
+
+
+def test_batch_autotune_keeps_runs_on_the_oracle(B):
+    """ibm_batch_autotune times real batched steps of every candidate (row
+    block shape, cached-row fraction, stencil-box mode per delta width);
+    afterwards every run is where its oracle is after the same number of
+    steps, and the chosen settings step on in agreement with the oracle."""
+    runs = [Run(B, spec) for spec in CASES]
+    batch = B.Batch([r.lat for r in runs])
+    chosen = batch.autotune(16)
+    n = runs[0].lat.steps
+    say("  batch autotune chose", chosen, "after", n, "steps")
+    assert chosen["waves_per_block"] in (1, 2, 4) and chosen["cached_rows_div"] in (0, 2, 4)
+    assert all(chosen["stencil_box"][m] in (0, 1, 3, 5) for m in (2, 3, 4))
+    assert chosen["persistent"] in (0, 1)
+    for r in runs:
+        assert r.lat.steps == n
+        r.advance_oracle(n)
+    check(runs, 1e-3, 1e-2, 1e-4)
+    batch.step(33)
+    for r in runs:
+        r.advance_oracle(33)
+    check(runs, 1e-3, 1e-2, 1e-4)
+    batch.close()
+    for r in runs:
+        r.lat.close()
+
+
+def test_batch_persistent_launch_matches_oracle(B):
+    """The batched step as one cooperative launch per step (every phase of
+    every run, grid barriers between the phases): five uneven runs against
+    their oracles after 1 and 40 steps, with the velocity field for some
+    delta widths and LDS boxes for others (autotuner-style per-width modes are
+    exercised by the autotune test)."""
+    runs = [Run(B, spec) for spec in CASES]
+    batch = B.Batch([r.lat for r in runs])
+    batch.set_persistent(True)
+    batch.step(1)
+    for r in runs:
+        r.advance_oracle(1)
+    check(runs, 1e-6)
+    batch.step(40)
+    for r in runs:
+        r.advance_oracle(40)
+    assert all(r.lat.steps == 41 for r in runs)
+    check(runs, 2e-5, 1e-3)
+    batch.close()
+    for r in runs:
+        r.lat.close()
 
 
 def test_batch_matches_oracle_per_run(B):
