@@ -60,18 +60,11 @@ LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
   LatticeLayout l{};
   l.N = (long long)nx * ny * nz;
   l.S = (long long)round_up((size_t)l.N, 64);
-  // x rows padded to a multiple of 4 values (aligned 4-node vectors); rows per
-  // group: the smallest power of two (up to 8) whose group holds at least 128
-  // values per population, so short rows still fill cache lines
-  l.nxs = (nx + 3) / 4 * 4;
-  l.gsh = 0;
-  while (l.gsh < 3 && ((long long)l.nxs << l.gsh) < 128) ++l.gsh;
-  const long long rows = (long long)ny * nz;
-  const long long g = 1LL << l.gsh;
-  l.pop_elems = (long long)ibm::Q * ((rows + g - 1) / g * g) * l.nxs;
-  // the row form of the collide-stream kernel: a row in one wavefront, and
-  // 32-bit group-row indices (padded rows times Q below 2^32)
-  l.tpr = (l.nxs / 4 <= 64 && (rows + g - 1) / g * g * ibm::Q < (1LL << 32)) ? l.nxs / 4 : 0;
+  const ibm::PopGeometry pg = ibm::pop_geometry(nx, ny, nz);
+  l.nxs = pg.nxs;
+  l.gsh = pg.gsh;
+  l.pop_elems = pg.pop_elems;
+  l.tpr = pg.tpr;
   l.tnx = (nx + ibm::TILE_X - 1) / ibm::TILE_X;
   l.tny = (ny + ibm::TILE_Y - 1) / ibm::TILE_Y;
   l.tnz = (nz + ibm::TILE_Z - 1) / ibm::TILE_Z;

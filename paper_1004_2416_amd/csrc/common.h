@@ -229,18 +229,44 @@ __device__ __forceinline__ int stencil_lo(float p) {
 // that are megabytes apart.  The padding (x >= nx) holds no lattice node.
 // pidx(L, i, row, x) = prow(L, row) + i pstride(L) + x: a per-row offset and
 // a stride between the populations of a group that is the same for all rows.
-__device__ __forceinline__ long long prow(const LatDev &L, long long row) {
+__host__ __device__ __forceinline__ long long prow(const LatDev &L, long long row) {
   const long long g = row >> L.gsh, r = row - (g << L.gsh);
   return (((g * Q) << L.gsh) + r) * (long long)L.nxs;
 }
-__device__ __forceinline__ long long pstride(const LatDev &L) { return (long long)L.nxs << L.gsh; }
-__device__ __forceinline__ long long pidx(const LatDev &L, int i, long long row, int x) {
+__host__ __device__ __forceinline__ long long pstride(const LatDev &L) {
+  return (long long)L.nxs << L.gsh;
+}
+__host__ __device__ __forceinline__ long long pidx(const LatDev &L, int i, long long row, int x) {
   return prow(L, row) + i * pstride(L) + x;
 }
 // The same for a compile-time direction i: the offset of population i comes
 // from the table (one 64-bit add per access instead of a multiply).
-__device__ __forceinline__ long long pidx_c(const LatDev &L, int i, long long row, int x) {
+__host__ __device__ __forceinline__ long long pidx_c(const LatDev &L, int i, long long row, int x) {
   return prow(L, row) + L.pst[i] + x;
+}
+
+// Population storage geometry of an nx x ny x nz lattice: x rows padded to
+// nxs, a multiple of 4 values (aligned 4-node vectors); 2^gsh rows per group,
+// the smallest power of two (up to 8) whose group holds at least 128 values
+// per population, so short rows still fill cache lines; the row form of the
+// collide-stream kernel (tpr lanes per row, rpw rows per wavefront) where a
+// padded row fits one wavefront and the padded row count times Q stays below
+// 2^32 (its 32-bit group-row indices, see grow32), else tpr = rpw = 0.
+struct PopGeometry {
+  int nxs, gsh, tpr, rpw;
+  long long pop_elems;  // elements of one population buffer
+};
+__host__ __device__ inline PopGeometry pop_geometry(int nx, int ny, int nz) {
+  PopGeometry p{};
+  p.nxs = (nx + 3) / 4 * 4;
+  p.gsh = 0;
+  while (p.gsh < 3 && ((long long)p.nxs << p.gsh) < 128) ++p.gsh;
+  const long long g = 1LL << p.gsh;
+  const long long rows = ((long long)ny * nz + g - 1) / g * g;
+  p.pop_elems = (long long)Q * rows * p.nxs;
+  p.tpr = (p.nxs / 4 <= 64 && rows * Q < (1LL << 32)) ? p.nxs / 4 : 0;
+  p.rpw = p.tpr ? 64 / p.tpr : 0;
+  return p;
 }
 
 __device__ __forceinline__ int wrap_mod(int a, int n) {

@@ -214,11 +214,11 @@ __device__ __forceinline__ float wall_kick_scaled(int i, float uw) {
 // 32-bit form of prow / nx (the group-row index of an x row): row + (Q - 1) G
 // (row / G).  Valid while the padded row count times Q is below 2^32, which
 // the launchers of its users check.
-__device__ __forceinline__ unsigned grow32(const LatDev &L, unsigned row) {
+__host__ __device__ __forceinline__ unsigned grow32(const LatDev &L, unsigned row) {
   return row + (((row >> L.gsh) * (unsigned)(Q - 1)) << L.gsh);
 }
 // Element offset of (row, x) within population 0 of its group.
-__device__ __forceinline__ unsigned long long rowoff(const LatDev &L, unsigned row, int x) {
+__host__ __device__ __forceinline__ unsigned long long rowoff(const LatDev &L, unsigned row, int x) {
   return (unsigned long long)grow32(L, row) * (unsigned)L.nxs + (unsigned)x;
 }
 
