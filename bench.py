@@ -66,7 +66,7 @@ def measured_traffic(workload: str, storage: str):
 
 
 def setup(workload: str, storage: str, graph: bool, variant: int = -1, box: int = -1,
-          overlap: int = -1):
+          overlap: int = -1, streaming: int = -1):
     from paper_1004_2416_amd import binding as B
     from paper_1004_2416_amd import workloads as W
 
@@ -82,6 +82,8 @@ def setup(workload: str, storage: str, graph: bool, variant: int = -1, box: int 
         lat.set_option(B.OPT_STENCIL_BOX, int(box))
     if overlap >= 0:
         lat.set_option(B.OPT_OVERLAP, int(overlap))
+    if streaming >= 0:
+        lat.set_option(B.OPT_STREAMING, int(streaming))
     return wl, lat
 
 
@@ -194,7 +196,7 @@ def single_leg(args, workload: str, storage: str, roofline: bool):
     """One lattice workload in the benchmark's launch configuration: warm-up
     and graph capture, then exactly args.steps timed steps."""
     wl, lat = setup(workload, storage, not args.no_graph, args.lbm_variant,
-                    args.stencil_box, args.overlap)
+                    args.stencil_box, args.overlap, args.streaming)
     tuned = lat.autotune(64) if args.autotune else None
     split_box = lat.split_box()
     prime(lat, args.warmup)
@@ -293,6 +295,9 @@ def main():
     ap.add_argument("--overlap", type=int, default=1,
                     help="IBM_OPT_OVERLAP: 1 (default) splits the lattice update where it pays, "
                          "0 off, -1 library default")
+    ap.add_argument("--streaming", type=int, default=-1,
+                    help="population streaming pattern: 0 two buffers, 1 AA (one buffer); "
+                         "-1 the library's default")
     ap.add_argument("--sensitivity", action="store_true",
                     help="time the tangent-model gradient of D instead of the step")
     ap.add_argument("--autotune", action="store_true",

@@ -167,6 +167,26 @@ extern "C" {
                                   split pays there).  0 (default): off.
                                   Results are those of the plain step       */
 
+#define IBM_OPT_STREAMING 8    /* 0 (default): two population buffers,
+                                  collide and push to the neighbours of
+                                  the other buffer; 1: the AA pattern in
+                                  one buffer: even steps collide in place
+                                  into the opposite slots, odd steps gather
+                                  from the neighbours and push back (Bailey
+                                  et al.'s access pattern): the same 152
+                                  bytes per node and step, half the
+                                  population memory, which the 256 MB
+                                  last-level cache then holds better.  AA
+                                  needs the row form (nx <= 256), nx a
+                                  multiple of 4 and no tangent; the adjoint
+                                  and batches need two buffers.  Changes
+                                  only after an even number of steps;
+                                  populations can be set then only.
+                                  Results are those of two buffers (to FP32
+                                  rounding)                                 */
+#define IBM_STREAM_TWO_BUFFERS 0
+#define IBM_STREAM_AA 1
+
 typedef struct ibm_lattice ibm_lattice;
 
 /* Bytes of device memory the lattice state needs (two population buffers,

@@ -28,7 +28,8 @@ ERRORS = {
 STORAGE = {"fp32": 0, "fp16": 1}
 FIELD_POPS, FIELD_RHO, FIELD_U, FIELD_FORCE = 0, 1, 2, 3
 OPT_GRAPH, OPT_EQUILIBRIUM, OPT_ADVECTION, OPT_RECENTER, OPT_LBM_VARIANT = 0, 1, 2, 3, 4
-OPT_STENCIL_BOX, OPT_OVERLAP = 6, 7
+OPT_STENCIL_BOX, OPT_OVERLAP, OPT_STREAMING = 6, 7, 8
+STREAM_TWO_BUFFERS, STREAM_AA = 0, 1
 PHASES = ("forces", "spread", "lbm", "interp")
 OBS_FIELDS = ("V", "cx", "cy", "cz", "D", "theta", "ra", "rb", "rc", "area",
               "Ixx", "Iyy", "Izz", "Ixy", "Ixz", "Iyz")

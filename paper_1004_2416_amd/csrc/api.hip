@@ -214,6 +214,15 @@ void reset_force_state(ibm_lattice *lat, hipStream_t s) {
 // boxes) over the per-stencil-node evaluation.
 int interp_mode(int box_mode) { return (box_mode & 4) ? 2 : ((box_mode & 2) ? 1 : 0); }
 
+// Population state after `steps` completed steps, as the readers take it
+// (pop_post, stored_post): two buffers, the buffer steps & 1; the AA pattern,
+// buffer 0 after an even number of steps and the swapped state 2 after an odd
+// number.
+int pop_state(const ibm_lattice *lat, int64_t steps) {
+  if (lat->L.aa) return (steps & 1) ? 2 : 0;
+  return (int)(steps & 1);
+}
+
 // Enqueue one full timestep on stream s (Sec. II.C, sub-steps 1-5).
 void enqueue_step(ibm_lattice *lat, hipStream_t s, int advect) {
   const int src = (int)(lat->steps & 1);
@@ -229,8 +238,9 @@ void enqueue_step(ibm_lattice *lat, hipStream_t s, int advect) {
       // before the positions move: the tangent needs x(t)
       ibm::launch_tangent_interp(lat->L, lat->M, lat->T, src ^ 1, par, s);
     }
-    ibm::launch_interp_advect(lat->L, lat->M, lat->storage, src ^ 1,     // 4, 5
-                              par, advect, interp_mode(lat->box_mode), s);
+    ibm::launch_interp_advect(lat->L, lat->M, lat->storage,              // 4, 5
+                              pop_state(lat, lat->steps + 1), par, advect,
+                              interp_mode(lat->box_mode), s);
   } else {
     ibm::launch_collide_stream(lat->L, lat->storage, src, par, false, lat->eq_linear != 0,
                                lat->lbm_variant, s);
@@ -257,7 +267,7 @@ bool split_update(const ibm_lattice *lat) {
 // their traffic, so a narrower box in y measured slower.)
 int refresh_slab(ibm_lattice *lat) {
   int zlo = 0, zhi = lat->nz, ylo = 0, yhi = lat->ny;
-  if (lat->overlap && lat->has_mem && !lat->has_tan && lat->L.tpr > 0) {
+  if (lat->overlap && lat->has_mem && !lat->has_tan && lat->L.tpr > 0 && !lat->L.aa) {
     ibm::launch_node_range(lat->M, lat->L.ctrl, lat->stream);
     int r[4] = {0, 0, 0, 0};  // zmin, zmax, ymin, ymax
     IBM_HIP(hipMemcpyAsync(r, &lat->L.ctrl->zmin, sizeof(r), hipMemcpyDeviceToHost, lat->stream));
@@ -588,6 +598,7 @@ int batch_sync_tables(ibm_batch *b) {
     if (lat->stream != r0->stream)
       return fail(IBM_ERR_BAD_STATE, "batched runs must share one stream");
     if (lat->has_tan) return fail(IBM_ERR_BAD_STATE, "batched runs cannot carry a tangent");
+    if (lat->L.aa) return fail(IBM_ERR_BAD_STATE, "batched runs use two population buffers");
     if (lat->has_mem && lat->have_prev_u != batch_prev_u(b))
       return fail(IBM_ERR_BAD_STATE, "batched runs differ in their stored node velocities");
   }
@@ -752,6 +763,7 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
   L.inv_tau = (float)(1.0 / tau);
   L.guo_pre = (float)(1.0 - 0.5 / tau);
   L.uw = 0.0f;
+  L.aa = 0;
   L.zlo = 0;
   L.zhi = nz;
   L.ylo = 0;
@@ -1029,7 +1041,7 @@ int64_t ibm_step_count(const ibm_lattice *lat) { return lat ? lat->steps : -1; }
 int ibm_get_fields(ibm_lattice *lat, int what, double *dst_dev) {
   if (!lat || !dst_dev) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
   if (what < IBM_FIELD_POPS || what > IBM_FIELD_FORCE) return fail(IBM_ERR_INVALID_ARG, "unknown field %d", what);
-  const int src = (int)(lat->steps & 1);
+  const int src = pop_state(lat, lat->steps);
   const int gpar = (lat->has_mem && lat->steps > 0) ? (int)((lat->steps - 1) & 1) : -1;
   ibm::launch_get_field(lat->L, lat->storage, src, gpar, what, dst_dev, lat->stream);
   IBM_HIP(hipGetLastError());
@@ -1040,7 +1052,11 @@ int ibm_get_fields(ibm_lattice *lat, int what, double *dst_dev) {
 int ibm_set_fields(ibm_lattice *lat, int what, const double *src_dev) {
   if (!lat || !src_dev) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
   if (what != IBM_FIELD_POPS) return fail(IBM_ERR_INVALID_ARG, "only the populations can be set");
-  ibm::launch_set_pops(lat->L, lat->storage, (int)(lat->steps & 1), src_dev, lat->stream);
+  if (lat->L.aa && (lat->steps & 1))
+    return fail(IBM_ERR_BAD_STATE,
+                "with the AA pattern the populations can be set after an even number of steps only");
+  ibm::launch_set_pops(lat->L, lat->storage, lat->L.aa ? 0 : (int)(lat->steps & 1), src_dev,
+                       lat->stream);
   IBM_HIP(hipGetLastError());
   return ok();
 }
@@ -1107,7 +1123,7 @@ int ibm_lattice_totals(ibm_lattice *lat, void *work_dev, size_t work_bytes, doub
     return fail(IBM_ERR_INVALID_ARG, "work_dev has %zu bytes, %zu needed", work_bytes, need);
   if (((uintptr_t)work_dev) % 32 || ((uintptr_t)out_dev) % 8)
     return fail(IBM_ERR_INVALID_ARG, "work_dev must be 32-byte and out_dev 8-byte aligned");
-  ibm::launch_totals(lat->L, lat->storage, (int)(lat->steps & 1), static_cast<double4 *>(work_dev),
+  ibm::launch_totals(lat->L, lat->storage, pop_state(lat, lat->steps), static_cast<double4 *>(work_dev),
                      out_dev, lat->stream);
   IBM_HIP(hipGetLastError());
   return ok();
@@ -1171,7 +1187,7 @@ int ibm_lattice_totals_noalloc(ibm_lattice *lat, double *out_dev) {
   if (rc) return rc;
   // every partial the final pass reads is written first by this call, so
   // nothing needs clearing
-  ibm::launch_totals(lat->L, lat->storage, (int)(lat->steps & 1), part, out_dev, lat->stream);
+  ibm::launch_totals(lat->L, lat->storage, pop_state(lat, lat->steps), part, out_dev, lat->stream);
   IBM_HIP(hipGetLastError());
   return ok();
 }
@@ -1211,6 +1227,21 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
       if (value < 0 || value > 2) return fail(IBM_ERR_INVALID_ARG, "overlap is 0, 1 or 2");
       lat->overlap = value;
       invalidate_graph(lat);
+      break;
+    case IBM_OPT_STREAMING:
+      if (value != IBM_STREAM_TWO_BUFFERS && value != IBM_STREAM_AA)
+        return fail(IBM_ERR_INVALID_ARG, "streaming is 0 (two buffers) or 1 (AA)");
+      if (value == IBM_STREAM_AA && (lat->L.tpr <= 0 || lat->nx % 4 || lat->has_tan))
+        return fail(IBM_ERR_BAD_STATE,
+                    "the AA pattern needs rows of at most 256 nodes, nx a multiple of 4 and no tangent");
+      if (value != lat->L.aa && (lat->steps & 1))
+        return fail(IBM_ERR_BAD_STATE, "the streaming pattern changes after an even number of steps only");
+      lat->L.aa = value;
+      // the split update has no AA form: back to the whole lattice at once
+      if (value && split_update(lat)) {
+        int rc = refresh_slab(lat);
+        if (rc) return rc;
+      }
       break;
     case IBM_OPT_STENCIL_BOX:
       if (value < 0 || value > 7) return fail(IBM_ERR_INVALID_ARG, "stencil box mode is 0..7");
@@ -1352,8 +1383,8 @@ static int profile_steps(ibm_lattice *lat, int64_t n, double *ms_per_phase, doub
       ibm::launch_collide_stream(lat->L, lat->storage, src, par, true, lat->eq_linear != 0,
                                  lat->lbm_variant, s, 0, -1, t);
       IBM_HIP(hipEventRecord(e[3], s));
-      ibm::launch_interp_advect(lat->L, lat->M, lat->storage, src ^ 1, par, advect_mode(lat),
-                                interp_mode(lat->box_mode), s);
+      ibm::launch_interp_advect(lat->L, lat->M, lat->storage, pop_state(lat, lat->steps + 1), par,
+                                advect_mode(lat), interp_mode(lat->box_mode), s);
       IBM_HIP(hipEventRecord(e[4], s));
       if (lat->ab2) lat->have_prev_u = true;
     } else {
@@ -1454,6 +1485,7 @@ int ibm_tangent_attach(ibm_lattice *lat, const double *dks, const double *dka, d
   if (!lat) return fail(IBM_ERR_INVALID_ARG, "lat is NULL");
   if (lat->storage != IBM_STORAGE_FP32)
     return fail(IBM_ERR_BAD_STATE, "the tangent model needs FP32 population storage");
+  if (lat->L.aa) return fail(IBM_ERR_BAD_STATE, "the tangent model needs two population buffers");
   if (lat->has_mem && (!dks || !dka)) return fail(IBM_ERR_INVALID_ARG, "dks and dka are needed");
   if (!std::isfinite(duw)) return fail(IBM_ERR_INVALID_ARG, "duw must be finite");
   const TangentLayout tl = tangent_layout(lat);
@@ -1610,6 +1642,7 @@ int ibm_adjoint_gradient(ibm_lattice *lat, int64_t steps, int checkpoint_every, 
     return fail(IBM_ERR_INVALID_ARG, "NULL argument");
   if (!lat->has_mem) return fail(IBM_ERR_BAD_STATE, "no membrane attached");
   if (lat->storage != IBM_STORAGE_FP32) return fail(IBM_ERR_BAD_STATE, "the adjoint needs FP32 storage");
+  if (lat->L.aa) return fail(IBM_ERR_BAD_STATE, "the adjoint needs two population buffers");
   if (lat->ab2) return fail(IBM_ERR_BAD_STATE, "the adjoint follows Euler advection only");
   if (lat->has_tan) return fail(IBM_ERR_BAD_STATE, "detach the tangent first");
   if (capsule < 0 || capsule >= lat->M.n_caps) return fail(IBM_ERR_INVALID_ARG, "no capsule %d", capsule);

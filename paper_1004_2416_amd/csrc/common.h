@@ -60,6 +60,8 @@ struct LatDev {
   int nxs;                // population row stride: nx rounded up to a multiple of 4
   int tpr, rpw;           // row form: lanes per row (nxs / 4) and rows per
                           // wavefront (64 / tpr), or 0 where it does not apply
+  int aa;                 // 1: the AA streaming pattern in buffer 0 (see
+                          // collide_stream_rowseg_a); 0: two buffers
   int cached_rows;        // the row form writes the new populations of rows
                           // z ny + y below this with ordinary (cached) stores,
                           // the others with non-temporal ones

@@ -303,29 +303,46 @@ struct Pop4<__half> {
   }
 };
 
+// Streaming patterns of the row form (template argument AA):
+//   0  two buffers: read f(t) at the node from buffer src, push the
+//      post-collision values to the neighbours in buffer src ^ 1;
+//   1  AA, even step, one buffer (buffer 0): read the node's own values,
+//      write the post-collision values back to the same node in the opposite
+//      slot, A[opp(i)][x] = f*_i(x) (no streaming);
+//   2  AA, odd step, buffer 0: the post-stream values of the even step are
+//      gathered, f_i(x) = A[opp(i)][x - c_i] (or, arriving from a wall,
+//      A[i][x] less the wall term of the opposite direction), collided and
+//      pushed, A[i][x + c_i] = f**_i(x) (at a wall: back into the node's
+//      opposite slot with the wall term), which leaves post-stream values at
+//      their own nodes again.
+// In the AA steps every location a node reads is written only by that node,
+// after its reads (all 19 values are loaded before any store), so one buffer
+// suffices.  AA needs rows that are a multiple of 4 long (no padding).
+
 // x row `row`, segment t (lane `lane` of its wavefront).  All lanes of the
 // wavefront call this together (the shuffles need every lane); `live` is
 // false for idle lanes and rows beyond the lattice.  PAD: nx is not a
 // multiple of 4.
-template <typename T, bool LINEAR, bool FORCE, bool PAD, bool NT>
+template <typename T, bool LINEAR, bool FORCE, bool PAD, bool NT, int AA = 0>
 __device__ __forceinline__ void collide_stream_rowseg_a(const LatDev &L, int src, int par, int row,
                                                         int t, int lane, bool live);
 
 // cached: this wavefront stores with cached writes (uniform across it)
-template <typename T, bool LINEAR, bool FORCE, bool PAD>
+template <typename T, bool LINEAR, bool FORCE, bool PAD, int AA = 0>
 __device__ __forceinline__ void collide_stream_rowseg(const LatDev &L, int src, int par, int row,
                                                       int t, int lane, bool live, bool cached) {
   if (cached)
-    collide_stream_rowseg_a<T, LINEAR, FORCE, PAD, false>(L, src, par, row, t, lane, live);
+    collide_stream_rowseg_a<T, LINEAR, FORCE, PAD, false, AA>(L, src, par, row, t, lane, live);
   else
-    collide_stream_rowseg_a<T, LINEAR, FORCE, PAD, true>(L, src, par, row, t, lane, live);
+    collide_stream_rowseg_a<T, LINEAR, FORCE, PAD, true, AA>(L, src, par, row, t, lane, live);
 }
 
 // NT: non-temporal population stores (see Pop4); the loads are always
 // non-temporal
-template <typename T, bool LINEAR, bool FORCE, bool PAD, bool NT>
+template <typename T, bool LINEAR, bool FORCE, bool PAD, bool NT, int AA>
 __device__ __forceinline__ void collide_stream_rowseg_a(const LatDev &L, int src, int par, int row,
                                                         int t, int lane, bool live) {
+  static_assert(!(AA && PAD), "the AA pattern needs rows that are a multiple of 4 long");
   // FP16 values are used in their storage units (collide<..., SCALED>)
   constexpr bool SC = sizeof(T) == 2;
   const int tpr = L.tpr, last = tpr - 1;
@@ -340,20 +357,67 @@ __device__ __forceinline__ void collide_stream_rowseg_a(const LatDev &L, int src
   const long long n0 = ((long long)z * L.ny + y) * L.nx + x0;
   const unsigned row0 = (unsigned)(z * L.ny + y);
   const unsigned long long off0 = rowoff(L, row0, x0);
-  T *__restrict__ fd = static_cast<T *>(L.f[src ^ 1]);
+  T *__restrict__ fd = static_cast<T *>(L.f[AA ? 0 : (src ^ 1)]);
   // lanes holding the left and right neighbours of this segment in the row
   const int row_lane0 = lane - t;
   const int left = live ? row_lane0 + (t == 0 ? last : t - 1) : lane;
   const int right = live ? row_lane0 + (t == last ? 0 : t + 1) : lane;
 
   float d[4][Q];
-  if (live) {
+  if constexpr (AA == 2) {
+    // gather the even step's post-collision values from the neighbours; the
+    // +-x shift by lane shuffles (every lane takes part)
+    const T *fa = static_cast<const T *>(L.f[0]);
+    const int ysm = (y == 0) ? L.ny - 1 : y - 1, ysp = (y == L.ny - 1) ? 0 : y + 1;
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      float v[4];
-      Pop4<T>::template ld<true>(static_cast<const T *>(L.f[src]) + L.pst[i], off0, 1.0f, v);
+      float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      const int zs = z - cz(i);
+      const bool wall = cz(i) != 0 && (zs < 0 || zs >= L.nz);
+      if (live) {
+        if (wall) {
+          Pop4<T>::template ld<true>(fa + L.pst[i], off0, 1.0f, v);
+          const float kick = SC ? wall_kick_scaled(opp(i), L.uw) : wall_kick(opp(i), L.uw);
+#pragma unroll
+          for (int k = 0; k < 4; ++k) v[k] -= kick;
+        } else {
+          const int ys = cy(i) > 0 ? ysm : (cy(i) < 0 ? ysp : y);
+          Pop4<T>::template ld<true>(fa + L.pst[opp(i)], rowoff(L, (unsigned)(zs * L.ny + ys), x0), 1.0f,
+                                     v);
+        }
+      }
+      // node x takes the value of x - c_x: from the left neighbour's last
+      // node for c_x > 0, the right neighbour's first for c_x < 0
+      if (cx(i) > 0) {
+        const float in = __shfl(v[3], left);
+        if (!wall) {
+          v[3] = v[2];
+          v[2] = v[1];
+          v[1] = v[0];
+          v[0] = in;
+        }
+      } else if (cx(i) < 0) {
+        const float in = __shfl(v[0], right);
+        if (!wall) {
+          v[0] = v[1];
+          v[1] = v[2];
+          v[2] = v[3];
+          v[3] = in;
+        }
+      }
 #pragma unroll
       for (int k = 0; k < 4; ++k) d[k][i] = v[k];
+    }
+  }
+  if (live) {
+    if constexpr (AA != 2) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        float v[4];
+        Pop4<T>::template ld<true>(static_cast<const T *>(L.f[AA ? 0 : src]) + L.pst[i], off0, 1.0f, v);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) d[k][i] = v[k];
+      }
     }
     float g[4][3];
 #pragma unroll
@@ -401,6 +465,15 @@ __device__ __forceinline__ void collide_stream_rowseg_a(const LatDev &L, int src
       for (int k = 0; k < 4; ++k) d[k][i] = 0.0f;
   }
 
+  if constexpr (AA == 1) {
+    // the even step: post-collision values to the node's own opposite slots
+    if (live) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i)
+        Pop4<T>::template st<NT>(fd + L.pst[opp(i)], off0, d[0][i], d[1][i], d[2][i], d[3][i], 1.0f);
+    }
+    return;
+  }
   const int ym = (y == 0) ? L.ny - 1 : y - 1;
   const int yp = (y == L.ny - 1) ? 0 : y + 1;
   const bool wrap = PAD && t == last;  // this segment holds x = nx - 1 at slot e

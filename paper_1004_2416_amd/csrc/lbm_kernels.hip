@@ -110,8 +110,9 @@ __global__ __launch_bounds__(256) void k_collide_stream(LatDev L, int src, int p
   collide_stream_nodes<T, LINEAR, FORCE, VEC, NT>(L, src, par, x0, y, z);
 }
 
-// The rows of set rs, rpw consecutive ones per wavefront.
-template <typename T, bool LINEAR, bool FORCE, bool PAD>
+// The rows of set rs, rpw consecutive ones per wavefront.  AA: the
+// streaming pattern (collide_stream_rowseg_a).
+template <typename T, bool LINEAR, bool FORCE, bool PAD, int AA = 0>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_collide_stream_rows(
     LatDev L, int src, int par, RowSet rs) {
   const int lane = threadIdx.x & 63;
@@ -121,8 +122,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int k = wave * L.rpw + r;
   const bool live = r < L.rpw && k < rs.n0 + rs.n1;
   // a single lattice stores all rows or none with cached writes
-  collide_stream_rowseg<T, LINEAR, FORCE, PAD>(L, src, par, live ? rowset_row(rs, L, k) : 0, t, lane,
-                                               live, L.cached_rows != 0);
+  collide_stream_rowseg<T, LINEAR, FORCE, PAD, AA>(L, src, par, live ? rowset_row(rs, L, k) : 0, t,
+                                                   lane, live, L.cached_rows != 0);
 }
 
 // Row kernels index x rows with grow32: the padded row count times Q must stay
@@ -153,6 +154,20 @@ static void launch_cs_rows_p(const LatDev &L, int src, int par, bool force, bool
   }
 }
 
+// The AA pattern (L.aa; rows a multiple of 4 long): the even step for src =
+// 0, the odd step for src = 1 (the step count's parity), both in buffer 0.
+template <typename T, int AA>
+static void launch_cs_rows_aa(const LatDev &L, int par, bool force, bool linear, dim3 g, dim3 b,
+                              const RowSet &rs, hipStream_t s, const DispatchTimer *t) {
+  if (force) {
+    if (linear) launch_k(k_collide_stream_rows<T, true, true, false, AA>, g, b, s, t, L, 0, par, rs);
+    else launch_k(k_collide_stream_rows<T, false, true, false, AA>, g, b, s, t, L, 0, par, rs);
+  } else {
+    if (linear) launch_k(k_collide_stream_rows<T, true, false, false, AA>, g, b, s, t, L, 0, par, rs);
+    else launch_k(k_collide_stream_rows<T, false, false, false, AA>, g, b, s, t, L, 0, par, rs);
+  }
+}
+
 // wpb: wavefronts per block (1, 2 or 4)
 template <typename T>
 static bool launch_cs_rows(const LatDev &L, int src, int par, bool force, bool linear,
@@ -162,8 +177,14 @@ static bool launch_cs_rows(const LatDev &L, int src, int par, bool force, bool l
   const long long waves = ((long long)rs.n0 + rs.n1 + L.rpw - 1) / L.rpw;
   if (waves <= 0) return true;
   const dim3 g((unsigned)((waves + wpb - 1) / wpb)), b((unsigned)(64 * wpb));
-  if (L.nx % 4) launch_cs_rows_p<T, true>(L, src, par, force, linear, g, b, rs, s, t);
-  else launch_cs_rows_p<T, false>(L, src, par, force, linear, g, b, rs, s, t);
+  if (L.aa) {
+    if (src) launch_cs_rows_aa<T, 2>(L, par, force, linear, g, b, rs, s, t);
+    else launch_cs_rows_aa<T, 1>(L, par, force, linear, g, b, rs, s, t);
+  } else if (L.nx % 4) {
+    launch_cs_rows_p<T, true>(L, src, par, force, linear, g, b, rs, s, t);
+  } else {
+    launch_cs_rows_p<T, false>(L, src, par, force, linear, g, b, rs, s, t);
+  }
   return true;
 }
 
@@ -206,7 +227,8 @@ static void launch_cs_t(const LatDev &L, int src, int par, bool force, bool line
   // blocks (256 otherwise)
   const RowSet rs{z0 * L.ny, (z1 - z0) * L.ny, 0, 0, 1, 0};
   const int wpb = (variant & 128) ? 1 : ((variant & 64) ? 2 : 4);
-  if ((variant & 16) && launch_cs_rows<T>(L, src, par, force, linear, rs, s, t, wpb)) return;
+  // the AA pattern exists in the row form only (it is allowed only there)
+  if ((variant & 16 || L.aa) && launch_cs_rows<T>(L, src, par, force, linear, rs, s, t, wpb)) return;
   const bool vec2 = (variant & 1) && (L.nx % 2 == 0);
   const bool nt = (variant & 2) != 0;
   const int threads = (variant & 4) ? 128 : 256;
@@ -277,6 +299,27 @@ __device__ __forceinline__ double stored_deviation<__half>(const __half *f, long
 }
 
 
+// The post-stream deviation f_i - w_i at node (x, y, z) of population state
+// `state`, converted exactly: 0 or 1, buffer 0 or 1; 2, the AA pattern after
+// an even step (the value leaving the source node in the opposite slot of
+// buffer 0, or, coming back from a wall, the node's own slot i less the wall
+// term of the opposite direction; see collide_stream_rowseg_a).
+template <typename T>
+__device__ __forceinline__ double stored_post(const LatDev &L, int state, int i, int x, int y,
+                                              int z) {
+  if (state < 2)
+    return stored_deviation<T>(static_cast<const T *>(L.f[state]),
+                               pidx(L, i, (long long)z * L.ny + y, x), L.h_scale[i]);
+  const T *f = static_cast<const T *>(L.f[0]);
+  const int zs = z - cz(i);
+  if (cz(i) != 0 && (zs < 0 || zs >= L.nz))
+    return stored_deviation<T>(f, pidx(L, i, (long long)z * L.ny + y, x), L.h_scale[i]) -
+           (double)wall_kick(opp(i), L.uw);
+  const int xs = x - cx(i) < 0 ? L.nx - 1 : (x - cx(i) >= L.nx ? 0 : x - cx(i));
+  const int ys = y - cy(i) < 0 ? L.ny - 1 : (y - cy(i) >= L.ny ? 0 : y - cy(i));
+  return stored_deviation<T>(f, pidx(L, opp(i), (long long)zs * L.ny + ys, xs), L.h_scale[i]);
+}
+
 // what: 0 populations, 1 density, 2 velocity, 3 force density.  gpar: the
 // field of the last step (its tiles stamped with that step), or -1 for none.
 template <typename T>
@@ -288,7 +331,6 @@ __global__ __launch_bounds__(256) void k_get_field(LatDev L, int src, int gpar, 
   if (x >= L.nx || y >= L.ny) return;
   const long long N = (long long)L.nx * L.ny * L.nz;
   const long long n = ((long long)z * L.ny + y) * L.nx + x;
-  const T *f = static_cast<const T *>(L.f[src]);
   double gx = 0.0, gy = 0.0, gz = 0.0;
   if (gpar >= 0 && L.stamp[gpar][tile_of(L, x, y, z)] == L.ctrl->step - 1) {
     gx = L.g[gpar][n];
@@ -304,7 +346,7 @@ __global__ __launch_bounds__(256) void k_get_field(LatDev L, int src, int gpar, 
   double drho = 0.0, jx = 0.0, jy = 0.0, jz = 0.0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const double d = stored_deviation<T>(f, pidx(L, i, (long long)z * L.ny + y, x), L.h_scale[i]);
+    const double d = stored_post<T>(L, src, i, x, y, z);
     if (what == 0) out[i * N + n] = wgt(i) + d;
     drho += d;
     jx += cx(i) * d;
@@ -792,16 +834,15 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_totals_partial(LatDev L, int src, double4 *part) {
   const long long N = (long long)L.nx * L.ny * L.nz;
   const long long n0 = (long long)blockIdx.x * TOTALS_NODES;
-  const T *f = static_cast<const T *>(L.f[src]);
   double v[4] = {0.0, 0.0, 0.0, 0.0};
   for (int k = threadIdx.x; k < TOTALS_NODES; k += blockDim.x) {
     const long long n = n0 + k;
     if (n >= N) break;
     const long long row = n / L.nx;
-    const int x = (int)(n - row * L.nx);
+    const int x = (int)(n - row * L.nx), y = (int)(row % L.ny), z = (int)(row / L.ny);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-      const double d = stored_deviation<T>(f, pidx_c(L, i, row, x), L.h_scale[i]);
+      const double d = stored_post<T>(L, src, i, x, y, z);
       v[0] += d;
       if (cx(i)) v[1] += cx(i) * d;
       if (cy(i)) v[2] += cy(i) * d;

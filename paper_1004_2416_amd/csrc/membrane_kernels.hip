@@ -501,16 +501,59 @@ __device__ __forceinline__ float ld_pop<__half>(const __half *p, long long idx, 
   return __half2float(p[idx]) * inv_scale;
 }
 
-// Lattice velocity u(X, t+1) of Eq. (velocityinterpolation) at lattice node n.
+// The post-stream population deviation f_i - w_i at node (X, Y, Z) of the
+// state `state`: 0 or 1, buffer 0 or 1 (two buffers; or the AA pattern after
+// an odd step, buffer 0); 2, the AA pattern after an even step: the
+// post-collision values sit in the opposite slots of the nodes they leave,
+// f_i(X) = A[opp(i)][X - c_i], or A[i][X] less the wall term of opp(i) for a
+// population coming back from a wall (collide_stream_rowseg_a).
 template <typename T>
-__device__ __forceinline__ float3 lattice_velocity(const LatDev &L, const T *f, const float *g,
-                                                   int X, int Y, int Z) {
+__device__ __forceinline__ float pop_post(const LatDev &L, int state, int i, int X, int Y, int Z) {
+  if (state < 2)
+    return ld_pop<T>(static_cast<const T *>(L.f[state]), pidx(L, i, (long long)Z * L.ny + Y, X),
+                     L.h_inv[i]);
+  const T *f = static_cast<const T *>(L.f[0]);
+  const int zs = Z - cz(i);
+  if (cz(i) != 0 && (zs < 0 || zs >= L.nz))
+    return ld_pop<T>(f, pidx(L, i, (long long)Z * L.ny + Y, X), L.h_inv[i]) - wall_kick(opp(i), L.uw);
+  const int xs = X - cx(i) < 0 ? L.nx - 1 : (X - cx(i) >= L.nx ? 0 : X - cx(i));
+  const int ys = Y - cy(i) < 0 ? L.ny - 1 : (Y - cy(i) >= L.ny ? 0 : Y - cy(i));
+  return ld_pop<T>(f, pidx(L, opp(i), (long long)zs * L.ny + ys, xs), L.h_inv[i]);
+}
+
+// Lattice velocity u(X, t+1) of Eq. (velocityinterpolation) from the
+// post-stream populations at their own nodes of the buffer f (a state or a
+// checkpoint of the adjoint).
+template <typename T>
+__device__ __forceinline__ float3 lattice_velocity_of(const LatDev &L, const T *f, const float *g,
+                                                      int X, int Y, int Z) {
   const long long row = (long long)Z * L.ny + Y;
   const long long n = row * L.nx + X;
   float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const float d = ld_pop<T>(f, pidx(L, i, row, X), L.h_inv[i]);
+    drho += d;
+    if (cx(i)) jx += cx(i) * d;
+    if (cy(i)) jy += cy(i) * d;
+    if (cz(i)) jz += cz(i) * d;
+  }
+  const float inv_rho = 1.0f / (1.0f + drho);
+  return make_float3((jx + 0.5f * g[n]) * inv_rho, (jy + 0.5f * g[L.S + n]) * inv_rho,
+                     (jz + 0.5f * g[2 * L.S + n]) * inv_rho);
+}
+
+// Lattice velocity u(X, t+1) of Eq. (velocityinterpolation) at lattice node n
+// of population state `state` (pop_post).
+template <typename T>
+__device__ __forceinline__ float3 lattice_velocity(const LatDev &L, int state, const float *g,
+                                                   int X, int Y, int Z) {
+  const long long row = (long long)Z * L.ny + Y;
+  const long long n = row * L.nx + X;
+  float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    const float d = pop_post<T>(L, state, i, X, Y, Z);
     drho += d;
     if (cx(i)) jx += cx(i) * d;
     if (cy(i)) jy += cy(i) * d;
@@ -549,13 +592,12 @@ __device__ __forceinline__ void node_velocity_range(const LatDev &L, int fsrc, i
     cnt += __popcll(mask);
   }
   __syncthreads();
-  const T *f = static_cast<const T *>(L.f[fsrc]);
   const float *g = L.g[par];
   for (int j = lane; j < cnt; j += 64) {
     const long long n = w0 + wl[j];
     const long long row = n / L.nx;
     const int X = (int)(n - row * L.nx), Y = (int)(row % L.ny), Z = (int)(row / L.ny);
-    const float3 u = lattice_velocity<T>(L, f, g, X, Y, Z);
+    const float3 u = lattice_velocity<T>(L, fsrc, g, X, Y, Z);
     L.U[n] = make_float4(u.x, u.y, u.z, 0.0f);
   }
 }
@@ -621,7 +663,6 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
       w[q] = wq;
     }
   }
-  const T *f = static_cast<const T *>(L.f[fsrc]);
   const float *g = L.g[par];
   Box b{0, 0, 0, 1, 1, 1, 0, false};
   // the LDS box covers the stencils of the block's major capsule only (see
@@ -659,7 +700,7 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
     __syncthreads();
     for (int c = threadIdx.x; c < V; c += blockDim.x) {
       if (!sm.mark[c]) continue;
-      const float3 u = lattice_velocity<T>(L, f, g, wrap_mod(x0 + c % ex, L.nx),
+      const float3 u = lattice_velocity<T>(L, fsrc, g, wrap_mod(x0 + c % ex, L.nx),
                                            wrap_mod(y0 + (c / ex) % ey, L.ny), z0 + c / (ex * ey));
       sm.box[0][c] = u.x;
       sm.box[1][c] = u.y;
@@ -680,7 +721,7 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
       const int cell = ((gz[q] - z0) * ey + (gy[q] - y0)) * ex + (gx[q] - x0);
       u = make_float3(sm.box[0][cell], sm.box[1][cell], sm.box[2][cell]);
     } else {
-      u = lattice_velocity<T>(L, f, g, wrap_mod(gx[q], L.nx), wrap_mod(gy[q], L.ny), gz[q]);
+      u = lattice_velocity<T>(L, fsrc, g, wrap_mod(gx[q], L.nx), wrap_mod(gy[q], L.ny), gz[q]);
     }
     ux += w[q] * u.x;
     uy += w[q] * u.y;
@@ -960,7 +1001,7 @@ __global__ __launch_bounds__(256) void k_adj_interp(LatDev L, MemDev Mm, AdjDev 
       const float wx = phi<M>(rx), wy = phi<M>(ry), wz = phi<M>(rz);
       const float dx = dphi<M>(rx) * wy * wz, dy = wx * dphi<M>(ry) * wz, dz = wx * wy * dphi<M>(rz);
       const int X = wrap_mod(o.x + lx, L.nx), Y = wrap_mod(o.y + ly, L.ny);
-      const float3 U = lattice_velocity<float>(L, f1, L.g[par], X, Y, Z);
+      const float3 U = lattice_velocity_of<float>(L, f1, L.g[par], X, Y, Z);
       const float su = U.x * lu.x + U.y * lu.y + U.z * lu.z;
       gx = -su * dx;
       gy = -su * dy;

@@ -1,0 +1,137 @@
+"""The AA streaming pattern (IBM_OPT_STREAMING = 1: one population buffer,
+even steps collide in place into the opposite slots, odd steps gather from
+the neighbours and push back) against the FP64 oracle: the lattice update
+alone, coupled steps with each delta width and both interpolation forms
+(which read the swapped state after even steps), FP16 storage, the device
+totals and field read-back after odd step counts, and the refused
+combinations."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1004_2416_amd import workloads as W
+from parity_helpers import Case, O, rel_err, scaled_err
+from test_gpu_parity import W19, small_case
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def B():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_1004_2416_amd import binding
+    return binding
+
+
+@pytest.mark.parametrize("shape,tau,linear", [((32, 20, 12), 1.0, False), ((64, 8, 6), 0.8, False),
+                                              ((4, 3, 5), 1.7, True), ((256, 4, 4), 0.6, False)])
+def test_aa_lattice_update(B, shape, tau, linear):
+    """Five single steps (both kinds, the read-back after even and odd
+    counts) and then 37 graph-replayed steps, walls moving."""
+    nx, ny, nz = shape
+    wl = W.Workload("lbm", nx, ny, nz, tau, 0.03, 2, 0, [])
+    c = Case(wl, perturb=0.02, seed=3)
+    lat = c.gpu(graph=True)
+    lat.set_option(B.OPT_EQUILIBRIUM, int(linear))
+    lat.set_option(B.OPT_STREAMING, B.STREAM_AA)
+    f = c.f0
+    for k in range(5):
+        lat.step(1)
+        f = O.lbm_step(f, None, tau, 0.03, linear=linear)
+        assert rel_err(lat.populations().cpu().numpy(), f) < 1e-5, k
+    lat.step(37)
+    for _ in range(37):
+        f = O.lbm_step(f, None, tau, 0.03, linear=linear)
+    got = lat.populations().cpu().numpy()
+    mass = lat.totals()[0]
+    lat.close()
+    say("  AA lattice %s: 42 steps, f %.2e, mass %.15g vs %.15g" % (shape, rel_err(got, f), mass,
+                                                                    f.sum()))
+    assert rel_err(got, f) < 1e-5
+    assert abs(mass - f.sum()) < 1e-9 * f[0].size
+
+
+@pytest.mark.parametrize("m,box,storage", [(2, 3, "fp32"), (3, 3, "fp32"), (4, 3, "fp32"),
+                                           (2, 5, "fp32"), (3, 5, "fp32"), (3, 0, "fp32"),
+                                           (3, 3, "fp16")])
+def test_aa_coupled_steps(B, m, box, storage):
+    """A capsule (and its stencils across the periodic x end): 1 step, then
+    48 graph-replayed steps, populations, nodes and forces against the
+    oracle; box 3 interpolates through LDS boxes, box 5 from the velocity
+    field, box 0 per stencil node, each reading the swapped state after the
+    even steps."""
+    c = small_case(n=(32, 20, 16), m=m, level=2, r=4.0, ca=0.02, uw=0.03,
+                   center=(30.6, 9.3, 7.6))
+    lat = c.gpu(storage=storage, graph=True)
+    lat.set_option(B.OPT_STENCIL_BOX, box)
+    lat.set_option(B.OPT_STREAMING, B.STREAM_AA)
+    sim = c.oracle(f=lat.populations().cpu().numpy())
+    for n in (1, 48):
+        lat.step(n)
+        assert sim.run(n) == 0
+        f = lat.populations().cpu().numpy()
+        xg, Fg, ug = [a.cpu().numpy() for a in lat.mesh()]
+        ef, ex = rel_err(f, sim.f), float(np.max(np.abs(xg - sim.x)))
+        eu = scaled_err(ug, sim.un)
+        say("  AA m=%d box %d %s after %d: f %.2e  u %.2e  x %.2e" % (m, box, storage, sim.t, ef,
+                                                                     eu, ex))
+        if storage == "fp32":
+            assert ef < 1e-5 and eu < 1e-4 and ex < 1e-4
+        else:
+            dev = np.max(np.abs(sim.f - W19))
+            assert np.max(np.abs(f - sim.f)) < sim.t * 2.0 ** -11 * dev and ex < 1e-3
+    lat.close()
+
+
+def test_aa_matches_two_buffers(B):
+    """The same coupled run with both streaming patterns: 33 steps (ending
+    odd, the swapped state) and 64, then the fields and the totals."""
+    c = small_case(n=(32, 20, 16), m=3, level=2, r=4.0, ca=0.02, uw=0.03)
+    out = {}
+    for pattern in (B.STREAM_TWO_BUFFERS, B.STREAM_AA):
+        lat = c.gpu(graph=True)
+        lat.set_option(B.OPT_STREAMING, pattern)
+        res = []
+        for n in (33, 31):
+            lat.step(n)
+            res.append((lat.populations().cpu().numpy(), lat.velocity().cpu().numpy(),
+                        lat.mesh()[0].cpu().numpy(), lat.totals()))
+        lat.close()
+        out[pattern] = res
+    for k in range(2):
+        a, b = out[B.STREAM_TWO_BUFFERS][k], out[B.STREAM_AA][k]
+        say("  AA vs two buffers, step %d: f %.2e  u %.2e  x %.2e  totals %.2e" % (
+            (33, 64)[k], rel_err(b[0], a[0]), scaled_err(b[1], a[1]),
+            float(np.max(np.abs(b[2] - a[2]))), float(np.max(np.abs(b[3] - a[3])))))
+        assert rel_err(b[0], a[0]) < 1e-6
+        assert scaled_err(b[1], a[1]) < 1e-5
+        assert np.max(np.abs(b[2] - a[2])) < 1e-5
+        assert np.max(np.abs(b[3] - a[3])) < 1e-9 * b[0][0].size
+
+
+def test_aa_refused_combinations(B):
+    c = small_case(n=(32, 20, 16), m=3)
+    lat = c.gpu(graph=False)
+    lat.set_option(B.OPT_STREAMING, B.STREAM_AA)
+    lat.step(1)
+    with pytest.raises(B.IBMError):
+        lat.set_populations(c.f0)           # odd count: the swapped state
+    with pytest.raises(B.IBMError):
+        lat.set_option(B.OPT_STREAMING, 0)  # changes only at even counts
+    lat.step(1)
+    with pytest.raises(B.IBMError):
+        lat.attach_tangent([1.0], [1.0], 0.0)
+    lat.set_option(B.OPT_STREAMING, 0)
+    lat.close()
+    odd = Case(W.Workload("odd", 30, 8, 8, 1.0, 0.01, 2, 0, []))
+    lat = odd.gpu(graph=False)
+    with pytest.raises(B.IBMError):
+        lat.set_option(B.OPT_STREAMING, B.STREAM_AA)  # nx not a multiple of 4
+    lat.close()
