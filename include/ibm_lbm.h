@@ -181,7 +181,11 @@ extern "C" {
                                   multiple of 4 and no tangent; the adjoint
                                   and batches need two buffers.  Changes
                                   only after an even number of steps;
-                                  populations can be set then only.
+                                  populations can be set then only.  After
+                                  an even step the interpolation goes
+                                  through the velocity field (stencil-box
+                                  bit 2), the one form that reads the
+                                  swapped state.
                                   Results are those of two buffers (to FP32
                                   rounding)                                 */
 #define IBM_STREAM_TWO_BUFFERS 0

@@ -215,7 +215,7 @@ void reset_force_state(ibm_lattice *lat, hipStream_t s) {
 int interp_mode(int box_mode) { return (box_mode & 4) ? 2 : ((box_mode & 2) ? 1 : 0); }
 
 // Population state after `steps` completed steps, as the readers take it
-// (pop_post, stored_post): two buffers, the buffer steps & 1; the AA pattern,
+// (pop_buffer and pop_swapped, stored_post): two buffers, the buffer steps & 1; the AA pattern,
 // buffer 0 after an even number of steps and the swapped state 2 after an odd
 // number.
 int pop_state(const ibm_lattice *lat, int64_t steps) {

@@ -501,18 +501,13 @@ __device__ __forceinline__ float ld_pop<__half>(const __half *p, long long idx, 
   return __half2float(p[idx]) * inv_scale;
 }
 
-// The post-stream population deviation f_i - w_i at node (X, Y, Z) of the
-// state `state`: 0 or 1, buffer 0 or 1 (two buffers; or the AA pattern after
-// an odd step, buffer 0); 2, the AA pattern after an even step: the
-// post-collision values sit in the opposite slots of the nodes they leave,
+// The post-stream population deviation f_i - w_i at node (X, Y, Z) in state
+// 2, the AA pattern after an even step (f: buffer 0): the post-collision
+// values sit in the opposite slots of the nodes they leave,
 // f_i(X) = A[opp(i)][X - c_i], or A[i][X] less the wall term of opp(i) for a
 // population coming back from a wall (collide_stream_rowseg_a).
 template <typename T>
-__device__ __forceinline__ float pop_post(const LatDev &L, int state, int i, int X, int Y, int Z) {
-  if (state < 2)
-    return ld_pop<T>(static_cast<const T *>(L.f[state]), pidx(L, i, (long long)Z * L.ny + Y, X),
-                     L.h_inv[i]);
-  const T *f = static_cast<const T *>(L.f[0]);
+__device__ __forceinline__ float pop_swapped(const LatDev &L, const T *f, int i, int X, int Y, int Z) {
   const int zs = Z - cz(i);
   if (cz(i) != 0 && (zs < 0 || zs >= L.nz))
     return ld_pop<T>(f, pidx(L, i, (long long)Z * L.ny + Y, X), L.h_inv[i]) - wall_kick(opp(i), L.uw);
@@ -543,17 +538,16 @@ __device__ __forceinline__ float3 lattice_velocity_of(const LatDev &L, const T *
                      (jz + 0.5f * g[2 * L.S + n]) * inv_rho);
 }
 
-// Lattice velocity u(X, t+1) of Eq. (velocityinterpolation) at lattice node n
-// of population state `state` (pop_post).
+// Lattice velocity u(X, t+1) of Eq. (velocityinterpolation) at lattice node
+// (X, Y, Z) in state 2 of the AA pattern (f: buffer 0, pop_swapped).
 template <typename T>
-__device__ __forceinline__ float3 lattice_velocity(const LatDev &L, int state, const float *g,
-                                                   int X, int Y, int Z) {
-  const long long row = (long long)Z * L.ny + Y;
-  const long long n = row * L.nx + X;
+__device__ __forceinline__ float3 lattice_velocity_swapped(const LatDev &L, const T *f,
+                                                           const float *g, int X, int Y, int Z) {
+  const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
   float drho = 0.0f, jx = 0.0f, jy = 0.0f, jz = 0.0f;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const float d = pop_post<T>(L, state, i, X, Y, Z);
+    const float d = pop_swapped<T>(L, f, i, X, Y, Z);
     drho += d;
     if (cx(i)) jx += cx(i) * d;
     if (cy(i)) jy += cy(i) * d;
@@ -566,7 +560,8 @@ __device__ __forceinline__ float3 lattice_velocity(const LatDev &L, int state, c
 
 // The lattice velocity u(X, t+1) of Eq. (velocityinterpolation) at every
 // node that this step's stencils touch with a nonzero weight (node stamp =
-// step), into L.U.  Each wavefront scans 512 consecutive nodes (lattice
+// step), into L.U, from population buffer fsrc, or (SW) from state 2 of the
+// AA pattern in buffer 0.  Each wavefront scans 512 consecutive nodes (lattice
 // order, x fastest) for marks, lists the marked ones in LDS in that order,
 // and then evaluates the list with all its lanes, so that neighbouring
 // marked nodes share cache lines and few lanes idle.  Each node is evaluated
@@ -574,7 +569,7 @@ __device__ __forceinline__ float3 lattice_velocity(const LatDev &L, int state, c
 // it; the block covers nodes [n0, n1), n1 - n0 <= NODE_VELOCITY_NODES.
 constexpr int NODE_VELOCITY_NODES = 2048;  // nodes per block: 512 per wavefront
 
-template <typename T>
+template <typename T, bool SW = false>
 __device__ __forceinline__ void node_velocity_range(const LatDev &L, int fsrc, int par,
                                                     long long n0, long long n1) {
   __shared__ int list[NODE_VELOCITY_NODES];
@@ -593,20 +588,22 @@ __device__ __forceinline__ void node_velocity_range(const LatDev &L, int fsrc, i
   }
   __syncthreads();
   const float *g = L.g[par];
+  const T *f = static_cast<const T *>(L.f[SW ? 0 : fsrc]);
   for (int j = lane; j < cnt; j += 64) {
     const long long n = w0 + wl[j];
     const long long row = n / L.nx;
     const int X = (int)(n - row * L.nx), Y = (int)(row % L.ny), Z = (int)(row / L.ny);
-    const float3 u = lattice_velocity<T>(L, fsrc, g, X, Y, Z);
+    const float3 u = SW ? lattice_velocity_swapped<T>(L, f, g, X, Y, Z)
+                        : lattice_velocity_of<T>(L, f, g, X, Y, Z);
     L.U[n] = make_float4(u.x, u.y, u.z, 0.0f);
   }
 }
 
-template <typename T>
+template <typename T, bool SW>
 __global__ __launch_bounds__(256) void k_node_velocity(LatDev L, int fsrc, int par) {
   const long long N = (long long)L.nx * L.ny * L.nz;
   const long long n0 = (long long)blockIdx.x * NODE_VELOCITY_NODES;
-  node_velocity_range<T>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES));
+  node_velocity_range<T, SW>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES));
 }
 
 // The lattice velocity is evaluated once per lattice node of the block's
@@ -663,6 +660,7 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
       w[q] = wq;
     }
   }
+  const T *f = static_cast<const T *>(L.f[fsrc]);
   const float *g = L.g[par];
   Box b{0, 0, 0, 1, 1, 1, 0, false};
   // the LDS box covers the stencils of the block's major capsule only (see
@@ -700,8 +698,8 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
     __syncthreads();
     for (int c = threadIdx.x; c < V; c += blockDim.x) {
       if (!sm.mark[c]) continue;
-      const float3 u = lattice_velocity<T>(L, fsrc, g, wrap_mod(x0 + c % ex, L.nx),
-                                           wrap_mod(y0 + (c / ex) % ey, L.ny), z0 + c / (ex * ey));
+      const float3 u = lattice_velocity_of<T>(L, f, g, wrap_mod(x0 + c % ex, L.nx),
+                                              wrap_mod(y0 + (c / ex) % ey, L.ny), z0 + c / (ex * ey));
       sm.box[0][c] = u.x;
       sm.box[1][c] = u.y;
       sm.box[2][c] = u.z;
@@ -721,7 +719,7 @@ __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, 
       const int cell = ((gz[q] - z0) * ey + (gy[q] - y0)) * ex + (gx[q] - x0);
       u = make_float3(sm.box[0][cell], sm.box[1][cell], sm.box[2][cell]);
     } else {
-      u = lattice_velocity<T>(L, fsrc, g, wrap_mod(gx[q], L.nx), wrap_mod(gy[q], L.ny), gz[q]);
+      u = lattice_velocity_of<T>(L, f, g, wrap_mod(gx[q], L.nx), wrap_mod(gy[q], L.ny), gz[q]);
     }
     ux += w[q] * u.x;
     uy += w[q] * u.y;
@@ -768,6 +766,10 @@ __global__ __launch_bounds__(256) void k_interp_field(LatDev L, MemDev Mm, int f
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
                           int advect, int mode, hipStream_t s) {
   if (M.nn <= 0) return;
+  // state 2 of the AA pattern (after an even step) is read by the velocity
+  // pass alone: the other forms would carry its gather in every kernel
+  const bool swapped = fsrc == 2;
+  if (swapped) mode = 2;
   const int gs = M.m == 2 ? group_size<2>() : (M.m == 3 ? group_size<3>() : group_size<4>());
   const long long lanes = (long long)M.nn * gs;
   const int nblocks = (int)((lanes + 255) / 256);
@@ -801,12 +803,14 @@ void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, 
   // the lattice velocity at the marked nodes, then the stencil sums from it
   const long long N = (long long)L.nx * L.ny * L.nz;
   const dim3 vgrid((unsigned)((N + NODE_VELOCITY_NODES - 1) / NODE_VELOCITY_NODES));
+  const int fb = swapped ? 0 : fsrc;  // the stencil sums read the field only
 #define IBM_LAUNCH_INTERP_FIELD(T)                                                                  \
   do {                                                                                              \
-    k_node_velocity<T><<<vgrid, block, 0, s>>>(L, fsrc, par);                                       \
-    if (M.m == 2) k_interp_field<T, 2><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);      \
-    else if (M.m == 3) k_interp_field<T, 3><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks); \
-    else k_interp_field<T, 4><<<grid, block, 0, s>>>(L, M, fsrc, par, advect, nblocks);             \
+    if (swapped) k_node_velocity<T, true><<<vgrid, block, 0, s>>>(L, 0, par);                       \
+    else k_node_velocity<T, false><<<vgrid, block, 0, s>>>(L, fsrc, par);                           \
+    if (M.m == 2) k_interp_field<T, 2><<<grid, block, 0, s>>>(L, M, fb, par, advect, nblocks);         \
+    else if (M.m == 3) k_interp_field<T, 3><<<grid, block, 0, s>>>(L, M, fb, par, advect, nblocks);    \
+    else k_interp_field<T, 4><<<grid, block, 0, s>>>(L, M, fb, par, advect, nblocks);                \
   } while (0)
   if (fp16) IBM_LAUNCH_INTERP_FIELD(__half);
   else IBM_LAUNCH_INTERP_FIELD(float);
@@ -1442,8 +1446,8 @@ static void launch_interp_far_t(const LatDev &L, const MemDev &M, int fsrc, int 
   const dim3 grid(xcd_grid(nblocks) + far_blocks(L, rs)), block(256);
   if (mode == 2) {
     const long long N = (long long)L.nx * L.ny * L.nz;
-    k_node_velocity<T><<<dim3((unsigned)((N + NODE_VELOCITY_NODES - 1) / NODE_VELOCITY_NODES)), block,
-                         0, s>>>(L, fsrc, par);
+    k_node_velocity<T, false><<<dim3((unsigned)((N + NODE_VELOCITY_NODES - 1) / NODE_VELOCITY_NODES)),
+                                block, 0, s>>>(L, fsrc, par);
   }
 #define IBM_LAUNCH_INTERP_FAR(MD)                                                                                \
   do {                                                                                                           \

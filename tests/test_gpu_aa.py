@@ -64,9 +64,9 @@ def test_aa_lattice_update(B, shape, tau, linear):
 def test_aa_coupled_steps(B, m, box, storage):
     """A capsule (and its stencils across the periodic x end): 1 step, then
     48 graph-replayed steps, populations, nodes and forces against the
-    oracle; box 3 interpolates through LDS boxes, box 5 from the velocity
-    field, box 0 per stencil node, each reading the swapped state after the
-    even steps."""
+    oracle.  After odd steps box 3 interpolates through LDS boxes, box 5 from
+    the velocity field and box 0 per stencil node; after even steps all
+    three go through the velocity field, which reads the swapped state."""
     c = small_case(n=(32, 20, 16), m=m, level=2, r=4.0, ca=0.02, uw=0.03,
                    center=(30.6, 9.3, 7.6))
     lat = c.gpu(storage=storage, graph=True)
