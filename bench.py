@@ -66,12 +66,12 @@ def measured_traffic(workload: str, storage: str):
 
 
 def setup(workload: str, storage: str, graph: bool, variant: int = -1, box: int = -1,
-          overlap: int = -1, streaming: int = -1):
+          overlap: int = -1, streaming: int = -1, one_buffer: bool = False):
     from paper_1004_2416_amd import binding as B
     from paper_1004_2416_amd import workloads as W
 
     wl = W.config(workload)
-    lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau, storage=storage)
+    lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau, storage=storage, one_buffer=one_buffer)
     lat.set_shear(wl.u_w, init_profile=True)
     meshes = [B.icosphere(c.level, c.r, c.center) for c in wl.capsules]
     lat.add_capsules(meshes, [c.ks for c in wl.capsules], [c.ka for c in wl.capsules], wl.m)
@@ -196,7 +196,7 @@ def single_leg(args, workload: str, storage: str, roofline: bool):
     """One lattice workload in the benchmark's launch configuration: warm-up
     and graph capture, then exactly args.steps timed steps."""
     wl, lat = setup(workload, storage, not args.no_graph, args.lbm_variant,
-                    args.stencil_box, args.overlap, args.streaming)
+                    args.stencil_box, args.overlap, args.streaming, args.one_buffer)
     tuned = lat.autotune(64) if args.autotune else None
     split_box = lat.split_box()
     prime(lat, args.warmup)
@@ -298,6 +298,8 @@ def main():
     ap.add_argument("--streaming", type=int, default=-1,
                     help="population streaming pattern: 0 two buffers, 1 AA (one buffer); "
                          "-1 the library's default")
+    ap.add_argument("--one-buffer", action="store_true",
+                    help="one population buffer (the AA pattern; nx a multiple of 4)")
     ap.add_argument("--sensitivity", action="store_true",
                     help="time the tangent-model gradient of D instead of the step")
     ap.add_argument("--autotune", action="store_true",
@@ -349,9 +351,13 @@ def main():
                   "u_w": wl.u_w, "tau": wl.tau, "lbm_variant": args.lbm_variant,
                   "stencil_box": args.stencil_box,
                   "overlap": args.overlap, "split_box": ex["split_box"],
+                  "streaming": ("aa_one_buffer" if args.one_buffer else
+                                "aa" if args.streaming == 1 else "two_buffers"),
                   "autotuned": ex["tuned"]}
         kernel = "k_collide_stream_rows"
-        traffic_key = wl.name
+        # the stored counters were taken on the two-buffer kernel
+        aa = args.one_buffer or args.streaming == 1
+        traffic_key = None if aa else wl.name
     algo = bytes_per_node(args.storage) * n_nodes
     achieved = algo / (ex["k1_ms"] * 1e-3) / 1e9
     out = {
@@ -375,7 +381,7 @@ def main():
         "roofline": {
             "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic(traffic_key, args.storage),
+            "traffic": measured_traffic(traffic_key, args.storage) if traffic_key else None,
             "kernel": kernel,
             "algorithmic_bytes_per_launch": algo,
             "kernel_us": round(ex["k1_ms"] * 1e3, 2),

@@ -58,10 +58,18 @@ extern "C" {
                                            check are not valid                  */
 
 /* ---- population storage ------------------------------------------------- */
-/* Populations are stored as deviations f_i - w_i from the lattice weights,
- * structure of arrays [19][nz][ny][nx] (x fastest), arithmetic in FP32. */
+/* Populations are stored as deviations f_i - w_i from the lattice weights in
+ * groups of x rows (x fastest), arithmetic in FP32; ibm_get_fields and
+ * ibm_set_fields exchange them as [19][nz][ny][nx] FP64 values. */
 #define IBM_STORAGE_FP32 0
 #define IBM_STORAGE_FP16 1   /* deviations scaled per direction, FP16 storage */
+#define IBM_STORAGE_ONE_BUFFER 4 /* or-ed with either: one population buffer
+                                    instead of two; the lattice then streams
+                                    with the AA pattern only
+                                    (IBM_OPT_STREAMING 1, fixed), needs nx a
+                                    multiple of 4 and at most 256, and takes
+                                    no tangent, adjoint or batch.  Lattices
+                                    about 1.6x larger fit the same memory */
 
 /* ---- equilibrium --------------------------------------------------------- */
 #define IBM_EQ_QUADRATIC 0   /* Sec. II.A, Eq. (equilibrium)                  */
@@ -194,8 +202,10 @@ extern "C" {
 typedef struct ibm_lattice ibm_lattice;
 
 /* Bytes of device memory the lattice state needs (two population buffers,
- * two force densities and their tile stamps, the interpolation velocity
- * field, control words).  storage: IBM_STORAGE_*. */
+ * or one with IBM_STORAGE_ONE_BUFFER, two force densities and their tile
+ * stamps, the node stamps, the interpolation velocity field, control words).
+ * storage: IBM_STORAGE_FP32 or IBM_STORAGE_FP16, optionally or-ed with
+ * IBM_STORAGE_ONE_BUFFER. */
 int ibm_lattice_bytes(int nx, int ny, int nz, int storage, size_t *bytes);
 
 /* Create a lattice of nx * ny * nz nodes with BGK relaxation time tau > 1/2

@@ -26,6 +26,7 @@ ERRORS = {
     -6: "IBM_ERR_INVERTED_FACE",
 }
 STORAGE = {"fp32": 0, "fp16": 1}
+STORAGE_ONE_BUFFER = 4
 FIELD_POPS, FIELD_RHO, FIELD_U, FIELD_FORCE = 0, 1, 2, 3
 OPT_GRAPH, OPT_EQUILIBRIUM, OPT_ADVECTION, OPT_RECENTER, OPT_LBM_VARIANT = 0, 1, 2, 3, 4
 OPT_STENCIL_BOX, OPT_OVERLAP, OPT_STREAMING = 6, 7, 8
@@ -148,20 +149,22 @@ class Lattice:
     nx, ny, nz   fluid nodes; walls at z = -1/2 and nz - 1/2 (Sec. II.A)
     tau          BGK relaxation time (> 1/2)
     storage      "fp32" or "fp16" (scaled deviations f_i - w_i)
+    one_buffer   one population buffer, streamed with the AA pattern
     stream       torch.cuda.Stream to enqueue on (default: the current one)
     """
 
     def __init__(self, nx: int, ny: int, nz: int, tau: float = 1.0, storage: str = "fp32",
-                 device="cuda", stream=None):
+                 device="cuda", stream=None, one_buffer: bool = False):
         torch = _torch()
         self.shape = (int(nz), int(ny), int(nx))
         self.device = torch.device(device)
         self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
         nbytes = ctypes.c_size_t()
-        _check(lib.ibm_lattice_bytes(nx, ny, nz, STORAGE[storage], ctypes.byref(nbytes)))
+        code = STORAGE[storage] | (STORAGE_ONE_BUFFER if one_buffer else 0)
+        _check(lib.ibm_lattice_bytes(nx, ny, nz, code, ctypes.byref(nbytes)))
         self._raw, self._state = _aligned_buffer(nbytes.value, self.device)
         h = ctypes.c_void_p()
-        _check(lib.ibm_lattice_create(nx, ny, nz, float(tau), STORAGE[storage],
+        _check(lib.ibm_lattice_create(nx, ny, nz, float(tau), code,
                                       ctypes.c_void_p(self._state.data_ptr()), nbytes.value,
                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)))
         self._h = h

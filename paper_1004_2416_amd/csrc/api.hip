@@ -69,7 +69,8 @@ LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
   l.tny = (ny + ibm::TILE_Y - 1) / ibm::TILE_Y;
   l.tnz = (nz + ibm::TILE_Z - 1) / ibm::TILE_Z;
   const size_t tiles = (size_t)l.tnx * l.tny * l.tnz;
-  const size_t es = storage == IBM_STORAGE_FP16 ? 2 : 4;
+  const size_t es = (storage & IBM_STORAGE_FP16) ? 2 : 4;
+  const int nbuf = (storage & IBM_STORAGE_ONE_BUFFER) ? 1 : 2;
   size_t off = 0;
   l.off_ctrl = off;
   off += round_up(sizeof(ibm::Ctrl), ALIGN);
@@ -86,8 +87,8 @@ LatticeLayout lattice_layout(int nx, int ny, int nz, int storage) {
     off += round_up(3 * (size_t)l.S * sizeof(float), ALIGN);
   }
   for (int k = 0; k < 2; ++k) {
-    l.off_f[k] = off;
-    off += round_up((size_t)l.pop_elems * es, ALIGN);
+    l.off_f[k] = k < nbuf ? off : l.off_f[0];  // one buffer: both names, one array
+    if (k < nbuf) off += round_up((size_t)l.pop_elems * es, ALIGN);
   }
   l.total = off;
   return l;
@@ -129,7 +130,8 @@ MembraneLayout membrane_layout(int nc, long long nn, long long nf) {
 }  // namespace
 
 struct ibm_lattice {
-  int nx = 0, ny = 0, nz = 0, storage = 0;
+  int nx = 0, ny = 0, nz = 0, storage = 0;  // storage: IBM_STORAGE_FP32 or IBM_STORAGE_FP16
+  bool one_buffer = false;                  // IBM_STORAGE_ONE_BUFFER: the AA pattern only
   double tau = 1.0, uw = 0.0;
   hipStream_t stream = nullptr;
   hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
@@ -708,8 +710,11 @@ int ibm_lattice_bytes(int nx, int ny, int nz, int storage, size_t *bytes) {
   if ((long long)nx * ny * nz > (1LL << 31))
     return fail(IBM_ERR_INVALID_ARG, "lattice larger than 2^31 nodes");
   if (nz > 65535 || ny > 65535 * 8) return fail(IBM_ERR_INVALID_ARG, "ny or nz beyond the launch grid");
-  if (storage != IBM_STORAGE_FP32 && storage != IBM_STORAGE_FP16)
+  if (storage & ~(IBM_STORAGE_FP16 | IBM_STORAGE_ONE_BUFFER))
     return fail(IBM_ERR_INVALID_ARG, "unknown storage %d", storage);
+  if ((storage & IBM_STORAGE_ONE_BUFFER) && (nx % 4 || ibm::pop_geometry(nx, ny, nz).tpr <= 0))
+    return fail(IBM_ERR_INVALID_ARG,
+                "one population buffer (the AA pattern) needs nx a multiple of 4 and at most 256");
   *bytes = lattice_layout(nx, ny, nz, storage).total;
   return ok();
 }
@@ -730,11 +735,13 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
   lat->nx = nx;
   lat->ny = ny;
   lat->nz = nz;
+  lat->one_buffer = (storage & IBM_STORAGE_ONE_BUFFER) != 0;
+  storage &= IBM_STORAGE_FP16;  // lat->storage: the precision
   lat->storage = storage;
   lat->tau = tau;
   lat->stream = static_cast<hipStream_t>(stream);
   lat->base = static_cast<char *>(dev_state);
-  lat->lay = lattice_layout(nx, ny, nz, storage);
+  lat->lay = lattice_layout(nx, ny, nz, storage | (lat->one_buffer ? IBM_STORAGE_ONE_BUFFER : 0));
   ibm::LatDev &L = lat->L;
   L.nx = nx;
   L.ny = ny;
@@ -763,7 +770,7 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
   L.inv_tau = (float)(1.0 / tau);
   L.guo_pre = (float)(1.0 - 0.5 / tau);
   L.uw = 0.0f;
-  L.aa = 0;
+  L.aa = lat->one_buffer ? 1 : 0;
   L.zlo = 0;
   L.zhi = nz;
   L.ylo = 0;
@@ -778,7 +785,7 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
     }
   }
   reset_force_state(lat, lat->stream);
-  for (int k = 0; k < 2; ++k) {
+  for (int k = 0; k < (lat->one_buffer ? 1 : 2); ++k) {
     const size_t words = ((size_t)lat->lay.pop_elems * (storage == IBM_STORAGE_FP16 ? 2 : 4) + 3) / 4;
     ibm::launch_fill_u32(L.f[k], (long long)words, 0u, lat->stream);  // at rest: f_i = w_i
   }
@@ -1234,6 +1241,8 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
       if (value == IBM_STREAM_AA && (lat->L.tpr <= 0 || lat->nx % 4 || lat->has_tan))
         return fail(IBM_ERR_BAD_STATE,
                     "the AA pattern needs rows of at most 256 nodes, nx a multiple of 4 and no tangent");
+      if (lat->one_buffer && value != IBM_STREAM_AA)
+        return fail(IBM_ERR_BAD_STATE, "a lattice with one population buffer streams with the AA pattern");
       if (value != lat->L.aa && (lat->steps & 1))
         return fail(IBM_ERR_BAD_STATE, "the streaming pattern changes after an even number of steps only");
       lat->L.aa = value;
@@ -1476,6 +1485,7 @@ TangentLayout tangent_layout(const ibm_lattice *lat) {
 
 int ibm_tangent_bytes(ibm_lattice *lat, size_t *bytes) {
   if (!lat || !bytes) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
+  if (lat->one_buffer) return fail(IBM_ERR_BAD_STATE, "the tangent model needs two population buffers");
   *bytes = tangent_layout(lat).total;
   return ok();
 }
@@ -1631,6 +1641,7 @@ int ibm_adjoint_bytes(ibm_lattice *lat, int64_t steps, int checkpoint_every, siz
   if (!lat || !bytes) return fail(IBM_ERR_INVALID_ARG, "NULL argument");
   if (!lat->has_mem) return fail(IBM_ERR_BAD_STATE, "no membrane attached");
   if (steps < 1 || checkpoint_every < 1) return fail(IBM_ERR_INVALID_ARG, "steps and checkpoint_every must be >= 1");
+  if (lat->one_buffer) return fail(IBM_ERR_BAD_STATE, "the adjoint needs two population buffers");
   *bytes = adjoint_layout(lat, steps, checkpoint_every).total;
   return ok();
 }
@@ -1785,8 +1796,10 @@ int ibm_adjoint_gradient(ibm_lattice *lat, int64_t steps, int checkpoint_every, 
 
 int ibm_batch_bytes(int n_runs, ibm_lattice *const *runs, size_t *bytes) {
   if (n_runs < 1 || !runs || !bytes) return fail(IBM_ERR_INVALID_ARG, "need n_runs >= 1 and runs");
-  for (int r = 0; r < n_runs; ++r)
+  for (int r = 0; r < n_runs; ++r) {
     if (!runs[r]) return fail(IBM_ERR_INVALID_ARG, "run %d is NULL", r);
+    if (runs[r]->one_buffer) return fail(IBM_ERR_BAD_STATE, "batched runs use two population buffers");
+  }
   std::vector<ibm_lattice *> v(runs, runs + n_runs);
   std::vector<int2> li, ni;
   batch_items(v, 1, li, ni);  // the most lattice items: one wavefront per block

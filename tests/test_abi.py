@@ -50,6 +50,17 @@ def test_size_queries_and_validation(B):
     m = ctypes.c_size_t()
     assert B.lib.ibm_lattice_bytes(128, 128, 128, 1, ctypes.byref(m)) == 0
     assert per16 * N <= m.value < 1.02 * per16 * N
+    # one population buffer (the AA pattern): 19 x 4 B less per node in FP32,
+    # 19 x 2 B in FP16; only for rows a multiple of 4 and at most 256 long
+    for storage, pop in ((0, 76), (1, 38)):
+        one, two = ctypes.c_size_t(), ctypes.c_size_t()
+        assert B.lib.ibm_lattice_bytes(128, 128, 128, storage | 4, ctypes.byref(one)) == 0
+        assert B.lib.ibm_lattice_bytes(128, 128, 128, storage, ctypes.byref(two)) == 0
+        assert two.value - one.value == pop * N
+    assert B.lib.ibm_lattice_bytes(30, 8, 8, 4, ctypes.byref(m)) == -1
+    assert "multiple of 4" in B.lib.ibm_last_error().decode()
+    assert B.lib.ibm_lattice_bytes(260, 8, 8, 4, ctypes.byref(m)) == -1
+    assert B.lib.ibm_lattice_bytes(8, 8, 8, 2, ctypes.byref(m)) == -1
     assert B.lib.ibm_lattice_bytes(0, 4, 4, 0, ctypes.byref(n)) == -1
     assert "lattice size" in B.lib.ibm_last_error().decode()
     assert B.lib.ibm_lattice_bytes(4, 4, 4, 7, ctypes.byref(n)) == -1

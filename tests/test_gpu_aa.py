@@ -135,3 +135,55 @@ def test_aa_refused_combinations(B):
     with pytest.raises(B.IBMError):
         lat.set_option(B.OPT_STREAMING, B.STREAM_AA)  # nx not a multiple of 4
     lat.close()
+
+
+def test_one_buffer_lattice(B):
+    """IBM_STORAGE_ONE_BUFFER: the lattice holds one population array and
+    streams with the AA pattern.  A coupled run (1 step, then 63 through the
+    graphs, ending odd; then 1 more) against the oracle and against the same
+    run on a two-buffer lattice with the AA pattern; the refused
+    combinations."""
+    c = small_case(n=(32, 20, 16), m=3, level=2, r=4.0, ca=0.02, uw=0.03)
+    wl = c.wl
+
+    def make(one_buffer):
+        lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau, one_buffer=one_buffer)
+        lat.set_shear(wl.u_w, init_profile=False)
+        lat.add_capsules(c.meshes(), c.ks, c.ka, wl.m)
+        lat.set_option(B.OPT_GRAPH, 1)
+        if not one_buffer:
+            lat.set_option(B.OPT_STREAMING, B.STREAM_AA)
+        lat.set_populations(c.f0)
+        return lat
+
+    one, two = make(True), make(False)
+    assert one._state.numel() < two._state.numel()
+    sim = c.oracle()
+    for n in (1, 63, 1):
+        one.step(n)
+        two.step(n)
+        assert sim.run(n) == 0
+        f1, f2 = one.populations().cpu().numpy(), two.populations().cpu().numpy()
+        x1 = one.mesh()[0].cpu().numpy()
+        x2 = two.mesh()[0].cpu().numpy()
+        say("  one buffer after %d: f %.2e (two buffers %.2e)  x %.2e  vs two %.2e" % (
+            sim.t, rel_err(f1, sim.f), rel_err(f2, sim.f), float(np.max(np.abs(x1 - sim.x))),
+            float(np.max(np.abs(x1 - x2)))))
+        assert rel_err(f1, sim.f) < 1e-5 and np.max(np.abs(x1 - sim.x)) < 1e-4
+        assert rel_err(f1, f2) < 1e-6 and np.max(np.abs(x1 - x2)) < 1e-5
+    assert abs(one.totals()[0] - sim.f.sum()) < 1e-9 * sim.f[0].size
+    with pytest.raises(B.IBMError):
+        one.set_option(B.OPT_STREAMING, B.STREAM_TWO_BUFFERS)
+    one.step(1)  # even count again
+    with pytest.raises(B.IBMError):
+        one.set_option(B.OPT_STREAMING, B.STREAM_TWO_BUFFERS)
+    with pytest.raises(B.IBMError):
+        one.attach_tangent([1.0], [1.0], 0.0)
+    with pytest.raises(B.IBMError):
+        one.adjoint_gradient(4, 2)
+    with pytest.raises(B.IBMError):
+        B.Batch([one])
+    one.close()
+    two.close()
+    with pytest.raises(B.IBMError):
+        B.Lattice(30, 8, 8, 1.0, one_buffer=True)
