@@ -457,7 +457,7 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
 }
 
 template <int M, bool BOX, bool HALF>
-__global__ __launch_bounds__(256) void k_spread(LatDev L, MemDev Mm, int par, int nblocks) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_spread(LatDev L, MemDev Mm, int par, int nblocks) {
   __shared__ SpreadLDS sm;
   const int blk = xcd_block(nblocks);
   if (blk >= 0) spread_lanes<M, BOX, HALF>(L, Mm, par, blk, sm);
@@ -1151,7 +1151,7 @@ void launch_adj_fem(const LatDev &L, const MemDev &M, const AdjDev &A, hipStream
 // run's own launch (so a block never mixes runs).  The delta width is chosen
 // per block.
 // Each run's spreading box (bit 0 of its cmode) is chosen per block.
-__global__ __launch_bounds__(256) void k_batch_spread(BatchDev B, int par) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_spread(BatchDev B, int par) {
   __shared__ SpreadLDS sm;
   const int b = xcd_block(B.n_node_items);
   if (b < 0) return;
