@@ -83,10 +83,9 @@ def test_full_length_trajectory_fp32(B, name):
 @pytest.mark.parametrize("name", ["c2", "c3"])
 def test_full_length_trajectory_fp16(B, name):
     """FP16 storage of the scaled deviations (16 (f_i - w_i) / w_i, 11
-    significant bits): every stored population is rounded to 2^-11 of its
-    deviation at every step, a relative perturbation of the flow of order
-    1e-4 per step that the viscous flow damps; the stated bound for the
-    trajectory is D within 2 % of each capsule's largest D."""
+    significant bits): every stored population is rounded to within 2^-11
+    of its deviation at every step.  The bound stated for the whole run is
+    D within 2 % of each capsule's largest D, and the mass within 1e-4."""
     eD, mass, wl = run_trajectory(B, name, "fp16")
     assert eD.max() < 2e-2
     N = wl.nx * wl.ny * wl.nz
