@@ -116,6 +116,39 @@ def test_aa_matches_two_buffers(B):
         assert np.max(np.abs(b[3] - a[3])) < 1e-9 * b[0][0].size
 
 
+@pytest.mark.parametrize("ab2,linear,storage", [(True, False, "fp32"), (False, True, "fp32"),
+                                                (True, True, "fp16")])
+def test_aa_variants_against_oracle(B, ab2, linear, storage):
+    """The paper's two variants (Adams-Bashforth advection, the linearised
+    equilibrium) on a one-buffer lattice: 1 step, then 99 through the
+    graphs, against the oracle (FP16: each step adds at most 2^-11 of the
+    largest deviation)."""
+    c = small_case(n=(32, 20, 16), m=3, level=2, r=4.0, ca=0.02, uw=0.03)
+    wl = c.wl
+    lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau, storage=storage, one_buffer=True)
+    lat.set_shear(wl.u_w, init_profile=False)
+    lat.add_capsules(c.meshes(), c.ks, c.ka, wl.m)
+    lat.set_option(B.OPT_GRAPH, 1)
+    lat.set_option(B.OPT_ADVECTION, int(ab2))
+    lat.set_option(B.OPT_EQUILIBRIUM, int(linear))
+    lat.set_populations(c.f0)
+    sim = c.oracle(f=lat.populations().cpu().numpy(), ab2=ab2, linear=linear)
+    lat.step(1)
+    lat.step(99)
+    assert sim.run(100) == 0
+    f = lat.populations().cpu().numpy()
+    xg = lat.mesh()[0].cpu().numpy()
+    lat.close()
+    ex = float(np.max(np.abs(xg - sim.x)))
+    say("  AA ab2 %s linear %s %s, 100 steps: f %.2e  x %.2e" % (ab2, linear, storage,
+                                                                rel_err(f, sim.f), ex))
+    if storage == "fp32":
+        assert rel_err(f, sim.f) < 1e-5 and ex < 1e-4
+    else:
+        dev = np.max(np.abs(sim.f - W19))
+        assert np.max(np.abs(f - sim.f)) < 100 * 2.0 ** -11 * dev and ex < 1e-3
+
+
 def test_aa_refused_combinations(B):
     c = small_case(n=(32, 20, 16), m=3)
     lat = c.gpu(graph=False)
