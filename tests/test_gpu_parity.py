@@ -192,7 +192,7 @@ def test_coupled_step_parity_crowded_overlapping_capsules(B):
 @pytest.mark.parametrize("box", [1, 2, 3, 4, 5])
 def test_stencil_box_modes(B, m, box):
     """Spreading and/or interpolation through per-block LDS boxes (bits 0, 1)
-    or interpolation from the tile-velocity field (bit 2) match the oracle
+    or interpolation from the velocity field (bit 2) match the oracle
     like the direct per-lane form."""
     say("stencil box", box, "m", m)
     c = small_case(n=(40, 36, 30), m=m, level=3, r=8.0, ca=0.02, uw=0.03)
