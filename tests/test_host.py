@@ -1,0 +1,146 @@
+"""CPU checks of the host side around the kernels: the seeded workloads
+(placements, parameter conversions, sizes), the stored oracle references
+against the workloads they claim to follow, and bench.py's contract pieces
+that need no GPU."""
+import os
+import subprocess
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1004_2416_amd import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+ETA = 1.0 / 6.0  # tau = 1: nu = (tau - 1/2) / 3
+
+
+def test_dense_suspension_placement():
+    """200 r = 8 capsules on 256 x 128 x 128: every pair at least 2 r + 2 apart
+    under the minimum image in x and y, every centre r + 2 clear of both walls,
+    the volume fraction 10.2 %, and k_s = gamma_dot eta r / G with G drawn from
+    [0.01, 0.1]."""
+    wl = W.config("c3")
+    assert (wl.nx, wl.ny, wl.nz, len(wl.capsules), wl.m, wl.steps) == (256, 128, 128, 200, 2, 10000)
+    c = np.array([cap.center for cap in wl.capsules])
+    d = c[:, None, :] - c[None, :, :]
+    d[..., 0] -= wl.nx * np.round(d[..., 0] / wl.nx)
+    d[..., 1] -= wl.ny * np.round(d[..., 1] / wl.ny)
+    dist = np.sqrt((d ** 2).sum(-1)) + np.eye(len(c)) * 1e9
+    assert dist.min() >= 18.0
+    assert c[:, 2].min() >= 10.0 and c[:, 2].max() <= wl.nz - 1 - 10.0
+    phi = len(c) * 4.0 / 3.0 * np.pi * 8.0 ** 3 / (wl.nx * wl.ny * wl.nz)
+    assert abs(phi - 0.102) < 5e-4
+    gamma = 2.0 * wl.u_w / wl.nz
+    G = np.array([gamma * ETA * cap.r / cap.ks for cap in wl.capsules])
+    assert G.min() >= 0.01 and G.max() <= 0.1
+    assert all(cap.ka == cap.ks for cap in wl.capsules)
+    assert wl.n_membrane_nodes == 200 * 642
+
+
+@pytest.mark.parametrize("name,n,r,level,m,ks", [("c1", 32, 6.0, 3, 3, 0.0125),
+                                                 ("c2", 128, 16.0, 4, 4, 1.0 / 30.0),
+                                                 ("c5", 64, 8.0, 3, 3, 1.0 / 120.0)])
+def test_single_capsule_workloads(name, n, r, level, m, ks):
+    """The centred single-capsule workloads: k_s from G = gamma_dot eta r / k_s
+    with gamma_dot = 2 u_w / n, capsule at the box centre."""
+    wl = W.config(name)
+    cap = wl.capsules[0]
+    assert (wl.nx, wl.ny, wl.nz, wl.m, cap.level, cap.r) == (n, n, n, m, level, r)
+    assert cap.center == ((n - 1) / 2.0,) * 3
+    assert abs(cap.ks - ks) < 1e-12 * ks and cap.ka == cap.ks
+
+
+def test_paper_case_parameters():
+    """Table 2's first case: H = 35, r = 3.5, G = 0.01, Re = 0.02 gives
+    gamma_dot = Re nu / r^2 and kappa t = 120 in 4410 steps."""
+    wl = W.paper_case(35, 3.5, 3, 2)
+    gamma = 0.02 * ETA / 3.5 ** 2
+    assert abs(2.0 * wl.u_w / wl.nz - gamma) < 1e-15
+    assert wl.steps == 4410
+    cap = wl.capsules[0]
+    assert abs(gamma * ETA * cap.r / cap.ks - 0.01) < 1e-15
+
+
+def test_batched_sweep_sizes():
+    """The 64-run sweep: 6.67 M lattice nodes and 78,048 membrane nodes in
+    all, every capsule's stencil (half-width m/2 + 1) clear of the walls."""
+    wls = W.sweep_workloads()
+    assert len(wls) == 64
+    n_lat = sum(w.n_nodes_lattice for w in wls)
+    n_mem = sum(w.n_membrane_nodes for w in wls)
+    assert n_mem == 78048
+    assert abs(n_lat / 6.67e6 - 1) < 1e-3
+    for w in wls:
+        cap = w.capsules[0]
+        reach = cap.r + w.m / 2.0 + 1.0
+        assert cap.center[2] - reach >= 0 and cap.center[2] + reach <= w.nz - 1
+        assert 0.003 <= 2.0 * w.u_w / w.nz * ETA * cap.r / cap.ks <= 0.1
+
+
+@pytest.mark.parametrize("name", ["c2", "c3"])
+def test_stored_trajectories_follow_their_workloads(name):
+    """The oracle references name the workload they were run on, hold D of
+    every capsule every 100 steps from 0 to the workload's length, and start
+    from the undeformed shape (D = 0 up to the FP32 rounding of the node
+    positions, which leaves D ~ 1e-8)."""
+    path = os.path.join(GOLDEN, "trajectory_%s.txt" % name)
+    wl = W.config(name)
+    head = [l for l in open(path) if l.startswith("#")]
+    assert any(("workload %s:" % wl.name) in l and ("%d capsules, %d steps" % (len(wl.capsules),
+                                                                               wl.steps)) in l
+               for l in head)
+    rows = np.loadtxt(path, comments="#", ndmin=2)
+    assert rows.shape == (wl.steps // 100 + 1, 1 + len(wl.capsules))
+    assert np.array_equal(rows[:, 0], np.arange(0, wl.steps + 1, 100))
+    assert np.max(np.abs(rows[0, 1:])) < 1e-6
+    assert np.all(rows[1:, 1:] > 0) and np.all(rows[1:, 1:] < 1)
+
+
+def test_stored_sensitivities_are_central_differences():
+    """Each row's dD/dp is (D(p(1+h)) - D(p(1-h))) / (2 h p) of its own
+    columns, h = 1e-4, and the parameters are the c5 workload's."""
+    wl = W.config("c5")
+    cap = wl.capsules[0]
+    want = {"ks": cap.ks, "C": cap.ka / cap.ks, "gamma": 2.0 * wl.u_w / wl.nz}
+    seen = set()
+    for line in open(os.path.join(GOLDEN, "sensitivities_c5_2000.txt")):
+        if line.startswith("#"):
+            continue
+        k, p, dp, dm, d = line.split()
+        p, dp, dm, d = float(p), float(dp), float(dm), float(d)
+        assert abs(p - want[k]) < 1e-12 * abs(want[k])
+        assert abs((dp - dm) / (2e-4 * p) - d) < 1e-9 * abs(d)
+        seen.add(k)
+    assert seen == set(want)
+
+
+def test_bench_refuses_several_gpus():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stdout
+
+
+def test_bench_traffic_lookup():
+    """bench.py reports HBM traffic from the committed counter summary only
+    while the collide-stream sources hash to the value recorded with it; the
+    recorded bytes then lie within 20 % above the algorithmic 152 B per node
+    update (76 B in FP16)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    src = bench.kernel_source_hash()
+    rows = [l.split() for l in open(bench.TRAFFIC_FILE) if not l.startswith("#") and l.strip()]
+    sizes = {"dense_suspension_256x128x128_200caps": 256 * 128 * 128,
+             "c2_128cube_r16_l4_phi4": 128 ** 3,
+             "batched_sweep_64runs": sum(w.n_nodes_lattice for w in W.sweep_workloads())}
+    for name, storage, fetch, write, h in rows:
+        got = bench.measured_traffic(name, storage)
+        if h != src:
+            assert got is None
+            continue
+        assert got == float(fetch) + float(write)
+        algo = bench.bytes_per_node(storage) * sizes[name]
+        assert algo <= got < 1.2 * algo, (name, storage, got / algo)
+    assert bench.measured_traffic("no_such_workload", "fp32") is None
