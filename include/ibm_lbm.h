@@ -182,9 +182,13 @@ extern "C" {
                                   into the opposite slots, odd steps gather
                                   from the neighbours and push back (Bailey
                                   et al.'s access pattern): the same 152
-                                  bytes per node and step, half the
-                                  population memory, which the 256 MB
-                                  last-level cache then holds better.  AA
+                                  bytes per node and step in one
+                                  population array, so a lattice created
+                                  with IBM_STORAGE_ONE_BUFFER needs only
+                                  that one (it streams this way only).
+                                  Slower than two buffers on the lattices
+                                  measured: the odd step gathers from and
+                                  pushes to nine rows per row.  AA
                                   needs the row form (nx <= 256), nx a
                                   multiple of 4 and no tangent; the adjoint
                                   and batches need two buffers.  Changes
