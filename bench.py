@@ -66,7 +66,8 @@ def measured_traffic(workload: str, storage: str):
 
 
 def setup(workload: str, storage: str, graph: bool, variant: int = -1, box: int = -1,
-          overlap: int = -1, streaming: int = -1, one_buffer: bool = False):
+          overlap: int = -1, streaming: int = -1, one_buffer: bool = False,
+          fp16_mass: bool = False):
     from paper_1004_2416_amd import binding as B
     from paper_1004_2416_amd import workloads as W
 
@@ -84,6 +85,8 @@ def setup(workload: str, storage: str, graph: bool, variant: int = -1, box: int 
         lat.set_option(B.OPT_OVERLAP, int(overlap))
     if streaming >= 0:
         lat.set_option(B.OPT_STREAMING, int(streaming))
+    if fp16_mass:
+        lat.set_option(B.OPT_FP16_MASS, 1)
     return wl, lat
 
 
@@ -196,7 +199,8 @@ def single_leg(args, workload: str, storage: str, roofline: bool):
     """One lattice workload in the benchmark's launch configuration: warm-up
     and graph capture, then exactly args.steps timed steps."""
     wl, lat = setup(workload, storage, not args.no_graph, args.lbm_variant,
-                    args.stencil_box, args.overlap, args.streaming, args.one_buffer)
+                    args.stencil_box, args.overlap, args.streaming, args.one_buffer,
+                    args.fp16_mass)
     tuned = lat.autotune(64) if args.autotune else None
     split_box = lat.split_box()
     prime(lat, args.warmup)
@@ -298,6 +302,9 @@ def main():
     ap.add_argument("--streaming", type=int, default=-1,
                     help="population streaming pattern: 0 two buffers, 1 AA (one buffer); "
                          "-1 the library's default")
+    ap.add_argument("--fp16-mass", action="store_true",
+                    help="FP16 storage: the rest population takes back the mass the node's "
+                         "other values lose to rounding (IBM_OPT_FP16_MASS)")
     ap.add_argument("--one-buffer", action="store_true",
                     help="one population buffer (the AA pattern; nx a multiple of 4)")
     ap.add_argument("--sensitivity", action="store_true",
@@ -351,13 +358,14 @@ def main():
                   "u_w": wl.u_w, "tau": wl.tau, "lbm_variant": args.lbm_variant,
                   "stencil_box": args.stencil_box,
                   "overlap": args.overlap, "split_box": ex["split_box"],
+                  "fp16_mass_correction": bool(args.fp16_mass),
                   "streaming": ("aa_one_buffer" if args.one_buffer else
                                 "aa" if args.streaming == 1 else "two_buffers"),
                   "autotuned": ex["tuned"]}
         kernel = "k_collide_stream_rows"
         # the stored counters were taken on the two-buffer kernel
         aa = args.one_buffer or args.streaming == 1
-        traffic_key = None if aa else wl.name
+        traffic_key = None if aa or args.fp16_mass else wl.name
     algo = bytes_per_node(args.storage) * n_nodes
     achieved = algo / (ex["k1_ms"] * 1e-3) / 1e9
     out = {

@@ -200,6 +200,21 @@ extern "C" {
                                   swapped state.
                                   Results are those of two buffers (to FP32
                                   rounding)                                 */
+#define IBM_OPT_FP16_MASS 9    /* FP16 storage: 0 (default): every
+                                  post-collision value is rounded to FP16
+                                  on its own (one step changes a population
+                                  by at most 2^-11 of its deviation, and
+                                  the roundings move the total mass, by up
+                                  to 2^-11 sum_i |f_i - w_i| per node and
+                                  step); 1: the rest population, which
+                                  stays at its node, also takes back the
+                                  mass the node's 18 other stored values
+                                  lose to rounding, so the stored values
+                                  carry the FP32 mass up to the rounding of
+                                  the rest population (Sec. II.A, Eq.
+                                  lbmmomenta0: the collision conserves
+                                  mass).  Needs the row form (nx <= 256);
+                                  the other populations are unchanged     */
 #define IBM_STREAM_TWO_BUFFERS 0
 #define IBM_STREAM_AA 1
 

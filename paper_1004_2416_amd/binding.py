@@ -29,7 +29,7 @@ STORAGE = {"fp32": 0, "fp16": 1}
 STORAGE_ONE_BUFFER = 4
 FIELD_POPS, FIELD_RHO, FIELD_U, FIELD_FORCE = 0, 1, 2, 3
 OPT_GRAPH, OPT_EQUILIBRIUM, OPT_ADVECTION, OPT_RECENTER, OPT_LBM_VARIANT = 0, 1, 2, 3, 4
-OPT_STENCIL_BOX, OPT_OVERLAP, OPT_STREAMING = 6, 7, 8
+OPT_STENCIL_BOX, OPT_OVERLAP, OPT_STREAMING, OPT_FP16_MASS = 6, 7, 8, 9
 STREAM_TWO_BUFFERS, STREAM_AA = 0, 1
 PHASES = ("forces", "spread", "lbm", "interp")
 OBS_FIELDS = ("V", "cx", "cy", "cz", "D", "theta", "ra", "rb", "rc", "area",

@@ -771,6 +771,7 @@ int ibm_lattice_create(int nx, int ny, int nz, double tau, int storage, void *de
   L.guo_pre = (float)(1.0 - 0.5 / tau);
   L.uw = 0.0f;
   L.aa = lat->one_buffer ? 1 : 0;
+  L.mass_fix = 0;
   L.zlo = 0;
   L.zhi = nz;
   L.ylo = 0;
@@ -1251,6 +1252,13 @@ int ibm_set_option(ibm_lattice *lat, int option, int value) {
         int rc = refresh_slab(lat);
         if (rc) return rc;
       }
+      break;
+    case IBM_OPT_FP16_MASS:
+      if (value != 0 && value != 1) return fail(IBM_ERR_INVALID_ARG, "FP16 mass correction is 0 or 1");
+      if (value && (lat->storage != IBM_STORAGE_FP16 || lat->L.tpr <= 0))
+        return fail(IBM_ERR_BAD_STATE,
+                    "the FP16 mass correction needs FP16 storage and the row form (nx <= 256)");
+      lat->L.mass_fix = value;
       break;
     case IBM_OPT_STENCIL_BOX:
       if (value < 0 || value > 7) return fail(IBM_ERR_INVALID_ARG, "stencil box mode is 0..7");

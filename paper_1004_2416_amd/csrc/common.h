@@ -60,6 +60,9 @@ struct LatDev {
   int nxs;                // population row stride: nx rounded up to a multiple of 4
   int tpr, rpw;           // row form: lanes per row (nxs / 4) and rows per
                           // wavefront (64 / tpr), or 0 where it does not apply
+  int mass_fix;           // FP16 row form: the rest population takes back
+                          // the mass the node's other values lose to
+                          // rounding (fp16_mass_fix)
   int aa;                 // 1: the AA streaming pattern in buffer 0 (see
                           // collide_stream_rowseg_a); 0: two buffers
   int cached_rows;        // the row form writes the new populations of rows

@@ -211,6 +211,33 @@ __device__ __forceinline__ float wall_kick_scaled(int i, float uw) {
   return 96.0f * (float)(cx(i) * (cz(i) < 0 ? -1 : 1)) * uw;
 }
 
+// FP16 storage, in storage units D_i = (f_i - w_i) 16 / w_i: rounding the 18
+// moving post-collision values of a node to FP16 changes the mass the node
+// passes on by sum_i (w_i / 16) e_i, e_i = v_i - fp16(v_i) for the value v_i
+// that is stored (D_i, less the wall term where the value bounces back from a
+// wall: KICK).  The rest population stays at the node; adding
+// sum_i (w_i / w_0) e_i to D_0 makes the node's stored values carry its FP32
+// mass, up to the rounding of D_0 itself (IBM_OPT_FP16_MASS).  The rounding
+// is the stores' own: to nearest even.
+template <bool KICK>
+__device__ __forceinline__ void fp16_mass_fix(const LatDev &L, int z, float (&d)[4][Q]) {
+  float r[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int zt = z + cz(i);
+    const bool wall = KICK && cz(i) != 0 && (zt < 0 || zt >= L.nz);
+    const float kick = wall ? wall_kick_scaled(i, L.uw) : 0.0f;
+    const float wr = (float)(wgt(i) / wgt(0));
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const float v = d[k][i] - kick;
+      r[k] += wr * (v - (float)(_Float16)v);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < 4; ++k) d[k][0] += r[k];
+}
+
 // 32-bit form of prow / nx (the group-row index of an x row): row + (Q - 1) G
 // (row / G).  Valid while the padded row count times Q is below 2^32, which
 // the launchers of its users check.
@@ -458,6 +485,9 @@ __device__ __forceinline__ void collide_stream_rowseg_a(const LatDev &L, int src
 #pragma unroll
     for (int k = 0; k < 4; ++k)
       collide<LINEAR, FORCE, SC>(d[k], g[k][0], g[k][1], g[k][2], L.inv_tau, L.guo_pre);
+    if constexpr (SC) {
+      if (L.mass_fix) fp16_mass_fix<AA != 1>(L, z, d);
+    }
   } else {
 #pragma unroll
     for (int i = 0; i < Q; ++i)

@@ -227,8 +227,10 @@ static void launch_cs_t(const LatDev &L, int src, int par, bool force, bool line
   // blocks (256 otherwise)
   const RowSet rs{z0 * L.ny, (z1 - z0) * L.ny, 0, 0, 1, 0};
   const int wpb = (variant & 128) ? 1 : ((variant & 64) ? 2 : 4);
-  // the AA pattern exists in the row form only (it is allowed only there)
-  if ((variant & 16 || L.aa) && launch_cs_rows<T>(L, src, par, force, linear, rs, s, t, wpb)) return;
+  // the AA pattern and the FP16 mass correction exist in the row form only
+  // (they are allowed only there)
+  if ((variant & 16 || L.aa || L.mass_fix) && launch_cs_rows<T>(L, src, par, force, linear, rs, s, t, wpb))
+    return;
   const bool vec2 = (variant & 1) && (L.nx % 2 == 0);
   const bool nt = (variant & 2) != 0;
   const int threads = (variant & 4) ? 128 : 256;

@@ -235,3 +235,86 @@ def test_fp16_collide_stream_forms_agree(B):
     with pytest.raises(B.IBMError):
         lat.set_option(B.OPT_LBM_VARIANT, 512)
     lat.close()
+
+
+def test_fp16_mass_correction(B):
+    """IBM_OPT_FP16_MASS: the rest population takes back the mass the node's
+    18 moving values lose to FP16 rounding.  One lattice step (walls moving,
+    no capsule: deterministic) from an FP16-representable state: the moving
+    populations are stored exactly as without the correction; the rest
+    population is off the FP64 step by at most the node's rounding budget
+    2^-11 sum_i |f_i - w_i|; the total mass is the FP32 step's, up to the
+    rounding of the rest populations.  Then 2000 steps: the mass drifts by
+    less than steps * 2^-11 * sum_X |f_0 - w_0|, the worst case of that
+    rounding, while without the correction it drifts by more."""
+    c = Case(W.Workload("mass16", 32, 12, 16, 1.0, 0.03, 2, 0, []), perturb=0.01, seed=7)
+    f_s = rep16(c.f0)
+    one = O.lbm_step(f_s, None, c.wl.tau, c.wl.u_w)
+    w = WEIGHTS[:, None, None, None]
+    res, mass = {}, {}
+    for fix in (0, 1):
+        lat = c.gpu(storage="fp16", graph=False)
+        lat.set_option(B.OPT_FP16_MASS, fix)
+        lat.set_populations(f_s)
+        lat.step(1)
+        res[fix] = lat.populations().cpu().numpy()
+        lat.set_option(B.OPT_GRAPH, 1)
+        lat.step(2000)
+        mass[fix] = float(lat.totals()[0])
+        f_end = lat.populations().cpu().numpy()
+        lat.close()
+    assert np.array_equal(res[0][1:], res[1][1:])
+    budget = 2.0 ** -11 * np.sum(np.abs(one - w), axis=0)
+    assert np.all(np.abs(res[1][0] - one[0]) <= 1.05 * budget + 1e-9)
+    m0 = float(np.sum(f_s))
+    m_rest = 2.0 ** -11 * float(np.sum(np.abs(one[0] - w[0])))
+    e0, e1 = abs(res[0].sum() - one.sum()), abs(res[1].sum() - one.sum())
+    say("  fp16 mass, one step: error %.2e without, %.2e with the correction (rest rounding %.2e)"
+        % (e0, e1, m_rest))
+    assert e1 <= 1.05 * m_rest + 1e-9 * m0
+    drift0, drift1 = abs(mass[0] - m0) / m0, abs(mass[1] - m0) / m0
+    bound = 2000 * 2.0 ** -11 * float(np.sum(np.abs(f_end[0] - w[0]))) / m0
+    say("  fp16 mass, 2000 steps: drift %.2e without, %.2e with the correction (bound %.2e)"
+        % (drift0, drift1, bound))
+    assert drift1 < bound + 1e-9
+    assert drift1 < drift0
+
+
+def test_fp16_mass_correction_coupled_and_aa(B):
+    """The correction with a capsule (forces in the collision), on a two-buffer
+    lattice and on a one-buffer (AA) lattice: 100 steps against the oracle
+    within the FP16 bars, mass drift within the rest populations' rounding
+    budget."""
+    c = small_case(m=3, n=(32, 20, 16))
+    wl = c.wl
+    w = WEIGHTS[:, None, None, None]
+    for one_buffer in (False, True):
+        lat = B.Lattice(wl.nx, wl.ny, wl.nz, wl.tau, storage="fp16", one_buffer=one_buffer)
+        lat.set_shear(wl.u_w, init_profile=False)
+        lat.add_capsules(c.meshes(), c.ks, c.ka, wl.m)
+        lat.set_option(B.OPT_FP16_MASS, 1)
+        lat.set_populations(c.f0)
+        f0 = lat.populations().cpu().numpy()
+        sim = c.oracle(f=f0)
+        lat.step(1)
+        lat.step(99)
+        assert sim.run(100) == 0
+        f = lat.populations().cpu().numpy()
+        xg = lat.mesh()[0].cpu().numpy()
+        mass = float(lat.totals()[0])
+        lat.close()
+        m0 = float(np.sum(f0))
+        bound = 100 * 2.0 ** -11 * float(np.sum(np.abs(f[0] - w[0]))) / m0
+        ef, ex = dev_err(f, sim.f), float(np.max(np.abs(xg - sim.x)))
+        say("  fp16 mass correction, capsule, one buffer %s: f_dev %.2e  x %.2e  mass drift %.2e"
+            " (bound %.2e)" % (one_buffer, ef, ex, abs(mass - m0) / m0, bound))
+        assert ef < 100 * HALF_ULP and ex < 1e-3
+        assert abs(mass - m0) / m0 < bound + 1e-9
+    lat = Case(W.Workload("wide", 300, 4, 4, 1.0, 0.01, 2, 0, [])).gpu(storage="fp16", graph=False)
+    with pytest.raises(B.IBMError):
+        lat.set_option(B.OPT_FP16_MASS, 1)  # nx > 256: no row form
+    lat.close()
+    lat = c.gpu(storage="fp32", graph=False)
+    with pytest.raises(B.IBMError):
+        lat.set_option(B.OPT_FP16_MASS, 1)
+    lat.close()
