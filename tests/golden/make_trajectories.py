@@ -9,6 +9,9 @@ positions rounded to the library's FP32 frame).  Nothing reads the HIP path.
                       Taylor deformation D every 100 steps up to 20000
   trajectory_c3.txt   256 x 128 x 128 with 200 r = 8 capsules, 2-point delta:
                       D of every capsule every 100 steps up to 10000
+  trajectory_c4.txt   the 64 independent runs of the batched sweep (24^3..64^3,
+                      one capsule each, 2-, 3- and 4-point deltas): D of
+                      every run every 100 steps up to 5000
   sensitivities_c5_2000.txt
                       64^3, one r = 8 capsule, 3-point delta: central
                       differences (h = 1e-4 relative) of D after 2000 steps
@@ -20,7 +23,8 @@ D is (r_a - r_c)/(r_a + r_c) from the inertia tensor of the closed mesh
 (Sec. III).  The runs take hours of CPU; each file is written under a
 '.partial' name row by row and renamed when complete.
 
-usage: python tests/golden/make_trajectories.py {c2,c3,c5} [--threads N]
+usage: python tests/golden/make_trajectories.py {c2,c3,c4,c5} [--threads N]
+(c4: N worker processes, one oracle thread each)
 """
 from __future__ import annotations
 
@@ -83,6 +87,46 @@ def trajectory(name, threads, out_dir):
     _finish(fh, path)
 
 
+def _sweep_run(args):
+    """D of one run of the batched sweep every EVERY steps (one oracle thread)."""
+    k, wl, steps = args
+    c = Case(wl)
+    sim = c.oracle(nthreads=1)
+    out = [c.observables(sim.x)[0]["D"]]
+    for s in range(EVERY, steps + 1, EVERY):
+        if sim.run(EVERY) != 0:
+            raise RuntimeError("oracle run %d failed at step %d" % (k, s))
+        out.append(c.observables(sim.x)[0]["D"])
+    return k, out
+
+
+def sweep_trajectories(processes, out_dir, steps=5000):
+    from multiprocessing import Pool
+    wls = W.sweep_workloads(steps=steps)
+    path = os.path.join(out_dir, "trajectory_c4.txt")
+    t0 = time.time()
+    res = {}
+    # the largest runs first, so that the pool ends evenly
+    order = sorted(range(len(wls)), key=lambda k: -wls[k].n_nodes_lattice)
+    with Pool(processes) as pool:
+        for k, D in pool.imap_unordered(_sweep_run, [(k, wls[k], steps) for k in order]):
+            res[k] = D
+            print("c4 run %d done (%d of %d)  %.0f s" % (k, len(res), len(wls), time.time() - t0),
+                  flush=True)
+    fh = _open(path, [
+        "oracle Taylor deformation D (Sec. III) of each run every %d steps" % EVERY,
+        "workload batched_sweep_64runs: %d runs %s, %d steps" % (
+            len(wls), " ".join("%dx%dx%d/m%d" % (w.nx, w.ny, w.nz, w.m) for w in wls), steps),
+        "start: Couette equilibrium rounded to FP32 deviations, undeformed capsules in the"
+        " library's FP32 frame (tests/parity_helpers.Case)",
+        "written by: python tests/golden/make_trajectories.py c4",
+        "columns: step, D of run 0 .. %d" % (len(wls) - 1),
+    ])
+    for j, s in enumerate(range(0, steps + 1, EVERY)):
+        fh.write("%d " % s + " ".join("%.12e" % res[k][j] for k in range(len(wls))) + "\n")
+    _finish(fh, path)
+
+
 def sensitivities(threads, out_dir, steps=2000):
     wl = W.config("c5")
     c = Case(wl)
@@ -125,12 +169,14 @@ def sensitivities(threads, out_dir, steps=2000):
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("what", choices=["c2", "c3", "c5"])
+    ap.add_argument("what", choices=["c2", "c3", "c4", "c5"])
     ap.add_argument("--threads", type=int, default=0)
     ap.add_argument("--out", default=HERE)
     a = ap.parse_args()
     if a.what == "c5":
         sensitivities(a.threads, a.out)
+    elif a.what == "c4":
+        sweep_trajectories(max(1, a.threads), a.out)
     else:
         trajectory(a.what, a.threads, a.out)
 

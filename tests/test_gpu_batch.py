@@ -265,7 +265,7 @@ def test_full_size_batched_sweep(B):
     """The 64-run sweep at its full sizes (6.67 M lattice nodes, 78 k membrane
     nodes, delta widths 2-4) in the launch configuration the benchmark times:
     one batch with its default stencil-box mode (box spreading, interpolation
-    from the tile-velocity field), cached stores for the first quarter of each
+    from the velocity field), cached stores for the first quarter of each
     run's rows, 16-step graphs.  Every capsule is deformed by ~2 % and
     injected.  After one step every run's populations, forces, node
     velocities and positions meet the per-step bar against its own oracle.

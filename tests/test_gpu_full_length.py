@@ -6,6 +6,7 @@ the oracle):
 
   128^3, one r = 16 capsule, 4-point delta: 20,000 steps
   256 x 128 x 128, 200 r = 8 capsules, 2-point delta: 10,000 steps
+  the batched sweep, 64 runs of 24^3..64^3 in one batch: 5000 steps
 
 The Taylor deformation D (Sec. III) of every capsule, every 100 steps, must
 stay within 1e-3 of that capsule's largest D over the run (FP32 storage).
@@ -125,6 +126,38 @@ def test_full_length_trajectory_fp16_mass_corrected(B, name):
     say("  %s fp16 with the mass correction: mass drift %.2e, bound %.2e" % (
         name, abs(mass / N - 1), bound))
     assert abs(mass / N - 1) < bound
+
+
+@pytest.mark.parametrize("storage", ["fp32", "fp16"])
+def test_full_length_batched_sweep(B, storage):
+    """The 64 independent runs of the batched sweep (24^3..64^3, delta widths
+    2-4) for their full 5000 steps as one batch in the benchmark's launch
+    configuration (the batch's defaults, 16-step graphs), against the
+    oracle's trajectories: D of every run every 100 steps within 1e-3 of that
+    run's largest D (FP32 storage), within 2e-2 with FP16 storage."""
+    path = os.path.join(GOLDEN, "trajectory_c4.txt")
+    if not os.path.exists(path):
+        pytest.skip("oracle trajectory %s not written yet (make_trajectories.py)" % path)
+    rows = np.loadtxt(path, comments="#", ndmin=2)
+    steps, Do = rows[:, 0].astype(int), rows[:, 1:]
+    wls = W.sweep_workloads()
+    assert Do.shape[1] == len(wls) and steps[-1] == wls[0].steps
+    lats = [Case(wl).gpu(storage=storage, graph=True) for wl in wls]
+    batch = B.Batch(lats)
+    Dg = [[lat.observables()[0, 4] for lat in lats]]
+    for s0, s1 in zip(steps[:-1], steps[1:]):
+        batch.step(int(s1 - s0))
+        Dg.append([lat.observables()[0, 4] for lat in lats])
+    batch.close()
+    for lat in lats:
+        lat.close()
+    Dg = np.array(Dg)
+    eD = np.max(np.abs(Dg - Do), axis=0) / np.max(np.abs(Do), axis=0)
+    worst = int(np.argmax(eD))
+    say("  batched sweep %s %d steps: worst run %d (%s, m=%d), D error %.2e of its max D; "
+        "median run %.2e" % (storage, steps[-1], worst, wls[worst].name, wls[worst].m,
+                             eD[worst], float(np.median(eD))))
+    assert eD.max() < (1e-3 if storage == "fp32" else 2e-2)
 
 
 def test_full_length_adjoint_c5(B):
