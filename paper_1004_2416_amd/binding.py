@@ -24,6 +24,7 @@ ERRORS = {
     -4: "IBM_ERR_STENCIL_HITS_WALL",
     -5: "IBM_ERR_NONFINITE",
     -6: "IBM_ERR_INVERTED_FACE",
+    -7: "IBM_ERR_OUTSIDE_SLAB",
 }
 STORAGE = {"fp32": 0, "fp16": 1}
 STORAGE_ONE_BUFFER = 4

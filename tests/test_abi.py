@@ -149,3 +149,18 @@ def test_deformation_function_marshals_the_adjoint_gradient(B):
     want_s = 7.0 * float(torch.sum(4.0 * ks0 * 1.5 * ks0) + torch.sum(1.5 * ks0))
     assert float(s.grad) == pytest.approx(want_s, rel=1e-12)
     assert float(uw.grad) == pytest.approx(7.0 * 15.0 * 0.02 ** 2, rel=1e-12)
+
+
+def test_binding_constants_match_the_header(B):
+    """Every error code, option, field selector, storage code and streaming
+    pattern the header defines has the same value in the binding."""
+    text = open(HEADER).read()
+    defs = {k: int(v) for k, v in re.findall(r"#define (IBM_[A-Z0-9_]+) \(?(-?\d+)\)?", text)}
+    errors = {v: k for k, v in defs.items() if k.startswith("IBM_ERR_")}
+    assert errors == B.ERRORS
+    for k, v in defs.items():
+        for prefix in ("IBM_OPT_", "IBM_FIELD_", "IBM_STREAM_"):
+            if k.startswith(prefix):
+                assert getattr(B, k[4:]) == v, k
+    assert B.STORAGE == {"fp32": defs["IBM_STORAGE_FP32"], "fp16": defs["IBM_STORAGE_FP16"]}
+    assert B.STORAGE_ONE_BUFFER == defs["IBM_STORAGE_ONE_BUFFER"]
