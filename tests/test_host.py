@@ -144,3 +144,19 @@ def test_bench_traffic_lookup():
         algo = bench.bytes_per_node(storage) * sizes[name]
         assert algo <= got < 1.2 * algo, (name, storage, got / algo)
     assert bench.measured_traffic("no_such_workload", "fp32") is None
+
+
+def test_stored_sweep_trajectories_follow_the_sweep():
+    """The batched sweep's oracle reference lists the 64 runs' shapes and
+    delta widths in the sweep's order and holds D of every run every 100
+    steps from 0 to 5000."""
+    wls = W.sweep_workloads()
+    path = os.path.join(GOLDEN, "trajectory_c4.txt")
+    head = [l for l in open(path) if l.startswith("#")]
+    shapes = " ".join("%dx%dx%d/m%d" % (w.nx, w.ny, w.nz, w.m) for w in wls)
+    assert any(("64 runs %s, %d steps" % (shapes, wls[0].steps)) in l for l in head)
+    rows = np.loadtxt(path, comments="#", ndmin=2)
+    assert rows.shape == (wls[0].steps // 100 + 1, 1 + len(wls))
+    assert np.array_equal(rows[:, 0], np.arange(0, wls[0].steps + 1, 100))
+    assert np.max(np.abs(rows[0, 1:])) < 1e-6
+    assert np.all(rows[1:, 1:] > 0) and np.all(rows[1:, 1:] < 1)
