@@ -43,6 +43,22 @@ int ok() {
 constexpr size_t ALIGN = 256;
 size_t round_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// HIP events of a profiling or tuning call, destroyed when the call returns,
+// also on its early error returns.
+struct EventPool {
+  std::vector<hipEvent_t> v;
+  hipError_t make(hipEvent_t *e) {
+    v.push_back(nullptr);
+    hipError_t r = hipEventCreate(&v.back());
+    *e = v.back();
+    return r;
+  }
+  ~EventPool() {
+    for (hipEvent_t e : v)
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 // Steps replayed per graph launch (even, so that the buffer parity returns).
 constexpr int GRAPH_STEPS = 16;
 
@@ -1277,9 +1293,10 @@ int ibm_autotune(ibm_lattice *lat, int steps_per_trial, int *chosen) {
   if (steps_per_trial < GRAPH_STEPS || steps_per_trial > 65536)
     return fail(IBM_ERR_INVALID_ARG, "steps_per_trial must be in %d..65536", GRAPH_STEPS);
   const int n = (steps_per_trial + GRAPH_STEPS - 1) / GRAPH_STEPS * GRAPH_STEPS;
+  EventPool pool;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  IBM_HIP(hipEventCreate(&e0));
-  IBM_HIP(hipEventCreate(&e1));
+  IBM_HIP(pool.make(&e0));
+  IBM_HIP(pool.make(&e1));
   int rc = IBM_OK;
   // the better of two timings of n steps, after a settling graph replay
   auto trial = [&](float &ms) -> int {
@@ -1358,8 +1375,6 @@ int ibm_autotune(ibm_lattice *lat, int steps_per_trial, int *chosen) {
     lat->overlap = (!rc && split_update(lat) && ms_on < ms_off) ? 1 : 0;  // 1 can fall back
     invalidate_graph(lat);
   }
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (rc) return rc;
   if (chosen) {
     chosen[0] = lat->lbm_variant;
@@ -1375,12 +1390,13 @@ static int profile_steps(ibm_lattice *lat, int64_t n, double *ms_per_phase, doub
   if (lat->has_tan) return fail(IBM_ERR_BAD_STATE, "detach the tangent before profiling");
   if (n < 1 || n > 4096) return fail(IBM_ERR_INVALID_ARG, "profile 1..4096 steps");
   const int ne = lat->has_mem ? 5 : 2;
+  EventPool pool;
   std::vector<hipEvent_t> ev((size_t)n * ne);
   std::vector<ibm::DispatchTimer> kt(kernel_ms ? (size_t)n : 0);
-  for (auto &e : ev) IBM_HIP(hipEventCreate(&e));
+  for (auto &e : ev) IBM_HIP(pool.make(&e));
   for (auto &t : kt) {
-    IBM_HIP(hipEventCreate(&t.start));
-    IBM_HIP(hipEventCreate(&t.stop));
+    IBM_HIP(pool.make(&t.start));
+    IBM_HIP(pool.make(&t.stop));
   }
   hipStream_t s = lat->stream;
   for (int64_t k = 0; k < n; ++k) {
@@ -1431,11 +1447,6 @@ static int profile_steps(ibm_lattice *lat, int64_t n, double *ms_per_phase, doub
       IBM_HIP(hipEventElapsedTime(&ms, kt[(size_t)k].start, kt[(size_t)k].stop));
       kacc += ms;
     }
-  }
-  for (auto &e : ev) (void)hipEventDestroy(e);
-  for (auto &t : kt) {
-    (void)hipEventDestroy(t.start);
-    (void)hipEventDestroy(t.stop);
   }
   if (ms_per_phase)
     for (int p = 0; p < IBM_N_PHASES; ++p) ms_per_phase[p] = acc[p] / (double)n;
@@ -1928,9 +1939,10 @@ int ibm_batch_autotune(ibm_batch *b, int steps_per_trial, int *chosen) {
   if (steps_per_trial < GRAPH_STEPS || steps_per_trial > 65536)
     return fail(IBM_ERR_INVALID_ARG, "steps_per_trial must be in %d..65536", GRAPH_STEPS);
   const int n = (steps_per_trial + GRAPH_STEPS - 1) / GRAPH_STEPS * GRAPH_STEPS;
+  EventPool pool;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  IBM_HIP(hipEventCreate(&e0));
-  IBM_HIP(hipEventCreate(&e1));
+  IBM_HIP(pool.make(&e0));
+  IBM_HIP(pool.make(&e1));
   // the better of two timings of n steps, after the graphs of the candidate
   // are captured and replayed once
   auto trial = [&](float &ms) -> int {
@@ -2011,8 +2023,6 @@ int ibm_batch_autotune(ibm_batch *b, int steps_per_trial, int *chosen) {
     }
   }
   batch_invalidate_graph(b);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (rc) return rc;
   if (chosen) {
     chosen[0] = b->wpb;
@@ -2029,12 +2039,13 @@ static int batch_profile_steps(ibm_batch *b, int64_t n, double *ms_per_phase, do
   int rc = batch_sync_tables(b);
   if (rc) return rc;
   ibm_lattice *r0 = b->runs[0];
+  EventPool pool;
   std::vector<hipEvent_t> ev((size_t)n * 4);
   std::vector<ibm::DispatchTimer> kt(kernel_ms ? (size_t)n : 0);
-  for (auto &e : ev) IBM_HIP(hipEventCreate(&e));
+  for (auto &e : ev) IBM_HIP(pool.make(&e));
   for (auto &t : kt) {
-    IBM_HIP(hipEventCreate(&t.start));
-    IBM_HIP(hipEventCreate(&t.stop));
+    IBM_HIP(pool.make(&t.start));
+    IBM_HIP(pool.make(&t.stop));
   }
   hipStream_t s = b->stream;
   for (int64_t k = 0; k < n; ++k) {
@@ -2077,11 +2088,6 @@ static int batch_profile_steps(ibm_batch *b, int64_t n, double *ms_per_phase, do
       IBM_HIP(hipEventElapsedTime(&ms, kt[(size_t)k].start, kt[(size_t)k].stop));
       kacc += ms;
     }
-  }
-  for (auto &e : ev) (void)hipEventDestroy(e);
-  for (auto &t : kt) {
-    (void)hipEventDestroy(t.start);
-    (void)hipEventDestroy(t.stop);
   }
   if (ms_per_phase)
     for (int p = 0; p < IBM_N_PHASES; ++p) ms_per_phase[p] = acc[p] / (double)n;
