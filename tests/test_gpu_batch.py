@@ -172,7 +172,7 @@ def test_batch_matches_oracle_per_run(B):
 @pytest.mark.parametrize("box", [5, 4, 2])
 def test_batch_interpolation_modes(B, box):
     """The batch's coupling kernels with the first run's stencil-box mode:
-    interpolation from the runs' tile-velocity fields (4, 5, the default of
+    interpolation from the runs' velocity fields (4, 5, the default of
     large batches) or through LDS boxes (2), over 40 steps."""
     runs = [Run(B, spec) for spec in CASES]
     runs[0].lat.set_option(B.OPT_STENCIL_BOX, box)

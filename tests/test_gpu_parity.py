@@ -276,7 +276,7 @@ def test_trajectory_c1(B):
 def test_trajectory_drifting_capsule_wraps_and_recentres(B, nx, box):
     """An off-centre capsule carried 18 lattice spacings along x by the shear
     flow: crosses the periodic end and has its frame re-centred many times;
-    with the tile-velocity field (box 4, 5) also on a lattice whose x extent
+    with the velocity field (box 4, 5) also on a lattice whose x extent
     is not a multiple of the tile size (tiles straddling the periodic end)."""
     say("drifting capsule", nx, box)
     ny, nz, uw, r = 16, 24, 0.04, 3.0
@@ -321,7 +321,7 @@ def test_split_update_overlap(B, box):
     split into the slab of rows stencils can reach (after spreading) and the
     other rows (without force, inside the coupling launches).  192 steps with
     two re-centrings against the oracle, with the default interpolation and
-    with the tile-velocity field (box 5); then the option off goes back to
+    with the velocity field (box 5); then the option off goes back to
     the whole lattice."""
     nx, ny, nz, uw, r = 24, 40, 64, 0.02, 4.0
     ks = W.ks_from_capillary(0.05, uw, nz, r)
