@@ -282,7 +282,9 @@ int ibm_get_fields(ibm_lattice *lat, int what, double *dst_dev);
 
 /* Overwrite the populations (what = IBM_FIELD_POPS) from the device FP64
  * buffer src [19][nz][ny][nx] of unshifted post-streaming values; they are
- * rounded to the storage format.  Enqueued, does not wait. */
+ * rounded to the storage format.  With the AA pattern (IBM_OPT_STREAMING 1 or
+ * a one-buffer lattice) only after an even number of steps, else
+ * IBM_ERR_BAD_STATE.  Enqueued, does not wait. */
 int ibm_set_fields(ibm_lattice *lat, int what, const double *src_dev);
 
 /* Write node positions (unwrapped lattice coordinates), the nodal forces
