@@ -63,6 +63,21 @@ def test_paper_case_parameters():
     assert abs(gamma * ETA * cap.r / cap.ks - 0.01) < 1e-15
 
 
+@pytest.mark.parametrize("H,r,level", [(35, 3.5, 3), (70, 7.0, 4), (140, 14.0, 5)])
+def test_paper_series_follows_table2(orc, H, r, level):
+    """Table 2's three resolutions: the printed face counts N_f, H / r = 10, kappa t = 120 (steps = 120 G / gamma_dot)
+    and the mesh ratio 0.53 (mean edge length over the lattice spacing)."""
+    wl = W.paper_case(H, r, level, 3)
+    gamma = 2.0 * wl.u_w / wl.nz
+    assert (wl.nx, wl.ny, wl.nz) == (H, H, H) and wl.capsules[0].r == H / 10.0
+    assert wl.steps == int(round(120 * 0.01 / gamma))
+    x, t = orc.icosphere(level, r, (0.0, 0.0, 0.0))
+    assert len(t) == {35: 1280, 70: 5120, 140: 20480}[H]
+    e = np.concatenate([t[:, [0, 1]], t[:, [1, 2]], t[:, [2, 0]]])
+    L = np.linalg.norm(x[e[:, 0]] - x[e[:, 1]], axis=1).mean()
+    assert abs(L - 0.53) < 0.01
+
+
 def test_batched_sweep_sizes():
     """The 64-run sweep: 6.67 M lattice nodes and 78,048 membrane nodes in
     all, every capsule's stencil (half-width m/2 + 1) clear of the walls."""
