@@ -51,6 +51,13 @@ struct alignas(256) Ctrl {
   int pad[58];
 };
 
+// Index of component c of node n in the force density fields L.g: the three
+// components of a node are adjacent, so the spreading's atomic adds for a run
+// of nodes along x cover one contiguous span (atomics cost per span they touch
+// as well as per element), and the velocity pass finds a node's force in one
+// cache line.
+__host__ __device__ __forceinline__ long long gix(long long n, int c) { return 3 * n + c; }
+
 // Everything the lattice kernels need, passed by value.
 struct LatDev {
   int nx, ny, nz;
@@ -69,7 +76,8 @@ struct LatDev {
                           // z ny + y below this with ordinary (cached) stores,
                           // the others with non-temporal ones
   void *f[2];             // population buffers (float or __half), see pidx
-  float *g[2];            // force density [3][S] of even and odd steps
+  float *g[2];            // force density of even and odd steps, [S][3]:
+                          // the components of a node adjacent (gix)
   int *stamp[2];          // per-tile step stamps of the two fields
   int *nstamp;            // per node [S]: the last step whose stencils gave
                           // it a nonzero weight (the nodes interpolation reads)

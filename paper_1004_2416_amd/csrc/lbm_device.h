@@ -380,7 +380,6 @@ __device__ __forceinline__ void collide_stream_rowseg_a(const LatDev &L, int src
   // last segment
   const int nval = PAD ? min(4, L.nx - x0) : 4;
   const int e = PAD ? L.nx - 1 - 4 * last : 3;
-  const long long S = L.S;
   const long long n0 = ((long long)z * L.ny + y) * L.nx + x0;
   const unsigned row0 = (unsigned)(z * L.ny + y);
   const unsigned long long off0 = rowoff(L, row0, x0);
@@ -450,35 +449,44 @@ __device__ __forceinline__ void collide_stream_rowseg_a(const LatDev &L, int src
 #pragma unroll
     for (int k = 0; k < 4; ++k) g[k][0] = g[k][1] = g[k][2] = 0.0f;
     if (FORCE) {
-      // the force density is unpadded, [3][S] with x fastest: aligned vectors
-      // only when nx is a multiple of 4
+      // the force density is unpadded, three components per node (gix): the
+      // segment's 12 values are three aligned vectors when nx is a multiple
+      // of 4
       const int step = L.ctrl->step;
       const int tile = tile_of(L, x0, y, z);
       if (L.stamp[par][tile] == step) {
+        if (PAD) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if (PAD) {
+          for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-              if (k < nval) g[k][c] = L.g[par][c * S + n0 + k];
-          } else {
-            float v[4];
-            Pop4<float>::ld(L.g[par], c * S + n0, 1.0f, v);
+            for (int c = 0; c < 3; ++c)
+              if (k < nval) g[k][c] = L.g[par][gix(n0 + k, c)];
+        } else {
+          float v[12];
 #pragma unroll
-            for (int k = 0; k < 4; ++k) g[k][c] = v[k];
+          for (int h = 0; h < 3; ++h) {
+            float w4[4];
+            Pop4<float>::ld(L.g[par], gix(n0, 0) + 4 * h, 1.0f, w4);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) v[4 * h + k] = w4[k];
           }
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) g[k][c] = v[3 * k + c];
         }
       }
       if (L.stamp[par ^ 1][tile] == step - 1) {
+        if (PAD) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) {
-          if (PAD) {
+          for (int k = 0; k < 4; ++k)
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-              if (k < nval) L.g[par ^ 1][c * S + n0 + k] = 0.0f;
-          } else {
-            Pop4<float>::st(L.g[par ^ 1], c * S + n0, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f);
-          }
+            for (int c = 0; c < 3; ++c)
+              if (k < nval) L.g[par ^ 1][gix(n0 + k, c)] = 0.0f;
+        } else {
+#pragma unroll
+          for (int h = 0; h < 3; ++h)
+            Pop4<float>::st(L.g[par ^ 1], gix(n0, 0) + 4 * h, 0.0f, 0.0f, 0.0f, 0.0f, 1.0f);
         }
       }
     }

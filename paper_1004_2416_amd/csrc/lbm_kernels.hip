@@ -25,7 +25,6 @@ namespace ibm {
 template <typename T, bool LINEAR, bool FORCE, int VEC, bool NT>
 __device__ __forceinline__ void collide_stream_nodes(const LatDev &L, int src, int par, int x0,
                                                      int y, int z) {
-  const long long S = L.S;
   const long long nxl = L.nx;
   const long long plane = nxl * L.ny;
   const long long n0 = (long long)z * plane + (long long)y * nxl + x0;
@@ -52,20 +51,18 @@ __device__ __forceinline__ void collide_stream_nodes(const LatDev &L, int src, i
     if (L.stamp[par][tile] == t) {
       const float *gp = L.g[par];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if constexpr (VEC == 2) Pop<float>::template ld2<false>(gp, c * S + n0, 1.0f, g[0][c], g[1][c]);
-        else g[0][c] = gp[c * S + n0];
-      }
+      for (int v = 0; v < VEC; ++v)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) g[v][c] = gp[gix(n0 + v, c)];
     }
     // The other field was spread one step ago and has been interpolated
     // from; clear it where it was touched so the next spreading starts at 0.
     if (L.stamp[par ^ 1][tile] == t - 1) {
       float *go = L.g[par ^ 1];
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        if constexpr (VEC == 2) Pop<float>::template st2<false>(go, c * S + n0, 0.0f, 0.0f, 1.0f);
-        else go[c * S + n0] = 0.0f;
-      }
+      for (int v = 0; v < VEC; ++v)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) go[gix(n0 + v, c)] = 0.0f;
     }
   }
 #pragma unroll
@@ -335,9 +332,9 @@ __global__ __launch_bounds__(256) void k_get_field(LatDev L, int src, int gpar, 
   const long long n = ((long long)z * L.ny + y) * L.nx + x;
   double gx = 0.0, gy = 0.0, gz = 0.0;
   if (gpar >= 0 && L.stamp[gpar][tile_of(L, x, y, z)] == L.ctrl->step - 1) {
-    gx = L.g[gpar][n];
-    gy = L.g[gpar][L.S + n];
-    gz = L.g[gpar][2 * L.S + n];
+    gx = L.g[gpar][gix(n, 0)];
+    gy = L.g[gpar][gix(n, 1)];
+    gz = L.g[gpar][gix(n, 2)];
   }
   if (what == 3) {
     out[n] = gx;
@@ -419,9 +416,9 @@ __global__ __launch_bounds__(256) void k_tangent_collide_stream(LatDev L, TanDev
   const int step = L.ctrl->step;
   const int tile = tile_of(L, x, y, z);
   if (L.stamp[par][tile] == step) {
-    gx = L.g[par][n0];
-    gy = L.g[par][S + n0];
-    gz = L.g[par][2 * S + n0];
+    gx = L.g[par][gix(n0, 0)];
+    gy = L.g[par][gix(n0, 1)];
+    gz = L.g[par][gix(n0, 2)];
     hx = Tn.dg[par][n0];
     hy = Tn.dg[par][S + n0];
     hz = Tn.dg[par][2 * S + n0];
@@ -580,8 +577,8 @@ __global__ __launch_bounds__(256) void k_adj_velocity(LatDev L, AdjDev A, const 
   }
   const float inv_rho = 1.0f / (1.0f + drho);
   const float *g = L.g[par];
-  const float ux = (jx + 0.5f * g[n]) * inv_rho, uy = (jy + 0.5f * g[S + n]) * inv_rho,
-              uz = (jz + 0.5f * g[2 * S + n]) * inv_rho;
+  const float ux = (jx + 0.5f * g[gix(n, 0)]) * inv_rho, uy = (jy + 0.5f * g[gix(n, 1)]) * inv_rho,
+              uz = (jz + 0.5f * g[gix(n, 2)]) * inv_rho;
   const float au = ax * ux + ay * uy + az * uz;
   float *lf = A.lf[cur];
 #pragma unroll
@@ -651,7 +648,7 @@ __global__ __launch_bounds__(256) void k_adj_collide_stream(LatDev L, AdjDev A, 
   // the force density is zero outside the tiles spreading touched; its
   // adjoint is needed wherever the step's stencils reach
   const bool stamped = A.stamp[tile_of(L, x, y, z)] == step;
-  const float gx = L.g[par][n], gy = L.g[par][S + n], gz = L.g[par][2 * S + n];
+  const float gx = L.g[par][gix(n, 0)], gy = L.g[par][gix(n, 1)], gz = L.g[par][gix(n, 2)];
   const float rho = 1.0f + drho, inv_rho = 1.0f / rho;
   const float ux = (jx + 0.5f * gx) * inv_rho, uy = (jy + 0.5f * gy) * inv_rho,
               uz = (jz + 0.5f * gz) * inv_rho;

@@ -363,9 +363,9 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
       if (w[q] == 0.0f) continue;
       const int X = wrap_mod(gx[q], L.nx), Y = wrap_mod(gy[q], L.ny);
       const long long n = ((long long)gz[q] * L.ny + Y) * L.nx + X;
-      unsafeAtomicAdd(g + n, w[q] * fx);
-      unsafeAtomicAdd(g + L.S + n, w[q] * fy);
-      unsafeAtomicAdd(g + 2 * L.S + n, w[q] * fz);
+      unsafeAtomicAdd(g + gix(n, 0), w[q] * fx);
+      unsafeAtomicAdd(g + gix(n, 1), w[q] * fy);
+      unsafeAtomicAdd(g + gix(n, 2), w[q] * fz);
       L.stamp[par][tile_of(L, X, Y, gz[q])] = step;
       L.nstamp[n] = step;
     }
@@ -416,9 +416,9 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
     } else {
       const int X = wrap_mod(gx[q], L.nx), Y = wrap_mod(gy[q], L.ny);
       const long long n = ((long long)gz[q] * L.ny + Y) * L.nx + X;
-      unsafeAtomicAdd(g + n, w[q] * fx);
-      unsafeAtomicAdd(g + L.S + n, w[q] * fy);
-      unsafeAtomicAdd(g + 2 * L.S + n, w[q] * fz);
+      unsafeAtomicAdd(g + gix(n, 0), w[q] * fx);
+      unsafeAtomicAdd(g + gix(n, 1), w[q] * fy);
+      unsafeAtomicAdd(g + gix(n, 2), w[q] * fz);
       L.stamp[par][tile_of(L, X, Y, gz[q])] = step;
       L.nstamp[n] = step;
     }
@@ -426,17 +426,18 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   if (!fits) return;  // the whole block
   __syncthreads();
   // only in-range z received force (see above); every node a nonzero weight
-  // touched is marked for interpolation, whatever its force
-  for (int c = threadIdx.x; c < V; c += blockDim.x) {
+  // touched is marked for interpolation, whatever its force.  One component
+  // per thread, consecutive threads on consecutive addresses: the adds of a
+  // run of box nodes along x fall into one contiguous span of the field.
+  for (int k = threadIdx.x; k < 3 * V; k += blockDim.x) {
+    const int c = k / 3, comp = k - 3 * c;
     if (!sm.nflag[c]) continue;
-    const float vx = sm.box[0][c], vy = sm.box[1][c], vz = sm.box[2][c];
+    const float v = sm.box[comp][c];
     const int X = wrap_mod(x0 + c % ex, L.nx), Y = wrap_mod(y0 + (c / ex) % ey, L.ny);
     const int Z = z0 + c / (ex * ey);
     const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
-    L.nstamp[n] = step;
-    if (vx != 0.0f) unsafeAtomicAdd(g + n, vx);
-    if (vy != 0.0f) unsafeAtomicAdd(g + L.S + n, vy);
-    if (vz != 0.0f) unsafeAtomicAdd(g + 2 * L.S + n, vz);
+    if (comp == 0) L.nstamp[n] = step;
+    if (v != 0.0f) unsafeAtomicAdd(g + gix(n, comp), v);
   }
   // Every tile a nonzero weight touches, once per block.  Where nx or ny is
   // not a multiple of 4, the four wrapped positions of an unwrapped tile fall
@@ -534,8 +535,8 @@ __device__ __forceinline__ float3 lattice_velocity_of(const LatDev &L, const T *
     if (cz(i)) jz += cz(i) * d;
   }
   const float inv_rho = 1.0f / (1.0f + drho);
-  return make_float3((jx + 0.5f * g[n]) * inv_rho, (jy + 0.5f * g[L.S + n]) * inv_rho,
-                     (jz + 0.5f * g[2 * L.S + n]) * inv_rho);
+  return make_float3((jx + 0.5f * g[gix(n, 0)]) * inv_rho, (jy + 0.5f * g[gix(n, 1)]) * inv_rho,
+                     (jz + 0.5f * g[gix(n, 2)]) * inv_rho);
 }
 
 // Lattice velocity u(X, t+1) of Eq. (velocityinterpolation) at lattice node
@@ -554,8 +555,8 @@ __device__ __forceinline__ float3 lattice_velocity_swapped(const LatDev &L, cons
     if (cz(i)) jz += cz(i) * d;
   }
   const float inv_rho = 1.0f / (1.0f + drho);
-  return make_float3((jx + 0.5f * g[n]) * inv_rho, (jy + 0.5f * g[L.S + n]) * inv_rho,
-                     (jz + 0.5f * g[2 * L.S + n]) * inv_rho);
+  return make_float3((jx + 0.5f * g[gix(n, 0)]) * inv_rho, (jy + 0.5f * g[gix(n, 1)]) * inv_rho,
+                     (jz + 0.5f * g[gix(n, 2)]) * inv_rho);
 }
 
 // The lattice velocity u(X, t+1) of Eq. (velocityinterpolation) at every
@@ -928,9 +929,9 @@ __global__ __launch_bounds__(256) void k_tangent_interp(LatDev L, MemDev Mm, Tan
       }
       const float *g = L.g[par], *dg = Tn.dg[par];
       const float inv_rho = 1.0f / (1.0f + drho);
-      const float vx = (jx + 0.5f * g[n]) * inv_rho;
-      const float vy = (jy + 0.5f * g[L.S + n]) * inv_rho;
-      const float vz = (jz + 0.5f * g[2 * L.S + n]) * inv_rho;
+      const float vx = (jx + 0.5f * g[gix(n, 0)]) * inv_rho;
+      const float vy = (jy + 0.5f * g[gix(n, 1)]) * inv_rho;
+      const float vz = (jz + 0.5f * g[gix(n, 2)]) * inv_rho;
       const float tvx = (tjx + 0.5f * dg[n] - vx * trho) * inv_rho;
       const float tvy = (tjy + 0.5f * dg[L.S + n] - vy * trho) * inv_rho;
       const float tvz = (tjz + 0.5f * dg[2 * L.S + n] - vz * trho) * inv_rho;
