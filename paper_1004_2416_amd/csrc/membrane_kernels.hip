@@ -205,14 +205,18 @@ __device__ __forceinline__ float group_sum(float v) {
 // adds are distinct and coalesced.
 // Bounding box of the block's nonzero-weight stencil nodes (unwrapped lattice
 // coordinates): wave-level min / max with shuffles, then across the block's
-// waves in LDS.  All threads of the block must call it.
+// waves in LDS.  With AMAX, also the block's largest `amax` (the bits of a
+// non-negative float or NaN, which order as integers like the values, NaN
+// above infinity).  All threads of the block must call it.
 struct Box {
   int x0, y0, z0, ex, ey, ez, V;
   bool fits;
+  int amax;
 };
 
+template <bool AMAX = false>
 __device__ __forceinline__ Box block_box(int gx0, int gy0, int gz0, int gx1, int gy1, int gz1,
-                                         bool has, int capacity, int *bb) {
+                                         bool has, int capacity, int *bb, int amax = 0) {
   int v[6] = {has ? gx0 : 0x7fffffff, has ? gy0 : 0x7fffffff, has ? gz0 : 0x7fffffff,
               has ? gx1 : -0x7fffffff, has ? gy1 : -0x7fffffff, has ? gz1 : -0x7fffffff};
 #pragma unroll
@@ -222,8 +226,9 @@ __device__ __forceinline__ Box block_box(int gx0, int gy0, int gz0, int gx1, int
       v[k] = min(v[k], __shfl_xor(v[k], off, 64));
       v[k + 3] = max(v[k + 3], __shfl_xor(v[k + 3], off, 64));
     }
+    if (AMAX) amax = max(amax, __shfl_xor(amax, off, 64));
   }
-  if (threadIdx.x < 6) bb[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
+  if (threadIdx.x < (AMAX ? 7 : 6)) bb[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : (threadIdx.x < 6 ? -0x7fffffff : 0);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
@@ -231,9 +236,11 @@ __device__ __forceinline__ Box block_box(int gx0, int gy0, int gz0, int gx1, int
       atomicMin(&bb[k], v[k]);
       atomicMax(&bb[k + 3], v[k + 3]);
     }
+    if (AMAX) atomicMax(&bb[6], amax);
   }
   __syncthreads();
   Box b;
+  b.amax = AMAX ? bb[6] : 0;
   b.x0 = bb[0];
   b.y0 = bb[1];
   b.z0 = bb[2];
@@ -247,15 +254,26 @@ __device__ __forceinline__ Box block_box(int gx0, int gy0, int gz0, int gx1, int
 
 // Up to SPREAD_BOX lattice nodes per box; its tiles, counted in unwrapped
 // coordinates, number at most (ceil(ex/4) + 1)(ceil(ey/4) + 1)(ceil(ez/4) + 1)
-// <= 1028 for ex ey ez <= 1024.
-constexpr int SPREAD_BOX = 1024;
-constexpr int SPREAD_BOX_TILES = 1032;
+// <= 772 for ex ey ez <= 768.  The box sums are 64-bit fixed point (see
+// spread_lanes): LDS float atomics measured slow here (a block's three adds
+// per stencil node took as long as the rest of its LDS work together, plain
+// or integer adds a small part of that), integer ones are fast, and the fixed
+// point sum is exact whatever the order of the adds.  20.0 KB per block:
+// eight blocks of 256 threads per compute unit.
+constexpr int SPREAD_BOX = 768;
+constexpr int SPREAD_BOX_TILES = 776;
 struct SpreadLDS {
-  float box[3][SPREAD_BOX];
-  unsigned char nflag[SPREAD_BOX];  // box nodes some stencil weights nonzero
+  unsigned long long box[3][SPREAD_BOX];  // two's complement fixed point
+  unsigned char nflag[SPREAD_BOX];        // box nodes some stencil weights nonzero
   unsigned char tflag[SPREAD_BOX_TILES];
-  int bb[6];
+  int bb[7];
 };
+// Fixed point of the box sums: a block whose largest force component has
+// magnitude below 2^e counts in units of 2^(e - SPREAD_FIX_BITS).  Every
+// contribution w F (w <= 1) is then below 2^SPREAD_FIX_BITS units and the at
+// most 512 of a block sum to below 2^61; each is represented to 2^-52 of the
+// block's largest force, far below FP32's own rounding.
+constexpr int SPREAD_FIX_BITS = 52;
 
 // The capsule holding most of a block's nodes [first, first + count): a block
 // that straddles the end of one capsule holds two compact patches far apart,
@@ -291,6 +309,15 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   const int lane = threadIdx.x & (GS - 1);
   const int node = (blk * (int)blockDim.x + (int)threadIdx.x) / GS;
   const bool live = node < Mm.nn;  // whole groups alike
+  const int npb = (int)blockDim.x / GS;
+  // The loads the stencil and the LDS box need do not depend on the force:
+  // issued here, their dependent chains (node -> capsule -> origin, and the
+  // block's major capsule) overlap the force's instead of following it.
+  const int cap = live ? Mm.node_cap[node] : -1;
+  const float4 p = live ? Mm.x[node] : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  const int4 o = live ? Mm.origin[cap] : make_int4(0, 0, 0, 0);
+  const int major = (BOX && Mm.n_caps > 1) ? block_major_capsule(Mm, blk * npb, npb) : cap;
+  const int step = L.ctrl->step;
   // Eq. (forcefromenergy): F_n = -sum over the faces at n of d(A0 w_S)/dx_n,
   // one incident face per lane (each face is evaluated by each of its corners)
   float fx = 0.0f, fy = 0.0f, fz = 0.0f;
@@ -317,6 +344,9 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   fy = group_sum<GS>(fy);
   fz = group_sum<GS>(fz);
   if (live && lane == 0) Mm.F[node] = make_float4(fx, fy, fz, 0.0f);
+  // the bits of the largest |component| (NaN stays NaN: compared as integers)
+  const int fbits = max(max(__float_as_int(fabsf(fx)), __float_as_int(fabsf(fy))),
+                        __float_as_int(fabsf(fz)));
   // this lane's stencil nodes lane, lane + GS, ..., in unwrapped lattice
   // coordinates
   int gx[PPL], gy[PPL], gz[PPL];
@@ -326,10 +356,7 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
     gx[q] = gy[q] = gz[q] = 0;
     w[q] = 0.0f;
   }
-  const int cap = live ? Mm.node_cap[node] : -1;
   if (live) {
-    const float4 p = Mm.x[node];
-    const int4 o = Mm.origin[cap];
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
       const int sidx = lane + q * GS;
@@ -356,7 +383,6 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
     }
   }
   float *g = L.g[par];
-  const int step = L.ctrl->step;
   if constexpr (!BOX) {
 #pragma unroll
     for (int q = 0; q < PPL; ++q) {
@@ -373,8 +399,7 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   }
   // the lane's own extent over its nonzero-weight stencil nodes, if its
   // capsule is the block's major one
-  const int npb = (int)blockDim.x / GS;
-  const bool inbox = Mm.n_caps == 1 || cap == block_major_capsule(Mm, blk * npb, npb);
+  const bool inbox = Mm.n_caps == 1 || cap == major;
   bool has = false;
   int bx0 = 0, by0 = 0, bz0 = 0, bx1 = 0, by1 = 0, bz1 = 0;
 #pragma unroll
@@ -388,17 +413,22 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
     bz1 = has ? max(bz1, gz[q]) : gz[q];
     has = true;
   }
-  const Box b = block_box(bx0, by0, bz0, bx1, by1, bz1, has, SPREAD_BOX, sm.bb);
-  const bool fits = b.fits;
+  const Box b = block_box<true>(bx0, by0, bz0, bx1, by1, bz1, has, SPREAD_BOX, sm.bb, fbits);
+  // a block with a non-finite force goes through the per-lane path (which
+  // carries it into the field as the FP32 atomics would)
+  const bool fits = b.fits && b.amax <= 0x7f7fffff;
   const int x0 = b.x0, y0 = b.y0, z0 = b.z0, ex = b.ex, ey = b.ey;
-  const int V = b.V;
+  const int V = fits ? b.V : 0;
+  int fe;
+  (void)frexpf(__int_as_float(fits ? b.amax : 0), &fe);
+  const double to_fix = ldexp(1.0, SPREAD_FIX_BITS - fe), from_fix = ldexp(1.0, fe - SPREAD_FIX_BITS);
   // the box's tiles in unwrapped coordinates (>> 2 floors negative ones too)
   const int tx0 = x0 >> 2, ty0 = y0 >> 2, tz0 = z0 >> 2;
   const int ntx = fits ? ((x0 + ex - 1) >> 2) - tx0 + 1 : 0;
   const int nty = fits ? ((y0 + ey - 1) >> 2) - ty0 + 1 : 0;
   const int NT = fits ? ntx * nty * (((z0 + b.ez - 1) >> 2) - tz0 + 1) : 0;
   for (int c = threadIdx.x; c < V; c += blockDim.x) {
-    sm.box[0][c] = sm.box[1][c] = sm.box[2][c] = 0.0f;
+    sm.box[0][c] = sm.box[1][c] = sm.box[2][c] = 0ull;
     sm.nflag[c] = 0;
   }
   for (int q = threadIdx.x; q < NT; q += blockDim.x) sm.tflag[q] = 0;
@@ -408,9 +438,9 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
     if (w[q] == 0.0f) continue;
     if (fits && inbox) {
       const int c = ((gz[q] - z0) * ey + (gy[q] - y0)) * ex + (gx[q] - x0);
-      atomicAdd(&sm.box[0][c], w[q] * fx);
-      atomicAdd(&sm.box[1][c], w[q] * fy);
-      atomicAdd(&sm.box[2][c], w[q] * fz);
+      atomicAdd(&sm.box[0][c], (unsigned long long)__double2ll_rn((double)(w[q] * fx) * to_fix));
+      atomicAdd(&sm.box[1][c], (unsigned long long)__double2ll_rn((double)(w[q] * fy) * to_fix));
+      atomicAdd(&sm.box[2][c], (unsigned long long)__double2ll_rn((double)(w[q] * fz) * to_fix));
       sm.nflag[c] = 1;
       sm.tflag[(((gz[q] >> 2) - tz0) * nty + ((gy[q] >> 2) - ty0)) * ntx + ((gx[q] >> 2) - tx0)] = 1;
     } else {
@@ -432,7 +462,7 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   for (int k = threadIdx.x; k < 3 * V; k += blockDim.x) {
     const int c = k / 3, comp = k - 3 * c;
     if (!sm.nflag[c]) continue;
-    const float v = sm.box[comp][c];
+    const float v = (float)((double)(long long)sm.box[comp][c] * from_fix);
     const int X = wrap_mod(x0 + c % ex, L.nx), Y = wrap_mod(y0 + (c / ex) % ey, L.ny);
     const int Z = z0 + c / (ex * ey);
     const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
