@@ -190,6 +190,25 @@ __device__ __forceinline__ float group_sum(float v) {
   return v;
 }
 
+// Minimum and maximum over the 64 lanes of a wavefront (all active) with DPP
+// lane moves: within quads, half rows, rows, then rows 1 and 3 take row 0's and
+// row 2's last lane, and rows 2 and 3 lane 31; lane 63 ends with the result.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ int dpp_mov(int v) {
+  return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xf, false);
+}
+template <bool MAX>
+__device__ __forceinline__ int wave_extreme(int v) {
+  auto op = [](int a, int b) { return MAX ? max(a, b) : min(a, b); };
+  v = op(v, dpp_mov<0xb1>(v));        // quad_perm [1,0,3,2]
+  v = op(v, dpp_mov<0x4e>(v));        // quad_perm [2,3,0,1]
+  v = op(v, dpp_mov<0x141>(v));       // row_half_mirror
+  v = op(v, dpp_mov<0x140>(v));       // row_mirror
+  v = op(v, dpp_mov<0x142, 0xa>(v));  // row_bcast:15
+  v = op(v, dpp_mov<0x143, 0xc>(v));  // row_bcast:31
+  return __builtin_amdgcn_readlane(v, 63);
+}
+
 // ---- spreading, Eq. (forcespreading) -------------------------------------------
 // One lane group per membrane node: the group first forms the node's Skalak
 // force from its incident faces (Sec. II.B), then each lane adds
@@ -205,18 +224,15 @@ __device__ __forceinline__ float group_sum(float v) {
 // adds are distinct and coalesced.
 // Bounding box of the block's nonzero-weight stencil nodes (unwrapped lattice
 // coordinates): wave-level min / max with shuffles, then across the block's
-// waves in LDS.  With AMAX, also the block's largest `amax` (the bits of a
-// non-negative float or NaN, which order as integers like the values, NaN
-// above infinity).  All threads of the block must call it.
+// waves in LDS.  All threads of the block must call it.
 struct Box {
   int x0, y0, z0, ex, ey, ez, V;
   bool fits;
-  int amax;
+  int amax;  // block_box_slots only
 };
 
-template <bool AMAX = false>
 __device__ __forceinline__ Box block_box(int gx0, int gy0, int gz0, int gx1, int gy1, int gz1,
-                                         bool has, int capacity, int *bb, int amax = 0) {
+                                         bool has, int capacity, int *bb) {
   int v[6] = {has ? gx0 : 0x7fffffff, has ? gy0 : 0x7fffffff, has ? gz0 : 0x7fffffff,
               has ? gx1 : -0x7fffffff, has ? gy1 : -0x7fffffff, has ? gz1 : -0x7fffffff};
 #pragma unroll
@@ -226,9 +242,8 @@ __device__ __forceinline__ Box block_box(int gx0, int gy0, int gz0, int gx1, int
       v[k] = min(v[k], __shfl_xor(v[k], off, 64));
       v[k + 3] = max(v[k + 3], __shfl_xor(v[k + 3], off, 64));
     }
-    if (AMAX) amax = max(amax, __shfl_xor(amax, off, 64));
   }
-  if (threadIdx.x < (AMAX ? 7 : 6)) bb[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : (threadIdx.x < 6 ? -0x7fffffff : 0);
+  if (threadIdx.x < 6) bb[threadIdx.x] = threadIdx.x < 3 ? 0x7fffffff : -0x7fffffff;
   __syncthreads();
   if ((threadIdx.x & 63) == 0) {
 #pragma unroll
@@ -236,11 +251,10 @@ __device__ __forceinline__ Box block_box(int gx0, int gy0, int gz0, int gx1, int
       atomicMin(&bb[k], v[k]);
       atomicMax(&bb[k + 3], v[k + 3]);
     }
-    if (AMAX) atomicMax(&bb[6], amax);
   }
   __syncthreads();
   Box b;
-  b.amax = AMAX ? bb[6] : 0;
+  b.amax = 0;
   b.x0 = bb[0];
   b.y0 = bb[1];
   b.z0 = bb[2];
@@ -248,6 +262,60 @@ __device__ __forceinline__ Box block_box(int gx0, int gy0, int gz0, int gx1, int
   b.ey = bb[4] - bb[1] + 1;
   b.ez = bb[5] - bb[2] + 1;
   b.fits = bb[0] <= bb[3] && (long long)b.ex * b.ey * b.ez <= capacity;
+  b.V = b.fits ? b.ex * b.ey * b.ez : 0;
+  return b;
+}
+
+// The same box, and the block's largest `amax` (bits of a non-negative float
+// or NaN, which order as integers like the values, NaN above infinity),
+// with one barrier.  wave_box: each wavefront reduces with DPP and writes its
+// seven values to its own slots of `slots` ([4][8], at most four
+// wavefronts).  block_box_slots, after a barrier: every thread combines the
+// slots.  All threads of the block must call both.
+__device__ __forceinline__ void wave_box(int gx0, int gy0, int gz0, int gx1, int gy1, int gz1,
+                                         bool has, int amax, int *slots) {
+  const int v0 = wave_extreme<false>(has ? gx0 : 0x7fffffff);
+  const int v1 = wave_extreme<false>(has ? gy0 : 0x7fffffff);
+  const int v2 = wave_extreme<false>(has ? gz0 : 0x7fffffff);
+  const int v3 = wave_extreme<true>(has ? gx1 : -0x7fffffff);
+  const int v4 = wave_extreme<true>(has ? gy1 : -0x7fffffff);
+  const int v5 = wave_extreme<true>(has ? gz1 : -0x7fffffff);
+  const int v6 = wave_extreme<true>(amax);
+  if ((threadIdx.x & 63) == 0) {
+    int *o = slots + 8 * (threadIdx.x >> 6);
+    o[0] = v0;
+    o[1] = v1;
+    o[2] = v2;
+    o[3] = v3;
+    o[4] = v4;
+    o[5] = v5;
+    o[6] = v6;
+  }
+}
+
+__device__ __forceinline__ Box block_box_slots(const int *slots, int capacity) {
+  int e[7] = {slots[0], slots[1], slots[2], slots[3], slots[4], slots[5], slots[6]};
+  for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+    const int *o = slots + 8 * w;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      e[k] = min(e[k], o[k]);
+      e[k + 3] = max(e[k + 3], o[k + 3]);
+    }
+    e[6] = max(e[6], o[6]);
+  }
+  // the same in every lane: kept in scalar registers
+#pragma unroll
+  for (int k = 0; k < 7; ++k) e[k] = __builtin_amdgcn_readfirstlane(e[k]);
+  Box b;
+  b.amax = e[6];
+  b.x0 = e[0];
+  b.y0 = e[1];
+  b.z0 = e[2];
+  b.ex = e[3] - e[0] + 1;
+  b.ey = e[4] - e[1] + 1;
+  b.ez = e[5] - e[2] + 1;
+  b.fits = e[0] <= e[3] && (long long)b.ex * b.ey * b.ez <= capacity;
   b.V = b.fits ? b.ex * b.ey * b.ez : 0;
   return b;
 }
@@ -266,8 +334,9 @@ struct SpreadLDS {
   unsigned long long box[3][SPREAD_BOX];  // two's complement fixed point
   unsigned char nflag[SPREAD_BOX];        // box nodes some stencil weights nonzero
   unsigned char tflag[SPREAD_BOX_TILES];
-  int bb[7];
+  int slots[4][8];                        // wave_box
 };
+static_assert(SPREAD_BOX % 4 == 0 && SPREAD_BOX_TILES % 4 == 0, "flags are cleared in words");
 // Fixed point of the box sums: a block whose largest force component has
 // magnitude below 2^e counts in units of 2^(e - SPREAD_FIX_BITS).  Every
 // contribution w F (w <= 1) is then below 2^SPREAD_FIX_BITS units and the at
@@ -318,6 +387,14 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   const int4 o = live ? Mm.origin[cap] : make_int4(0, 0, 0, 0);
   const int major = (BOX && Mm.n_caps > 1) ? block_major_capsule(Mm, blk * npb, npb) : cap;
   const int step = L.ctrl->step;
+  if constexpr (BOX) {
+    // the whole LDS box is cleared before its extent is known
+    for (int c = threadIdx.x; c < 3 * SPREAD_BOX; c += blockDim.x) (&sm.box[0][0])[c] = 0ull;
+    for (int c = threadIdx.x; c < SPREAD_BOX / 4; c += blockDim.x)
+      reinterpret_cast<unsigned *>(sm.nflag)[c] = 0u;
+    for (int c = threadIdx.x; c < SPREAD_BOX_TILES / 4; c += blockDim.x)
+      reinterpret_cast<unsigned *>(sm.tflag)[c] = 0u;
+  }
   // Eq. (forcefromenergy): F_n = -sum over the faces at n of d(A0 w_S)/dx_n,
   // one incident face per lane (each face is evaluated by each of its corners)
   float fx = 0.0f, fy = 0.0f, fz = 0.0f;
@@ -413,7 +490,11 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
     bz1 = has ? max(bz1, gz[q]) : gz[q];
     has = true;
   }
-  const Box b = block_box<true>(bx0, by0, bz0, bx1, by1, bz1, has, SPREAD_BOX, sm.bb, fbits);
+  wave_box(bx0, by0, bz0, bx1, by1, bz1, has, fbits, &sm.slots[0][0]);
+  // one barrier orders the slots and the clearing of the box (at the start)
+  // before their use
+  __syncthreads();
+  const Box b = block_box_slots(&sm.slots[0][0], SPREAD_BOX);
   // a block with a non-finite force goes through the per-lane path (which
   // carries it into the field as the FP32 atomics would)
   const bool fits = b.fits && b.amax <= 0x7f7fffff;
@@ -427,12 +508,6 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   const int ntx = fits ? ((x0 + ex - 1) >> 2) - tx0 + 1 : 0;
   const int nty = fits ? ((y0 + ey - 1) >> 2) - ty0 + 1 : 0;
   const int NT = fits ? ntx * nty * (((z0 + b.ez - 1) >> 2) - tz0 + 1) : 0;
-  for (int c = threadIdx.x; c < V; c += blockDim.x) {
-    sm.box[0][c] = sm.box[1][c] = sm.box[2][c] = 0ull;
-    sm.nflag[c] = 0;
-  }
-  for (int q = threadIdx.x; q < NT; q += blockDim.x) sm.tflag[q] = 0;
-  __syncthreads();
 #pragma unroll
   for (int q = 0; q < PPL; ++q) {
     if (w[q] == 0.0f) continue;
