@@ -547,9 +547,14 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   // Every tile a nonzero weight touches, once per block.  Where nx or ny is
   // not a multiple of 4, the four wrapped positions of an unwrapped tile fall
   // into up to three tiles along that axis: stamp all of them.
+  const bool whole_tiles = (L.nx % TILE_X) == 0 && (L.ny % TILE_Y) == 0;
   for (int q = threadIdx.x; q < NT; q += blockDim.x) {
     if (!sm.tflag[q]) continue;
     const int ux = tx0 + q % ntx, uy = ty0 + (q / ntx) % nty, uz = tz0 + q / (ntx * nty);
+    if (whole_tiles) {  // an unwrapped tile is one tile of the lattice
+      L.stamp[par][(uz * L.tny + wrap_mod(uy, L.tny)) * L.tnx + wrap_mod(ux, L.tnx)] = step;
+      continue;
+    }
     int tx[3], ty[3], nxt = 0, nyt = 0;
 #pragma unroll
     for (int d = 0; d < 4; ++d) {
