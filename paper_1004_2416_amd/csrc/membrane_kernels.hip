@@ -534,12 +534,26 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   // touched is marked for interpolation, whatever its force.  One component
   // per thread, consecutive threads on consecutive addresses: the adds of a
   // run of box nodes along x fall into one contiguous span of the field.
+  // where the box spans at most one period along x and y, its wrapped start
+  // and one conditional subtraction give each node's wrapped position
+  const bool one_period = ex <= L.nx && ey <= L.ny;
+  const int wx0 = wrap_mod(x0, L.nx), wy0 = wrap_mod(y0, L.ny);
   for (int k = threadIdx.x; k < 3 * V; k += blockDim.x) {
     const int c = k / 3, comp = k - 3 * c;
     if (!sm.nflag[c]) continue;
     const float v = (float)((double)(long long)sm.box[comp][c] * from_fix);
-    const int X = wrap_mod(x0 + c % ex, L.nx), Y = wrap_mod(y0 + (c / ex) % ey, L.ny);
-    const int Z = z0 + c / (ex * ey);
+    const int row = c / ex, cx = c - row * ex, plane = row / ey, cy = row - plane * ey;
+    int X, Y;
+    if (one_period) {
+      X = wx0 + cx;
+      X -= X >= L.nx ? L.nx : 0;
+      Y = wy0 + cy;
+      Y -= Y >= L.ny ? L.ny : 0;
+    } else {
+      X = wrap_mod(x0 + cx, L.nx);
+      Y = wrap_mod(y0 + cy, L.ny);
+    }
+    const int Z = z0 + plane;
     const long long n = ((long long)Z * L.ny + Y) * L.nx + X;
     if (comp == 0) L.nstamp[n] = step;
     if (v != 0.0f) unsafeAtomicAdd(g + gix(n, comp), v);
