@@ -450,8 +450,8 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
         wq = 0.0f;
       }
       // a split lattice update assumes no force outside the rows zlo <= z < zhi,
-      // ylo <= y < yhi
-      if (wq != 0.0f) {
+      // ylo <= y < yhi (nothing to check where they are the whole lattice)
+      if (wq != 0.0f && (L.zlo > 0 || L.zhi < L.nz || L.ylo > 0 || L.yhi < L.ny)) {
         const int Y = wrap_mod(gy[q], L.ny);
         if (gz[q] < L.zlo || gz[q] >= L.zhi || Y < L.ylo || Y >= L.yhi)
           atomicOr(&L.ctrl->err, ERR_SLAB);
@@ -561,11 +561,24 @@ __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, 
   // Every tile a nonzero weight touches, once per block.  Where nx or ny is
   // not a multiple of 4, the four wrapped positions of an unwrapped tile fall
   // into up to three tiles along that axis: stamp all of them.
+  // an unwrapped tile is one tile of the lattice where nx and ny are
+  // multiples of the tile size; its wrapped position follows from the box's
+  // wrapped first tile where the box spans at most one period of tiles
   const bool whole_tiles = (L.nx % TILE_X) == 0 && (L.ny % TILE_Y) == 0;
+  const bool one_tile_period = whole_tiles && ntx <= L.tnx && nty <= L.tny;
+  const int wtx0 = wrap_mod(tx0, L.tnx), wty0 = wrap_mod(ty0, L.tny);
   for (int q = threadIdx.x; q < NT; q += blockDim.x) {
     if (!sm.tflag[q]) continue;
-    const int ux = tx0 + q % ntx, uy = ty0 + (q / ntx) % nty, uz = tz0 + q / (ntx * nty);
-    if (whole_tiles) {  // an unwrapped tile is one tile of the lattice
+    const int row = q / ntx, qx = q - row * ntx, qz = row / nty, qy = row - qz * nty;
+    const int ux = tx0 + qx, uy = ty0 + qy, uz = tz0 + qz;
+    if (one_tile_period) {
+      int tx = wtx0 + qx, ty = wty0 + qy;
+      tx -= tx >= L.tnx ? L.tnx : 0;
+      ty -= ty >= L.tny ? L.tny : 0;
+      L.stamp[par][(uz * L.tny + ty) * L.tnx + tx] = step;
+      continue;
+    }
+    if (whole_tiles) {
       L.stamp[par][(uz * L.tny + wrap_mod(uy, L.tny)) * L.tnx + wrap_mod(ux, L.tnx)] = step;
       continue;
     }
