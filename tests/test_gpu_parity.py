@@ -148,6 +148,20 @@ def test_coupled_step_parity_periodic_wrap(B):
     compare_one_step(B, c, f_s, x_s)
 
 
+@pytest.mark.parametrize("n,m", [((4, 4, 16), 2), ((6, 5, 16), 3), ((4, 6, 18), 4)])
+def test_coupled_step_parity_capsule_wider_than_the_lattice(B, n, m):
+    """A capsule of radius 3 on lattices 4 to 6 nodes wide in x and y: its
+    stencils wrap onto its own periodic images, and a spreading box spans
+    more than one period, so the box flush and the tile stamps take their
+    general wrapped-index paths (nx not a multiple of 4 included)."""
+    say("capsule wider than the lattice", n, "m", m)
+    nx, ny, nz = n
+    c = small_case(n=n, m=m, level=2, r=3.0, ca=0.02,
+                   center=((nx - 1) / 2 + 0.3, (ny - 1) / 2 - 0.2, (nz - 1) / 2 + 0.1))
+    f_s, x_s = deformed_state(c, 5)
+    compare_one_step(B, c, f_s, x_s)
+
+
 def test_coupled_step_parity_several_capsules(B):
     say("several capsules")
     nx, ny, nz, uw = 40, 24, 20, 0.02
