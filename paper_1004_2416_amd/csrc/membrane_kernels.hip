@@ -217,14 +217,16 @@ __device__ __forceinline__ int wave_extreme(int v) {
 // stamps X's tile with the step number.
 // The block's M^3 contributions of 256 / GS membrane nodes are first summed
 // in an LDS box spanning their stencils (when it has at most SPREAD_BOX
-// lattice nodes), then every touched box node is added to the global field
-// once per component, consecutive threads on consecutive x.  Overlapping
-// stencils of neighbouring nodes would otherwise send many atomics to the
-// same addresses at once, which serialises them; spread over the box, the
-// adds are distinct and coalesced.
-// Bounding box of the block's nonzero-weight stencil nodes (unwrapped lattice
-// coordinates): wave-level min / max with shuffles, then across the block's
-// waves in LDS.  All threads of the block must call it.
+// lattice nodes; in fixed point, see SpreadLDS), then every touched box node
+// is added to the global field once per component, consecutive threads on
+// consecutive addresses.  Overlapping stencils of neighbouring nodes would
+// otherwise send many atomics to the same addresses at once, which
+// serialises them; spread over the box, the adds are distinct and coalesced.
+// block_box: the bounding box of the block's nonzero-weight stencil nodes
+// (unwrapped lattice coordinates): wave-level min / max with shuffles, then
+// across the block's waves in LDS (the interpolation's box; spreading uses
+// wave_box and block_box_slots below).  All threads of the block must call
+// it.
 struct Box {
   int x0, y0, z0, ex, ey, ez, V;
   bool fits;
