@@ -169,6 +169,33 @@ def test_batch_matches_oracle_per_run(B):
         r.lat.close()
 
 
+def test_batch_oversized_and_wrapping_boxes(B):
+    """Runs whose spreading boxes exceed the LDS box (a 42-node capsule of
+    radius 14: the per-lane path) or span more than one period (a radius-3
+    capsule on a 4 x 4 lattice: the general wrapped indices), batched with
+    an ordinary run: 1 step, then 16 graph-replayed steps, each run against
+    its own oracle."""
+    specs = [dict(n=(40, 40, 40), m=3, level=1, r=14.0, uw=0.03),
+             dict(n=(4, 4, 16), m=2, level=2, r=3.0, uw=0.02),
+             CASES[0]]
+    runs = [Run(B, spec) for spec in specs]
+    batch = B.Batch([r.lat for r in runs])
+    say("oversized and wrapping boxes: 1 step")
+    batch.step(1)
+    for r in runs:
+        r.advance_oracle(1)
+    check(runs, 1e-6)
+    say("oversized and wrapping boxes: 16 more steps")
+    batch.step(16)
+    for r in runs:
+        r.advance_oracle(16)
+    check(runs, 2e-5, 1e-3)
+    batch.close()
+    for r in runs:
+        r.lat.synchronize()
+        r.lat.close()
+
+
 @pytest.mark.parametrize("box", [5, 4, 2])
 def test_batch_interpolation_modes(B, box):
     """The batch's coupling kernels with the first run's stencil-box mode:
