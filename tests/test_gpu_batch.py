@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 
 from paper_1004_2416_amd import workloads as W
-from parity_helpers import Case, O, deformed_mesh, rel_err, rep_positions, scaled_err
+from parity_helpers import Case, O, WEIGHTS, deformed_mesh, rel_err, rep_positions, scaled_err
 
 pytestmark = pytest.mark.gpu
 
@@ -266,6 +266,54 @@ def test_batch_and_single_runs_agree(B):
     batch.close()
     for r in runs:
         r.lat.close()
+
+
+def test_batch_fp16_mass_correction_per_run(B):
+    """FP16 runs in one batch keep their own IBM_OPT_FP16_MASS.  Capsule-free
+    runs (walls moving, no atomics): a run with the correction, its twin
+    without it, and a run of another shape without it.  After one batched
+    step each run lies within one FP16 unit of its largest deviation of the
+    same run stepped alone (the batch and single kernels round alike up to
+    the contraction of a few operations, and FP16 storage turns such
+    differences into at most a unit).  After 400 more batched steps the
+    corrected run's mass stays within the rounding budget of its rest
+    populations, 400 * 2^-11 sum_X |f_0 - w_0|, and drifts less than its
+    uncorrected twin's."""
+    specs = [dict(n=(32, 12, 16), m=2, level=1, r=3.0, uw=0.03, capsule=False)] * 2 + \
+        [dict(n=(24, 20, 14), m=2, level=1, r=3.0, uw=0.02, tau=0.8, capsule=False)]
+    fixes = (1, 0, 0)
+
+    def make(spec, fix):
+        lat = run_case(**spec).gpu(storage="fp16", graph=True)
+        lat.set_option(B.OPT_FP16_MASS, fix)
+        return lat
+
+    batched = [make(sp, fx) for sp, fx in zip(specs, fixes)]
+    alone = [make(sp, fx) for sp, fx in zip(specs, fixes)]
+    m0 = [float(lat.totals()[0]) for lat in batched]
+    batch = B.Batch(batched)
+    batch.step(1)
+    for lat in alone:
+        lat.step(1)
+    w = WEIGHTS[:, None, None, None]
+    for k, (a, b) in enumerate(zip(batched, alone)):
+        fa, fb = a.populations().cpu().numpy(), b.populations().cpu().numpy()
+        dev = float(np.max(np.abs(fb - w)))
+        diff = float(np.max(np.abs(fa - fb)))
+        say("   fp16 run %d (correction %d), one step: max |batch - alone| %.2e, max |f - w| %.2e"
+            % (k, fixes[k], diff, dev))
+        assert diff <= 2.0 ** -11 * dev
+    batch.step(400)
+    drift = [abs(float(lat.totals()[0]) - m) for lat, m in zip(batched, m0)]
+    f_end = batched[0].populations().cpu().numpy()
+    budget = 400 * 2.0 ** -11 * float(np.sum(np.abs(f_end[0] - w[0])))
+    say("   400 more steps: mass drift %.2e with the correction (budget %.2e), %.2e without"
+        % (drift[0], budget, drift[1]))
+    assert drift[0] <= budget + 1e-9 * m0[0]
+    assert drift[0] < drift[1]
+    batch.close()
+    for lat in batched + alone:
+        lat.close()
 
 
 def test_batch_rejects_inconsistent_runs(B):
