@@ -702,17 +702,21 @@ __device__ __forceinline__ float3 lattice_velocity_swapped(const LatDev &L, cons
 // node that this step's stencils touch with a nonzero weight (node stamp =
 // step), into L.U, from population buffer fsrc, or (SW) from state 2 of the
 // AA pattern in buffer 0.  Each wavefront scans 512 consecutive nodes (lattice
-// order, x fastest) for marks, lists the marked ones in LDS in that order,
-// and then evaluates the list with all its lanes, so that neighbouring
-// marked nodes share cache lines and few lanes idle.  Each node is evaluated
-// once, however many stencils overlap on it.  All threads of the block call
-// it; the block covers nodes [n0, n1), n1 - n0 <= NODE_VELOCITY_NODES.
+// order, x fastest) for marks and lists the marked ones in LDS in that order;
+// the block's four lists, taken one after the other, are then evaluated by
+// all 256 threads, so that neighbouring marked nodes share cache lines and
+// the wavefronts share the work however the marks fall in the block's range
+// (a block runs as few dependent rounds of loads as its count allows).  Each
+// node is evaluated once, however many stencils overlap on it.  All 256
+// threads of the block call it; the block covers nodes [n0, n1),
+// n1 - n0 <= NODE_VELOCITY_NODES.
 constexpr int NODE_VELOCITY_NODES = 2048;  // nodes per block: 512 per wavefront
 
 template <typename T, bool SW = false>
 __device__ __forceinline__ void node_velocity_range(const LatDev &L, int fsrc, int par,
                                                     long long n0, long long n1) {
   __shared__ int list[NODE_VELOCITY_NODES];
+  __shared__ int wcount[4];
   const int step = L.ctrl->step;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int *wl = list + wave * 512;
@@ -726,11 +730,17 @@ __device__ __forceinline__ void node_velocity_range(const LatDev &L, int fsrc, i
     if (marked) wl[cnt + __popcll(mask & ((1ull << lane) - 1))] = k * 64 + lane;
     cnt += __popcll(mask);
   }
+  if (lane == 0) wcount[wave] = cnt;
   __syncthreads();
+  // position j of the block's list: entry j - c[w] of wavefront w's list,
+  // where c[w] counts the entries of the wavefronts before w
+  const int c1 = wcount[0], c2 = c1 + wcount[1], c3 = c2 + wcount[2], total = c3 + wcount[3];
   const float *g = L.g[par];
   const T *f = static_cast<const T *>(L.f[SW ? 0 : fsrc]);
-  for (int j = lane; j < cnt; j += 64) {
-    const long long n = w0 + wl[j];
+  for (int j = (int)threadIdx.x; j < total; j += 256) {
+    const int w = (j >= c1) + (j >= c2) + (j >= c3);
+    const int before = w == 0 ? 0 : (w == 1 ? c1 : (w == 2 ? c2 : c3));
+    const long long n = n0 + (long long)w * 512 + list[w * 512 + (j - before)];
     const long long row = n / L.nx;
     const int X = (int)(n - row * L.nx), Y = (int)(row % L.ny), Z = (int)(row / L.ny);
     const float3 u = SW ? lattice_velocity_swapped<T>(L, f, g, X, Y, Z)
@@ -1337,8 +1347,10 @@ __global__ __launch_bounds__(256) void k_batch_interp(BatchDev B, int fsrc, int 
   else batch_interp_m<T, 4>(L, Mm, fsrc, par, advect, it.y, sm);
 }
 
-// The velocity pass of every run, on the lattice work items: the nb blocks
-// of a run take its nodes in equal ranges.
+// The velocity pass of every run, on the lattice work items: block k of a
+// run takes its nodes [k, k + 1) * NODE_VELOCITY_NODES.  A run has at least
+// that many items (a lattice-update block covers at most 1024 nodes), and
+// the ones past its last node return at once.
 template <typename T>
 __global__ __launch_bounds__(256) void k_batch_node_velocity(BatchDev B, int fsrc, int par) {
   if ((int)blockIdx.x >= B.n_lat_items) return;
@@ -1347,14 +1359,9 @@ __global__ __launch_bounds__(256) void k_batch_node_velocity(BatchDev B, int fsr
   // no capsule (nothing is marked), or a run interpolating otherwise
   if (!B.mem[it.x].nn || !(B.mem[it.x].cmode & 4)) return;
   const long long N = (long long)L.nx * L.ny * L.nz;
-  const long long nb = batch_lat_blocks(L, B.wpb);
-  long long per = (N + nb - 1) / nb;
-  if (per > NODE_VELOCITY_NODES) per = NODE_VELOCITY_NODES;  // not reached: a block of
-                                                             // the lattice update covers
-                                                             // at most 1024 nodes
-  const long long n0 = (long long)it.y * per;
+  const long long n0 = (long long)it.y * NODE_VELOCITY_NODES;
   if (n0 >= N) return;  // uniform across the block
-  node_velocity_range<T>(L, fsrc, par, n0, min(N, n0 + per));
+  node_velocity_range<T>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES));
 }
 
 void launch_batch_spread(const BatchDev &B, int par, hipStream_t s) {
@@ -1440,11 +1447,9 @@ __global__ __launch_bounds__(256) void k_batch_persistent(BatchDev B, int src, i
       const LatDev &L = B.lat[it.x];
       if (!B.mem[it.x].nn || !(B.mem[it.x].cmode & 4)) continue;  // uniform across the block
       const long long N = (long long)L.nx * L.ny * L.nz;
-      const long long nb = batch_lat_blocks(L, B.wpb);
-      const long long per = (N + nb - 1) / nb;
-      const long long n0 = (long long)it.y * per;
+      const long long n0 = (long long)it.y * NODE_VELOCITY_NODES;  // as k_batch_node_velocity
       if (n0 >= N) continue;
-      node_velocity_range<T>(L, src ^ 1, par, n0, min(N, n0 + per));
+      node_velocity_range<T>(L, src ^ 1, par, n0, min(N, n0 + NODE_VELOCITY_NODES));
       __syncthreads();  // the node list is reused by the next item
     }
     grid.sync();
