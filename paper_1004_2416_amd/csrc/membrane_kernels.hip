@@ -368,13 +368,20 @@ template <int M, bool HALF>
 __host__ __device__ constexpr int spread_group_size() {
   return M == 2 ? 8 : (HALF ? group_size<M>() / 2 : group_size<M>());
 }
+// QUARTER (the batched kernels): four stencil nodes per lane for the wider
+// deltas (27 or 64 of them on 8 or 16 lanes), so that the many small
+// membranes of a batch make fewer, fuller blocks.
+template <int M, bool HALF, bool QUARTER>
+__host__ __device__ constexpr int coupling_group_size() {
+  return (M != 2 && QUARTER) ? group_size<M>() / 4 : spread_group_size<M, HALF>();
+}
 // HALF where the full lane groups would make at least this many wavefronts
 constexpr long long SPREAD_HALF_WAVES = 1024;
 
-template <int M, bool BOX, bool HALF = true>
+template <int M, bool BOX, bool HALF = true, bool QUARTER = false>
 __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, int par, int blk,
                                              SpreadLDS &sm) {
-  constexpr int GS = spread_group_size<M, HALF>();
+  constexpr int GS = coupling_group_size<M, HALF, QUARTER>();
   constexpr int M3 = M * M * M;
   constexpr int PPL = (M3 + GS - 1) / GS;  // stencil nodes per lane
   const int lane = threadIdx.x & (GS - 1);
@@ -771,10 +778,10 @@ struct InterpLDS {
 // UF: read the lattice velocity from L.U (filled by the node-velocity pass
 // of this step) instead of evaluating it from the populations.
 // HALF: two stencil nodes per lane for the wider deltas, as in spreading.
-template <typename T, int M, bool BOX, bool UF, bool HALF = false>
+template <typename T, int M, bool BOX, bool UF, bool HALF = false, bool QUARTER = false>
 __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, int fsrc, int par,
                                              int advect, int blk, InterpLDS &sm) {
-  constexpr int GS = spread_group_size<M, HALF>();
+  constexpr int GS = coupling_group_size<M, HALF, QUARTER>();
   constexpr int M3 = M * M * M;
   constexpr int PPL = (M3 + GS - 1) / GS;  // stencil nodes per lane
   const int lane = threadIdx.x & (GS - 1);
@@ -1310,13 +1317,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   const MemDev &Mm = B.mem[it.x];
   const int m = Mm.m;
   if (Mm.cmode & 1) {
-    if (m == 2) spread_lanes<2, true>(L, Mm, par, it.y, sm);
-    else if (m == 3) spread_lanes<3, true>(L, Mm, par, it.y, sm);
-    else spread_lanes<4, true>(L, Mm, par, it.y, sm);
+    if (m == 2) spread_lanes<2, true, true, true>(L, Mm, par, it.y, sm);
+    else if (m == 3) spread_lanes<3, true, true, true>(L, Mm, par, it.y, sm);
+    else spread_lanes<4, true, true, true>(L, Mm, par, it.y, sm);
   } else {
-    if (m == 2) spread_lanes<2, false>(L, Mm, par, it.y, sm);
-    else if (m == 3) spread_lanes<3, false>(L, Mm, par, it.y, sm);
-    else spread_lanes<4, false>(L, Mm, par, it.y, sm);
+    if (m == 2) spread_lanes<2, false, true, true>(L, Mm, par, it.y, sm);
+    else if (m == 3) spread_lanes<3, false, true, true>(L, Mm, par, it.y, sm);
+    else spread_lanes<4, false, true, true>(L, Mm, par, it.y, sm);
   }
 }
 
@@ -1327,9 +1334,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 template <typename T, int M>
 __device__ __forceinline__ void batch_interp_m(const LatDev &L, const MemDev &Mm, int fsrc, int par,
                                                int advect, int blk, InterpLDS &sm) {
-  if (Mm.cmode & 4) interp_lanes<T, M, false, true, true>(L, Mm, fsrc, par, advect, blk, sm);
-  else if (Mm.cmode & 2) interp_lanes<T, M, true, false, true>(L, Mm, fsrc, par, advect, blk, sm);
-  else interp_lanes<T, M, false, false, true>(L, Mm, fsrc, par, advect, blk, sm);
+  if (Mm.cmode & 4) interp_lanes<T, M, false, true, true, true>(L, Mm, fsrc, par, advect, blk, sm);
+  else if (Mm.cmode & 2) interp_lanes<T, M, true, false, true, true>(L, Mm, fsrc, par, advect, blk, sm);
+  else interp_lanes<T, M, false, false, true, true>(L, Mm, fsrc, par, advect, blk, sm);
 }
 
 template <typename T>
@@ -1427,13 +1434,13 @@ __global__ __launch_bounds__(256) void k_batch_persistent(BatchDev B, int src, i
     const MemDev &Mm = B.mem[it.x];
     const int m = Mm.m;
     if (Mm.cmode & 1) {
-      if (m == 2) spread_lanes<2, true>(L, Mm, par, it.y, ss);
-      else if (m == 3) spread_lanes<3, true>(L, Mm, par, it.y, ss);
-      else spread_lanes<4, true>(L, Mm, par, it.y, ss);
+      if (m == 2) spread_lanes<2, true, true, true>(L, Mm, par, it.y, ss);
+      else if (m == 3) spread_lanes<3, true, true, true>(L, Mm, par, it.y, ss);
+      else spread_lanes<4, true, true, true>(L, Mm, par, it.y, ss);
     } else {
-      if (m == 2) spread_lanes<2, false>(L, Mm, par, it.y, ss);
-      else if (m == 3) spread_lanes<3, false>(L, Mm, par, it.y, ss);
-      else spread_lanes<4, false>(L, Mm, par, it.y, ss);
+      if (m == 2) spread_lanes<2, false, true, true>(L, Mm, par, it.y, ss);
+      else if (m == 3) spread_lanes<3, false, true, true>(L, Mm, par, it.y, ss);
+      else spread_lanes<4, false, true, true>(L, Mm, par, it.y, ss);
     }
     __syncthreads();  // the LDS box is reused by the next item
   }
