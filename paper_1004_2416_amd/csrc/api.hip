@@ -567,12 +567,8 @@ BatchLayout batch_layout(size_t n, size_t cap_lat, size_t cap_node) {
 
 long long ceil_div(long long a, long long b) { return (a + b - 1) / b; }
 
-// Lanes per membrane node in the batched coupling kernels: they give the
-// 3- and 4-point deltas four stencil nodes per lane (a quarter of the full
-// groups).
-int group_lanes(int m) {
-  return m == 2 ? ibm::group_size<2>() : (m == 3 ? ibm::group_size<3>() / 4 : ibm::group_size<4>() / 4);
-}
+// Lanes per membrane node in the batched coupling kernels.
+int group_lanes(int m) { return ibm::batch_group_size(m); }
 
 // Work items of the batched kernels for the runs' current state, with wpb
 // wavefronts per block of the lattice update (batch_lat_blocks).

@@ -368,20 +368,18 @@ template <int M, bool HALF>
 __host__ __device__ constexpr int spread_group_size() {
   return M == 2 ? 8 : (HALF ? group_size<M>() / 2 : group_size<M>());
 }
-// QUARTER (the batched kernels): four stencil nodes per lane for the wider
-// deltas (27 or 64 of them on 8 or 16 lanes), so that the many small
-// membranes of a batch make fewer, fuller blocks.
-template <int M, bool HALF, bool QUARTER>
+// BATCH: the batched kernels' lane groups (batch_group_size).
+template <int M, bool HALF, bool BATCH>
 __host__ __device__ constexpr int coupling_group_size() {
-  return (M != 2 && QUARTER) ? group_size<M>() / 4 : spread_group_size<M, HALF>();
+  return BATCH ? batch_group_size(M) : spread_group_size<M, HALF>();
 }
 // HALF where the full lane groups would make at least this many wavefronts
 constexpr long long SPREAD_HALF_WAVES = 1024;
 
-template <int M, bool BOX, bool HALF = true, bool QUARTER = false>
+template <int M, bool BOX, bool HALF = true, bool BATCH = false>
 __device__ __forceinline__ void spread_lanes(const LatDev &L, const MemDev &Mm, int par, int blk,
                                              SpreadLDS &sm) {
-  constexpr int GS = coupling_group_size<M, HALF, QUARTER>();
+  constexpr int GS = coupling_group_size<M, HALF, BATCH>();
   constexpr int M3 = M * M * M;
   constexpr int PPL = (M3 + GS - 1) / GS;  // stencil nodes per lane
   const int lane = threadIdx.x & (GS - 1);
@@ -778,10 +776,10 @@ struct InterpLDS {
 // UF: read the lattice velocity from L.U (filled by the node-velocity pass
 // of this step) instead of evaluating it from the populations.
 // HALF: two stencil nodes per lane for the wider deltas, as in spreading.
-template <typename T, int M, bool BOX, bool UF, bool HALF = false, bool QUARTER = false>
+template <typename T, int M, bool BOX, bool UF, bool HALF = false, bool BATCH = false>
 __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, int fsrc, int par,
                                              int advect, int blk, InterpLDS &sm) {
-  constexpr int GS = coupling_group_size<M, HALF, QUARTER>();
+  constexpr int GS = coupling_group_size<M, HALF, BATCH>();
   constexpr int M3 = M * M * M;
   constexpr int PPL = (M3 + GS - 1) / GS;  // stencil nodes per lane
   const int lane = threadIdx.x & (GS - 1);
