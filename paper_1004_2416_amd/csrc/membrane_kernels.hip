@@ -1338,7 +1338,7 @@ __device__ __forceinline__ void batch_interp_m(const LatDev &L, const MemDev &Mm
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void k_batch_interp(BatchDev B, int fsrc, int par, int advect) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k_batch_interp(BatchDev B, int fsrc, int par, int advect) {
   __shared__ InterpLDS sm;
   const int b = xcd_block(B.n_node_items);
   if (b < 0) return;
