@@ -297,12 +297,5 @@ template <int M>
 __host__ __device__ constexpr int group_size() {
   return M == 2 ? 8 : (M == 3 ? 32 : 64);
 }
-// Lanes per membrane node in the batched coupling kernels (spreading and
-// interpolation): the 3- and 4-point deltas take four stencil nodes per
-// lane, so that the many small membranes of a batch make fewer, fuller
-// blocks.
-__host__ __device__ constexpr int batch_group_size(int m) {
-  return m == 2 ? 8 : (m == 3 ? 8 : 16);
-}
 
 }  // namespace ibm

@@ -5,6 +5,14 @@
 
 namespace ibm {
 
+// Lanes per membrane node in the batched coupling kernels (spreading and
+// interpolation): the 3- and 4-point deltas take four stencil nodes per
+// lane, so that the many small membranes of a batch make fewer, fuller
+// blocks.  The kernels and the batches' work-item tables both use it.
+__host__ __device__ constexpr int batch_group_size(int m) {
+  return m == 2 ? 8 : (m == 3 ? 8 : 16);
+}
+
 // Events that take the start and end timestamps of one kernel's own dispatch
 // (hipExtLaunchKernel), so that their elapsed time is the kernel's execution
 // alone, without the launch gaps that marker events around it include.
