@@ -373,6 +373,13 @@ template <int M, bool HALF, bool BATCH>
 __host__ __device__ constexpr int coupling_group_size() {
   return BATCH ? batch_group_size(M) : spread_group_size<M, HALF>();
 }
+// Interpolation from the node-velocity field gathers 16 bytes per stencil
+// node: each lane takes two stencil nodes (4, 16 or 32 lanes per membrane
+// node), which halves the wavefronts of that short, latency-bound launch.
+template <int M>
+__host__ __device__ constexpr int field_group_size() {
+  return M == 2 ? 4 : group_size<M>() / 2;
+}
 // HALF where the full lane groups would make at least this many wavefronts
 constexpr long long SPREAD_HALF_WAVES = 1024;
 
@@ -776,10 +783,13 @@ struct InterpLDS {
 // UF: read the lattice velocity from L.U (filled by the node-velocity pass
 // of this step) instead of evaluating it from the populations.
 // HALF: two stencil nodes per lane for the wider deltas, as in spreading.
-template <typename T, int M, bool BOX, bool UF, bool HALF = false, bool BATCH = false>
+// FIELD: the lane groups of field_group_size (UF only)
+template <typename T, int M, bool BOX, bool UF, bool HALF = false, bool BATCH = false,
+          bool FIELD = false>
 __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, int fsrc, int par,
                                              int advect, int blk, InterpLDS &sm) {
-  constexpr int GS = coupling_group_size<M, HALF, BATCH>();
+  static_assert(!FIELD || UF, "field lane groups read the velocity field");
+  constexpr int GS = FIELD ? field_group_size<M>() : coupling_group_size<M, HALF, BATCH>();
   constexpr int M3 = M * M * M;
   constexpr int PPL = (M3 + GS - 1) / GS;  // stencil nodes per lane
   const int lane = threadIdx.x & (GS - 1);
@@ -915,7 +925,7 @@ __global__ __launch_bounds__(256) void k_interp_field(LatDev L, MemDev Mm, int f
   __shared__ InterpLDS sm;
   if (blockIdx.x == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
   const int blk = xcd_block(nblocks);
-  if (blk >= 0) interp_lanes<T, M, false, true>(L, Mm, fsrc, par, advect, blk, sm);
+  if (blk >= 0) interp_lanes<T, M, false, true, false, false, true>(L, Mm, fsrc, par, advect, blk, sm);
 }
 
 void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, int par,
@@ -959,13 +969,16 @@ void launch_interp_advect(const LatDev &L, const MemDev &M, int fp16, int fsrc, 
   const long long N = (long long)L.nx * L.ny * L.nz;
   const dim3 vgrid((unsigned)((N + NODE_VELOCITY_NODES - 1) / NODE_VELOCITY_NODES));
   const int fb = swapped ? 0 : fsrc;  // the stencil sums read the field only
+  const int fgs = M.m == 2 ? field_group_size<2>() : (M.m == 3 ? field_group_size<3>() : field_group_size<4>());
+  const int nbf = (int)(((long long)M.nn * fgs + 255) / 256);
+  const dim3 fgrid(xcd_grid(nbf));
 #define IBM_LAUNCH_INTERP_FIELD(T)                                                                  \
   do {                                                                                              \
     if (swapped) k_node_velocity<T, true><<<vgrid, block, 0, s>>>(L, 0, par);                       \
     else k_node_velocity<T, false><<<vgrid, block, 0, s>>>(L, fsrc, par);                           \
-    if (M.m == 2) k_interp_field<T, 2><<<grid, block, 0, s>>>(L, M, fb, par, advect, nblocks);         \
-    else if (M.m == 3) k_interp_field<T, 3><<<grid, block, 0, s>>>(L, M, fb, par, advect, nblocks);    \
-    else k_interp_field<T, 4><<<grid, block, 0, s>>>(L, M, fb, par, advect, nblocks);                \
+    if (M.m == 2) k_interp_field<T, 2><<<fgrid, block, 0, s>>>(L, M, fb, par, advect, nbf);         \
+    else if (M.m == 3) k_interp_field<T, 3><<<fgrid, block, 0, s>>>(L, M, fb, par, advect, nbf);    \
+    else k_interp_field<T, 4><<<fgrid, block, 0, s>>>(L, M, fb, par, advect, nbf);                \
   } while (0)
   if (fp16) IBM_LAUNCH_INTERP_FIELD(__half);
   else IBM_LAUNCH_INTERP_FIELD(float);
