@@ -723,12 +723,15 @@ __device__ __forceinline__ float3 lattice_velocity_swapped(const LatDev &L, cons
 // threads of the block call it; the block covers nodes [n0, n1),
 // n1 - n0 <= NODE_VELOCITY_NODES.
 constexpr int NODE_VELOCITY_NODES = 2048;  // nodes per block: 512 per wavefront
+struct VelocityLDS {
+  int list[NODE_VELOCITY_NODES];  // the wavefronts' lists, 512 entries each
+  int wcount[4];                  // their lengths
+};
 
 template <typename T, bool SW = false>
 __device__ __forceinline__ void node_velocity_range(const LatDev &L, int fsrc, int par,
-                                                    long long n0, long long n1) {
-  __shared__ int list[NODE_VELOCITY_NODES];
-  __shared__ int wcount[4];
+                                                    long long n0, long long n1, VelocityLDS &sm) {
+  int *list = sm.list, *wcount = sm.wcount;
   const int step = L.ctrl->step;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int *wl = list + wave * 512;
@@ -763,9 +766,10 @@ __device__ __forceinline__ void node_velocity_range(const LatDev &L, int fsrc, i
 
 template <typename T, bool SW>
 __global__ __launch_bounds__(256) void k_node_velocity(LatDev L, int fsrc, int par) {
+  __shared__ VelocityLDS sm;
   const long long N = (long long)L.nx * L.ny * L.nz;
   const long long n0 = (long long)blockIdx.x * NODE_VELOCITY_NODES;
-  node_velocity_range<T, SW>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES));
+  node_velocity_range<T, SW>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES), sm);
 }
 
 // The lattice velocity is evaluated once per lattice node of the block's
@@ -1371,6 +1375,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
 // the ones past its last node return at once.
 template <typename T>
 __global__ __launch_bounds__(256) void k_batch_node_velocity(BatchDev B, int fsrc, int par) {
+  __shared__ VelocityLDS sm;
   if ((int)blockIdx.x >= B.n_lat_items) return;
   const int2 it = B.lat_items[blockIdx.x];
   const LatDev &L = B.lat[it.x];
@@ -1379,7 +1384,7 @@ __global__ __launch_bounds__(256) void k_batch_node_velocity(BatchDev B, int fsr
   const long long N = (long long)L.nx * L.ny * L.nz;
   const long long n0 = (long long)it.y * NODE_VELOCITY_NODES;
   if (n0 >= N) return;  // uniform across the block
-  node_velocity_range<T>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES));
+  node_velocity_range<T>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES), sm);
 }
 
 void launch_batch_spread(const BatchDev &B, int par, hipStream_t s) {
@@ -1436,8 +1441,12 @@ __device__ __forceinline__ void batch_cs_item(const BatchDev &B, int2 it, int sr
 
 template <typename T, bool LINEAR>
 __global__ __launch_bounds__(256) void k_batch_persistent(BatchDev B, int src, int par, int advect) {
-  __shared__ SpreadLDS ss;
-  __shared__ InterpLDS si;
+  // the phases, separated by grid barriers, share one LDS allocation
+  __shared__ union {
+    SpreadLDS s;
+    InterpLDS i;
+    VelocityLDS v;
+  } sm;
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   for (int b = blockIdx.x; b < B.n_node_items; b += gridDim.x) {
     const int2 it = B.node_items[b];
@@ -1445,13 +1454,13 @@ __global__ __launch_bounds__(256) void k_batch_persistent(BatchDev B, int src, i
     const MemDev &Mm = B.mem[it.x];
     const int m = Mm.m;
     if (Mm.cmode & 1) {
-      if (m == 2) spread_lanes<2, true, true, true>(L, Mm, par, it.y, ss);
-      else if (m == 3) spread_lanes<3, true, true, true>(L, Mm, par, it.y, ss);
-      else spread_lanes<4, true, true, true>(L, Mm, par, it.y, ss);
+      if (m == 2) spread_lanes<2, true, true, true>(L, Mm, par, it.y, sm.s);
+      else if (m == 3) spread_lanes<3, true, true, true>(L, Mm, par, it.y, sm.s);
+      else spread_lanes<4, true, true, true>(L, Mm, par, it.y, sm.s);
     } else {
-      if (m == 2) spread_lanes<2, false, true, true>(L, Mm, par, it.y, ss);
-      else if (m == 3) spread_lanes<3, false, true, true>(L, Mm, par, it.y, ss);
-      else spread_lanes<4, false, true, true>(L, Mm, par, it.y, ss);
+      if (m == 2) spread_lanes<2, false, true, true>(L, Mm, par, it.y, sm.s);
+      else if (m == 3) spread_lanes<3, false, true, true>(L, Mm, par, it.y, sm.s);
+      else spread_lanes<4, false, true, true>(L, Mm, par, it.y, sm.s);
     }
     __syncthreads();  // the LDS box is reused by the next item
   }
@@ -1467,7 +1476,7 @@ __global__ __launch_bounds__(256) void k_batch_persistent(BatchDev B, int src, i
       const long long N = (long long)L.nx * L.ny * L.nz;
       const long long n0 = (long long)it.y * NODE_VELOCITY_NODES;  // as k_batch_node_velocity
       if (n0 >= N) continue;
-      node_velocity_range<T>(L, src ^ 1, par, n0, min(N, n0 + NODE_VELOCITY_NODES));
+      node_velocity_range<T>(L, src ^ 1, par, n0, min(N, n0 + NODE_VELOCITY_NODES), sm.v);
       __syncthreads();  // the node list is reused by the next item
     }
     grid.sync();
@@ -1478,9 +1487,9 @@ __global__ __launch_bounds__(256) void k_batch_persistent(BatchDev B, int src, i
     const MemDev &Mm = B.mem[it.x];
     if (it.y == 0 && threadIdx.x == 0) L.ctrl->step = L.ctrl->step + 1;
     const int m = Mm.m;
-    if (m == 2) batch_interp_m<T, 2>(L, Mm, src ^ 1, par, advect, it.y, si);
-    else if (m == 3) batch_interp_m<T, 3>(L, Mm, src ^ 1, par, advect, it.y, si);
-    else batch_interp_m<T, 4>(L, Mm, src ^ 1, par, advect, it.y, si);
+    if (m == 2) batch_interp_m<T, 2>(L, Mm, src ^ 1, par, advect, it.y, sm.i);
+    else if (m == 3) batch_interp_m<T, 3>(L, Mm, src ^ 1, par, advect, it.y, sm.i);
+    else batch_interp_m<T, 4>(L, Mm, src ^ 1, par, advect, it.y, sm.i);
     __syncthreads();
   }
 }
