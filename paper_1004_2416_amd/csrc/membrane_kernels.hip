@@ -787,7 +787,8 @@ struct InterpLDS {
 // UF: read the lattice velocity from L.U (filled by the node-velocity pass
 // of this step) instead of evaluating it from the populations.
 // HALF: two stencil nodes per lane for the wider deltas, as in spreading.
-// FIELD: the lane groups of field_group_size (UF only)
+// BATCH: the batched kernels' lane groups (batch_group_size), as in spreading.
+// FIELD: the lane groups of field_group_size (UF only).
 template <typename T, int M, bool BOX, bool UF, bool HALF = false, bool BATCH = false,
           bool FIELD = false>
 __device__ __forceinline__ void interp_lanes(const LatDev &L, const MemDev &Mm, int fsrc, int par,
