@@ -55,7 +55,9 @@ extern "C" {
 #define IBM_ERR_OUTSIDE_SLAB (-7)       /* IBM_OPT_OVERLAP: a stencil reached the
                                            part of the lattice updated without
                                            force; the steps since the last
-                                           check are not valid                  */
+                                           check are not valid (the slab is
+                                           measured again before the next
+                                           step)                                */
 
 /* ---- population storage ------------------------------------------------- */
 /* Populations are stored as deviations f_i - w_i from the lattice weights in

@@ -388,6 +388,9 @@ int check_device(ibm_lattice *lat) {
   if (err) {
     int zero = 0;
     IBM_HIP(hipMemcpy(&lat->L.ctrl->err, &zero, sizeof(int), hipMemcpyHostToDevice));
+    // after a stencil outside the split update's slab, the slab is measured
+    // again from the nodes' current extent before the next step
+    if (err & ibm::ERR_SLAB) lat->slab_stale = true;
     if (err & ibm::ERR_WALL)
       return fail(IBM_ERR_STENCIL_HITS_WALL, "a delta stencil reached beyond a wall");
     if (err & ibm::ERR_FACE)
