@@ -169,6 +169,30 @@ def test_batch_matches_oracle_per_run(B):
         r.lat.close()
 
 
+def test_batch_with_long_rows(B):
+    """Runs whose rows are longer than 256 nodes take the per-node lattice
+    update inside the batch while the others take the row form, and every
+    run's coupling and velocity-pass work items still cover all of its
+    nodes: three runs against their oracles after 1 and 24 steps (graphs)."""
+    specs = [dict(n=(260, 10, 12), m=3, level=1, r=3.0, uw=0.02),
+             dict(n=(257, 12, 11), m=4, level=1, r=2.5, uw=0.015, tau=0.9),
+             dict(n=(27, 22, 24), m=4, level=3, r=5.0, uw=0.015, tau=1.3)]
+    runs = [Run(B, spec) for spec in specs]
+    batch = B.Batch([r.lat for r in runs])
+    batch.step(1)
+    for r in runs:
+        r.advance_oracle(1)
+    check(runs, 1e-6)
+    batch.step(24)
+    for r in runs:
+        r.advance_oracle(24)
+    assert all(r.lat.steps == 25 for r in runs)
+    check(runs, 2e-5, 1e-3)
+    batch.close()
+    for r in runs:
+        r.lat.close()
+
+
 def test_batch_oversized_and_wrapping_boxes(B):
     """Runs whose spreading boxes exceed the LDS box (a 42-node capsule of
     radius 14: the per-lane path) or span more than one period (a radius-3
