@@ -713,7 +713,7 @@ __device__ __forceinline__ float3 lattice_velocity_swapped(const LatDev &L, cons
 // The lattice velocity u(X, t+1) of Eq. (velocityinterpolation) at every
 // node that this step's stencils touch with a nonzero weight (node stamp =
 // step), into L.U, from population buffer fsrc, or (SW) from state 2 of the
-// AA pattern in buffer 0.  Each wavefront scans 512 consecutive nodes (lattice
+// AA pattern in buffer 0.  Each wavefront scans WN consecutive nodes (lattice
 // order, x fastest) for marks and lists the marked ones in LDS in that order;
 // the block's four lists, taken one after the other, are then evaluated by
 // all 256 threads, so that neighbouring marked nodes share cache lines and
@@ -721,24 +721,37 @@ __device__ __forceinline__ float3 lattice_velocity_swapped(const LatDev &L, cons
 // (a block runs as few dependent rounds of loads as its count allows).  Each
 // node is evaluated once, however many stencils overlap on it.  All 256
 // threads of the block call it; the block covers nodes [n0, n1),
-// n1 - n0 <= NODE_VELOCITY_NODES.
-constexpr int NODE_VELOCITY_NODES = 2048;  // nodes per block: 512 per wavefront
+// n1 - n0 <= 4 WN.
+// Single lattices: 256 nodes per block.  Many small blocks keep blocks in
+// every phase (scan, gather) at once, so the memory system stays busy while
+// others scan (measured on the dense suspension: 2048, 1024, 512 and 256 nodes
+// per block, each faster than the one before).
+constexpr int NODE_VELOCITY_WN = 64;
+constexpr int NODE_VELOCITY_NODES = 4 * NODE_VELOCITY_WN;  // nodes per block
+// Batched runs: a lattice-update work item covers at most 1024 nodes, so a
+// run has at least N / 1024 items, and item k takes the run's nodes
+// [1024 k, 1024 (k + 1)) in the velocity pass (the items past the run's
+// last node return at once).  (Splitting an item over four blocks made the
+// many idle blocks of the batch cost more than the smaller ranges gave.)
+constexpr int BATCH_ITEM_NODES = 1024;
+template <int WN>
 struct VelocityLDS {
-  int list[NODE_VELOCITY_NODES];  // the wavefronts' lists, 512 entries each
-  int wcount[4];                  // their lengths
+  int list[4 * WN];  // the wavefronts' lists, WN entries each
+  int wcount[4];     // their lengths
 };
 
-template <typename T, bool SW = false>
+template <typename T, bool SW, int WN>
 __device__ __forceinline__ void node_velocity_range(const LatDev &L, int fsrc, int par,
-                                                    long long n0, long long n1, VelocityLDS &sm) {
+                                                    long long n0, long long n1,
+                                                    VelocityLDS<WN> &sm) {
   int *list = sm.list, *wcount = sm.wcount;
   const int step = L.ctrl->step;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  int *wl = list + wave * 512;
-  const long long w0 = n0 + (long long)wave * 512;
+  int *wl = list + wave * WN;
+  const long long w0 = n0 + (long long)wave * WN;
   int cnt = 0;
 #pragma unroll
-  for (int k = 0; k < 8; ++k) {
+  for (int k = 0; k < WN / 64; ++k) {
     const long long n = w0 + k * 64 + lane;
     const bool marked = n < n1 && L.nstamp[n] == step;
     const unsigned long long mask = __ballot(marked);
@@ -755,7 +768,7 @@ __device__ __forceinline__ void node_velocity_range(const LatDev &L, int fsrc, i
   for (int j = (int)threadIdx.x; j < total; j += 256) {
     const int w = (j >= c1) + (j >= c2) + (j >= c3);
     const int before = w == 0 ? 0 : (w == 1 ? c1 : (w == 2 ? c2 : c3));
-    const long long n = n0 + (long long)w * 512 + list[w * 512 + (j - before)];
+    const long long n = n0 + (long long)w * WN + list[w * WN + (j - before)];
     const long long row = n / L.nx;
     const int X = (int)(n - row * L.nx), Y = (int)(row % L.ny), Z = (int)(row / L.ny);
     const float3 u = SW ? lattice_velocity_swapped<T>(L, f, g, X, Y, Z)
@@ -766,10 +779,10 @@ __device__ __forceinline__ void node_velocity_range(const LatDev &L, int fsrc, i
 
 template <typename T, bool SW>
 __global__ __launch_bounds__(256) void k_node_velocity(LatDev L, int fsrc, int par) {
-  __shared__ VelocityLDS sm;
+  __shared__ VelocityLDS<NODE_VELOCITY_WN> sm;
   const long long N = (long long)L.nx * L.ny * L.nz;
   const long long n0 = (long long)blockIdx.x * NODE_VELOCITY_NODES;
-  node_velocity_range<T, SW>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES), sm);
+  node_velocity_range<T, SW, NODE_VELOCITY_WN>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES), sm);
 }
 
 // The lattice velocity is evaluated once per lattice node of the block's
@@ -1370,22 +1383,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8))) void k
   else batch_interp_m<T, 4>(L, Mm, fsrc, par, advect, it.y, sm);
 }
 
-// The velocity pass of every run, on the lattice work items: block k of a
-// run takes its nodes [k, k + 1) * NODE_VELOCITY_NODES.  A run has at least
-// that many items (a lattice-update block covers at most 1024 nodes), and
-// the ones past its last node return at once.
+// The velocity pass of every run, on the lattice work items: item k of a
+// run takes its nodes [k, k + 1) * BATCH_ITEM_NODES.
 template <typename T>
 __global__ __launch_bounds__(256) void k_batch_node_velocity(BatchDev B, int fsrc, int par) {
-  __shared__ VelocityLDS sm;
+  __shared__ VelocityLDS<BATCH_ITEM_NODES / 4> sm;
   if ((int)blockIdx.x >= B.n_lat_items) return;
   const int2 it = B.lat_items[blockIdx.x];
   const LatDev &L = B.lat[it.x];
   // no capsule (nothing is marked), or a run interpolating otherwise
   if (!B.mem[it.x].nn || !(B.mem[it.x].cmode & 4)) return;
   const long long N = (long long)L.nx * L.ny * L.nz;
-  const long long n0 = (long long)it.y * NODE_VELOCITY_NODES;
+  const long long n0 = (long long)it.y * BATCH_ITEM_NODES;
   if (n0 >= N) return;  // uniform across the block
-  node_velocity_range<T>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES), sm);
+  node_velocity_range<T, false, BATCH_ITEM_NODES / 4>(L, fsrc, par, n0, min(N, n0 + BATCH_ITEM_NODES), sm);
 }
 
 void launch_batch_spread(const BatchDev &B, int par, hipStream_t s) {
@@ -1446,7 +1457,7 @@ __global__ __launch_bounds__(256) void k_batch_persistent(BatchDev B, int src, i
   __shared__ union {
     SpreadLDS s;
     InterpLDS i;
-    VelocityLDS v;
+    VelocityLDS<BATCH_ITEM_NODES / 4> v;
   } sm;
   cooperative_groups::grid_group grid = cooperative_groups::this_grid();
   for (int b = blockIdx.x; b < B.n_node_items; b += gridDim.x) {
@@ -1475,10 +1486,11 @@ __global__ __launch_bounds__(256) void k_batch_persistent(BatchDev B, int src, i
       const LatDev &L = B.lat[it.x];
       if (!B.mem[it.x].nn || !(B.mem[it.x].cmode & 4)) continue;  // uniform across the block
       const long long N = (long long)L.nx * L.ny * L.nz;
-      const long long n0 = (long long)it.y * NODE_VELOCITY_NODES;  // as k_batch_node_velocity
+      const long long n0 = (long long)it.y * BATCH_ITEM_NODES;  // the item's whole range
       if (n0 >= N) continue;
-      node_velocity_range<T>(L, src ^ 1, par, n0, min(N, n0 + NODE_VELOCITY_NODES), sm.v);
-      __syncthreads();  // the node list is reused by the next item
+      node_velocity_range<T, false, BATCH_ITEM_NODES / 4>(L, src ^ 1, par, n0,
+                                                          min(N, n0 + BATCH_ITEM_NODES), sm.v);
+      __syncthreads();  // the node lists are reused by the next item
     }
     grid.sync();
   }
