@@ -777,12 +777,28 @@ __device__ __forceinline__ void node_velocity_range(const LatDev &L, int fsrc, i
   }
 }
 
+// Single lattices.  FP32: each thread takes one node and evaluates it if it
+// is marked (no lists: four wavefronts issuing their own gathers measured
+// 0.9 % faster steps on the dense suspension than one wavefront issuing the
+// block's compacted list); FP16 keeps the lists (1.4 % faster there).
 template <typename T, bool SW>
 __global__ __launch_bounds__(256) void k_node_velocity(LatDev L, int fsrc, int par) {
-  __shared__ VelocityLDS<NODE_VELOCITY_WN> sm;
   const long long N = (long long)L.nx * L.ny * L.nz;
   const long long n0 = (long long)blockIdx.x * NODE_VELOCITY_NODES;
-  node_velocity_range<T, SW, NODE_VELOCITY_WN>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES), sm);
+  if constexpr (sizeof(T) == 4) {
+    static_assert(NODE_VELOCITY_NODES == 256, "one node per thread of a 256-thread block");
+    const long long n = n0 + threadIdx.x;
+    if (n >= N || L.nstamp[n] != L.ctrl->step) return;
+    const long long row = n / L.nx;
+    const int X = (int)(n - row * L.nx), Y = (int)(row % L.ny), Z = (int)(row / L.ny);
+    const float *g = L.g[par];
+    const T *f = static_cast<const T *>(L.f[SW ? 0 : fsrc]);
+    const float3 u = SW ? lattice_velocity_swapped<T>(L, f, g, X, Y, Z) : lattice_velocity_of<T>(L, f, g, X, Y, Z);
+    L.U[n] = make_float4(u.x, u.y, u.z, 0.0f);
+  } else {
+    __shared__ VelocityLDS<NODE_VELOCITY_WN> sm;
+    node_velocity_range<T, SW, NODE_VELOCITY_WN>(L, fsrc, par, n0, min(N, n0 + NODE_VELOCITY_NODES), sm);
+  }
 }
 
 // The lattice velocity is evaluated once per lattice node of the block's
